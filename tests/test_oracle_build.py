@@ -1,0 +1,158 @@
+"""Pins of the oracle's Algorithm 1 (adaptive sketching H^2 construction) and H^2 matvec."""
+import numpy as np
+import pytest
+
+from oracle.build import SampleLimitError, _Builder, build_h2
+from oracle.h2 import power_method_error, relative_fro_error
+from oracle.kernels import CallbackOperator, KernelOperator
+from paper_2506_16759_amd.workloads import SMALL_2D, uniform_points
+
+
+def _monomials(pts, degree):
+    dim, n = pts.shape
+    cols = [np.ones(n)]
+    if dim == 2:
+        for a in range(degree + 1):
+            for b in range(degree + 1 - a):
+                if a + b:
+                    cols.append(pts[0] ** a * pts[1] ** b)
+    else:
+        for a in range(degree + 1):
+            for b in range(degree + 1 - a):
+                for c in range(degree + 1 - a - b):
+                    if a + b + c:
+                        cols.append(pts[0] ** a * pts[1] ** b * pts[2] ** c)
+    return np.stack(cols, axis=1)
+
+
+@pytest.fixture(scope="module")
+def small2d():
+    w = SMALL_2D
+    pts = w.points()
+    op = KernelOperator(pts, w.kernel, w.length)
+    h = build_h2(op, pts, w.leaf_size, w.eta, w.tol, w.d0, w.d_inc, 1024, w.omega_seed)
+    return w, pts, op, h
+
+
+def test_blocked_sketch_equals_dense_product():
+    pts = uniform_points(700, 3, 2)
+    op = KernelOperator(pts, "exp", 0.2, block_rows=64)
+    om = np.random.default_rng(0).standard_normal((700, 5))
+    np.testing.assert_allclose(op.sketch(om), op.dense() @ om, rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,degree", [(2, 3), (3, 2)])
+def test_exact_low_rank_recovered(dim, degree):
+    # K = Phi Phi^T has rank r = #monomials (10): every far block is exact, the
+    # ranks never exceed r and the whole matrix is reproduced to rounding.
+    pts = uniform_points(2048, dim, 21)
+    Phi = _monomials(pts, degree)
+    r = Phi.shape[1]
+    op = CallbackOperator(2048, sketch=lambda om: Phi @ (Phi.T @ om),
+                          entries=lambda i, j: Phi[i] @ Phi[j].T)
+    h = build_h2(op, pts, leaf_size=32, eta=0.7, tol=1e-13, d0=16, d_inc=8, seed=5)
+    K = Phi @ Phi.T
+    assert max(v.max() for v in h.ranks().values()) <= r
+    assert relative_fro_error(K, h.dense()) < 1e-12
+    x = np.random.default_rng(1).standard_normal((2048, 3))
+    np.testing.assert_allclose(h.matvec(x), K @ x, rtol=0, atol=1e-11 * np.abs(K @ x).max())
+
+
+def test_small_2d_errors_within_ten_tol(small2d):
+    w, pts, op, h = small2d
+    K = op.dense()
+    KH = h.dense()
+    assert relative_fro_error(K, KH) <= 10 * w.tol
+    x = np.random.default_rng(8).standard_normal((w.n, 8))
+    assert np.linalg.norm(K @ x - h.matvec(x)) / np.linalg.norm(K @ x) <= 10 * w.tol
+    e2 = power_method_error(lambda v: KH @ v - K @ v, lambda v: K @ v, w.n)
+    assert e2 <= 10 * w.tol
+
+
+def test_matvec_equals_dense_reconstruction(small2d):
+    # two independent evaluations of the same H^2 matrix: the nested-basis
+    # product and the explicitly assembled blocks
+    w, pts, op, h = small2d
+    x = np.random.default_rng(9).standard_normal((w.n, 3))
+    np.testing.assert_allclose(h.matvec(x), h.dense() @ x, rtol=1e-12, atol=1e-12)
+
+
+def test_near_blocks_and_identity_rows(small2d):
+    w, pts, op, h = small2d
+    perm = h.tree.perm
+    for (s, b), Dsb in list(h.Dn.items())[:50]:
+        np.testing.assert_array_equal(Dsb, op.entries(perm[h.rows(h.tree.depth, s)],
+                                                       perm[h.rows(h.tree.depth, b)]))
+    D = h.tree.depth
+    for i in range(1 << D):
+        sk = h.skel[(D, i)] - h.tree.begin[(1 << D) - 1 + i]
+        np.testing.assert_array_equal(h.U[i][sk], np.eye(len(sk)))
+
+
+def test_far_blocks_within_tol(small2d):
+    # nested basis (eq. nested_basis) reproduces each admissible block
+    w, pts, op, h = small2d
+    perm = h.tree.perm
+    K = op.dense()
+    for t in range(h.top, h.tree.depth + 1):
+        bases = [h.basis(t, i) for i in range(1 << t)]
+        for (tt, s, b), B in h.B.items():
+            if tt != t:
+                continue
+            rs, rb = perm[h.rows(t, s)], perm[h.rows(t, b)]
+            blk = K[np.ix_(rs, rb)]
+            err = np.linalg.norm(blk - bases[s] @ B @ bases[b].T)
+            assert err <= 10 * w.tol * np.linalg.norm(K) / np.sqrt(len(h.B))
+
+
+def test_leaf_local_samples_equal_masked_product():
+    # Y_loc of a leaf = K(I_tau, complement of the near field) Omega(complement, :)
+    pts = uniform_points(1500, 2, 4)
+    op = KernelOperator(pts, "exp", 0.1)
+    b = _Builder(op, pts, 32, 0.7, 1e-6, 16, 8, 1024, 77, "fro_scaled")
+    h = b.run()
+    D = h.tree.depth
+    perm = h.tree.perm
+    d_leaf = b.om_in[D][0].shape[1]
+    from oracle.philox import gaussian
+    om = gaussian(77, perm, 0, d_leaf)                     # tree order
+    K = op.dense()[np.ix_(perm, perm)]
+    npp, ni = h.lists.near_ptr, h.lists.near_idx
+    for s in (0, 5, (1 << D) - 1):
+        rows = h.rows(D, s)
+        mask = np.ones(h.tree.n, dtype=bool)
+        for j in range(npp[s], npp[s + 1]):
+            mask[h.rows(D, int(ni[j]))] = False
+        ref = K[np.ix_(rows, np.nonzero(mask)[0])] @ om[mask]
+        yloc = b.y_out[D][s]                                 # = Y_loc(J, :)
+        J = b.J[(D, s)]
+        np.testing.assert_allclose(yloc, ref[J], rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_adaptive_rounds_add_samples_and_stay_accurate():
+    # tight tol and few initial samples force adaptive rounds (Sec. III-B)
+    pts = uniform_points(3000, 3, 6)
+    op = KernelOperator(pts, "exp", 0.2)
+    h = build_h2(op, pts, leaf_size=48, eta=0.7, tol=1e-7, d0=8, d_inc=8, seed=3)
+    assert h.samples > 8 and sum(h.rounds.values()) >= 1
+    K = op.dense()
+    assert relative_fro_error(K, h.dense()) <= 10 * 1e-7
+
+
+def test_sample_limit_raises():
+    pts = uniform_points(3000, 3, 6)
+    op = KernelOperator(pts, "exp", 0.2)
+    with pytest.raises(SampleLimitError):
+        build_h2(op, pts, leaf_size=48, eta=0.7, tol=1e-10, d0=8, d_inc=8, d_max=16, seed=3)
+
+
+def test_degenerate_inputs():
+    pts = uniform_points(40, 2, 1)
+    op = KernelOperator(pts, "gauss", 0.3)
+    h = build_h2(op, pts, leaf_size=64)                  # single leaf: one dense block
+    np.testing.assert_array_equal(h.dense(), op.dense())
+    pts = uniform_points(600, 2, 1)
+    op = KernelOperator(pts, "exp", 0.1)
+    h = build_h2(op, pts, leaf_size=16, eta=1e-12)       # nothing admissible
+    np.testing.assert_array_equal(h.dense(), op.dense())
+    assert h.samples == 0
