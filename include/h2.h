@@ -1,0 +1,207 @@
+/*
+ * h2.h -- C ABI of the MI355X (gfx950) H^2 construction library.
+ *
+ * Builds an H^2 matrix of a symmetric kernel matrix K(x_i, x_j) on a point
+ * cloud with the bottom-up adaptive-sketching construction of
+ * "Adaptive Sketching Based Construction of H2 Matrices on GPUs"
+ * (Boukaram, Liu, Ghysels, Li; arXiv 2506.16759), Algorithm 1 with the
+ * adaptive sampling of Sec. III-B.
+ *
+ * Conventions shared by every call
+ *   - Every function returns an h2_status (0 = H2_OK, negative = error) and
+ *     never throws.  On error, output handles are set to NULL, nothing is
+ *     leaked, and h2_last_error() returns a thread-local message.
+ *   - Points are structure-of-arrays float64: a (dim x n) row-major array,
+ *     coordinate a of point i at points[a*n + i]; 1 <= dim <= 3, n < 2^31.
+ *   - Dense vectors/matrices are column-major float64 with a leading
+ *     dimension argument (ld >= rows).  "Original order" means the caller's
+ *     point order.
+ *   - Device pointers must be allocations on the context's device; host
+ *     pointers are plain host memory.  The library never frees caller memory.
+ *   - Calls that take an h2_ctx enqueue on the context's stream.  h2_build is
+ *     synchronous (it returns after the build completed); h2_matvec,
+ *     h2_sketch and h2_gaussian are stream-ordered (synchronise the stream
+ *     before reading results on the host).
+ *   - One context per host thread; a context's calls must not overlap.
+ */
+#ifndef H2_H
+#define H2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_ARG = -1,       /* invalid argument (NULL, size, ld, option out of range) */
+  H2_ERR_HIP = -2,       /* a HIP runtime call failed */
+  H2_ERR_OOM = -3,       /* device allocation failed */
+  H2_ERR_CALLBACK = -4,  /* reserved: a user callback returned non-zero */
+  H2_ERR_SAMPLES = -5,   /* adaptive sampling reached d_max unconverged */
+  H2_ERR_STATE = -6,     /* object in the wrong state (e.g. export of a missing part) */
+  H2_ERR_UNSUPPORTED = -7 /* request outside what this build implements */
+} h2_status;
+
+/* Kernel functions kappa(r), r = |x - y| (Sec. V-A).  kappa(0) = 1. */
+typedef enum {
+  H2_K_EXP = 1,   /* exponential covariance exp(-r / length), eq. (cov) */
+  H2_K_GAUSS = 2  /* Gaussian covariance exp(-r^2 / (2 length^2)) */
+} h2_kernel_kind;
+
+typedef struct {
+  int32_t kind;   /* h2_kernel_kind */
+  double length;  /* correlation length l > 0 */
+} h2_kernel;
+
+/* Arithmetic of the sketch and near-field products (the construction's
+ * stopping test, norm downdating and interpolation solve are always FP64). */
+typedef enum { H2_FP64 = 0 } h2_precision;
+
+/* How the absolute ID/stopping threshold delta is derived from tol
+ * (Sec. III-B: "an approximate norm of the matrix ... via sketching"):
+ *   nu = ||Y_0||_F / sqrt(d0)  (unbiased estimate of ||K||_F)
+ *   H2_NORM_FRO_SCALED: delta = tol * nu / sqrt(#leaves)
+ *   H2_NORM_LITERAL:    delta = tol * nu                                    */
+typedef enum { H2_NORM_FRO_SCALED = 0, H2_NORM_LITERAL = 1 } h2_norm_mode;
+
+typedef struct {
+  double tol;         /* relative compression tolerance epsilon, > 0 (Alg. 1 input) */
+  int32_t leaf_size;  /* KD-tree leaf size m0, 2..256 */
+  double eta;         /* general admissibility parameter (Sec. II-A), > 0 */
+  int32_t d0;         /* initial sample columns (Alg. 1 "sample block size"), 1..128 */
+  int32_t d_inc;      /* columns added per adaptive round (Sec. III-B), 1..128 */
+  int32_t d_max;      /* cap on total columns, <= 128; exceeding it -> H2_ERR_SAMPLES */
+  uint64_t seed;      /* key of the counter-based Gaussian test matrix */
+  int32_t precision;  /* h2_precision */
+  int32_t norm_mode;  /* h2_norm_mode */
+} h2_opts;
+
+typedef struct h2_ctx h2_ctx;
+typedef struct h2_matrix h2_matrix;
+typedef struct h2_plan h2_plan;
+
+/* Fills defaults: tol 1e-6, leaf 64, eta 0.7, d0 32, d_inc 16, d_max 128,
+ * seed 1000, FP64, FRO_SCALED. */
+h2_status h2_opts_default(h2_opts* opts);
+
+const char* h2_status_string(h2_status s);
+const char* h2_last_error(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context bound to HIP device `device` and stream `stream`
+ * (a hipStream_t passed as void*; NULL = the default stream).  The stream is
+ * borrowed and must outlive the context. */
+h2_status h2_ctx_create(int device, void* stream, h2_ctx** out);
+h2_status h2_ctx_destroy(h2_ctx* ctx);
+
+/* ------------------------------------------------ host-only cluster plan */
+
+/* Cluster tree and interaction lists of Sec. II-A, computed on the host with
+ * no GPU involved (the same code h2_build runs).  KD bisection with tight
+ * boxes, widest axis (lowest on ties), stable median by (coordinate, original
+ * index), left child floor(n/2); leaves all at depth D = min{d : ceil(n/2^d)
+ * <= leaf_size}; general admissibility (D(s)+D(t))/2 <= eta*Dist(s,t)
+ * evaluated without square roots, touching boxes never admissible; dual-tree
+ * traversal from (root, root).  points: HOST, (dim x n) SoA. */
+h2_status h2_plan_create(int64_t n, int32_t dim, const double* points_host, int32_t leaf_size,
+                         double eta, h2_plan** out);
+h2_status h2_plan_free(h2_plan* plan);
+
+/* Parts exported by h2_plan_export and h2_export.  `depth` selects the tree
+ * depth where a part is per depth; node indices inside a depth are local
+ * (heap id - (2^depth - 1)). */
+typedef enum {
+  H2_PART_DEPTH = 0,     /* int32[1]: D */
+  H2_PART_PERM = 1,      /* int32[n]: tree position -> original index */
+  H2_PART_NODES = 2,     /* int32[2 * (2^(D+1)-1)]: [begin, end) per heap node */
+  H2_PART_BOXES = 3,     /* float64[(2^(D+1)-1) * 2 * dim]: lo[dim], hi[dim] per node */
+  H2_PART_NEAR_PTR = 4,  /* int32[2^D + 1]: CSR row pointers of N_tau (leaf depth) */
+  H2_PART_NEAR_IDX = 5,  /* int32[nnz]: ascending local leaf indices */
+  H2_PART_FAR_PTR = 6,   /* int32[2^depth + 1]: CSR of F_tau at `depth` */
+  H2_PART_FAR_IDX = 7,   /* int32[nnz] */
+  /* parts below exist only for built matrices (h2_export) */
+  H2_PART_RANKS = 8,     /* int32[2^depth]: k_tau at `depth` (0 above the top depth) */
+  H2_PART_SKEL = 9,      /* int32[sum k]: skeleton ORIGINAL indices, node by node */
+  H2_PART_BASIS = 10,    /* float64: the ID matrix of every node at `depth`, node by node,
+                            each m_tau x k_tau column-major (leaf: U_tau; inner: [E_nu1; E_nu2]) */
+  H2_PART_COUPLING = 11, /* float64: B_{s,b} for the far pairs at `depth` in CSR order,
+                            each k_s x k_b column-major */
+  H2_PART_DENSE = 12,    /* float64: D_{s,b} for the near pairs in CSR order, each
+                            m_s x m_b column-major (rows/cols in tree order) */
+  H2_PART_TOP = 13,      /* int32[1]: coarsest processed depth */
+  H2_PART_SKEL_POS = 14  /* int32[sum k]: skeleton tree positions, node by node */
+} h2_part;
+
+/* Copies a part into host memory dst (dst_bytes large).  dst == NULL only
+ * reports the size in *needed (bytes). */
+h2_status h2_plan_export(const h2_plan* plan, int32_t part, int32_t depth, void* dst,
+                         size_t dst_bytes, size_t* needed);
+
+/* ------------------------------------------------------------ step calls */
+
+/* Counter-based Gaussian test matrix of Alg. 1 (batchedRand):
+ *   out[p + c*ldo] = Omega(rows[p], col0 + c), p < nrows, c < ncols,
+ * with Omega(i, j) = sqrt(-2 ln u1) cos(2 pi u2), (u1, u2) from the first two
+ * words of Philox4x64-10 (counter (i, j, 0, 0), key (seed, 0)) mapped to (0,1)
+ * as (w >> 11) * 2^-53 + 2^-54.  rows: DEVICE int32 original indices; out:
+ * DEVICE.  Stream-ordered. */
+h2_status h2_gaussian(h2_ctx* ctx, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0,
+                      int32_t ncols, double* out, int64_t ldo);
+
+/* Dense on-the-fly sketch Y = K(X, X) * Omega without storing K (the black box
+ * Y = K_blk(Omega) of Alg. 1 for a kernel matrix): kernel tiles are generated
+ * in registers and contracted with Omega on the matrix cores.
+ * points: DEVICE (dim x n) SoA; omega: DEVICE n x ncols (ld ldo); y: DEVICE
+ * n x ncols (ld ldy), overwritten.  ncols <= 128.  Stream-ordered. */
+h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                    int32_t precision, int32_t ncols, const double* omega, int64_t ldo, double* y,
+                    int64_t ldy);
+
+/* ------------------------------------------------------------------ build */
+
+/* Algorithm 1 + adaptive sampling (Sec. III) for the kernel matrix
+ * K(i, j) = kappa(|x_i - x_j|).  points: DEVICE (dim x n) SoA, borrowed for
+ * the call.  Synchronous.  *out owns every result until h2_free. */
+h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                   const h2_opts* opts, h2_matrix** out);
+
+/* y = K_H x for nrhs columns, x and y DEVICE n x nrhs in ORIGINAL order
+ * (ld >= n); y overwritten.  Standard H^2 product: upsweep through the
+ * nested basis, coupling, downsweep, near field.  Stream-ordered. */
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* h, int32_t nrhs, const double* x, int64_t ldx,
+                    double* y, int64_t ldy);
+
+/* Same parts as h2_plan_export plus the built factors (RANKS .. SKEL_POS).
+ * Copies to HOST memory; synchronises the matrix's stream. */
+h2_status h2_export(const h2_matrix* h, int32_t part, int32_t depth, void* dst, size_t dst_bytes,
+                    size_t* needed);
+
+typedef struct {
+  int64_t n;
+  int32_t dim, depth, top;     /* tree depth D, coarsest processed depth */
+  int32_t samples;             /* total sample columns drawn */
+  int32_t rounds;              /* adaptive rounds over all levels */
+  int32_t rank_min, rank_max;  /* over all processed nodes */
+  double delta;                /* absolute threshold used */
+  double norm_estimate;        /* nu = ||Y_0||_F / sqrt(d0) */
+  int64_t near_blocks, far_blocks;
+  int64_t bytes_dense, bytes_coupling, bytes_basis; /* stored factor sizes */
+  /* phase times in milliseconds (HIP events on the context stream) */
+  double t_total, t_tree, t_sample, t_near_gen, t_subtract, t_convtest, t_id, t_upsweep,
+      t_coupling, t_misc;
+  double sketch_flops;         /* algorithmic 2*n*n*columns summed over sketch passes */
+  double sketch_entries;       /* kernel entries evaluated by the sketch passes */
+} h2_info;
+
+h2_status h2_query(const h2_matrix* h, h2_info* info);
+h2_status h2_free(h2_matrix* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2_H */

@@ -1,0 +1,197 @@
+"""Python binding of libh2, the MI355X H^2 construction library (include/h2.h).
+
+Argument marshalling only: every step of the construction runs in the HIP
+kernels behind the C ABI.  PyTorch provides device memory and the stream.
+Column-major (n x c) device matrices are represented by the transpose view of
+a C-contiguous (c, n) torch tensor, so ``t.data_ptr()`` is the column-major
+buffer with leading dimension n.
+
+The library is loaded lazily; importing this package needs neither the GPU nor
+the built library (``workloads`` and ``plan_create`` work on any host).
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
+
+__all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "H2Matrix",
+           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "NORM_FRO_SCALED", "NORM_LITERAL"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def kernel_spec(kind, length: float) -> _lib.Kernel:
+    k = {"exp": K_EXP, "gauss": K_GAUSS}.get(kind, kind)
+    return _lib.Kernel(int(k), float(length))
+
+
+def opts_default(**over) -> _lib.Opts:
+    o = _lib.Opts()
+    _lib.check(_lib.load().h2_opts_default(C.byref(o)), "h2_opts_default")
+    for k, v in over.items():
+        if k == "norm_mode" and isinstance(v, str):
+            v = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _export(fn, handle, name: str, depth: int = 0) -> np.ndarray:
+    part = _lib.PART[name]
+    need = C.c_size_t(0)
+    _lib.check(fn(handle, part, depth, None, 0, C.byref(need)), "export")
+    dt = np.dtype(_lib.PART_DTYPE[name])
+    out = np.empty(need.value // dt.itemsize, dtype=dt)
+    if need.value:
+        _lib.check(fn(handle, part, depth, out.ctypes.data_as(C.c_void_p), need.value, C.byref(need)), "export")
+    return out
+
+
+class Plan:
+    """Host-only cluster tree + interaction lists (h2_plan_*)."""
+
+    def __init__(self, points: np.ndarray, leaf_size: int, eta: float):
+        self._h = None
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        dim, n = pts.shape
+        h = C.c_void_p()
+        lib = _lib.load()
+        _lib.check(lib.h2_plan_create(n, dim, pts.ctypes.data_as(C.c_void_p), leaf_size, float(eta), C.byref(h)),
+                   "h2_plan_create")
+        self._h = h
+        self.n, self.dim = n, dim
+
+    def export(self, name: str, depth: int = 0) -> np.ndarray:
+        return _export(_lib.load().h2_plan_export, self._h, name, depth)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().h2_plan_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def plan_create(points: np.ndarray, leaf_size: int = 64, eta: float = 0.7) -> Plan:
+    return Plan(points, leaf_size, eta)
+
+
+class Context:
+    """h2_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._h = None
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library needs an MI355X")
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        _lib.check(_lib.load().h2_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)), "h2_ctx_create")
+        self._h = h
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().h2_ctx_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def _colmajor(t, rows: int):
+    """Check that t is a (rows, c) view of a contiguous (c, rows) float64 cuda tensor."""
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("expected a float64 cuda tensor")
+    if t.dim() != 2 or t.shape[0] != rows or t.stride(0) != 1 or t.stride(1) < rows:
+        raise ValueError("expected an (n, c) column-major view (the transpose of a contiguous (c, n) tensor)")
+    return t.stride(1)
+
+
+def empty_colmajor(n: int, c: int, device="cuda"):
+    return _torch().empty((c, n), dtype=_torch().float64, device=device).T
+
+
+def gaussian(ctx: Context, seed: int, rows, col0: int, ncols: int):
+    """Omega(rows, col0:col0+ncols) as an (len(rows), ncols) column-major tensor (h2_gaussian)."""
+    torch = _torch()
+    rows = rows.to(device="cuda", dtype=torch.int32).contiguous()
+    n = rows.numel()
+    out = empty_colmajor(n, ncols)
+    _lib.check(_lib.load().h2_gaussian(ctx._h, seed, n, C.c_void_p(rows.data_ptr()), col0, ncols,
+                                       C.c_void_p(out.data_ptr()), max(n, 1)), "h2_gaussian")
+    return out
+
+
+def sketch(ctx: Context, points, kernel, length: float, omega, precision: int = FP64):
+    """Y = K(points, points) Omega with the fused on-the-fly kernel (h2_sketch)."""
+    torch = _torch()
+    pts = points.to(device="cuda", dtype=torch.float64).contiguous()
+    dim, n = pts.shape
+    ldo = _colmajor(omega, n)
+    nc = omega.shape[1]
+    y = empty_colmajor(n, nc)
+    k = kernel_spec(kernel, length)
+    _lib.check(_lib.load().h2_sketch(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), C.byref(k), precision, nc,
+                                     C.c_void_p(omega.data_ptr()), ldo, C.c_void_p(y.data_ptr()), max(n, 1)),
+               "h2_sketch")
+    return y
+
+
+class H2Matrix:
+    """A built H^2 matrix (h2_matrix): matvec, export, query."""
+
+    def __init__(self, ctx: Context, handle, n: int):
+        self.ctx, self._h, self.n = ctx, handle, n
+
+    def matvec(self, x):
+        """K_H x for x an (n, c) column-major cuda tensor (or an (n,) vector)."""
+        vec = x.dim() == 1
+        if vec:
+            x = x.reshape(1, -1).T
+        ldx = _colmajor(x, self.n)
+        c = x.shape[1]
+        y = empty_colmajor(self.n, c)
+        _lib.check(_lib.load().h2_matvec(self.ctx._h, self._h, c, C.c_void_p(x.data_ptr()), ldx,
+                                         C.c_void_p(y.data_ptr()), self.n), "h2_matvec")
+        return y[:, 0] if vec else y
+
+    def export(self, name: str, depth: int = 0) -> np.ndarray:
+        return _export(_lib.load().h2_export, self._h, name, depth)
+
+    def info(self) -> dict:
+        inf = _lib.Info()
+        _lib.check(_lib.load().h2_query(self._h, C.byref(inf)), "h2_query")
+        return inf.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().h2_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+
+def build(ctx: Context, points, kernel="exp", length: float = 0.2, opts: _lib.Opts | None = None,
+          **opt_over) -> H2Matrix:
+    """Algorithm 1 with adaptive sampling on the GPU (h2_build).  points: (dim, n)."""
+    torch = _torch()
+    pts = torch.as_tensor(points).to(device="cuda", dtype=torch.float64).contiguous()
+    dim, n = pts.shape
+    o = opts if opts is not None else opts_default(**opt_over)
+    k = kernel_spec(kernel, length)
+    h = C.c_void_p()
+    _lib.check(_lib.load().h2_build(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), C.byref(k), C.byref(o),
+                                    C.byref(h)), "h2_build")
+    return H2Matrix(ctx, h, n)

@@ -1,0 +1,952 @@
+// C ABI of the H^2 construction library: argument checking, device memory,
+// and the host-driven level loop of Algorithm 1 with adaptive sampling
+// (Sec. III-A, III-B).  All arithmetic runs in the kernels of h2_kernels.hip;
+// the host only plans (cluster tree, interaction lists, offsets) and decides
+// when to draw more samples.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "h2.h"
+#include "h2_device.hpp"
+#include "h2_plan.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  h2_status status;
+  Error(h2_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+#define H2_HIP(expr)                                                                                    \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      throw Error(e_ == hipErrorOutOfMemory ? H2_ERR_OOM : H2_ERR_HIP,                                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                                   \
+  } while (0)
+
+#define H2_REQUIRE(cond, msg)                   \
+  do {                                          \
+    if (!(cond)) throw Error(H2_ERR_ARG, msg);  \
+  } while (0)
+
+template <typename F>
+h2_status guarded(F&& f) {
+  try {
+    f();
+    return H2_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
+    return H2_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return H2_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return H2_ERR_HIP;
+  }
+}
+
+// Stream-ordered device array.
+template <typename T>
+class DevArray {
+ public:
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  DevArray& operator=(const DevArray&) = delete;
+  DevArray(DevArray&& o) noexcept { *this = std::move(o); }
+  DevArray& operator=(DevArray&& o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      s_ = o.s_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+    }
+    return *this;
+  }
+  ~DevArray() { release(); }
+
+  void alloc(size_t n, hipStream_t s) {
+    release();
+    s_ = s;
+    n_ = n;
+    if (n == 0) return;
+    void* p = nullptr;
+    H2_HIP(hipMallocAsync(&p, n * sizeof(T), s));
+    p_ = static_cast<T*>(p);
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size(), s);
+    if (!h.empty()) H2_HIP(hipMemcpyAsync(p_, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void release() {
+    if (p_) (void)hipFreeAsync(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  size_t bytes() const { return n_ * sizeof(T); }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+};
+
+template <typename T>
+std::vector<T> download(const T* d, size_t n, hipStream_t s) {
+  std::vector<T> h(n);
+  if (n) {
+    H2_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+  }
+  return h;
+}
+
+// Phase timer on HIP events: record pairs, resolve after the stream is synchronised.
+class PhaseTimer {
+ public:
+  explicit PhaseTimer(hipStream_t s) : s_(s) {}
+  ~PhaseTimer() {
+    for (auto& r : recs_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+  int begin(int phase) {
+    Rec r{phase, nullptr, nullptr};
+    H2_HIP(hipEventCreate(&r.a));
+    H2_HIP(hipEventCreate(&r.b));
+    H2_HIP(hipEventRecord(r.a, s_));
+    recs_.push_back(r);
+    return static_cast<int>(recs_.size()) - 1;
+  }
+  void end(int h) { H2_HIP(hipEventRecord(recs_[h].b, s_)); }
+  void totals(double* out, int nphase) {
+    H2_HIP(hipStreamSynchronize(s_));
+    for (int p = 0; p < nphase; ++p) out[p] = 0;
+    for (auto& r : recs_) {
+      float ms = 0;
+      H2_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      out[r.phase] += ms;
+    }
+  }
+
+ private:
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  hipStream_t s_;
+  std::vector<Rec> recs_;
+};
+
+enum Phase { kTree, kSample, kNearGen, kSubtract, kConv, kId, kUpsweep, kCoupling, kMisc, kNumPhase };
+
+// Per-depth results of the construction.  Rows of depth t live in row space
+// R_t (in-rows, `rowoff`) and the skeleton rows in R_{t-1} (`koff`).
+struct Level {
+  int t = 0, nn = 0;
+  bool processed = false;
+  std::vector<int32_t> rowoff_h, k_h, koff_h;
+  std::vector<int64_t> joff_h, uoff_h;
+  int max_m = 0, max_k = 0;
+  DevArray<int32_t> rowoff, koff, J, pos_out;
+  DevArray<int64_t> joff, uoff;
+  DevArray<double> U, xs_out;
+  // far blocks at this depth
+  std::vector<int32_t> fptr_h, fidx_h;
+  std::vector<int64_t> boff_h;
+  DevArray<int32_t> fptr, fidx;
+  DevArray<int64_t> boff;
+  DevArray<double> B;
+  // sample buffers of row space R_t (capacity columns), only during a build
+  DevArray<double> om, y;
+  int64_t M = 0;
+};
+
+}  // namespace
+
+struct h2_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t lds_limit = 65536;
+};
+
+struct h2_plan {
+  h2::Plan plan;
+};
+
+struct h2_matrix {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  h2::Plan plan;
+  h2_kernel kernel{};
+  h2_opts opts{};
+  int top = 1;
+  double delta = 0, nu = 0;
+  int samples = 0, rounds = 0;
+  DevArray<int32_t> perm;
+  DevArray<double> X;  // tree-ordered SoA points
+  DevArray<int32_t> nptr, nidx, leafoff;
+  DevArray<int64_t> doff;
+  std::vector<int64_t> doff_h;
+  std::vector<int32_t> leafoff_h;
+  DevArray<double> Dblk;
+  std::vector<Level> lv;  // indexed by depth
+  double phase_ms[kNumPhase] = {};
+  double total_ms = 0;
+  double sketch_flops = 0, sketch_entries = 0;
+};
+
+namespace {
+
+h2dev::KernelFn kernel_fn(const h2_kernel& k) {
+  h2dev::KernelFn f;
+  f.kind = k.kind;
+  f.scale = k.kind == H2_K_EXP ? 1.0 / k.length : 1.0 / (2.0 * k.length * k.length);
+  return f;
+}
+
+void check_kernel(const h2_kernel* k) {
+  H2_REQUIRE(k != nullptr, "kernel is NULL");
+  H2_REQUIRE(k->kind == H2_K_EXP || k->kind == H2_K_GAUSS, "unknown kernel kind");
+  H2_REQUIRE(k->length > 0.0 && std::isfinite(k->length), "kernel length must be finite and > 0");
+}
+
+void check_opts(const h2_opts* o) {
+  H2_REQUIRE(o != nullptr, "opts is NULL");
+  H2_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be finite and > 0");
+  H2_REQUIRE(o->leaf_size >= 2 && o->leaf_size <= 256, "leaf_size must be in [2, 256]");
+  H2_REQUIRE(o->eta > 0.0 && std::isfinite(o->eta), "eta must be finite and > 0");
+  H2_REQUIRE(o->d0 >= 1 && o->d0 <= 128, "d0 must be in [1, 128]");
+  H2_REQUIRE(o->d_inc >= 1 && o->d_inc <= 128, "d_inc must be in [1, 128]");
+  H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 128, "d_max must be in [d0, 128]");
+  H2_REQUIRE(o->precision == H2_FP64, "only H2_FP64 is implemented");
+  H2_REQUIRE(o->norm_mode == H2_NORM_FRO_SCALED || o->norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
+}
+
+int top_depth(const h2::Plan& p) {
+  for (int t = 1; t <= p.depth; ++t)
+    if (!p.far_idx[t].empty()) return t;
+  return p.depth + 1;
+}
+
+template <typename T>
+std::vector<T> prefix(const std::vector<T>& sizes) {
+  std::vector<T> off(sizes.size() + 1, 0);
+  for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + sizes[i];
+  return off;
+}
+
+class Builder {
+ public:
+  Builder(h2_ctx* ctx, h2_matrix* h) : ctx_(ctx), h_(h), s_(ctx->stream), timer_(ctx->stream) {}
+
+  void run(int64_t n, int dim, const double* points) {
+    hipEvent_t t0, t1;
+    H2_HIP(hipEventCreate(&t0));
+    H2_HIP(hipEventCreate(&t1));
+    H2_HIP(hipEventRecord(t0, s_));
+    try {
+      run_inner(n, dim, points);
+    } catch (...) {
+      (void)hipStreamSynchronize(s_);
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      throw;
+    }
+    H2_HIP(hipEventRecord(t1, s_));
+    H2_HIP(hipStreamSynchronize(s_));
+    float ms = 0;
+    H2_HIP(hipEventElapsedTime(&ms, t0, t1));
+    h_->total_ms = ms;
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    timer_.totals(h_->phase_ms, kNumPhase);
+    // drop the build-only sample buffers
+    for (auto& L : h_->lv) {
+      L.om.release();
+      L.y.release();
+    }
+  }
+
+ private:
+  h2_ctx* ctx_;
+  h2_matrix* h_;
+  hipStream_t s_;
+  PhaseTimer timer_;
+  h2dev::KernelFn kf_{};
+  int dcap_ = 0, d_ = 0;
+  DevArray<double> gws_;
+  DevArray<int64_t> gws_off_;
+  DevArray<int32_t> conv_, counter_;
+  DevArray<double> minr_;
+
+  void run_inner(int64_t n, int dim, const double* points) {
+    h2_matrix& h = *h_;
+    const h2_opts& o = h.opts;
+    kf_ = kernel_fn(h.kernel);
+    // ---- plan (host): tree + lists
+    int ph = timer_.begin(kTree);
+    std::vector<double> pts_h(static_cast<size_t>(n) * dim);
+    H2_HIP(hipMemcpyAsync(pts_h.data(), points, pts_h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
+    H2_HIP(hipStreamSynchronize(s_));
+    h.plan = h2::make_plan(n, dim, pts_h.data(), o.leaf_size, o.eta);
+    const h2::Plan& p = h.plan;
+    const int D = p.depth;
+    h.perm.upload(p.perm, s_);
+    h.X.alloc(static_cast<size_t>(n) * dim, s_);
+    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
+    timer_.end(ph);
+
+    // ---- dense near-field blocks D_{tau,b} = K(I_tau, I_b)  (Alg. 1 batchedGen)
+    ph = timer_.begin(kNearGen);
+    const int nleaves = 1 << D;
+    h.leafoff_h.assign(nleaves + 1, 0);
+    for (int i = 0; i < nleaves; ++i) h.leafoff_h[i] = p.begin[p.level_begin(D) + i];
+    h.leafoff_h[nleaves] = static_cast<int32_t>(n);
+    std::vector<int64_t> dsz(p.near_idx.size());
+    int leaf_max = 0;
+    for (int s = 0; s < nleaves; ++s) {
+      const int ms = h.leafoff_h[s + 1] - h.leafoff_h[s];
+      leaf_max = std::max(leaf_max, ms);
+      for (int j = p.near_ptr[s]; j < p.near_ptr[s + 1]; ++j) {
+        const int b = p.near_idx[j];
+        dsz[j] = int64_t(ms) * (h.leafoff_h[b + 1] - h.leafoff_h[b]);
+      }
+    }
+    h.doff_h = prefix(dsz);
+    h.nptr.upload(p.near_ptr, s_);
+    h.nidx.upload(p.near_idx, s_);
+    h.leafoff.upload(h.leafoff_h, s_);
+    h.doff.upload(h.doff_h, s_);
+    h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), s_);
+    H2_HIP(h2dev::gen_blocks(s_, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim, h.X.get(), n,
+                             kf_, h.Dblk.get()));
+    timer_.end(ph);
+
+    h.lv.clear();
+    h.lv.resize(D + 1);
+    for (int t = 0; t <= D; ++t) {
+      h.lv[t].t = t;
+      h.lv[t].nn = 1 << t;
+    }
+    h.top = top_depth(p);
+    if (h.top > D) return;  // no admissible block: the dense blocks are the whole matrix
+
+    // ---- first sketch Y = K Omega  (Alg. 1 batchedRand + black box)
+    ph = timer_.begin(kSample);
+    dcap_ = o.d_max;
+    Level& leaf = h.lv[D];
+    leaf.M = n;
+    leaf.om.alloc(static_cast<size_t>(n) * dcap_, s_);
+    leaf.y.alloc(static_cast<size_t>(n) * dcap_, s_);
+    draw(0, o.d0);
+    d_ = o.d0;
+    // nu = ||Y_0||_F / sqrt(d0): deterministic two-stage sum
+    const int nb = 512;
+    DevArray<double> part;
+    part.alloc(nb, s_);
+    H2_HIP(h2dev::sumsq_partial(s_, n, o.d0, leaf.y.get(), n, part.get(), nb));
+    std::vector<double> part_h = download(part.get(), nb, s_);
+    double ss = 0;
+    for (double v : part_h) ss += v;
+    h.nu = std::sqrt(ss) / std::sqrt(double(o.d0));
+    h.delta = o.norm_mode == H2_NORM_FRO_SCALED ? o.tol * h.nu / std::sqrt(double(nleaves)) : o.tol * h.nu;
+    timer_.end(ph);
+
+    conv_.alloc(static_cast<size_t>(nleaves), s_);
+    minr_.alloc(static_cast<size_t>(nleaves), s_);
+    counter_.alloc(1, s_);
+
+    for (int t = D; t >= h.top; --t) level(t);
+    h.samples = d_;
+  }
+
+  // Omega columns [c0, c0+nc) in tree order, then Y = K Omega for them.
+  void draw(int c0, int nc) {
+    h2_matrix& h = *h_;
+    Level& leaf = h.lv[h.plan.depth];
+    const int64_t n = h.plan.n;
+    H2_HIP(h2dev::gaussian(s_, h.opts.seed, n, h.perm.get(), c0, nc, leaf.om.get() + int64_t(c0) * n, n));
+    H2_HIP(h2dev::sketch_f64(s_, n, h.plan.dim, h.X.get(), n, kf_, nc, leaf.om.get() + int64_t(c0) * n, n,
+                             leaf.y.get() + int64_t(c0) * n, n));
+    h.sketch_flops += 2.0 * double(n) * double(n) * nc;
+    h.sketch_entries += double(n) * double(n);
+  }
+
+  // Y_loc = Y^l - (near or far contributions) on columns [c0, c0+nc) at depth t.
+  void subtract(int t, int c0, int nc) {
+    h2_matrix& h = *h_;
+    const int D = h.plan.depth;
+    Level& L = h.lv[t];
+    if (t == D) {
+      H2_HIP(h2dev::bsr_gemm(s_, L.nn, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
+                             L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
+                             L.max_m));
+    } else {
+      Level& C = h.lv[t + 1];
+      H2_HIP(h2dev::bsr_gemm(s_, C.nn, C.fptr.get(), C.fidx.get(), C.koff.get(), C.boff.get(), C.B.get(),
+                             L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
+                             std::max(C.max_k, 1)));
+    }
+  }
+
+  // Shrink + upsweep of depth t (its ID already computed) on columns [c0, c0+nc).
+  void upsweep(int t, int c0, int nc) {
+    h2_matrix& h = *h_;
+    Level& L = h.lv[t];
+    Level& P = h.lv[t - 1];
+    H2_HIP(h2dev::shrink_up(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(), L.uoff.get(),
+                            L.y.get() + int64_t(c0) * L.M, L.M, L.om.get() + int64_t(c0) * L.M, L.M,
+                            P.y.get() + int64_t(c0) * P.M, P.M, P.om.get() + int64_t(c0) * P.M, P.M, nc));
+  }
+
+  void ensure_gws(int nn, int max_m, int d) {
+    const int64_t per = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
+    if (gws_.size() >= size_t(per) * nn) return;
+    gws_.alloc(size_t(per) * nn, s_);
+    std::vector<int64_t> off(nn);
+    for (int i = 0; i < nn; ++i) off[i] = per * i;
+    gws_off_.upload(off, s_);
+  }
+
+  void level(int t) {
+    h2_matrix& h = *h_;
+    const h2::Plan& p = h.plan;
+    const int D = p.depth;
+    Level& L = h.lv[t];
+    L.processed = true;
+    // in-rows of the clusters at depth t
+    if (t == D) {
+      L.rowoff_h = h.leafoff_h;
+    } else {
+      const Level& C = h.lv[t + 1];
+      L.rowoff_h.resize(L.nn + 1);
+      for (int i = 0; i <= L.nn; ++i) L.rowoff_h[i] = C.koff_h[2 * i];
+      L.M = C.koff_h.back();
+    }
+    L.max_m = 0;
+    for (int i = 0; i < L.nn; ++i) L.max_m = std::max(L.max_m, L.rowoff_h[i + 1] - L.rowoff_h[i]);
+    L.rowoff.upload(L.rowoff_h, s_);
+
+    int ph = timer_.begin(kSubtract);
+    subtract(t, 0, d_);
+    timer_.end(ph);
+
+    // adaptive sampling (Sec. III-B)
+    while (true) {
+      ph = timer_.begin(kConv);
+      H2_HIP(hipMemsetAsync(counter_.get(), 0, sizeof(int32_t), s_));
+      const size_t qbytes = size_t(L.max_m | 1) * size_t(d_) * sizeof(double);
+      if (qbytes > ctx_->lds_limit) ensure_gws(L.nn, L.max_m, d_);
+      H2_HIP(h2dev::qr_test(s_, L.nn, L.rowoff.get(), L.y.get(), L.M, d_, h.delta, conv_.get(), minr_.get(),
+                            counter_.get(), L.max_m, ctx_->lds_limit, gws_.get(), gws_off_.get()));
+      const int32_t unconv = download(counter_.get(), 1, s_)[0];
+      timer_.end(ph);
+      if (unconv == 0) break;
+      if (d_ + h.opts.d_inc > h.opts.d_max)
+        throw Error(H2_ERR_SAMPLES, "adaptive sampling did not converge within d_max = " +
+                                        std::to_string(h.opts.d_max) + " columns at depth " + std::to_string(t));
+      const int c0 = d_, nc = h.opts.d_inc;
+      ph = timer_.begin(kSample);
+      draw(c0, nc);
+      timer_.end(ph);
+      // updateSamples: sweep the new columns up through the finished levels
+      for (int tt = D; tt >= t; --tt) {
+        ph = timer_.begin(kSubtract);
+        subtract(tt, c0, nc);
+        timer_.end(ph);
+        if (tt > t) {
+          ph = timer_.begin(kUpsweep);
+          upsweep(tt, c0, nc);
+          timer_.end(ph);
+        }
+      }
+      d_ += nc;
+      h.rounds++;
+    }
+
+    // row ID of every cluster (batchedID)
+    ph = timer_.begin(kId);
+    std::vector<int64_t> jsz(L.nn), usz(L.nn);
+    for (int i = 0; i < L.nn; ++i) {
+      const int m = L.rowoff_h[i + 1] - L.rowoff_h[i];
+      jsz[i] = std::min(m, d_);
+      usz[i] = int64_t(m) * std::min(m, d_);
+    }
+    L.joff_h = prefix(jsz);
+    L.uoff_h = prefix(usz);
+    L.joff.upload(L.joff_h, s_);
+    L.uoff.upload(L.uoff_h, s_);
+    L.J.alloc(static_cast<size_t>(L.joff_h.back()), s_);
+    L.U.alloc(static_cast<size_t>(L.uoff_h.back()), s_);
+    DevArray<int32_t> kdev;
+    kdev.alloc(L.nn, s_);
+    const size_t cbytes = size_t(3) * L.max_m * sizeof(double) + size_t(d_ | 1) * L.max_m * sizeof(double);
+    if (cbytes > ctx_->lds_limit) ensure_gws(L.nn, L.max_m, d_);
+    H2_HIP(h2dev::cpqr_id(s_, L.nn, L.rowoff.get(), L.y.get(), L.M, d_, h.delta, kdev.get(), L.J.get(), L.joff.get(),
+                          L.U.get(), L.uoff.get(), L.max_m, ctx_->lds_limit, gws_.get(), gws_off_.get()));
+    L.k_h = download(kdev.get(), L.nn, s_);
+    L.koff_h = prefix(L.k_h);
+    L.koff.upload(L.koff_h, s_);
+    L.max_k = 0;
+    for (int k : L.k_h) L.max_k = std::max(L.max_k, k);
+    timer_.end(ph);
+
+    // shrink + upsweep into the next level's row space R_{t-1}
+    ph = timer_.begin(kUpsweep);
+    const int64_t Mn = L.koff_h.back();
+    Level& P = h.lv[t - 1];
+    if (t > h.top) {
+      P.M = Mn;
+      P.om.alloc(static_cast<size_t>(Mn) * dcap_, s_);
+      P.y.alloc(static_cast<size_t>(Mn) * dcap_, s_);
+      upsweep(t, 0, d_);
+    }
+    // skeleton tree positions and coordinates
+    L.pos_out.alloc(static_cast<size_t>(Mn), s_);
+    L.xs_out.alloc(static_cast<size_t>(Mn) * p.dim, s_);
+    const int32_t* pos_in = (t == D) ? nullptr : h.lv[t + 1].pos_out.get();
+    H2_HIP(h2dev::skeleton(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), pos_in, L.pos_out.get(),
+                           p.dim, h.X.get(), p.n, L.xs_out.get(), Mn));
+    timer_.end(ph);
+
+    // coupling matrices B_{tau,b} = K(I~_tau, I~_b), b in F_tau  (batchedGen)
+    ph = timer_.begin(kCoupling);
+    L.fptr_h = p.far_ptr[t];
+    L.fidx_h = p.far_idx[t];
+    std::vector<int64_t> bsz(L.fidx_h.size());
+    for (int s = 0; s < L.nn; ++s)
+      for (int j = L.fptr_h[s]; j < L.fptr_h[s + 1]; ++j) bsz[j] = int64_t(L.k_h[s]) * L.k_h[L.fidx_h[j]];
+    L.boff_h = prefix(bsz);
+    L.fptr.upload(L.fptr_h, s_);
+    L.fidx.upload(L.fidx_h, s_);
+    L.boff.upload(L.boff_h, s_);
+    L.B.alloc(static_cast<size_t>(L.boff_h.back()), s_);
+    H2_HIP(h2dev::gen_blocks(s_, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), L.boff.get(), p.dim,
+                             L.xs_out.get(), Mn, kf_, L.B.get()));
+    timer_.end(ph);
+  }
+};
+
+size_t copy_part(const void* src, size_t bytes, void* dst, size_t dst_bytes, size_t* needed, bool device,
+                 hipStream_t s) {
+  if (needed) *needed = bytes;
+  if (!dst) return bytes;
+  if (dst_bytes < bytes) throw Error(H2_ERR_ARG, "destination too small");
+  if (bytes == 0) return 0;
+  if (device) {
+    H2_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(dst, src, bytes);
+  }
+  return bytes;
+}
+
+void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst, size_t dst_bytes, size_t* needed) {
+  switch (part) {
+    case H2_PART_DEPTH: {
+      const int32_t d = p.depth;
+      copy_part(&d, sizeof d, dst, dst_bytes, needed, false, nullptr);
+      return;
+    }
+    case H2_PART_PERM:
+      copy_part(p.perm.data(), p.perm.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      return;
+    case H2_PART_NODES: {
+      std::vector<int32_t> v(2 * p.begin.size());
+      for (size_t i = 0; i < p.begin.size(); ++i) {
+        v[2 * i] = p.begin[i];
+        v[2 * i + 1] = p.end[i];
+      }
+      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      return;
+    }
+    case H2_PART_BOXES: {
+      std::vector<double> v;
+      v.reserve(p.lo.size() * 2);
+      for (int i = 0; i < p.num_nodes(); ++i) {
+        for (int a = 0; a < p.dim; ++a) v.push_back(p.lo[size_t(i) * p.dim + a]);
+        for (int a = 0; a < p.dim; ++a) v.push_back(p.hi[size_t(i) * p.dim + a]);
+      }
+      copy_part(v.data(), v.size() * 8, dst, dst_bytes, needed, false, nullptr);
+      return;
+    }
+    case H2_PART_NEAR_PTR:
+      copy_part(p.near_ptr.data(), p.near_ptr.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      return;
+    case H2_PART_NEAR_IDX:
+      copy_part(p.near_idx.data(), p.near_idx.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      return;
+    case H2_PART_FAR_PTR:
+    case H2_PART_FAR_IDX: {
+      H2_REQUIRE(depth >= 0 && depth <= p.depth, "depth out of range");
+      const auto& v = part == H2_PART_FAR_PTR ? p.far_ptr[depth] : p.far_idx[depth];
+      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      return;
+    }
+    default:
+      throw Error(H2_ERR_STATE, "part not available for this object");
+  }
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+
+extern "C" {
+
+h2_status h2_opts_default(h2_opts* o) {
+  return guarded([&] {
+    H2_REQUIRE(o != nullptr, "opts is NULL");
+    o->tol = 1e-6;
+    o->leaf_size = 64;
+    o->eta = 0.7;
+    o->d0 = 32;
+    o->d_inc = 16;
+    o->d_max = 128;
+    o->seed = 1000;
+    o->precision = H2_FP64;
+    o->norm_mode = H2_NORM_FRO_SCALED;
+  });
+}
+
+const char* h2_status_string(h2_status s) {
+  switch (s) {
+    case H2_OK: return "ok";
+    case H2_ERR_ARG: return "invalid argument";
+    case H2_ERR_HIP: return "HIP runtime error";
+    case H2_ERR_OOM: return "out of device memory";
+    case H2_ERR_CALLBACK: return "callback failed";
+    case H2_ERR_SAMPLES: return "adaptive sampling reached d_max";
+    case H2_ERR_STATE: return "invalid state";
+    case H2_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* h2_last_error(void) { return g_last_error.c_str(); }
+
+h2_status h2_ctx_create(int device, void* stream, h2_ctx** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    H2_REQUIRE(out != nullptr, "out is NULL");
+    int count = 0;
+    H2_HIP(hipGetDeviceCount(&count));
+    H2_REQUIRE(device >= 0 && device < count, "device out of range");
+    H2_HIP(hipSetDevice(device));
+    auto c = std::make_unique<h2_ctx>();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    int lds = 0;
+    H2_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    c->lds_limit = lds > 2048 ? size_t(lds) - 1024 : size_t(lds);
+    // keep freed device memory in the stream-ordered pool between builds
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    *out = c.release();
+  });
+}
+
+h2_status h2_ctx_destroy(h2_ctx* ctx) {
+  return guarded([&] {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    delete ctx;
+  });
+}
+
+h2_status h2_plan_create(int64_t n, int32_t dim, const double* points_host, int32_t leaf_size, double eta,
+                         h2_plan** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    H2_REQUIRE(out != nullptr, "out is NULL");
+    auto p = std::make_unique<h2_plan>();
+    p->plan = h2::make_plan(n, dim, points_host, leaf_size, eta);
+    *out = p.release();
+  });
+}
+
+h2_status h2_plan_free(h2_plan* plan) {
+  return guarded([&] { delete plan; });
+}
+
+h2_status h2_plan_export(const h2_plan* plan, int32_t part, int32_t depth, void* dst, size_t dst_bytes,
+                         size_t* needed) {
+  return guarded([&] {
+    H2_REQUIRE(plan != nullptr, "plan is NULL");
+    export_plan_part(plan->plan, part, depth, dst, dst_bytes, needed);
+  });
+}
+
+h2_status h2_gaussian(h2_ctx* ctx, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0, int32_t ncols,
+                      double* out, int64_t ldo) {
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr, "ctx is NULL");
+    H2_REQUIRE(nrows >= 0 && ncols >= 0 && col0 >= 0, "negative size");
+    H2_REQUIRE(ldo >= std::max<int64_t>(nrows, 1), "ldo < nrows");
+    H2_REQUIRE((rows && out) || nrows * int64_t(ncols) == 0, "NULL pointer");
+    H2_HIP(hipSetDevice(ctx->device));
+    H2_HIP(h2dev::gaussian(ctx->stream, seed, nrows, rows, col0, ncols, out, ldo));
+  });
+}
+
+h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                    int32_t precision, int32_t ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr, "ctx is NULL");
+    check_kernel(kernel);
+    H2_REQUIRE(precision == H2_FP64, "only H2_FP64 is implemented");
+    H2_REQUIRE(n >= 0 && n < (int64_t{1} << 31), "n out of range");
+    H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
+    H2_REQUIRE(ncols >= 0 && ncols <= 128, "ncols must be in [0, 128]");
+    H2_REQUIRE(ldo >= std::max<int64_t>(n, 1) && ldy >= std::max<int64_t>(n, 1), "ld < n");
+    H2_REQUIRE((points && omega && y) || n * int64_t(ncols) == 0, "NULL pointer");
+    H2_HIP(hipSetDevice(ctx->device));
+    H2_HIP(h2dev::sketch_f64(ctx->stream, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
+  });
+}
+
+h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                   const h2_opts* opts, h2_matrix** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr && out != nullptr, "NULL argument");
+    H2_REQUIRE(points != nullptr, "points is NULL");
+    H2_REQUIRE(n >= 1 && n <= (int64_t{1} << 30), "n must be in [1, 2^30]");
+    H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
+    check_kernel(kernel);
+    check_opts(opts);
+    H2_HIP(hipSetDevice(ctx->device));
+    auto h = std::make_unique<h2_matrix>();
+    h->device = ctx->device;
+    h->stream = ctx->stream;
+    h->kernel = *kernel;
+    h->opts = *opts;
+    Builder b(ctx, h.get());
+    b.run(n, dim, points);
+    *out = h.release();
+  });
+}
+
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t nrhs, const double* x, int64_t ldx, double* y,
+                    int64_t ldy) {
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr && hm != nullptr, "NULL argument");
+    const h2_matrix& h = *hm;
+    const int64_t n = h.plan.n;
+    H2_REQUIRE(nrhs >= 0, "nrhs < 0");
+    if (nrhs == 0) return;
+    H2_REQUIRE(x && y, "NULL vector");
+    H2_REQUIRE(ldx >= n && ldy >= n, "ld < n");
+    H2_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    const int D = h.plan.depth;
+    const int nleaves = 1 << D;
+    int leaf_max = 0;
+    for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
+    const int chunk = 64;
+    DevArray<double> xt, yt;
+    xt.alloc(size_t(n) * chunk, s);
+    yt.alloc(size_t(n) * chunk, s);
+    std::vector<DevArray<double>> xh(D + 1), yh(D + 1);  // per depth t: R_{t-1} rows
+    for (int t = h.top; t <= D; ++t) {
+      const int64_t M = h.lv[t].koff_h.back();
+      xh[t].alloc(size_t(M) * chunk, s);
+      yh[t].alloc(size_t(M) * chunk, s);
+    }
+    for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+      const int nc = std::min(chunk, nrhs - c0);
+      H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), false, x + int64_t(c0) * ldx, ldx, xt.get(), n, nc));
+      H2_HIP(h2dev::fill_zero(s, yt.get(), n * nc));
+      if (h.top <= D) {
+        for (int t = D; t >= h.top; --t) {  // upsweep x_hat = U^T x, E^T x_hat
+          const Level& L = h.lv[t];
+          const int64_t M = L.koff_h.back();
+          const double* src = t == D ? xt.get() : xh[t + 1].get();
+          const int64_t lds = t == D ? n : h.lv[t + 1].koff_h.back();
+          H2_HIP(h2dev::shrink_up(s, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(),
+                                  L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t].get(), M, nc));
+          H2_HIP(h2dev::fill_zero(s, yh[t].get(), M * nc));
+        }
+        for (int t = h.top; t <= D; ++t) {  // coupling y_hat_s = sum B_{s,b} x_hat_b
+          const Level& L = h.lv[t];
+          const int64_t M = L.koff_h.back();
+          H2_HIP(h2dev::bsr_gemm(s, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), L.boff.get(), L.B.get(),
+                                 xh[t].get(), M, yh[t].get(), M, nc, 1.0, std::max(L.max_k, 1)));
+        }
+        for (int t = h.top; t <= D; ++t) {  // downsweep y_hat_child += E y_hat, y += U y_hat
+          const Level& L = h.lv[t];
+          const int64_t M = L.koff_h.back();
+          double* dst = t == D ? yt.get() : yh[t + 1].get();
+          const int64_t ldd = t == D ? n : h.lv[t + 1].koff_h.back();
+          H2_HIP(h2dev::expand(s, L.nn, L.rowoff.get(), L.koff.get(), L.U.get(), L.uoff.get(), yh[t].get(), M, dst,
+                               ldd, nc));
+        }
+      }
+      H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
+                             xt.get(), n, yt.get(), n, nc, 1.0, leaf_max));
+      H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), true, yt.get(), n, y + int64_t(c0) * ldy, ldy, nc));
+    }
+    // temporaries are released stream-ordered; inputs stay valid until the stream passes this point
+  });
+}
+
+h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst, size_t dst_bytes, size_t* needed) {
+  return guarded([&] {
+    H2_REQUIRE(hm != nullptr, "matrix is NULL");
+    const h2_matrix& h = *hm;
+    const h2::Plan& p = h.plan;
+    hipStream_t s = h.stream;
+    if (part <= H2_PART_FAR_IDX) {
+      export_plan_part(p, part, depth, dst, dst_bytes, needed);
+      return;
+    }
+    if (part == H2_PART_TOP) {
+      const int32_t v = h.top;
+      copy_part(&v, 4, dst, dst_bytes, needed, false, s);
+      return;
+    }
+    if (part == H2_PART_DENSE) {
+      copy_part(h.Dblk.get(), h.Dblk.bytes(), dst, dst_bytes, needed, true, s);
+      return;
+    }
+    H2_REQUIRE(depth >= 0 && depth <= p.depth, "depth out of range");
+    const Level& L = h.lv[depth];
+    const bool have = L.processed;
+    switch (part) {
+      case H2_PART_RANKS: {
+        std::vector<int32_t> k(size_t(1) << depth, 0);
+        if (have) k = L.k_h;
+        copy_part(k.data(), k.size() * 4, dst, dst_bytes, needed, false, s);
+        return;
+      }
+      case H2_PART_SKEL:
+      case H2_PART_SKEL_POS: {
+        if (!have) {
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          return;
+        }
+        std::vector<int32_t> pos(L.pos_out.size());
+        if (!pos.empty()) {
+          H2_HIP(hipMemcpyAsync(pos.data(), L.pos_out.get(), pos.size() * 4, hipMemcpyDeviceToHost, s));
+          H2_HIP(hipStreamSynchronize(s));
+        }
+        if (part == H2_PART_SKEL)
+          for (auto& v : pos) v = p.perm[v];
+        copy_part(pos.data(), pos.size() * 4, dst, dst_bytes, needed, false, s);
+        return;
+      }
+      case H2_PART_BASIS: {
+        if (!have) {
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          return;
+        }
+        // packed m x k per node (U is stored with capacity m x min(m, d))
+        std::vector<double> all(L.U.size());
+        if (!all.empty()) {
+          H2_HIP(hipMemcpyAsync(all.data(), L.U.get(), all.size() * 8, hipMemcpyDeviceToHost, s));
+          H2_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<double> packed;
+        for (int i = 0; i < L.nn; ++i) {
+          const int64_t m = L.rowoff_h[i + 1] - L.rowoff_h[i];
+          const int64_t k = L.k_h[i];
+          packed.insert(packed.end(), all.begin() + L.uoff_h[i], all.begin() + L.uoff_h[i] + m * k);
+        }
+        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, s);
+        return;
+      }
+      case H2_PART_COUPLING: {
+        if (!have) {
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          return;
+        }
+        copy_part(L.B.get(), L.B.bytes(), dst, dst_bytes, needed, true, s);
+        return;
+      }
+      default:
+        throw Error(H2_ERR_ARG, "unknown part");
+    }
+  });
+}
+
+h2_status h2_query(const h2_matrix* hm, h2_info* info) {
+  return guarded([&] {
+    H2_REQUIRE(hm != nullptr && info != nullptr, "NULL argument");
+    const h2_matrix& h = *hm;
+    h2_info r{};
+    r.n = h.plan.n;
+    r.dim = h.plan.dim;
+    r.depth = h.plan.depth;
+    r.top = h.top;
+    r.samples = h.samples;
+    r.rounds = h.rounds;
+    r.delta = h.delta;
+    r.norm_estimate = h.nu;
+    r.rank_min = 1 << 30;
+    r.rank_max = 0;
+    r.near_blocks = static_cast<int64_t>(h.plan.near_idx.size());
+    r.bytes_dense = static_cast<int64_t>(h.Dblk.bytes());
+    for (const Level& L : h.lv) {
+      if (!L.processed) continue;
+      for (int k : L.k_h) {
+        r.rank_min = std::min(r.rank_min, k);
+        r.rank_max = std::max(r.rank_max, k);
+      }
+      r.far_blocks += static_cast<int64_t>(L.fidx_h.size());
+      r.bytes_coupling += static_cast<int64_t>(L.B.bytes());
+      r.bytes_basis += static_cast<int64_t>(L.U.bytes());
+    }
+    if (r.rank_max == 0 && r.rank_min == (1 << 30)) r.rank_min = 0;
+    r.t_total = h.total_ms;
+    r.t_tree = h.phase_ms[kTree];
+    r.t_sample = h.phase_ms[kSample];
+    r.t_near_gen = h.phase_ms[kNearGen];
+    r.t_subtract = h.phase_ms[kSubtract];
+    r.t_convtest = h.phase_ms[kConv];
+    r.t_id = h.phase_ms[kId];
+    r.t_upsweep = h.phase_ms[kUpsweep];
+    r.t_coupling = h.phase_ms[kCoupling];
+    double acc = 0;
+    for (int ph = 0; ph < kNumPhase; ++ph) acc += h.phase_ms[ph];
+    r.t_misc = std::max(0.0, h.total_ms - acc);
+    r.sketch_flops = h.sketch_flops;
+    r.sketch_entries = h.sketch_entries;
+    *info = r;
+  });
+}
+
+h2_status h2_free(h2_matrix* h) {
+  return guarded([&] {
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+    // releases are stream-ordered; nothing else to wait for
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Launchers of the gfx950 kernels behind the C ABI.  All sizes are element
+// counts; all matrices are column-major float64 with explicit leading
+// dimensions; every launcher enqueues on `s` and returns hipSuccess or the
+// launch error.
+//
+// Row spaces.  The construction works level by level (Alg. 1).  The rows of
+// the sample matrices at depth t form a "row space" R_t: at the leaf depth it
+// is the n points in tree order; at an inner depth it is the concatenation of
+// the skeleton rows of the depth t+1 clusters, cluster by cluster.  A cluster
+// i at depth t owns rows [rowoff[i], rowoff[i+1]) of R_t, and its skeleton
+// (after its ID) owns rows [koff[i], koff[i+1]) of R_{t-1}.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2dev {
+
+enum KernelKind : int { kExp = 1, kGauss = 2 };
+
+struct KernelFn {
+  int kind;      // KernelKind
+  double scale;  // exp: 1/l (kappa = exp(-r*scale)); gauss: 1/(2 l^2) (kappa = exp(-r^2*scale))
+};
+
+// Omega(rows[p], col0 + c) -> out[p + c*ldo]; counter-based Philox4x64-10 + Box-Muller.
+hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0, int ncols,
+                    double* out, int64_t ldo);
+
+// Dense on-the-fly sketch y = K(X,X) omega (FP64 MFMA), X = (dim x n) SoA with leading dimension ldx.
+hipError_t sketch_f64(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
+                      const double* omega, int64_t ldo, double* y, int64_t ldy);
+
+// Kernel blocks of a CSR block pattern: for block row i and entry j in [ptr[i], ptr[i+1]) with
+// b = idx[j], writes kappa(X[rowoff[i] + r], X[rowoff[b] + c]) to out[blkoff[j] + r + c*m_i].
+hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                      const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out);
+
+// Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc columns.
+// max_m bounds every block-row height (<= 256).
+hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                    const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
+                    int64_t ldy, int nc, double alpha, int max_m);
+
+// Adaptive convergence test (Sec. III-B): per cluster, unpivoted Householder QR of its samples
+// Y[rowoff[i]..rowoff[i+1]) x [0,d); conv[i] = 1 if m <= d or min |R_jj| < delta.
+// minr[i] receives the smallest |R_jj| seen (0 when m <= d).  *unconverged counts clusters
+// with conv 0 (must be zeroed by the caller).  Panels larger than lds_limit bytes use gws.
+hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+                   double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m,
+                   size_t lds_limit, double* gws, const int64_t* gws_off);
+
+// Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
+// row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).
+hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+                   double delta, int32_t* kout, int32_t* J, const int64_t* joff, double* U, const int64_t* uoff,
+                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off);
+
+// Shrink and upsweep (Alg. 1 batchedShrink + batchedGemm) on nc columns:
+//   Yout[koff[i] + r, :] = Yloc[rowoff[i] + J[r], :]           (skipped when Yloc == nullptr)
+//   Wout[koff[i] + r, :] = sum_q U[q, r] Win[rowoff[i] + q, :]
+hipError_t shrink_up(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
+                     const int64_t* joff, const double* U, const int64_t* uoff, const double* Yloc, int64_t ldyl,
+                     const double* Win, int64_t ldwi, double* Yout, int64_t ldyo, double* Wout, int64_t ldwo,
+                     int nc);
+
+// Downsweep of the matvec: Yt[rowoff[i] + q, :] += sum_r U[q, r] Yh[koff[i] + r, :].
+hipError_t expand(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const double* U,
+                  const int64_t* uoff, const double* Yh, int64_t ldh, double* Yt, int64_t ldt, int nc);
+
+// Skeleton rows: pos_out[koff[i] + r] = pos_in[rowoff[i] + J[r]] (or rowoff[i] + J[r] when
+// pos_in == nullptr); Xs[a*ldxs + q] = X[a*ldx + pos_out[q]].
+hipError_t skeleton(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
+                    const int64_t* joff, const int32_t* pos_in, int32_t* pos_out, int dim, const double* X,
+                    int64_t ldx, double* Xs, int64_t ldxs);
+
+// dst[p + c*ldd] = src[idx[p] + c*lds] (gather, scatter = false) or dst[idx[p] + c*ldd] = src[p + c*lds].
+hipError_t permute_rows(hipStream_t s, int64_t n, const int32_t* idx, bool scatter, const double* src, int64_t lds,
+                        double* dst, int64_t ldd, int nc);
+
+// Partial sums of squares of an (n x nc) block: partial[b] for b < nblocks (fixed, deterministic).
+hipError_t sumsq_partial(hipStream_t s, int64_t n, int nc, const double* A, int64_t lda, double* partial,
+                         int nblocks);
+
+// Fill n doubles with zero (used instead of memset so the call is graph-capturable).
+hipError_t fill_zero(hipStream_t s, double* p, int64_t n);
+
+}  // namespace h2dev

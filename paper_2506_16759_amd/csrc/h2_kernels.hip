@@ -1,0 +1,819 @@
+// gfx950 kernels of the adaptive-sketching H^2 construction (Alg. 1, Sec. III-IV).
+//
+// Wave64 throughout.  The only dense contraction with real arithmetic
+// intensity -- the on-the-fly sketch Y = K Omega -- runs on the FP64 matrix
+// cores (v_mfma_f64_16x16x4); kernel entries are produced straight into the
+// MFMA A-operand lane layout, so no kernel tile ever touches LDS or HBM.  The
+// per-cluster QR / column-pivoted QR keep a cluster's sample panel in LDS with
+// one thread per panel column and wave shuffles for norms and the pivot argmax.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "h2_device.hpp"
+
+namespace h2dev {
+namespace {
+
+constexpr int kWave = 64;
+
+// ----------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+template <int KIND>
+__device__ __forceinline__ double kernel_of_r2(double r2, double scale) {
+  if constexpr (KIND == kExp) {
+    return exp(-sqrt(r2) * scale);
+  } else {
+    return exp(-r2 * scale);
+  }
+}
+
+__device__ __forceinline__ double kernel_dispatch(int kind, double r2, double scale) {
+  return kind == kExp ? kernel_of_r2<kExp>(r2, scale) : kernel_of_r2<kGauss>(r2, scale);
+}
+
+__device__ __forceinline__ double dist2(const double* X, int64_t ldx, int dim, int64_t i, int64_t j) {
+  double r2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    const double d = X[a * ldx + i] - X[a * ldx + j];
+    r2 += d * d;
+  }
+  return r2;
+}
+
+__device__ __forceinline__ double dist2_xy(const double* Xr, const double* Xc, int64_t ldx, int dim, int64_t i,
+                                           int64_t j) {
+  double r2 = 0.0;
+  for (int a = 0; a < dim; ++a) {
+    const double d = Xr[a * ldx + i] - Xc[a * ldx + j];
+    r2 += d * d;
+  }
+  return r2;
+}
+
+// ---------------------------------------------------------- Philox4x64-10
+
+constexpr uint64_t kPhM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhW1 = 0xBB67AE8584CAA73Bull;
+
+__device__ __forceinline__ void philox_block(uint64_t& c0, uint64_t& c1, uint64_t& c2, uint64_t& c3, uint64_t k0,
+                                             uint64_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += kPhW0;
+      k1 += kPhW1;
+    }
+    const uint64_t hi0 = __umul64hi(kPhM0, c0), lo0 = kPhM0 * c0;
+    const uint64_t hi1 = __umul64hi(kPhM1, c2), lo1 = kPhM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+__global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, int64_t nrows, const int32_t* __restrict__ rows,
+                                                       int64_t col0, int ncols, double* __restrict__ out,
+                                                       int64_t ldo) {
+  const int64_t total = nrows * ncols;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t p = e % nrows, c = e / nrows;
+    uint64_t c0 = static_cast<uint64_t>(rows[p]), c1 = static_cast<uint64_t>(col0 + c), c2 = 0, c3 = 0;
+    philox_block(c0, c1, c2, c3, seed, 0);
+    const double u1 = (static_cast<double>(c0 >> 11) + 0.5) * 0x1p-53;
+    const double u2 = (static_cast<double>(c1 >> 11) + 0.5) * 0x1p-53;
+    out[p + c * ldo] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+// ------------------------------------------------ dense on-the-fly sketch
+
+// One workgroup = 4 waves = 128 consecutive rows; each wave owns 32 rows as two
+// 16-row MFMA tiles and all NC output columns.  Columns of K (points j) are
+// streamed through LDS 64 at a time together with the matching Omega rows.
+// For v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
+// holds D[4*(l/16)+q][l%16] in accumulator element q.
+constexpr int kSkRows = 128;
+constexpr int kSkK = 64;
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                         double scale, int ncr, const double* __restrict__ omega,
+                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  constexpr int NB = NC / 16;
+  __shared__ double xs[DIM][kSkK];
+  __shared__ double om[kSkK][NC + 2];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int li = lane & 15, lk = lane >> 4;
+
+  double xa[DIM], xb[DIM];
+  {
+    const int64_t ia = row0 + li, ib = row0 + 16 + li;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      xa[a] = ia < n ? X[a * ldx + ia] : 0.0;
+      xb[a] = ib < n ? X[a * ldx + ib] : 0.0;
+    }
+  }
+  dbl4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    acc0[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    acc1[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
+    __syncthreads();
+    for (int e = tid; e < DIM * kSkK; e += 256) {
+      const int a = e / kSkK, jj = e % kSkK;
+      xs[a][jj] = (j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+    }
+    for (int e = tid; e < NC * kSkK; e += 256) {
+      const int c = e / kSkK, jj = e % kSkK;
+      om[jj][c] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kSkK / 4; ++kk) {
+      const int jj = kk * 4 + lk;
+      double ra = 0.0, rb = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double xj = xs[a][jj];
+        const double da = xa[a] - xj, db = xb[a] - xj;
+        ra += da * da;
+        rb += db * db;
+      }
+      const double ka = kernel_of_r2<KIND>(ra, scale);
+      const double kb = kernel_of_r2<KIND>(rb, scale);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double bv = om[jj][c * 16 + li];
+        acc0[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, bv, acc0[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, bv, acc1[c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = c * 16 + li;
+    if (col >= ncr) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ra = row0 + 4 * lk + q, rb = row0 + 16 + 4 * lk + q;
+      if (ra < n) y[col * ldy + ra] = acc0[c][q];
+      if (rb < n) y[col * ldy + rb] = acc1[c][q];
+    }
+  }
+}
+
+template <int DIM, int KIND>
+hipError_t launch_sketch_nc(hipStream_t s, int64_t n, const double* X, int64_t ldx, double scale, int ncr,
+                            const double* omega, int64_t ldo, double* y, int64_t ldy) {
+  const dim3 grid(static_cast<unsigned>((n + kSkRows - 1) / kSkRows));
+  if (ncr <= 16)
+    sketch_f64_kernel<DIM, KIND, 16><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+  else if (ncr <= 32)
+    sketch_f64_kernel<DIM, KIND, 32><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+  else if (ncr <= 48)
+    sketch_f64_kernel<DIM, KIND, 48><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+  else if (ncr <= 64)
+    sketch_f64_kernel<DIM, KIND, 64><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ kernel block gen
+
+__global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restrict__ ptr,
+                                                         const int32_t* __restrict__ idx,
+                                                         const int32_t* __restrict__ rowoff,
+                                                         const int64_t* __restrict__ blkoff, int dim,
+                                                         const double* __restrict__ X, int64_t ldx, int kind,
+                                                         double scale, double* __restrict__ out) {
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
+    const int b = idx[j];
+    const int c0 = rowoff[b], mb = rowoff[b + 1] - c0;
+    double* o = out + blkoff[j];
+    const int total = m * mb;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+      const int r = e % m, c = e / m;
+      o[e] = kernel_dispatch(kind, dist2(X, ldx, dim, r0 + r, c0 + c), scale);
+    }
+  }
+}
+
+// ------------------------------------------------------- block-sparse GEMM
+
+// One workgroup per block row; 256 threads as 8 row groups x 32 columns; each
+// thread accumulates U rows (r = ty + 8u) of one column.  Blocks and the
+// matching X rows are staged through LDS 32 inner indices at a time.
+constexpr int kBsrCols = 32;
+
+template <int U, int kBsrK = (U >= 32 ? 16 : 32)>
+__global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ rowoff,
+                                                       const int64_t* __restrict__ blkoff,
+                                                       const double* __restrict__ blocks, const double* __restrict__ X,
+                                                       int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
+                                                       double alpha) {
+  __shared__ double bs[kBsrK][8 * U + 1];
+  __shared__ double xs[kBsrK][kBsrCols + 1];
+  const int i = blockIdx.x;
+  const int c0 = blockIdx.y * kBsrCols;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int ncl = min(kBsrCols, nc - c0);
+  double acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = 0.0;
+
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
+    const int b = idx[j];
+    const int q0b = rowoff[b], mb = rowoff[b + 1] - q0b;
+    const double* blk = blocks + blkoff[j];
+    for (int q0 = 0; q0 < mb; q0 += kBsrK) {
+      const int kq = min(kBsrK, mb - q0);
+      __syncthreads();
+      for (int e = tid; e < m * kBsrK; e += 256) {
+        const int r = e % m, q = e / m;
+        bs[q][r] = q < kq ? blk[int64_t(q0 + q) * m + r] : 0.0;
+      }
+      for (int e = tid; e < kBsrK * kBsrCols; e += 256) {
+        const int q = e % kBsrK, c = e / kBsrK;
+        xs[q][c] = (q < kq && c < ncl) ? X[int64_t(c0 + c) * ldx + q0b + q0 + q] : 0.0;
+      }
+      __syncthreads();
+      for (int q = 0; q < kq; ++q) {
+        const double xv = xs[q][tx];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] += bs[q][ty + 8 * u] * xv;
+      }
+    }
+  }
+  if (tx < ncl) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = ty + 8 * u;
+      if (r < m) {
+        double* yp = Y + int64_t(c0 + tx) * ldy + r0 + r;
+        *yp += alpha * acc[u];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------- adaptive convergence test
+
+// Unpivoted Householder QR of a cluster's samples P (m x d, column-major in the
+// panel with odd leading dimension ldp).  Thread c owns column c.  The
+// reflector of step j is formed by wave 0 from column j; every other column
+// applies it on its own.  Stops at the first |R_jj| < delta.
+template <bool kLds>
+__global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy, int d,
+                               double delta, int32_t* __restrict__ conv, double* __restrict__ minr,
+                               int32_t* __restrict__ unconverged, double* __restrict__ gws,
+                               const int64_t* __restrict__ gws_off) {
+  extern __shared__ double smem[];
+  __shared__ double s_tau, s_beta;
+  __shared__ int s_stop;
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (m <= d) {  // as many samples as rows: nothing left to resolve
+    if (tid == 0) {
+      conv[i] = 1;
+      minr[i] = 0.0;
+    }
+    return;
+  }
+  const int ldp = m | 1;
+  double* P = kLds ? smem : gws + gws_off[i];
+  for (int e = tid; e < m * d; e += nt) {
+    const int r = e % m, c = e / m;
+    P[c * ldp + r] = Y[int64_t(c) * ldy + r0 + r];
+  }
+  if (tid == 0) s_stop = 0;
+  __syncthreads();
+  double mn = INFINITY;
+  for (int j = 0; j < d; ++j) {
+    double* pj = P + j * ldp;
+    if (tid < kWave) {
+      double sg = 0.0;
+      for (int r = j + 1 + tid; r < m; r += kWave) sg += pj[r] * pj[r];
+      sg = wave_sum(sg);
+      const double alpha = pj[j];
+      double beta, tau, scal;
+      if (sg == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+        scal = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + sg);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int r = j + 1 + tid; r < m; r += kWave) pj[r] *= scal;
+      if (tid == 0) {
+        s_tau = tau;
+        s_beta = beta;
+        if (fabs(beta) < delta) s_stop = 1;
+      }
+    }
+    __syncthreads();
+    mn = fmin(mn, fabs(s_beta));
+    if (s_stop) break;
+    const double tau = s_tau;
+    for (int c = j + 1 + tid; c < d; c += nt) {
+      double* pc = P + c * ldp;
+      double w0 = pc[j], w1 = 0.0;
+      int r = j + 1;
+      for (; r + 1 < m; r += 2) {
+        w0 += pj[r] * pc[r];
+        w1 += pj[r + 1] * pc[r + 1];
+      }
+      if (r < m) w0 += pj[r] * pc[r];
+      const double w = (w0 + w1) * tau;
+      pc[j] -= w;
+      for (int rr = j + 1; rr < m; ++rr) pc[rr] -= w * pj[rr];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int ok = mn < delta ? 1 : 0;
+    conv[i] = ok;
+    minr[i] = mn;
+    if (!ok) atomicAdd(unconverged, 1);
+  }
+}
+
+// ---------------------------------------------------------------- CPQR / ID
+
+// Column-pivoted Householder QR of A = Y_loc^T (d x m) held in the panel with
+// leading dimension lda = d | 1; thread c owns column c (a row of Y_loc).
+// Pivot = largest partial norm (ties -> lowest original column), norms are
+// downdated and recomputed once they lose about half their digits.  Truncates
+// at the first |R_jj| < delta.  Then T = R11^{-1} R12 by back substitution and
+// U (m x k) = rows J identity, other rows T^T.
+struct PivotCand {
+  double v;
+  int piv;
+  int pos;
+};
+
+__device__ __forceinline__ bool better(const PivotCand& a, const PivotCand& b) {
+  return a.v > b.v || (a.v == b.v && a.piv < b.piv);
+}
+
+__device__ __forceinline__ PivotCand wave_best(PivotCand c) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    PivotCand o;
+    o.v = __shfl_xor(c.v, off, kWave);
+    o.piv = __shfl_xor(c.piv, off, kWave);
+    o.pos = __shfl_xor(c.pos, off, kWave);
+    if (better(o, c)) c = o;
+  }
+  return c;
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y,
+                                                      int64_t ldy, int d, double delta, int32_t* __restrict__ kout,
+                                                      int32_t* __restrict__ Jout, const int64_t* __restrict__ joff,
+                                                      double* __restrict__ Uout, const int64_t* __restrict__ uoff,
+                                                      double* __restrict__ gws, const int64_t* __restrict__ gws_off) {
+  extern __shared__ double smem[];
+  __shared__ PivotCand s_best[4];
+  __shared__ double s_tau, s_scal;
+  __shared__ int s_p, s_stop;
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int lda = d | 1;
+  // LDS layout: vn1[m], vn2[m], piv[m] (as int in a double slot), panel
+  double* vn1 = smem;
+  double* vn2 = smem + m;
+  int* piv = reinterpret_cast<int*>(smem + 2 * m);
+  double* A = kLds ? smem + 3 * m : gws + gws_off[i];
+
+  for (int e = tid; e < m * d; e += nt) {
+    const int c = e % m, r = e / m;
+    A[c * lda + r] = Y[int64_t(r) * ldy + r0 + c];
+  }
+  __syncthreads();
+  for (int c = tid; c < m; c += nt) {
+    double s = 0.0;
+    for (int r = 0; r < d; ++r) s += A[c * lda + r] * A[c * lda + r];
+    vn1[c] = sqrt(s);
+    vn2[c] = vn1[c];
+    piv[c] = c;
+  }
+  if (tid == 0) s_stop = 0;
+  __syncthreads();
+
+  const int kmax = min(m, d);
+  int k = kmax;
+  const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  for (int j = 0; j < kmax; ++j) {
+    // pivot selection
+    PivotCand best{-1.0, 0x7fffffff, -1};
+    for (int c = j + tid; c < m; c += nt) {
+      PivotCand cand{vn1[c], piv[c], c};
+      if (better(cand, best)) best = cand;
+    }
+    best = wave_best(best);
+    if (lane == 0) s_best[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+      PivotCand b = s_best[0];
+      for (int w = 1; w < nw; ++w)
+        if (better(s_best[w], b)) b = s_best[w];
+      s_p = b.pos >= j ? b.pos : j;  // NaN norms never win a comparison: keep column j
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int r = tid; r < d; r += nt) {
+        const double t = A[j * lda + r];
+        A[j * lda + r] = A[p * lda + r];
+        A[p * lda + r] = t;
+      }
+      if (tid == 0) {
+        double t = vn1[j];
+        vn1[j] = vn1[p];
+        vn1[p] = t;
+        t = vn2[j];
+        vn2[j] = vn2[p];
+        vn2[p] = t;
+        const int ti = piv[j];
+        piv[j] = piv[p];
+        piv[p] = ti;
+      }
+      __syncthreads();
+    }
+    // Householder reflector of column j, rows j..d-1
+    double* aj = A + j * lda;
+    if (wave == 0) {
+      double sg = 0.0;
+      for (int r = j + 1 + lane; r < d; r += kWave) sg += aj[r] * aj[r];
+      sg = wave_sum(sg);
+      const double alpha = aj[j];
+      double beta, tau, scal;
+      if (sg == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+        scal = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + sg);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      if (lane == 0) {
+        s_tau = tau;
+        s_scal = scal;
+        if (fabs(beta) < delta || beta == 0.0) s_stop = 1;
+      }
+      // make sure every lane has read alpha before lane 0 overwrites it
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) aj[j] = beta;
+    }
+    __syncthreads();
+    if (s_stop) {
+      k = j;
+      break;
+    }
+    {
+      const double scal = s_scal;
+      for (int r = j + 1 + tid; r < d; r += nt) aj[r] *= scal;
+    }
+    __syncthreads();
+    const double tau = s_tau;
+    for (int c = j + 1 + tid; c < m; c += nt) {
+      double* ac = A + c * lda;
+      double w0 = ac[j], w1 = 0.0;
+      int r = j + 1;
+      for (; r + 1 < d; r += 2) {
+        w0 += aj[r] * ac[r];
+        w1 += aj[r + 1] * ac[r + 1];
+      }
+      if (r < d) w0 += aj[r] * ac[r];
+      const double w = (w0 + w1) * tau;
+      ac[j] -= w;
+      for (int rr = j + 1; rr < d; ++rr) ac[rr] -= w * aj[rr];
+      // norm downdate with recompute safeguard
+      if (vn1[c] != 0.0) {
+        double t = fabs(ac[j]) / vn1[c];
+        t = fmax(0.0, 1.0 - t * t);
+        const double ratio = vn1[c] / vn2[c];
+        const double t2 = t * ratio * ratio;
+        if (t2 <= tol3z) {
+          double s = 0.0;
+          for (int rr = j + 1; rr < d; ++rr) s += ac[rr] * ac[rr];
+          vn1[c] = sqrt(s);
+          vn2[c] = vn1[c];
+        } else {
+          vn1[c] = vn1[c] * sqrt(t);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // T = R11^{-1} R12, in place in rows 0..k-1 of the redundant columns
+  for (int c = k + tid; c < m; c += nt) {
+    double* ac = A + c * lda;
+    for (int r = k - 1; r >= 0; --r) {
+      double s = ac[r];
+      for (int l = r + 1; l < k; ++l) s -= A[l * lda + r] * ac[l];
+      ac[r] = s / A[r * lda + r];
+    }
+  }
+  __syncthreads();
+  if (tid == 0) kout[i] = k;
+  for (int r = tid; r < k; r += nt) Jout[joff[i] + r] = piv[r];
+  double* U = Uout + uoff[i];
+  for (int c = tid; c < m; c += nt) {
+    const int q = piv[c];
+    for (int r = 0; r < k; ++r) U[q + int64_t(r) * m] = (c < k) ? (c == r ? 1.0 : 0.0) : A[c * lda + r];
+  }
+}
+
+// ------------------------------------------------------ shrink / upsweep
+
+__global__ __launch_bounds__(256) void shrink_up_kernel(const int32_t* __restrict__ rowoff,
+                                                        const int32_t* __restrict__ koff,
+                                                        const int32_t* __restrict__ J,
+                                                        const int64_t* __restrict__ joff,
+                                                        const double* __restrict__ U,
+                                                        const int64_t* __restrict__ uoff,
+                                                        const double* __restrict__ Yloc, int64_t ldyl,
+                                                        const double* __restrict__ Win, int64_t ldwi,
+                                                        double* __restrict__ Yout, int64_t ldyo,
+                                                        double* __restrict__ Wout, int64_t ldwo, int nc) {
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int k0 = koff[i], k = koff[i + 1] - k0;
+  const int* Ji = J + joff[i];
+  const double* Ui = U + uoff[i];
+  for (int e = threadIdx.x; e < k * nc; e += blockDim.x) {
+    const int r = e % k, c = e / k;
+    if (Yloc) Yout[int64_t(c) * ldyo + k0 + r] = Yloc[int64_t(c) * ldyl + r0 + Ji[r]];
+    const double* u = Ui + int64_t(r) * m;
+    const double* w = Win + int64_t(c) * ldwi + r0;
+    double s0 = 0.0, s1 = 0.0;
+    int q = 0;
+    for (; q + 1 < m; q += 2) {
+      s0 += u[q] * w[q];
+      s1 += u[q + 1] * w[q + 1];
+    }
+    if (q < m) s0 += u[q] * w[q];
+    Wout[int64_t(c) * ldwo + k0 + r] = s0 + s1;
+  }
+}
+
+__global__ __launch_bounds__(256) void expand_kernel(const int32_t* __restrict__ rowoff, const int32_t* __restrict__ koff,
+                                                     const double* __restrict__ U, const int64_t* __restrict__ uoff,
+                                                     const double* __restrict__ Yh, int64_t ldh,
+                                                     double* __restrict__ Yt, int64_t ldt, int nc) {
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int k0 = koff[i], k = koff[i + 1] - k0;
+  const double* Ui = U + uoff[i];
+  for (int e = threadIdx.x; e < m * nc; e += blockDim.x) {
+    const int q = e % m, c = e / m;
+    const double* h = Yh + int64_t(c) * ldh + k0;
+    double s = 0.0;
+    for (int r = 0; r < k; ++r) s += Ui[q + int64_t(r) * m] * h[r];
+    Yt[int64_t(c) * ldt + r0 + q] += s;
+  }
+}
+
+__global__ __launch_bounds__(256) void skeleton_kernel(const int32_t* __restrict__ rowoff,
+                                                       const int32_t* __restrict__ koff,
+                                                       const int32_t* __restrict__ J,
+                                                       const int64_t* __restrict__ joff,
+                                                       const int32_t* __restrict__ pos_in,
+                                                       int32_t* __restrict__ pos_out, int dim,
+                                                       const double* __restrict__ X, int64_t ldx,
+                                                       double* __restrict__ Xs, int64_t ldxs) {
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i];
+  const int k0 = koff[i], k = koff[i + 1] - k0;
+  for (int r = threadIdx.x; r < k; r += blockDim.x) {
+    const int row = r0 + J[joff[i] + r];
+    const int pos = pos_in ? pos_in[row] : row;
+    pos_out[k0 + r] = pos;
+    for (int a = 0; a < dim; ++a) Xs[a * ldxs + k0 + r] = X[a * ldx + pos];
+  }
+}
+
+__global__ __launch_bounds__(256) void permute_rows_kernel(int64_t n, const int32_t* __restrict__ idx, int scatter,
+                                                           const double* __restrict__ src, int64_t lds,
+                                                           double* __restrict__ dst, int64_t ldd, int nc) {
+  const int64_t total = n * nc;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t p = e % n, c = e / n;
+    if (scatter)
+      dst[c * ldd + idx[p]] = src[c * lds + p];
+    else
+      dst[c * ldd + p] = src[c * lds + idx[p]];
+  }
+}
+
+__global__ __launch_bounds__(256) void sumsq_kernel(int64_t n, int nc, const double* __restrict__ A, int64_t lda,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const int64_t total = n * nc;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+    const double v = A[(e / n) * lda + e % n];
+    s += v * v;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(double* __restrict__ p, int64_t n) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    p[e] = 0.0;
+}
+
+unsigned grid_for(int64_t work, int64_t per_block = 256, unsigned cap = 65536) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return static_cast<unsigned>(g);
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+
+}  // namespace
+
+// ================================================================ launchers
+
+hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0, int ncols,
+                    double* out, int64_t ldo) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  gaussian_kernel<<<grid_for(nrows * ncols), 256, 0, s>>>(seed, nrows, rows, col0, ncols, out, ldo);
+  return hipGetLastError();
+}
+
+hipError_t sketch_f64(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
+                      const double* omega, int64_t ldo, double* y, int64_t ldy) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
+    const double* om = omega + int64_t(c0) * ldo;
+    double* yy = y + int64_t(c0) * ldy;
+    hipError_t e;
+    if (k.kind == kExp) {
+      if (dim == 1) e = launch_sketch_nc<1, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+      else if (dim == 2) e = launch_sketch_nc<2, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+      else e = launch_sketch_nc<3, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+    } else {
+      if (dim == 1) e = launch_sketch_nc<1, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+      else if (dim == 2) e = launch_sketch_nc<2, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+      else e = launch_sketch_nc<3, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                      const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out) {
+  if (nrows <= 0) return hipSuccess;
+  gen_blocks_kernel<<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, dim, X, ldx, k.kind, k.scale, out);
+  return hipGetLastError();
+}
+
+hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                    const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
+                    int64_t ldy, int nc, double alpha, int max_m) {
+  if (nrows <= 0 || nc <= 0) return hipSuccess;
+  const dim3 grid(nrows, (nc + kBsrCols - 1) / kBsrCols);
+  if (max_m <= 64)
+    bsr_gemm_kernel<8><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  else if (max_m <= 128)
+    bsr_gemm_kernel<16><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  else if (max_m <= 256)
+    bsr_gemm_kernel<32><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+                   double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m, size_t lds_limit,
+                   double* gws, const int64_t* gws_off) {
+  if (nnodes <= 0) return hipSuccess;
+  const int threads = d <= 64 ? 64 : (d <= 128 ? 128 : 256);
+  const size_t bytes = size_t(max_m | 1) * size_t(d) * sizeof(double);
+  if (bytes <= lds_limit) {
+    hipError_t e = allow_lds(qr_test_kernel<true>, bytes);
+    if (e != hipSuccess) return e;
+    qr_test_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, delta, conv, minr, unconverged, gws,
+                                                        gws_off);
+  } else {
+    if (!gws || !gws_off) return hipErrorInvalidValue;
+    qr_test_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, d, delta, conv, minr, unconverged, gws, gws_off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+                   double delta, int32_t* kout, int32_t* J, const int64_t* joff, double* U, const int64_t* uoff,
+                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off) {
+  if (nnodes <= 0) return hipSuccess;
+  const int threads = max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256);
+  const size_t small = size_t(3) * max_m * sizeof(double);
+  const size_t bytes = small + size_t(d | 1) * size_t(max_m) * sizeof(double);
+  if (bytes <= lds_limit) {
+    hipError_t e = allow_lds(cpqr_id_kernel<true>, bytes);
+    if (e != hipSuccess) return e;
+    cpqr_id_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, delta, kout, J, joff, U, uoff, gws,
+                                                        gws_off);
+  } else {
+    if (!gws || !gws_off) return hipErrorInvalidValue;
+    hipError_t e = allow_lds(cpqr_id_kernel<false>, small);
+    if (e != hipSuccess) return e;
+    cpqr_id_kernel<false><<<nnodes, threads, small, s>>>(rowoff, Y, ldy, d, delta, kout, J, joff, U, uoff, gws,
+                                                         gws_off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t shrink_up(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
+                     const int64_t* joff, const double* U, const int64_t* uoff, const double* Yloc, int64_t ldyl,
+                     const double* Win, int64_t ldwi, double* Yout, int64_t ldyo, double* Wout, int64_t ldwo,
+                     int nc) {
+  if (nnodes <= 0 || nc <= 0) return hipSuccess;
+  shrink_up_kernel<<<nnodes, 256, 0, s>>>(rowoff, koff, J, joff, U, uoff, Yloc, ldyl, Win, ldwi, Yout, ldyo, Wout,
+                                          ldwo, nc);
+  return hipGetLastError();
+}
+
+hipError_t expand(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const double* U,
+                  const int64_t* uoff, const double* Yh, int64_t ldh, double* Yt, int64_t ldt, int nc) {
+  if (nnodes <= 0 || nc <= 0) return hipSuccess;
+  expand_kernel<<<nnodes, 256, 0, s>>>(rowoff, koff, U, uoff, Yh, ldh, Yt, ldt, nc);
+  return hipGetLastError();
+}
+
+hipError_t skeleton(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
+                    const int64_t* joff, const int32_t* pos_in, int32_t* pos_out, int dim, const double* X,
+                    int64_t ldx, double* Xs, int64_t ldxs) {
+  if (nnodes <= 0) return hipSuccess;
+  skeleton_kernel<<<nnodes, 64, 0, s>>>(rowoff, koff, J, joff, pos_in, pos_out, dim, X, ldx, Xs, ldxs);
+  return hipGetLastError();
+}
+
+hipError_t permute_rows(hipStream_t s, int64_t n, const int32_t* idx, bool scatter, const double* src, int64_t lds,
+                        double* dst, int64_t ldd, int nc) {
+  if (n <= 0 || nc <= 0) return hipSuccess;
+  permute_rows_kernel<<<grid_for(n * nc), 256, 0, s>>>(n, idx, scatter ? 1 : 0, src, lds, dst, ldd, nc);
+  return hipGetLastError();
+}
+
+hipError_t sumsq_partial(hipStream_t s, int64_t n, int nc, const double* A, int64_t lda, double* partial,
+                         int nblocks) {
+  sumsq_kernel<<<nblocks, 256, 0, s>>>(n, nc, A, lda, partial);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero(hipStream_t s, double* p, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  fill_zero_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(p, n);
+  return hipGetLastError();
+}
+
+}  // namespace h2dev

@@ -1,0 +1,244 @@
+"""GPU parity of the HIP construction path against the FP64 oracle.
+
+Every case prints its name, sizes and seeds before touching the GPU.  Floating
+point tolerances:
+  * Omega: both sides evaluate the same Philox words; only log/cos/sqrt of the
+    two math libraries differ (a few ulps)  ->  |diff| <= 1e-13.
+  * dense sketch: same products summed in a different order, kernel entries
+    within a few ulps  ->  relative (to the column's max) <= 1e-12.
+  * dense blocks D: same formula, exp/sqrt ulps  ->  relative <= 1e-13.
+  * whole construction: randomised and adaptive, so the bar is the accuracy
+    bound (relative Frobenius and matvec error <= 10 tol against the exact K),
+    plus structural identities (tree/lists bit-exact, U(J,:) = I exactly).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_16759_amd as h2
+from paper_2506_16759_amd.workloads import CUBE_131K, SMALL_2D, uniform_points
+from oracle.build import build_h2
+from oracle.kernels import KernelOperator
+from oracle.philox import gaussian as oracle_gaussian
+from oracle.tree import build_lists, build_tree
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return h2.Context(0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _colmajor_from(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).cuda().T
+
+
+def _dense_from_matvec(H, n):
+    import torch
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    return _np(H.matvec(eye.T.contiguous().T))
+
+
+@pytest.mark.parametrize("n,col0,ncols,seed", [(1, 0, 1, 1), (1000, 0, 32, 1000), (4099, 48, 17, 7),
+                                               (70000, 5, 3, 123456789)])
+def test_gaussian_matches_oracle(ctx, n, col0, ncols, seed):
+    import torch
+    _say(f"gaussian n={n} col0={col0} ncols={ncols} seed={seed}")
+    rows = np.random.default_rng(n).permutation(max(n, 1) * 3)[:n].astype(np.int32)
+    out = _np(h2.gaussian(ctx, seed, torch.from_numpy(rows), col0, ncols))
+    ref = oracle_gaussian(seed, rows, col0, ncols)
+    np.testing.assert_allclose(out, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,dim,kind,length,ncols", [
+    (1000, 2, "exp", 0.1, 32), (3001, 3, "exp", 0.2, 48), (777, 3, "gauss", 0.15, 16), (129, 1, "exp", 0.3, 1),
+    (2500, 2, "gauss", 0.05, 80), (4096, 3, "exp", 0.2, 64), (200, 3, "exp", 0.2, 20),
+])
+def test_sketch_matches_oracle(ctx, n, dim, kind, length, ncols):
+    _say(f"sketch n={n} dim={dim} kernel={kind} l={length} ncols={ncols}")
+    pts = uniform_points(n, dim, 10 + n)
+    om = np.random.default_rng(n).standard_normal((n, ncols))
+    import torch
+    y = _np(h2.sketch(ctx, torch.from_numpy(pts), kind, length, _colmajor_from(om)))
+    ref = KernelOperator(pts, kind, length).sketch(om)
+    scale = np.abs(ref).max(axis=0)
+    assert (np.abs(y - ref).max(axis=0) <= 1e-12 * scale).all()
+
+
+def _check_tree_lists(H, pts, leaf, eta):
+    tr = build_tree(pts, leaf)
+    L = build_lists(tr, eta)
+    D = int(H.export("DEPTH")[0])
+    assert D == tr.depth
+    np.testing.assert_array_equal(H.export("PERM"), tr.perm)
+    np.testing.assert_array_equal(H.export("NEAR_PTR"), L.near_ptr)
+    np.testing.assert_array_equal(H.export("NEAR_IDX"), L.near_idx)
+    for t in range(D + 1):
+        np.testing.assert_array_equal(H.export("FAR_PTR", t), L.far_ptr[t])
+        np.testing.assert_array_equal(H.export("FAR_IDX", t), L.far_idx[t])
+    return tr, L
+
+
+def _check_identity_rows(H):
+    """U(J,:) = I exactly at every processed depth (the ID invariant)."""
+    D = int(H.export("DEPTH")[0])
+    top = int(H.export("TOP")[0])
+    nodes = H.export("NODES").reshape(-1, 2)
+    for t in range(top, D + 1):
+        ranks = H.export("RANKS", t)
+        basis = H.export("BASIS", t)
+        skel = H.export("SKEL_POS", t)
+        if t == D:
+            m = np.array([nodes[(1 << D) - 1 + i, 1] - nodes[(1 << D) - 1 + i, 0] for i in range(1 << D)])
+            rows_of = [np.arange(nodes[(1 << D) - 1 + i, 0], nodes[(1 << D) - 1 + i, 1]) for i in range(1 << D)]
+        else:
+            kc = H.export("RANKS", t + 1)
+            sk_c = H.export("SKEL_POS", t + 1)
+            offc = np.concatenate([[0], np.cumsum(kc)])
+            m = kc[0::2] + kc[1::2]
+            rows_of = [sk_c[offc[2 * i]:offc[2 * i + 2]] for i in range(1 << t)]
+        off_b, off_s = 0, 0
+        for i in range(1 << t):
+            k = int(ranks[i])
+            U = basis[off_b:off_b + m[i] * k].reshape(k, m[i]).T
+            sk = skel[off_s:off_s + k]
+            J = np.array([np.nonzero(rows_of[i] == s)[0][0] for s in sk], dtype=int)
+            np.testing.assert_array_equal(U[J], np.eye(k))
+            off_b += m[i] * k
+            off_s += k
+        assert off_b == basis.size and off_s == skel.size
+
+
+def test_build_small_2d_parity(ctx):
+    w = SMALL_2D
+    _say(f"build {w.name} n={w.n} tol={w.tol}")
+    pts = w.points()
+    H = h2.build(ctx, pts, w.kernel, w.length, tol=w.tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0,
+                 d_inc=w.d_inc, seed=w.omega_seed)
+    info = H.info()
+    _check_tree_lists(H, pts, w.leaf_size, w.eta)
+    _check_identity_rows(H)
+    op = KernelOperator(pts, w.kernel, w.length)
+    K = op.dense()
+    KH = _dense_from_matvec(H, w.n)
+    eF = np.linalg.norm(K - KH) / np.linalg.norm(K)
+    x = np.random.default_rng(8).standard_normal((w.n, 8))
+    y = _np(H.matvec(_colmajor_from(x)))
+    emv = np.linalg.norm(K @ x - y) / np.linalg.norm(K @ x)
+    _say(f"eF={eF:.3e} emv={emv:.3e} samples={info['samples']} ranks={info['rank_min']}..{info['rank_max']}")
+    assert eF <= 10 * w.tol and emv <= 10 * w.tol
+    # against the oracle's own construction of the same problem with the same Omega
+    ho = build_h2(op, pts, w.leaf_size, w.eta, w.tol, w.d0, w.d_inc, 128, w.omega_seed)
+    assert info["samples"] == ho.samples
+    assert abs(info["delta"] - ho.delta) <= 1e-12 * ho.delta
+    assert int(H.export("TOP")[0]) == ho.top
+    agree = []
+    for t in range(ho.top, ho.tree.depth + 1):
+        kg = H.export("RANKS", t)
+        ko = np.array([ho.rank(t, i) for i in range(1 << t)])
+        agree.append(np.mean(kg == ko))
+        assert np.abs(kg - ko).max() <= 2
+    _say(f"rank agreement per depth {np.round(agree, 3).tolist()}")
+    assert np.linalg.norm(KH - ho.dense()) / np.linalg.norm(K) <= 10 * w.tol
+    # dense near-field blocks are the kernel itself
+    Dg = H.export("DENSE")
+    perm = ho.tree.perm
+    off = 0
+    D = ho.tree.depth
+    npp, ni = ho.lists.near_ptr, ho.lists.near_idx
+    for s in range(1 << D):
+        for j in range(npp[s], npp[s + 1]):
+            b = int(ni[j])
+            ref = ho.Dn[(s, b)]
+            got = Dg[off:off + ref.size].reshape(ref.shape[1], ref.shape[0]).T
+            np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+            off += ref.size
+    assert off == Dg.size
+
+
+@pytest.mark.parametrize("n,dim,kind,length,leaf,tol,d0,dinc", [
+    (6000, 3, "exp", 0.2, 64, 1e-7, 16, 16),     # forces adaptive rounds
+    (3333, 2, "gauss", 0.1, 40, 1e-6, 32, 16),   # ragged leaves, Gaussian kernel
+    (2048, 3, "exp", 0.2, 32, 1e-8, 32, 16),
+])
+def test_build_matches_dense_bound(ctx, n, dim, kind, length, leaf, tol, d0, dinc):
+    _say(f"build n={n} dim={dim} {kind} l={length} leaf={leaf} tol={tol} d0={d0}+{dinc}")
+    pts = uniform_points(n, dim, 40 + n)
+    H = h2.build(ctx, pts, kind, length, tol=tol, leaf_size=leaf, eta=0.7, d0=d0, d_inc=dinc, seed=11)
+    info = H.info()
+    _check_tree_lists(H, pts, leaf, 0.7)
+    _check_identity_rows(H)
+    K = KernelOperator(pts, kind, length).dense()
+    KH = _dense_from_matvec(H, n)
+    eF = np.linalg.norm(K - KH) / np.linalg.norm(K)
+    _say(f"eF={eF:.3e} samples={info['samples']} rounds={info['rounds']} ranks={info['rank_min']}..{info['rank_max']}")
+    assert eF <= 10 * tol
+
+
+def test_edge_cases(ctx):
+    import torch
+    _say("edge: single leaf, nothing admissible, duplicates, n=1")
+    pts = uniform_points(50, 2, 1)
+    H = h2.build(ctx, pts, "exp", 0.2, leaf_size=64)
+    K = KernelOperator(pts, "exp", 0.2).dense()
+    np.testing.assert_allclose(_dense_from_matvec(H, 50), K, rtol=1e-14, atol=1e-15)
+    pts = uniform_points(600, 2, 2)
+    H = h2.build(ctx, pts, "gauss", 0.2, leaf_size=16, eta=1e-9)
+    assert H.info()["samples"] == 0
+    np.testing.assert_allclose(_dense_from_matvec(H, 600), KernelOperator(pts, "gauss", 0.2).dense(),
+                               rtol=1e-13, atol=1e-15)
+    pts = np.repeat(uniform_points(700, 3, 3), 2, axis=1)
+    H = h2.build(ctx, pts, "exp", 0.2, leaf_size=32, tol=1e-6)
+    K = KernelOperator(pts, "exp", 0.2).dense()
+    assert np.linalg.norm(K - _dense_from_matvec(H, 1400)) / np.linalg.norm(K) <= 1e-5
+    H = h2.build(ctx, np.array([[0.5], [0.25]]), "exp", 0.2)
+    assert abs(_np(H.matvec(torch.ones(1, dtype=torch.float64, device="cuda")))[0] - 1.0) < 1e-15
+
+
+def test_sample_limit_is_reported(ctx):
+    _say("error path: d_max reached")
+    pts = uniform_points(3000, 3, 6)
+    with pytest.raises(h2.H2Error) as ei:
+        h2.build(ctx, pts, "exp", 0.2, leaf_size=48, tol=1e-10, d0=8, d_inc=8, d_max=16)
+    assert ei.value.status == -5
+
+
+def test_full_size_cube_sampled_parity(ctx):
+    """The timed workload at full size: bit-exact tree/lists, sampled sketch rows,
+    sampled matvec rows against the oracle's dense products."""
+    import torch
+    w = CUBE_131K
+    _say(f"full size {w.name} n={w.n} tol={w.tol}")
+    pts = w.points()
+    H = h2.build(ctx, pts, w.kernel, w.length, tol=w.tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0,
+                 d_inc=w.d_inc, seed=w.omega_seed)
+    info = H.info()
+    _say(f"built: {info['t_total']:.1f} ms samples={info['samples']} ranks={info['rank_min']}..{info['rank_max']}")
+    _check_tree_lists(H, pts, w.leaf_size, w.eta)
+    op = KernelOperator(pts, w.kernel, w.length)
+    rng = np.random.default_rng(17)
+    rows = rng.choice(w.n, 64, replace=False)
+    # sketch at full size, sampled rows
+    om = np.random.default_rng(5).standard_normal((w.n, 32))
+    y = _np(h2.sketch(ctx, torch.from_numpy(pts), w.kernel, w.length, _colmajor_from(om)))
+    ref = op.sketch_rows(rows, om)
+    assert np.abs(y[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
+    # H^2 matvec against the exact dense product on sampled rows
+    x = np.random.default_rng(9).standard_normal((w.n, 4))
+    yh = _np(H.matvec(_colmajor_from(x)))
+    kx = op.entries(rows, np.arange(w.n)) @ x
+    emv = np.linalg.norm(yh[rows] - kx) / np.linalg.norm(kx)
+    _say(f"sampled-row matvec error {emv:.3e}")
+    assert emv <= 10 * w.tol
