@@ -1,0 +1,171 @@
+"""Benchmark: H^2 construction of the 131072-point exponential-covariance cube.
+
+One step = one complete h2_build (Algorithm 1 with adaptive sampling: tree and
+lists, Gaussian draw, dense on-the-fly sketch, near-field generation and
+subtraction, convergence tests, IDs, upsweeps, coupling generation) with the
+points already resident in HBM.  Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H2 build time (N=131072, tol 1e-6) + sketch TFLOP/s; mixed vs FP64 speedup"
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector (= FP64 matrix) peak
+
+
+def sketch_flops_per_entry(dim: int, ncols: int) -> float:
+    """Algorithmic FP64 operations per kernel entry of the fused sketch:
+    generation = dim differences + (2 dim - 1) square-accumulate + sqrt + scale + exp,
+    contraction = 2 * ncols (one multiply-add per output column)."""
+    return (3 * dim - 1 + 3) + 2 * ncols
+
+
+def cpu_baseline(w, samples_used: int, rows: int = 2048):
+    """The oracle's dense sketch on a sample of rows, scaled to the full pass count."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.kernels import KernelOperator
+    from oracle.philox import gaussian
+
+    pts = w.points()
+    op = KernelOperator(pts, w.kernel, w.length)
+    sel = np.arange(rows)
+    omega = gaussian(w.omega_seed, np.arange(w.n), 0, w.d0)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        op.sketch_rows(sel, omega)
+        dt = time.perf_counter() - t0
+    per_pass_full = dt * (w.n / rows)
+    # the build draws d0 columns, then d_inc per adaptive round; every pass costs the same
+    passes = 1 + max(0, samples_used - w.d0) // w.d_inc
+    return {
+        "value": per_pass_full * passes,
+        "unit": "s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle dense sketch of {rows} of {w.n} rows x {w.d0} columns ({dt:.2f} s), scaled to all rows "
+                   f"and the build's {passes} sketch passes; the oracle's O(N) steps are not included, so this is "
+                   f"a lower bound on its build time"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sketch-launches", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2506_16759_amd as h2
+    from paper_2506_16759_amd.workloads import CUBE_131K
+
+    w = CUBE_131K
+    tol = args.tol if args.tol is not None else w.tol
+    print(f"[bench] workload {w.name} n={w.n} tol={tol}", file=sys.stderr, flush=True)
+    ctx = h2.Context(0)
+    pts = torch.from_numpy(w.points()).cuda()
+    opts = h2.opts_default(tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed)
+
+    infos = []
+    for i in range(args.warmup):
+        H = h2.build(ctx, pts, w.kernel, w.length, opts=opts)
+        infos.append(H.info())
+        H.close()
+        print(f"[bench] warmup {i} {infos[-1]['t_total']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    times = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ts = time.perf_counter()
+        H = h2.build(ctx, pts, w.kernel, w.length, opts=opts)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        infos.append(H.info())
+        H.close()
+        print(f"[bench] step {i} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    info = infos[-1]
+    ms_per_step = total / args.steps * 1e3
+
+    # dominant kernel: the fused sketch, timed live on the library's stream
+    nc = w.d0
+    omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, nc)
+    h2.sketch(ctx, pts, w.kernel, w.length, omega)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(ctx.stream)
+    for _ in range(args.sketch_launches):
+        h2.sketch(ctx, pts, w.kernel, w.length, omega)
+    ev1.record(ctx.stream)
+    ev1.synchronize()
+    sk_ms = ev0.elapsed_time(ev1) / args.sketch_launches
+    entries = float(w.n) * w.n
+    achieved = sketch_flops_per_entry(w.dim, nc) * entries / (sk_ms * 1e-3) / 1e12
+    sketch_tflops = 2.0 * entries * nc / (sk_ms * 1e-3) / 1e12
+
+    out = {
+        "metric": METRIC,
+        "value": ms_per_step / 1e3,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "dim": w.dim, "kernel": f"exp(-r/{w.length})",
+                   "leaf_size": w.leaf_size, "eta": w.eta, "tol": tol, "d0": w.d0, "d_inc": w.d_inc,
+                   "precision": "fp64"},
+        "median_step_ms": statistics.median(times) * 1e3,
+        "sketch_tflops": sketch_tflops,
+        "sketch_entries_per_s": entries / (sk_ms * 1e-3),
+        "sketch_kernel_ms": sk_ms,
+        "mixed_vs_fp64_speedup": None,
+        "samples": info["samples"],
+        "adaptive_rounds": info["rounds"],
+        "rank_range": [info["rank_min"], info["rank_max"]],
+        "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")},
+        "bytes": {"dense": info["bytes_dense"], "coupling": info["bytes_coupling"], "basis": info["bytes_basis"]},
+        "roofline": {
+            "kernel": "sketch_f64_kernel<3,exp,32>",
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+        },
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, info["samples"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -66,7 +66,13 @@ class KernelOperator:
 
     def sketch_rows(self, rows: np.ndarray, omega: np.ndarray) -> np.ndarray:
         """(K Omega)(rows, :) only -- used to check sampled rows of a large sketch."""
-        return self.entries(rows, np.arange(self.n)) @ np.asarray(omega, dtype=np.float64)
+        rows = np.asarray(rows)
+        omega = np.asarray(omega, dtype=np.float64)
+        out = np.zeros((rows.shape[0], omega.shape[1]))
+        allc = np.arange(self.n)
+        for r0 in range(0, rows.shape[0], self.block_rows):
+            out[r0:r0 + self.block_rows] = self.entries(rows[r0:r0 + self.block_rows], allc) @ omega
+        return out
 
     sketch_t = sketch
 

@@ -114,7 +114,13 @@ def _colmajor(t, rows: int):
     torch = _torch()
     if t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError("expected a float64 cuda tensor")
-    if t.dim() != 2 or t.shape[0] != rows or t.stride(0) != 1 or t.stride(1) < rows:
+    if t.dim() != 2 or t.shape[0] != rows:
+        raise ValueError("expected an (n, c) tensor")
+    if t.shape[1] <= 1:             # a single column: its stride is irrelevant
+        if t.stride(0) != 1 and rows > 1:
+            raise ValueError("expected unit row stride")
+        return max(rows, 1)
+    if t.stride(0) != 1 or t.stride(1) < rows:
         raise ValueError("expected an (n, c) column-major view (the transpose of a contiguous (c, n) tensor)")
     return t.stride(1)
 

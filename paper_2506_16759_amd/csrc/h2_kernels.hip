@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, int64_t nr
 // 16-row MFMA tiles and all NC output columns.  Columns of K (points j) are
 // streamed through LDS 64 at a time together with the matching Omega rows.
 // For v_mfma_f64_16x16x4: lane l supplies A[l%16][l/16] and B[l/16][l%16] and
-// holds D[4*(l/16)+q][l%16] in accumulator element q.
+// holds D[l/16 + 4q][l%16] in accumulator element q (rows interleaved by 4).
 constexpr int kSkRows = 128;
 constexpr int kSkK = 64;
 
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double
     if (col >= ncr) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int64_t ra = row0 + 4 * lk + q, rb = row0 + 16 + 4 * lk + q;
+      const int64_t ra = row0 + lk + 4 * q, rb = row0 + 16 + lk + 4 * q;
       if (ra < n) y[col * ldy + ra] = acc0[c][q];
       if (rb < n) y[col * ldy + rb] = acc1[c][q];
     }
