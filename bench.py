@@ -31,6 +31,24 @@ def sketch_flops_per_entry(dim: int, ncols: int) -> float:
     return (3 * dim - 1 + 3) + 2 * ncols
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs
+    (profiles/sketch_traffic.json), or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "sketch_traffic.json")))
+        csrc = os.path.join(ROOT, "paper_2506_16759_amd", "csrc")
+        src = hashlib.sha256(open(os.path.join(csrc, "h2_kernels.hip"), "rb").read()
+                             + open(os.path.join(csrc, "h2_devmath.hpp"), "rb").read()).hexdigest()
+        if rec.get("source_sha256") != src or kernel not in rec["kernels"]:
+            return None
+        k = rec["kernels"][kernel]
+        return k["fetch_bytes"] + k["write_bytes"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def cpu_baseline(w, samples_used: int, rows: int = 2048):
     """The oracle's dense sketch on a sample of rows, scaled to the full pass count."""
     import numpy as np
@@ -69,6 +87,9 @@ def main():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sketch-launches", type=int, default=5)
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="only run the sketch (FP64, FP32, bf16x3; 32 columns) twice each and a 1 GiB copy of "
+                         "known size, for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -83,32 +104,61 @@ def main():
 
     w = CUBE_131K
     tol = args.tol if args.tol is not None else w.tol
+    if args.profile_kernels:
+        ctx = h2.Context(0)
+        pts = torch.from_numpy(w.points()).cuda()
+        omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, w.d0)
+        for prec in (h2.FP64, h2.FP32, h2.BF16X3):
+            for _ in range(2):
+                h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=prec)
+        # calibration: a plain device copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": "done", "copy_bytes": a.numel() * 8}), flush=True)
+        return
     print(f"[bench] workload {w.name} n={w.n} tol={tol}", file=sys.stderr, flush=True)
     ctx = h2.Context(0)
     pts = torch.from_numpy(w.points()).cuda()
     opts = h2.opts_default(tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed)
 
-    infos = []
-    for i in range(args.warmup):
-        H = h2.build(ctx, pts, w.kernel, w.length, opts=opts)
-        infos.append(H.info())
-        H.close()
-        print(f"[bench] warmup {i} {infos[-1]['t_total']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    times = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        ts = time.perf_counter()
-        H = h2.build(ctx, pts, w.kernel, w.length, opts=opts)
+    def timed_builds(o, label, steps, warmup):
+        infos = []
+        for i in range(warmup):
+            H = h2.build(ctx, pts, w.kernel, w.length, opts=o)
+            infos.append(H.info())
+            H.close()
+            print(f"[bench] {label} warmup {i} {infos[-1]['t_total']:.1f} ms", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        infos.append(H.info())
-        H.close()
-        print(f"[bench] step {i} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    info = infos[-1]
-    ms_per_step = total / args.steps * 1e3
+        times = []
+        t0 = time.perf_counter()
+        for i in range(steps):
+            ts = time.perf_counter()
+            H = h2.build(ctx, pts, w.kernel, w.length, opts=o)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            infos.append(H.info())
+            H.close()
+            print(f"[bench] {label} step {i} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3, times, infos[-1]
+
+    ms_per_step, times, info = timed_builds(opts, "fp64", args.steps, args.warmup)
+
+    # mixed precision: same workload and tolerance, FP32 sketch (and bf16x3, which
+    # may not reach tol 1e-6: its products carry ~2^-16 relative error)
+    mixed = {}
+    for name, prec in (("fp32", h2.FP32), ("bf16x3", h2.BF16X3)):
+        o = h2.opts_default(tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed,
+                            precision=prec)
+        try:
+            mms, mtimes, minfo = timed_builds(o, name, max(1, args.steps // 2 + 1), 1)
+            mixed[name] = {"ms_per_build": mms, "samples": minfo["samples"], "adaptive_rounds": minfo["rounds"],
+                           "rank_range": [minfo["rank_min"], minfo["rank_max"]],
+                           "sketch_phase_ms": minfo["t_sample"], "speedup_vs_fp64": ms_per_step / mms}
+        except h2.H2Error as exc:
+            mixed[name] = {"error": str(exc)}
 
     # dominant kernel: the fused sketch, timed live on the library's stream
     nc = w.d0
@@ -145,7 +195,8 @@ def main():
         "sketch_tflops": sketch_tflops,
         "sketch_entries_per_s": entries / (sk_ms * 1e-3),
         "sketch_kernel_ms": sk_ms,
-        "mixed_vs_fp64_speedup": None,
+        "mixed_vs_fp64_speedup": mixed.get("fp32", {}).get("speedup_vs_fp64"),
+        "mixed": mixed,
         "samples": info["samples"],
         "adaptive_rounds": info["rounds"],
         "rank_range": [info["rank_min"], info["rank_max"]],
@@ -158,7 +209,7 @@ def main():
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": measured_traffic("sketch_f64_kernel<3,exp,32>"),
         },
     }
     if not args.no_cpu_baseline:

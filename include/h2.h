@@ -56,9 +56,16 @@ typedef struct {
   double length;  /* correlation length l > 0 */
 } h2_kernel;
 
-/* Arithmetic of the sketch and near-field products (the construction's
- * stopping test, norm downdating and interpolation solve are always FP64). */
-typedef enum { H2_FP64 = 0 } h2_precision;
+/* Arithmetic of the dense sketch (and, in later versions, the near-field
+ * products).  Kernel blocks D and B are always evaluated and stored in FP64;
+ * the stopping test, CPQR norm downdating and interpolation solve are FP64.
+ *   H2_FP64:   FP64 entries, FP64 matrix cores.
+ *   H2_FP32:   FP32 entries, FP32 matrix cores (FP32 partial sums folded into
+ *              FP64 every 256 points).
+ *   H2_BF16X3: FP32 entries split into bf16 hi + lo, three bf16 products
+ *              (hi*hi + hi*lo + lo*hi) with FP32 accumulation, folded into FP64
+ *              likewise; about 2^-16 relative error per product. */
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2 } h2_precision;
 
 /* How the absolute ID/stopping threshold delta is derived from tol
  * (Sec. III-B: "an approximate norm of the matrix ... via sketching"):
@@ -77,6 +84,11 @@ typedef struct {
   uint64_t seed;      /* key of the counter-based Gaussian test matrix */
   int32_t precision;  /* h2_precision */
   int32_t norm_mode;  /* h2_norm_mode */
+  int32_t sketch_ahead; /* extra columns sketched whenever a sketch pass runs (0..128).  The
+                         * adaptive loop still grows d by d_inc; columns already sketched
+                         * are used without another pass.  Results are identical for any
+                         * value (Omega is counter-based); only the number of passes over
+                         * the O(n^2) black box changes. */
 } h2_opts;
 
 typedef struct h2_ctx h2_ctx;
@@ -84,7 +96,7 @@ typedef struct h2_matrix h2_matrix;
 typedef struct h2_plan h2_plan;
 
 /* Fills defaults: tol 1e-6, leaf 64, eta 0.7, d0 32, d_inc 16, d_max 128,
- * seed 1000, FP64, FRO_SCALED. */
+ * seed 1000, FP64, FRO_SCALED, sketch_ahead 32. */
 h2_status h2_opts_default(h2_opts* opts);
 
 const char* h2_status_string(h2_status s);
@@ -183,7 +195,8 @@ h2_status h2_export(const h2_matrix* h, int32_t part, int32_t depth, void* dst, 
 typedef struct {
   int64_t n;
   int32_t dim, depth, top;     /* tree depth D, coarsest processed depth */
-  int32_t samples;             /* total sample columns drawn */
+  int32_t samples;             /* sample columns used by the construction (d) */
+  int32_t sketched;            /* sample columns sketched (>= samples with look-ahead) */
   int32_t rounds;              /* adaptive rounds over all levels */
   int32_t rank_min, rank_max;  /* over all processed nodes */
   double delta;                /* absolute threshold used */
@@ -193,6 +206,7 @@ typedef struct {
   /* phase times in milliseconds (HIP events on the context stream) */
   double t_total, t_tree, t_sample, t_near_gen, t_subtract, t_convtest, t_id, t_upsweep,
       t_coupling, t_misc;
+  double t_host_plan;          /* host time of the tree + lists (overlaps the first sketch) */
   double sketch_flops;         /* algorithmic 2*n*n*columns summed over sketch passes */
   double sketch_entries;       /* kernel entries evaluated by the sketch passes */
 } h2_info;

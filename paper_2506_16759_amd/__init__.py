@@ -16,10 +16,11 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
+from ._lib import BF16X3, FP32, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "H2Matrix",
-           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "NORM_FRO_SCALED", "NORM_LITERAL"]
+           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "NORM_FRO_SCALED",
+           "NORM_LITERAL"]
 
 
 def _torch():
@@ -38,6 +39,8 @@ def opts_default(**over) -> _lib.Opts:
     for k, v in over.items():
         if k == "norm_mode" and isinstance(v, str):
             v = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[v]
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[v]
         setattr(o, k, v)
     return o
 

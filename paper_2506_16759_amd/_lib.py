@@ -12,7 +12,7 @@ STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_HIP", -3: "H2_ERR_OOM", -4: 
           -5: "H2_ERR_SAMPLES", -6: "H2_ERR_STATE", -7: "H2_ERR_UNSUPPORTED"}
 
 K_EXP, K_GAUSS = 1, 2
-FP64 = 0
+FP64, FP32, BF16X3 = 0, 1, 2
 NORM_FRO_SCALED, NORM_LITERAL = 0, 1
 
 PART = dict(DEPTH=0, PERM=1, NODES=2, BOXES=3, NEAR_PTR=4, NEAR_IDX=5, FAR_PTR=6, FAR_IDX=7, RANKS=8,
@@ -25,7 +25,7 @@ PART_DTYPE = dict(DEPTH="i4", PERM="i4", NODES="i4", BOXES="f8", NEAR_PTR="i4", 
 class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("leaf_size", C.c_int32), ("eta", C.c_double), ("d0", C.c_int32),
                 ("d_inc", C.c_int32), ("d_max", C.c_int32), ("seed", C.c_uint64), ("precision", C.c_int32),
-                ("norm_mode", C.c_int32)]
+                ("norm_mode", C.c_int32), ("sketch_ahead", C.c_int32)]
 
 
 class Kernel(C.Structure):
@@ -34,13 +34,15 @@ class Kernel(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("depth", C.c_int32), ("top", C.c_int32),
-                ("samples", C.c_int32), ("rounds", C.c_int32), ("rank_min", C.c_int32), ("rank_max", C.c_int32),
+                ("samples", C.c_int32), ("sketched", C.c_int32), ("rounds", C.c_int32), ("rank_min", C.c_int32),
+                ("rank_max", C.c_int32),
                 ("delta", C.c_double), ("norm_estimate", C.c_double), ("near_blocks", C.c_int64),
                 ("far_blocks", C.c_int64), ("bytes_dense", C.c_int64), ("bytes_coupling", C.c_int64),
                 ("bytes_basis", C.c_int64), ("t_total", C.c_double), ("t_tree", C.c_double),
                 ("t_sample", C.c_double), ("t_near_gen", C.c_double), ("t_subtract", C.c_double),
                 ("t_convtest", C.c_double), ("t_id", C.c_double), ("t_upsweep", C.c_double),
-                ("t_coupling", C.c_double), ("t_misc", C.c_double), ("sketch_flops", C.c_double),
+                ("t_coupling", C.c_double), ("t_misc", C.c_double), ("t_host_plan", C.c_double),
+                ("sketch_flops", C.c_double),
                 ("sketch_entries", C.c_double)]
 
     def as_dict(self):

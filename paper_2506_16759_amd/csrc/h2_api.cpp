@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -201,7 +202,8 @@ struct h2_matrix {
   h2_opts opts{};
   int top = 1;
   double delta = 0, nu = 0;
-  int samples = 0, rounds = 0;
+  int samples = 0, sketched = 0, rounds = 0;
+  double host_plan_ms = 0;
   DevArray<int32_t> perm;
   DevArray<double> X;  // tree-ordered SoA points
   DevArray<int32_t> nptr, nidx, leafoff;
@@ -238,8 +240,10 @@ void check_opts(const h2_opts* o) {
   H2_REQUIRE(o->d0 >= 1 && o->d0 <= 128, "d0 must be in [1, 128]");
   H2_REQUIRE(o->d_inc >= 1 && o->d_inc <= 128, "d_inc must be in [1, 128]");
   H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 128, "d_max must be in [d0, 128]");
-  H2_REQUIRE(o->precision == H2_FP64, "only H2_FP64 is implemented");
+  H2_REQUIRE(o->precision == H2_FP64 || o->precision == H2_FP32 || o->precision == H2_BF16X3,
+             "unknown precision");
   H2_REQUIRE(o->norm_mode == H2_NORM_FRO_SCALED || o->norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
+  H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 128, "sketch_ahead must be in [0, 128]");
 }
 
 int top_depth(const h2::Plan& p) {
@@ -293,7 +297,8 @@ class Builder {
   hipStream_t s_;
   PhaseTimer timer_;
   h2dev::KernelFn kf_{};
-  int dcap_ = 0, d_ = 0;
+  int dcap_ = 0, d_ = 0, dsk_ = 0, ahead_ = 0;
+  const double* points_ = nullptr;  // caller's points, original order (borrowed for the build)
   DevArray<double> gws_;
   DevArray<int64_t> gws_off_;
   DevArray<int32_t> conv_, counter_;
@@ -303,14 +308,38 @@ class Builder {
     h2_matrix& h = *h_;
     const h2_opts& o = h.opts;
     kf_ = kernel_fn(h.kernel);
-    // ---- plan (host): tree + lists
-    int ph = timer_.begin(kTree);
+    points_ = points;
+    dcap_ = o.d_max;
+    ahead_ = o.sketch_ahead;
     std::vector<double> pts_h(static_cast<size_t>(n) * dim);
     H2_HIP(hipMemcpyAsync(pts_h.data(), points, pts_h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
     H2_HIP(hipStreamSynchronize(s_));
+
+    // ---- first sketch Y = K Omega (Alg. 1 batchedRand + black box), enqueued in
+    // ORIGINAL point order so that it runs while the host builds the tree:
+    // Omega(i, j) depends on the original index i only.
+    int ph = timer_.begin(kSample);
+    const int first = std::min(o.d0 + ahead_, dcap_);
+    DevArray<double> om0, y0, part;
+    om0.alloc(static_cast<size_t>(n) * first, s_);
+    y0.alloc(static_cast<size_t>(n) * first, s_);
+    H2_HIP(h2dev::gaussian(s_, o.seed, n, nullptr, 0, first, om0.get(), n));
+    H2_HIP(h2dev::sketch(s_, o.precision, n, dim, points, n, kf_, first, om0.get(), n, y0.get(), n));
+    h.sketch_flops += 2.0 * double(n) * double(n) * first;
+    h.sketch_entries += double(n) * double(n);
+    const int nb = 512;
+    part.alloc(nb, s_);
+    // nu = ||Y_0||_F / sqrt(d0) from the first d0 columns: deterministic two-stage sum
+    H2_HIP(h2dev::sumsq_partial(s_, n, o.d0, y0.get(), n, part.get(), nb));
+    timer_.end(ph);
+
+    // ---- plan (host): tree + lists, overlapping the sketch on the device
+    const auto th0 = std::chrono::steady_clock::now();
     h.plan = h2::make_plan(n, dim, pts_h.data(), o.leaf_size, o.eta);
+    h.host_plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
     const h2::Plan& p = h.plan;
     const int D = p.depth;
+    ph = timer_.begin(kTree);
     h.perm.upload(p.perm, s_);
     h.X.alloc(static_cast<size_t>(n) * dim, s_);
     H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
@@ -323,10 +352,8 @@ class Builder {
     for (int i = 0; i < nleaves; ++i) h.leafoff_h[i] = p.begin[p.level_begin(D) + i];
     h.leafoff_h[nleaves] = static_cast<int32_t>(n);
     std::vector<int64_t> dsz(p.near_idx.size());
-    int leaf_max = 0;
     for (int s = 0; s < nleaves; ++s) {
       const int ms = h.leafoff_h[s + 1] - h.leafoff_h[s];
-      leaf_max = std::max(leaf_max, ms);
       for (int j = p.near_ptr[s]; j < p.near_ptr[s + 1]; ++j) {
         const int b = p.near_idx[j];
         dsz[j] = int64_t(ms) * (h.leafoff_h[b + 1] - h.leafoff_h[b]);
@@ -349,27 +376,28 @@ class Builder {
       h.lv[t].nn = 1 << t;
     }
     h.top = top_depth(p);
-    if (h.top > D) return;  // no admissible block: the dense blocks are the whole matrix
+    if (h.top > D) {  // no admissible block: the dense blocks are the whole matrix
+      h.sketch_flops = h.sketch_entries = 0;
+      return;
+    }
 
-    // ---- first sketch Y = K Omega  (Alg. 1 batchedRand + black box)
+    // ---- the first sketch in tree order; threshold from its first d0 columns
     ph = timer_.begin(kSample);
-    dcap_ = o.d_max;
     Level& leaf = h.lv[D];
     leaf.M = n;
     leaf.om.alloc(static_cast<size_t>(n) * dcap_, s_);
     leaf.y.alloc(static_cast<size_t>(n) * dcap_, s_);
-    draw(0, o.d0);
-    d_ = o.d0;
-    // nu = ||Y_0||_F / sqrt(d0): deterministic two-stage sum
-    const int nb = 512;
-    DevArray<double> part;
-    part.alloc(nb, s_);
-    H2_HIP(h2dev::sumsq_partial(s_, n, o.d0, leaf.y.get(), n, part.get(), nb));
+    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, om0.get(), n, leaf.om.get(), n, first));
+    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, y0.get(), n, leaf.y.get(), n, first));
     std::vector<double> part_h = download(part.get(), nb, s_);
     double ss = 0;
     for (double v : part_h) ss += v;
     h.nu = std::sqrt(ss) / std::sqrt(double(o.d0));
     h.delta = o.norm_mode == H2_NORM_FRO_SCALED ? o.tol * h.nu / std::sqrt(double(nleaves)) : o.tol * h.nu;
+    om0.release();
+    y0.release();
+    dsk_ = first;
+    d_ = o.d0;
     timer_.end(ph);
 
     conv_.alloc(static_cast<size_t>(nleaves), s_);
@@ -378,16 +406,23 @@ class Builder {
 
     for (int t = D; t >= h.top; --t) level(t);
     h.samples = d_;
+    h.sketched = dsk_;
   }
 
-  // Omega columns [c0, c0+nc) in tree order, then Y = K Omega for them.
+  // Omega columns [c0, c0+nc) and Y = K Omega for them, computed in ORIGINAL
+  // point order (like the first pass) and then gathered into tree order, so
+  // every column is evaluated identically whichever pass produced it.
   void draw(int c0, int nc) {
     h2_matrix& h = *h_;
     Level& leaf = h.lv[h.plan.depth];
     const int64_t n = h.plan.n;
-    H2_HIP(h2dev::gaussian(s_, h.opts.seed, n, h.perm.get(), c0, nc, leaf.om.get() + int64_t(c0) * n, n));
-    H2_HIP(h2dev::sketch_f64(s_, n, h.plan.dim, h.X.get(), n, kf_, nc, leaf.om.get() + int64_t(c0) * n, n,
-                             leaf.y.get() + int64_t(c0) * n, n));
+    DevArray<double> om, y;
+    om.alloc(static_cast<size_t>(n) * nc, s_);
+    y.alloc(static_cast<size_t>(n) * nc, s_);
+    H2_HIP(h2dev::gaussian(s_, h.opts.seed, n, nullptr, c0, nc, om.get(), n));
+    H2_HIP(h2dev::sketch(s_, h.opts.precision, n, h.plan.dim, points_, n, kf_, nc, om.get(), n, y.get(), n));
+    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, om.get(), n, leaf.om.get() + int64_t(c0) * n, n, nc));
+    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, y.get(), n, leaf.y.get() + int64_t(c0) * n, n, nc));
     h.sketch_flops += 2.0 * double(n) * double(n) * nc;
     h.sketch_entries += double(n) * double(n);
   }
@@ -400,7 +435,7 @@ class Builder {
     if (t == D) {
       H2_HIP(h2dev::bsr_gemm(s_, L.nn, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             L.max_m));
+                             L.max_m, h.opts.precision));
     } else {
       Level& C = h.lv[t + 1];
       H2_HIP(h2dev::bsr_gemm(s_, C.nn, C.fptr.get(), C.fidx.get(), C.koff.get(), C.boff.get(), C.B.get(),
@@ -448,7 +483,7 @@ class Builder {
     L.rowoff.upload(L.rowoff_h, s_);
 
     int ph = timer_.begin(kSubtract);
-    subtract(t, 0, d_);
+    subtract(t, 0, dsk_);  // every sketched column, used or not yet
     timer_.end(ph);
 
     // adaptive sampling (Sec. III-B)
@@ -465,22 +500,27 @@ class Builder {
       if (d_ + h.opts.d_inc > h.opts.d_max)
         throw Error(H2_ERR_SAMPLES, "adaptive sampling did not converge within d_max = " +
                                         std::to_string(h.opts.d_max) + " columns at depth " + std::to_string(t));
-      const int c0 = d_, nc = h.opts.d_inc;
-      ph = timer_.begin(kSample);
-      draw(c0, nc);
-      timer_.end(ph);
-      // updateSamples: sweep the new columns up through the finished levels
-      for (int tt = D; tt >= t; --tt) {
-        ph = timer_.begin(kSubtract);
-        subtract(tt, c0, nc);
+      const int need = d_ + h.opts.d_inc;
+      if (need > dsk_) {
+        // sketch the missing columns plus the look-ahead, then updateSamples:
+        // sweep them up through the finished levels
+        const int c0 = dsk_, nc = std::min(need - dsk_ + ahead_, dcap_ - dsk_);
+        ph = timer_.begin(kSample);
+        draw(c0, nc);
         timer_.end(ph);
-        if (tt > t) {
-          ph = timer_.begin(kUpsweep);
-          upsweep(tt, c0, nc);
+        for (int tt = D; tt >= t; --tt) {
+          ph = timer_.begin(kSubtract);
+          subtract(tt, c0, nc);
           timer_.end(ph);
+          if (tt > t) {
+            ph = timer_.begin(kUpsweep);
+            upsweep(tt, c0, nc);
+            timer_.end(ph);
+          }
         }
+        dsk_ += nc;
       }
-      d_ += nc;
+      d_ = need;
       h.rounds++;
     }
 
@@ -519,7 +559,7 @@ class Builder {
       P.M = Mn;
       P.om.alloc(static_cast<size_t>(Mn) * dcap_, s_);
       P.y.alloc(static_cast<size_t>(Mn) * dcap_, s_);
-      upsweep(t, 0, d_);
+      upsweep(t, 0, dsk_);
     }
     // skeleton tree positions and coordinates
     L.pos_out.alloc(static_cast<size_t>(Mn), s_);
@@ -627,6 +667,7 @@ h2_status h2_opts_default(h2_opts* o) {
     o->seed = 1000;
     o->precision = H2_FP64;
     o->norm_mode = H2_NORM_FRO_SCALED;
+    o->sketch_ahead = 32;
   });
 }
 
@@ -718,14 +759,14 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
   return guarded([&] {
     H2_REQUIRE(ctx != nullptr, "ctx is NULL");
     check_kernel(kernel);
-    H2_REQUIRE(precision == H2_FP64, "only H2_FP64 is implemented");
+    H2_REQUIRE(precision == H2_FP64 || precision == H2_FP32 || precision == H2_BF16X3, "unknown precision");
     H2_REQUIRE(n >= 0 && n < (int64_t{1} << 31), "n out of range");
     H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
     H2_REQUIRE(ncols >= 0 && ncols <= 128, "ncols must be in [0, 128]");
     H2_REQUIRE(ldo >= std::max<int64_t>(n, 1) && ldy >= std::max<int64_t>(n, 1), "ld < n");
     H2_REQUIRE((points && omega && y) || n * int64_t(ncols) == 0, "NULL pointer");
     H2_HIP(hipSetDevice(ctx->device));
-    H2_HIP(h2dev::sketch_f64(ctx->stream, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
+    H2_HIP(h2dev::sketch(ctx->stream, precision, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
   });
 }
 
@@ -903,6 +944,8 @@ h2_status h2_query(const h2_matrix* hm, h2_info* info) {
     r.depth = h.plan.depth;
     r.top = h.top;
     r.samples = h.samples;
+    r.sketched = h.sketched;
+    r.t_host_plan = h.host_plan_ms;
     r.rounds = h.rounds;
     r.delta = h.delta;
     r.norm_estimate = h.nu;

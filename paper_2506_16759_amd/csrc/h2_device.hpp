@@ -25,12 +25,17 @@ struct KernelFn {
 };
 
 // Omega(rows[p], col0 + c) -> out[p + c*ldo]; counter-based Philox4x64-10 + Box-Muller.
+// rows == nullptr means row p is original index p.
 hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0, int ncols,
                     double* out, int64_t ldo);
 
-// Dense on-the-fly sketch y = K(X,X) omega (FP64 MFMA), X = (dim x n) SoA with leading dimension ldx.
-hipError_t sketch_f64(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
-                      const double* omega, int64_t ldo, double* y, int64_t ldy);
+// Dense on-the-fly sketch y = K(X,X) omega, X = (dim x n) SoA with leading
+// dimension ldx.  precision 0: FP64 entries and FP64 MFMA; 1: FP32 entries
+// and FP32 MFMA; 2: FP32 entries split into bf16 pairs, three bf16 MFMA
+// products.  Mixed modes fold FP32 partial sums into FP64 every 256 points;
+// y is always FP64.
+hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
+                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy);
 
 // Kernel blocks of a CSR block pattern: for block row i and entry j in [ptr[i], ptr[i+1]) with
 // b = idx[j], writes kappa(X[rowoff[i] + r], X[rowoff[b] + c]) to out[blkoff[j] + r + c*m_i].
@@ -38,10 +43,12 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out);
 
 // Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc columns.
-// max_m bounds every block-row height (<= 256).
+// max_m bounds every block-row height (<= 256).  precision 0: FP64 matrix
+// cores; otherwise blocks and X are rounded to FP32, multiplied on the FP32
+// matrix cores and each block's partial sums folded into FP64.
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m);
+                    int64_t ldy, int nc, double alpha, int max_m, int precision = 0);
 
 // Adaptive convergence test (Sec. III-B): per cluster, unpivoted Householder QR of its samples
 // Y[rowoff[i]..rowoff[i+1]) x [0,d); conv[i] = 1 if m <= d or min |R_jj| < delta.

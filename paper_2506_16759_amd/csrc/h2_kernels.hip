@@ -12,6 +12,7 @@
 #include <cstdint>
 
 #include "h2_device.hpp"
+#include "h2_devmath.hpp"
 
 namespace h2dev {
 namespace {
@@ -26,36 +27,15 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// kappa as a function of the squared distance; c2 = -scale * log2(e) so that
+// exp(-scale * x) = 2^(c2 * x).
 template <int KIND>
-__device__ __forceinline__ double kernel_of_r2(double r2, double scale) {
+__device__ __forceinline__ double kernel_of_r2(double r2, double c2) {
   if constexpr (KIND == kExp) {
-    return exp(-sqrt(r2) * scale);
+    return exp2_nonpos(c2 * sqrt_nonneg(r2));
   } else {
-    return exp(-r2 * scale);
+    return exp2_nonpos(c2 * r2);
   }
-}
-
-__device__ __forceinline__ double kernel_dispatch(int kind, double r2, double scale) {
-  return kind == kExp ? kernel_of_r2<kExp>(r2, scale) : kernel_of_r2<kGauss>(r2, scale);
-}
-
-__device__ __forceinline__ double dist2(const double* X, int64_t ldx, int dim, int64_t i, int64_t j) {
-  double r2 = 0.0;
-  for (int a = 0; a < dim; ++a) {
-    const double d = X[a * ldx + i] - X[a * ldx + j];
-    r2 += d * d;
-  }
-  return r2;
-}
-
-__device__ __forceinline__ double dist2_xy(const double* Xr, const double* Xc, int64_t ldx, int dim, int64_t i,
-                                           int64_t j) {
-  double r2 = 0.0;
-  for (int a = 0; a < dim; ++a) {
-    const double d = Xr[a * ldx + i] - Xc[a * ldx + j];
-    r2 += d * d;
-  }
-  return r2;
 }
 
 // ---------------------------------------------------------- Philox4x64-10
@@ -89,7 +69,7 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, int64_t nr
   const int64_t total = nrows * ncols;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t p = e % nrows, c = e / nrows;
-    uint64_t c0 = static_cast<uint64_t>(rows[p]), c1 = static_cast<uint64_t>(col0 + c), c2 = 0, c3 = 0;
+    uint64_t c0 = static_cast<uint64_t>(rows ? rows[p] : p), c1 = static_cast<uint64_t>(col0 + c), c2 = 0, c3 = 0;
     philox_block(c0, c1, c2, c3, seed, 0);
     const double u1 = (static_cast<double>(c0 >> 11) + 0.5) * 0x1p-53;
     const double u2 = (static_cast<double>(c1 >> 11) + 0.5) * 0x1p-53;
@@ -111,7 +91,7 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int DIM, int KIND, int NC>
 __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                         double scale, int ncr, const double* __restrict__ omega,
+                                                         double c2, int ncr, const double* __restrict__ omega,
                                                          int64_t ldo, double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
   __shared__ double xs[DIM][kSkK];
@@ -160,8 +140,8 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double
         ra += da * da;
         rb += db * db;
       }
-      const double ka = kernel_of_r2<KIND>(ra, scale);
-      const double kb = kernel_of_r2<KIND>(rb, scale);
+      const double ka = kernel_of_r2<KIND>(ra, c2);
+      const double kb = kernel_of_r2<KIND>(rb, c2);
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const double bv = om[jj][c * 16 + li];
@@ -183,103 +163,457 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double
   }
 }
 
-template <int DIM, int KIND>
-hipError_t launch_sketch_nc(hipStream_t s, int64_t n, const double* X, int64_t ldx, double scale, int ncr,
+// --------------------------------------------- mixed-precision sketches
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// kappa in FP32 from the hardware square root and base-2 exponential.
+template <int KIND>
+__device__ __forceinline__ float kernel_of_r2_f32(float r2, float c2) {
+  if constexpr (KIND == kExp) {
+    return __builtin_amdgcn_exp2f(c2 * __builtin_amdgcn_sqrtf(r2));
+  } else {
+    return __builtin_amdgcn_exp2f(c2 * r2);
+  }
+}
+
+// FP32 partial sums are folded into FP64 accumulators every kFlush stages of
+// kSkK points, so the FP32 rounding error never grows with n.
+constexpr int kFlush = 4;
+
+// FP32 entries, v_mfma_f32_16x16x4_f32.  Same tiling as the FP64 kernel:
+// lane l supplies A[l%16][l/16], B[l/16][l%16] and holds D[4*(l/16)+q][l%16].
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_f32_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                         float c2, int ncr, const double* __restrict__ omega,
+                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  constexpr int NB = NC / 16;
+  __shared__ float xs[DIM][kSkK];
+  __shared__ float om[kSkK][NC + 4];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  float xa[DIM], xb[DIM];
+  {
+    const int64_t ia = row0 + li, ib = row0 + 16 + li;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      xa[a] = ia < n ? float(X[a * ldx + ia]) : 0.0f;
+      xb[a] = ib < n ? float(X[a * ldx + ib]) : 0.0f;
+    }
+  }
+  flt4 acc0[NB], acc1[NB];
+  double ya[NB][4], yb[NB][4];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    acc0[c] = flt4{0.f, 0.f, 0.f, 0.f};
+    acc1[c] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ya[c][q] = yb[c][q] = 0.0;
+  }
+  int stage = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
+    __syncthreads();
+    for (int e = tid; e < DIM * kSkK; e += 256) {
+      const int a = e / kSkK, jj = e % kSkK;
+      xs[a][jj] = (j0 + jj < n) ? float(X[a * ldx + j0 + jj]) : 0.0f;
+    }
+    for (int e = tid; e < NC * kSkK; e += 256) {
+      const int c = e / kSkK, jj = e % kSkK;
+      om[jj][c] = (j0 + jj < n && c < ncr) ? float(omega[c * ldo + j0 + jj]) : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kSkK / 4; ++kk) {
+      const int jj = kk * 4 + lk;
+      float ra = 0.f, rb = 0.f;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const float xj = xs[a][jj];
+        const float da = xa[a] - xj, db = xb[a] - xj;
+        ra += da * da;
+        rb += db * db;
+      }
+      const float ka = kernel_of_r2_f32<KIND>(ra, c2);
+      const float kb = kernel_of_r2_f32<KIND>(rb, c2);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const float bv = om[jj][c * 16 + li];
+        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ka, bv, acc0[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(kb, bv, acc1[c], 0, 0, 0);
+      }
+    }
+    if (++stage == kFlush || j0 + kSkK >= n) {
+      stage = 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ya[c][q] += double(acc0[c][q]);
+          yb[c][q] += double(acc1[c][q]);
+        }
+        acc0[c] = flt4{0.f, 0.f, 0.f, 0.f};
+        acc1[c] = flt4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = c * 16 + li;
+    if (col >= ncr) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ra = row0 + 4 * lk + q, rb = row0 + 16 + 4 * lk + q;
+      if (ra < n) y[col * ldy + ra] = ya[c][q];
+      if (rb < n) y[col * ldy + rb] = yb[c][q];
+    }
+  }
+}
+
+// Split a float into bf16 hi (truncated) and bf16 lo = bf16(x - hi) (truncated):
+// hi*hi + hi*lo + lo*hi reproduces the FP32 product to about 2^-16 relative.
+__device__ __forceinline__ void split_bf16(float v, uint32_t& hi, uint32_t& lo) {
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t h = b & 0xffff0000u;
+  hi = h >> 16;
+  lo = __float_as_uint(v - __uint_as_float(h)) >> 16;
+}
+
+// Entries in FP32 split into bf16 pairs, v_mfma_f32_16x16x32_bf16 (three
+// products per tile).  Lane l supplies A[l%16][8*(l/16)+e] and
+// B[8*(l/16)+e][l%16], e = 0..7, and holds D[4*(l/16)+q][l%16].  The Omega
+// tile is staged pre-split as [column][point] bf16 so each lane reads its 8
+// points with one 16-byte LDS load.
+constexpr int kBfK = 64;  // points per stage (two MFMA k-steps of 32)
+
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_bf16x3_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                            float c2, int ncr, const double* __restrict__ omega,
+                                                            int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  constexpr int NB = NC / 16;
+  constexpr int LDP = kBfK / 2 + 4;  // dwords per staged column (2 bf16 per dword)
+  __shared__ float xs[DIM][kBfK];
+  __shared__ uint32_t omh[NC * LDP];
+  __shared__ uint32_t oml[NC * LDP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  float xa[DIM], xb[DIM];
+  {
+    const int64_t ia = row0 + li, ib = row0 + 16 + li;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      xa[a] = ia < n ? float(X[a * ldx + ia]) : 0.0f;
+      xb[a] = ib < n ? float(X[a * ldx + ib]) : 0.0f;
+    }
+  }
+  flt4 acc0[NB], acc1[NB];
+  double ya[NB][4], yb[NB][4];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    acc0[c] = flt4{0.f, 0.f, 0.f, 0.f};
+    acc1[c] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ya[c][q] = yb[c][q] = 0.0;
+  }
+  int stage = 0;
+  for (int64_t j0 = 0; j0 < n; j0 += kBfK) {
+    __syncthreads();
+    for (int e = tid; e < DIM * kBfK; e += 256) {
+      const int a = e / kBfK, jj = e % kBfK;
+      xs[a][jj] = (j0 + jj < n) ? float(X[a * ldx + j0 + jj]) : 0.0f;
+    }
+    // pairs of points per thread: dword (c, p) holds points 2p, 2p+1 of column c
+    for (int e = tid; e < NC * (kBfK / 2); e += 256) {
+      const int c = e / (kBfK / 2), pp = e % (kBfK / 2);
+      const int64_t j = j0 + 2 * pp;
+      float v0 = 0.f, v1 = 0.f;
+      if (c < ncr) {
+        if (j < n) v0 = float(omega[c * ldo + j]);
+        if (j + 1 < n) v1 = float(omega[c * ldo + j + 1]);
+      }
+      uint32_t h0, l0, h1, l1;
+      split_bf16(v0, h0, l0);
+      split_bf16(v1, h1, l1);
+      omh[c * LDP + pp] = h0 | (h1 << 16);
+      oml[c * LDP + pp] = l0 | (l1 << 16);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kBfK; ks += 32) {
+      const int jb = ks + 8 * lk;  // first of this lane's 8 points
+      u32x4 ah0, al0, ah1, al1;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        float kv[2][2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int jj = jb + 2 * w + e;
+          float ra = 0.f, rb = 0.f;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            const float xj = xs[a][jj];
+            const float da = xa[a] - xj, db = xb[a] - xj;
+            ra += da * da;
+            rb += db * db;
+          }
+          kv[0][e] = kernel_of_r2_f32<KIND>(ra, c2);
+          kv[1][e] = kernel_of_r2_f32<KIND>(rb, c2);
+        }
+        uint32_t h0, l0, h1, l1;
+        split_bf16(kv[0][0], h0, l0);
+        split_bf16(kv[0][1], h1, l1);
+        ah0[w] = h0 | (h1 << 16);
+        al0[w] = l0 | (l1 << 16);
+        split_bf16(kv[1][0], h0, l0);
+        split_bf16(kv[1][1], h1, l1);
+        ah1[w] = h0 | (h1 << 16);
+        al1[w] = l0 | (l1 << 16);
+      }
+      const bf16x8 Ah0 = __builtin_bit_cast(bf16x8, ah0), Al0 = __builtin_bit_cast(bf16x8, al0);
+      const bf16x8 Ah1 = __builtin_bit_cast(bf16x8, ah1), Al1 = __builtin_bit_cast(bf16x8, al1);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const int col = c * 16 + li;
+        const u32x4 bh = *reinterpret_cast<const u32x4*>(&omh[col * LDP + jb / 2]);
+        const u32x4 bl = *reinterpret_cast<const u32x4*>(&oml[col * LDP + jb / 2]);
+        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh), Bl = __builtin_bit_cast(bf16x8, bl);
+        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah0, Bh, acc0[c], 0, 0, 0);
+        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah0, Bl, acc0[c], 0, 0, 0);
+        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al0, Bh, acc0[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah1, Bh, acc1[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah1, Bl, acc1[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al1, Bh, acc1[c], 0, 0, 0);
+      }
+    }
+    if (++stage == kFlush || j0 + kBfK >= n) {
+      stage = 0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          ya[c][q] += double(acc0[c][q]);
+          yb[c][q] += double(acc1[c][q]);
+        }
+        acc0[c] = flt4{0.f, 0.f, 0.f, 0.f};
+        acc1[c] = flt4{0.f, 0.f, 0.f, 0.f};
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = c * 16 + li;
+    if (col >= ncr) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ra = row0 + 4 * lk + q, rb = row0 + 16 + 4 * lk + q;
+      if (ra < n) y[col * ldy + ra] = ya[c][q];
+      if (rb < n) y[col * ldy + rb] = yb[c][q];
+    }
+  }
+}
+
+template <int P, int DIM, int KIND, int NC>
+void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
+                       const double* omega, int64_t ldo, double* y, int64_t ldy) {
+  if constexpr (P == 0)
+    sketch_f64_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+  else if constexpr (P == 1)
+    sketch_f32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+  else
+    sketch_bf16x3_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+}
+
+template <int P, int DIM, int KIND>
+hipError_t launch_sketch_nc(hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
                             const double* omega, int64_t ldo, double* y, int64_t ldy) {
   const dim3 grid(static_cast<unsigned>((n + kSkRows - 1) / kSkRows));
   if (ncr <= 16)
-    sketch_f64_kernel<DIM, KIND, 16><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 16>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else if (ncr <= 32)
-    sketch_f64_kernel<DIM, KIND, 32><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 32>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else if (ncr <= 48)
-    sketch_f64_kernel<DIM, KIND, 48><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 48>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else if (ncr <= 64)
-    sketch_f64_kernel<DIM, KIND, 64><<<grid, 256, 0, s>>>(n, X, ldx, scale, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 64>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
+template <int P>
+hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const double* X, int64_t ldx, double c2,
+                           int nc, const double* om, int64_t ldo, double* yy, int64_t ldy) {
+  if (kind == kExp) {
+    if (dim == 1) return launch_sketch_nc<P, 1, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+    if (dim == 2) return launch_sketch_nc<P, 2, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+    return launch_sketch_nc<P, 3, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+  }
+  if (dim == 1) return launch_sketch_nc<P, 1, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+  if (dim == 2) return launch_sketch_nc<P, 2, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+  return launch_sketch_nc<P, 3, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+}
+
 // ------------------------------------------------------ kernel block gen
 
+// One workgroup per block row.  The row cluster's coordinates stay in LDS for
+// the whole row; each column cluster's coordinates are staged per block.
+// Consecutive threads write consecutive rows of the column-major block.
+constexpr int kGenMax = 256;
+
+template <int DIM, int KIND>
 __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const int32_t* __restrict__ rowoff,
-                                                         const int64_t* __restrict__ blkoff, int dim,
-                                                         const double* __restrict__ X, int64_t ldx, int kind,
-                                                         double scale, double* __restrict__ out) {
-  const int i = blockIdx.x;
+                                                         const int64_t* __restrict__ blkoff,
+                                                         const double* __restrict__ X, int64_t ldx, double c2,
+                                                         double* __restrict__ out) {
+  __shared__ double xr[DIM][kGenMax];
+  __shared__ double xc[DIM][kGenMax];
+  const int i = blockIdx.x, tid = threadIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  if (ptr[i] == ptr[i + 1] || m == 0) return;
+  for (int e = tid; e < DIM * m; e += 256) xr[e / m][e % m] = X[(e / m) * ldx + r0 + e % m];
+  const int dr = 256 % m, dc = 256 / m;
   for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
     const int b = idx[j];
     const int c0 = rowoff[b], mb = rowoff[b + 1] - c0;
+    __syncthreads();
+    for (int e = tid; e < DIM * mb; e += 256) xc[e / mb][e % mb] = X[(e / mb) * ldx + c0 + e % mb];
+    __syncthreads();
     double* o = out + blkoff[j];
-    const int total = m * mb;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int r = e % m, c = e / m;
-      o[e] = kernel_dispatch(kind, dist2(X, ldx, dim, r0 + r, c0 + c), scale);
+    int r = tid % m, c = tid / m;
+    for (int e = tid; e < m * mb; e += 256) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const double d = xr[a][r] - xc[a][c];
+        r2 += d * d;
+      }
+      o[e] = kernel_of_r2<KIND>(r2, c2);
+      r += dr;
+      c += dc;
+      if (r >= m) {
+        r -= m;
+        ++c;
+      }
     }
   }
 }
 
 // ------------------------------------------------------- block-sparse GEMM
 
-// One workgroup per block row; 256 threads as 8 row groups x 32 columns; each
-// thread accumulates U rows (r = ty + 8u) of one column.  Blocks and the
-// matching X rows are staged through LDS 32 inner indices at a time.
-constexpr int kBsrCols = 32;
-
-template <int U, int kBsrK = (U >= 32 ? 16 : 32)>
+// Y[rows_i, c] += alpha * sum_j Blk_j X[rows_b, c] on the FP64 matrix cores.
+// One workgroup (4 waves) per block row and 16*NB columns; wave w owns the
+// 16-row tiles w, w+4, ... (RT of them).  The X rows of the current column
+// block are staged in LDS ([q][c], shared by the 4 waves); the blocks stream
+// from HBM straight into the MFMA A operand (lane l reads row l%16 of column
+// l/16 of a 16x4 slice: four 128-byte runs per load).
+template <int NB, int RT, bool F32>
 __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rowoff,
                                                        const int64_t* __restrict__ blkoff,
                                                        const double* __restrict__ blocks, const double* __restrict__ X,
                                                        int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
                                                        double alpha) {
-  __shared__ double bs[kBsrK][8 * U + 1];
-  __shared__ double xs[kBsrK][kBsrCols + 1];
-  const int i = blockIdx.x;
-  const int c0 = blockIdx.y * kBsrCols;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  // F32: blocks and X are rounded to FP32 at load, the products run on the
+  // FP32 matrix cores and each block's FP32 partial sums are folded into FP64.
+  constexpr int LDB = NB * 16;
+  extern __shared__ double xb[];
+  float* xbf = reinterpret_cast<float*>(xb);
+  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  const int ncl = min(kBsrCols, nc - c0);
-  double acc[U];
+  const int c0 = blockIdx.y * LDB;
+  const int ncl = min(LDB, nc - c0);
+  dbl4 acc[RT][NB];
 #pragma unroll
-  for (int u = 0; u < U; ++u) acc[u] = 0.0;
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
   for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
     const int b = idx[j];
-    const int q0b = rowoff[b], mb = rowoff[b + 1] - q0b;
+    const int q0b = rowoff[b], mb = rowoff[b + 1] - q0b, mb4 = (mb + 3) & ~3;
     const double* blk = blocks + blkoff[j];
-    for (int q0 = 0; q0 < mb; q0 += kBsrK) {
-      const int kq = min(kBsrK, mb - q0);
-      __syncthreads();
-      for (int e = tid; e < m * kBsrK; e += 256) {
-        const int r = e % m, q = e / m;
-        bs[q][r] = q < kq ? blk[int64_t(q0 + q) * m + r] : 0.0;
+    __syncthreads();
+    for (int q = lane; q < mb4; q += 64)
+      for (int c = wave; c < LDB; c += 4) {
+        const double v = (q < mb && c < ncl) ? X[int64_t(c0 + c) * ldx + q0b + q] : 0.0;
+        if constexpr (F32)
+          xbf[q * LDB + c] = float(v);
+        else
+          xb[q * LDB + c] = v;
       }
-      for (int e = tid; e < kBsrK * kBsrCols; e += 256) {
-        const int q = e % kBsrK, c = e / kBsrK;
-        xs[q][c] = (q < kq && c < ncl) ? X[int64_t(c0 + c) * ldx + q0b + q0 + q] : 0.0;
-      }
-      __syncthreads();
-      for (int q = 0; q < kq; ++q) {
-        const double xv = xs[q][tx];
+    __syncthreads();
+    if constexpr (F32) {
+      flt4 part[RT][NB];
 #pragma unroll
-        for (int u = 0; u < U; ++u) acc[u] += bs[q][ty + 8 * u] * xv;
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) part[t][c] = flt4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+      for (int k = 0; k < mb4; k += 4) {
+        const int q = k + lk;
+        float a[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int row = (wave + 4 * t) * 16 + li;
+          a[t] = (row < m && q < mb) ? float(blk[int64_t(q) * m + row]) : 0.0f;
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const float bv = xbf[q * LDB + c * 16 + li];
+#pragma unroll
+          for (int t = 0; t < RT; ++t) part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], bv, part[t][c], 0, 0, 0);
+        }
+      }
+      // FP32 layout D[4*(l/16)+q][l%16] -> FP64 layout D[l/16+4q][l%16]: keep the
+      // FP32 layout in the FP64 accumulators (the store below follows F32).
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[t][c][q] += double(part[t][c][q]);
+    } else {
+#pragma unroll 4
+      for (int k = 0; k < mb4; k += 4) {
+        const int q = k + lk;
+        double a[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int row = (wave + 4 * t) * 16 + li;
+          a[t] = (row < m && q < mb) ? blk[int64_t(q) * m + row] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const double bv = xb[q * LDB + c * 16 + li];
+#pragma unroll
+          for (int t = 0; t < RT; ++t) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv, acc[t][c], 0, 0, 0);
+        }
       }
     }
   }
-  if (tx < ncl) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int r = ty + 8 * u;
-      if (r < m) {
-        double* yp = Y + int64_t(c0 + tx) * ldy + r0 + r;
-        *yp += alpha * acc[u];
+  for (int t = 0; t < RT; ++t)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int col = c * 16 + li;
+      if (col >= ncl) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = (wave + 4 * t) * 16 + (F32 ? 4 * lk + q : lk + 4 * q);
+        if (row < m) {
+          double* yp = Y + int64_t(c0 + col) * ldy + r0 + row;
+          *yp += alpha * acc[t][c][q];
+        }
       }
     }
-  }
 }
 
 // ------------------------------------------------- adaptive convergence test
@@ -687,23 +1021,23 @@ hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* 
   return hipGetLastError();
 }
 
-hipError_t sketch_f64(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
-                      const double* omega, int64_t ldo, double* y, int64_t ldy) {
+hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
+                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
+  const double c2 = -k.scale * kLog2e;
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
     const double* om = omega + int64_t(c0) * ldo;
     double* yy = y + int64_t(c0) * ldy;
     hipError_t e;
-    if (k.kind == kExp) {
-      if (dim == 1) e = launch_sketch_nc<1, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-      else if (dim == 2) e = launch_sketch_nc<2, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-      else e = launch_sketch_nc<3, kExp>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-    } else {
-      if (dim == 1) e = launch_sketch_nc<1, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-      else if (dim == 2) e = launch_sketch_nc<2, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-      else e = launch_sketch_nc<3, kGauss>(s, n, X, ldx, k.scale, nc, om, ldo, yy, ldy);
-    }
+    if (precision == 0)
+      e = launch_sketch_p<0>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+    else if (precision == 1)
+      e = launch_sketch_p<1>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+    else if (precision == 2)
+      e = launch_sketch_p<2>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+    else
+      return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -712,24 +1046,67 @@ hipError_t sketch_f64(hipStream_t s, int64_t n, int dim, const double* X, int64_
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out) {
   if (nrows <= 0) return hipSuccess;
-  gen_blocks_kernel<<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, dim, X, ldx, k.kind, k.scale, out);
+  const double c2 = -k.scale * kLog2e;
+#define H2_GEN(D, K) gen_blocks_kernel<D, K><<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, c2, out)
+  if (k.kind == kExp) {
+    if (dim == 1) H2_GEN(1, kExp);
+    else if (dim == 2) H2_GEN(2, kExp);
+    else H2_GEN(3, kExp);
+  } else {
+    if (dim == 1) H2_GEN(1, kGauss);
+    else if (dim == 2) H2_GEN(2, kGauss);
+    else H2_GEN(3, kGauss);
+  }
+#undef H2_GEN
   return hipGetLastError();
+}
+
+template <int NB, bool F32>
+hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                         const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
+                         int64_t ldy, int nc, double alpha, int max_m) {
+  const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
+  const size_t lds = size_t((max_m + 3) & ~3) * NB * 16 * sizeof(double);
+  hipError_t e = hipSuccess;
+  if (max_m <= 64) {
+    if ((e = allow_lds(bsr_gemm_kernel<NB, 1, F32>, lds)) != hipSuccess) return e;
+    bsr_gemm_kernel<NB, 1, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  } else if (max_m <= 128) {
+    if ((e = allow_lds(bsr_gemm_kernel<NB, 2, F32>, lds)) != hipSuccess) return e;
+    bsr_gemm_kernel<NB, 2, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  } else if (max_m <= 256) {
+    if ((e = allow_lds(bsr_gemm_kernel<NB, 4, F32>, lds)) != hipSuccess) return e;
+    bsr_gemm_kernel<NB, 4, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <bool F32>
+hipError_t bsr_gemm_p(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                      const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
+                      int64_t ldy, int nc, double alpha, int max_m) {
+  // at most 64 columns per workgroup, and at most 64 KB of staged X
+  int nb = (nc + 15) / 16;
+  if (nb > 4) nb = 4;
+  while (nb > 1 && size_t((max_m + 3) & ~3) * nb * 16 * sizeof(double) > 65536) --nb;
+  switch (nb) {
+    case 1: return launch_bsr_nb<1, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+    case 2: return launch_bsr_nb<2, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+    case 3: return launch_bsr_nb<3, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+    default:
+      return launch_bsr_nb<4, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+  }
 }
 
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m) {
+                    int64_t ldy, int nc, double alpha, int max_m, int precision) {
   if (nrows <= 0 || nc <= 0) return hipSuccess;
-  const dim3 grid(nrows, (nc + kBsrCols - 1) / kBsrCols);
-  if (max_m <= 64)
-    bsr_gemm_kernel<8><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
-  else if (max_m <= 128)
-    bsr_gemm_kernel<16><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
-  else if (max_m <= 256)
-    bsr_gemm_kernel<32><<<grid, 256, 0, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (max_m < 1) max_m = 1;
+  if (precision == 0) return bsr_gemm_p<false>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+  return bsr_gemm_p<true>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
 }
 
 hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,

@@ -8,6 +8,8 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <atomic>
+#include <thread>
 #include <utility>
 
 #pragma clang fp contract(off)
@@ -41,37 +43,41 @@ bool admissible(const double* lo_s, const double* hi_s, const double* lo_t, cons
 
 namespace {
 
-struct Traversal {
-  const Plan& p;
-  std::vector<std::vector<std::pair<int32_t, int32_t>>> far;  // per depth (s_local, t_local)
-  std::vector<std::pair<int32_t, int32_t>> near;
+// Runs f(i) for i in [0, n) on up to 16 host threads (the GPU machine's CPU share).
+template <typename F>
+void parallel_for(int n, F&& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = static_cast<int>(std::min<unsigned>(std::min(hw, 16u), static_cast<unsigned>((n + 63) / 64)));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  std::atomic<int> next{0};
+  for (int w = 0; w < nt; ++w)
+    pool.emplace_back([&] {
+      for (;;) {
+        const int i0 = next.fetch_add(32);
+        if (i0 >= n) break;
+        for (int i = i0; i < std::min(n, i0 + 32); ++i) f(i);
+      }
+    });
+  for (auto& t : pool) t.join();
+}
 
-  explicit Traversal(const Plan& plan) : p(plan), far(plan.depth + 1) {}
-
-  void visit(int s, int t, int depth) {
-    const int dim = p.dim;
-    const int base = p.level_begin(depth);
-    if (admissible(&p.lo[s * dim], &p.hi[s * dim], &p.lo[t * dim], &p.hi[t * dim], dim, p.eta)) {
-      far[depth].emplace_back(s - base, t - base);
-    } else if (depth == p.depth) {
-      near.emplace_back(s - base, t - base);
-    } else {
-      for (int i = 2 * s + 1; i <= 2 * s + 2; ++i)
-        for (int j = 2 * t + 1; j <= 2 * t + 2; ++j) visit(i, j, depth + 1);
+void tight_box(const Plan& p, const double* points, int node, double* lo, double* hi) {
+  const int b = p.begin[node], e = p.end[node];
+  for (int a = 0; a < p.dim; ++a) {
+    const double* x = points + static_cast<size_t>(a) * p.n;
+    double mn = x[p.perm[b]], mx = mn;
+    for (int q = b + 1; q < e; ++q) {
+      const double v = x[p.perm[q]];
+      if (v < mn) mn = v;
+      if (v > mx) mx = v;
     }
+    lo[a] = mn;
+    hi[a] = mx;
   }
-};
-
-void to_csr(std::vector<std::pair<int32_t, int32_t>>& pairs, int rows, std::vector<int32_t>& ptr,
-            std::vector<int32_t>& idx) {
-  std::sort(pairs.begin(), pairs.end());
-  ptr.assign(rows + 1, 0);
-  idx.resize(pairs.size());
-  for (size_t k = 0; k < pairs.size(); ++k) {
-    ptr[pairs[k].first + 1]++;
-    idx[k] = pairs[k].second;
-  }
-  for (int r = 0; r < rows; ++r) ptr[r + 1] += ptr[r];
 }
 
 }  // namespace
@@ -91,6 +97,7 @@ Plan make_plan(int64_t n, int dim, const double* points, int leaf_size, double e
   p.leaf_size = leaf_size;
   p.eta = eta;
   p.depth = tree_depth(n, leaf_size);
+  const int D = p.depth;
   const int nn = p.num_nodes();
   p.perm.resize(n);
   std::iota(p.perm.begin(), p.perm.end(), 0);
@@ -98,25 +105,20 @@ Plan make_plan(int64_t n, int dim, const double* points, int leaf_size, double e
   p.end.assign(nn, 0);
   p.lo.assign(static_cast<size_t>(nn) * dim, 0.0);
   p.hi.assign(static_cast<size_t>(nn) * dim, 0.0);
-  p.begin[0] = 0;
   p.end[0] = static_cast<int32_t>(n);
 
-  for (int node = 0; node < nn; ++node) {
-    const int b = p.begin[node], e = p.end[node];
-    double* lo = &p.lo[static_cast<size_t>(node) * dim];
-    double* hi = &p.hi[static_cast<size_t>(node) * dim];
-    for (int a = 0; a < dim; ++a) {
-      const double* x = points + static_cast<size_t>(a) * n;
-      double mn = x[p.perm[b]], mx = mn;
-      for (int q = b + 1; q < e; ++q) {
-        const double v = x[p.perm[q]];
-        if (v < mn) mn = v;
-        if (v > mx) mx = v;
-      }
-      lo[a] = mn;
-      hi[a] = mx;
-    }
-    if (2 * node + 2 < nn) {
+  // Tree, one depth at a time.  Above the last split only the membership of
+  // each half matters (the children reorder their own points), so a partial
+  // partition suffices; the last split sorts fully, which fixes the order of
+  // the points inside every leaf.
+  for (int t = 0; t <= D; ++t) {
+    const int base = p.level_begin(t);
+    parallel_for(1 << t, [&](int i) {
+      const int node = base + i;
+      double* lo = &p.lo[static_cast<size_t>(node) * dim];
+      double* hi = &p.hi[static_cast<size_t>(node) * dim];
+      tight_box(p, points, node, lo, hi);
+      if (t == D) return;
       int axis = 0;
       double widest = hi[0] - lo[0];
       for (int a = 1; a < dim; ++a) {
@@ -127,23 +129,64 @@ Plan make_plan(int64_t n, int dim, const double* points, int leaf_size, double e
         }
       }
       const double* x = points + static_cast<size_t>(axis) * n;
-      std::sort(p.perm.begin() + b, p.perm.begin() + e, [x](int32_t i, int32_t j) {
-        return x[i] < x[j] || (x[i] == x[j] && i < j);
-      });
+      auto less = [x](int32_t a, int32_t b) { return x[a] < x[b] || (x[a] == x[b] && a < b); };
+      const int b = p.begin[node], e = p.end[node];
       const int mid = b + (e - b) / 2;
+      if (t == D - 1) {
+        std::sort(p.perm.begin() + b, p.perm.begin() + e, less);
+      } else if (mid > b && mid < e) {
+        std::nth_element(p.perm.begin() + b, p.perm.begin() + mid, p.perm.begin() + e, less);
+      }
       p.begin[2 * node + 1] = b;
       p.end[2 * node + 1] = mid;
       p.begin[2 * node + 2] = mid;
       p.end[2 * node + 2] = e;
-    }
+    });
   }
 
-  Traversal tr(p);
-  tr.visit(0, 0, 0);
-  p.far_ptr.resize(p.depth + 1);
-  p.far_idx.resize(p.depth + 1);
-  for (int t = 0; t <= p.depth; ++t) to_csr(tr.far[t], 1 << t, p.far_ptr[t], p.far_idx[t]);
-  to_csr(tr.near, 1 << p.depth, p.near_ptr, p.near_idx);
+  // Dual-tree traversal, breadth first: the candidate partners of s at depth
+  // t are the children of the clusters that were inadmissible with s's
+  // parent at depth t-1.  Those lists are ascending, so every list below
+  // comes out ascending without a sort.
+  std::vector<std::vector<int32_t>> inadm(1);
+  p.far_ptr.assign(D + 1, {});
+  p.far_idx.assign(D + 1, {});
+  auto flatten = [](const std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& ptr,
+                    std::vector<int32_t>& idx) {
+    ptr.assign(rows.size() + 1, 0);
+    for (size_t r = 0; r < rows.size(); ++r) ptr[r + 1] = ptr[r] + static_cast<int32_t>(rows[r].size());
+    idx.resize(ptr.back());
+    for (size_t r = 0; r < rows.size(); ++r) std::copy(rows[r].begin(), rows[r].end(), idx.begin() + ptr[r]);
+  };
+  for (int t = 0; t <= D; ++t) {
+    const int cnt = 1 << t, base = p.level_begin(t);
+    std::vector<std::vector<int32_t>> far(cnt), keep(cnt);
+    parallel_for(cnt, [&](int i) {
+      const int s = base + i;
+      auto test = [&](int c) {  // c: local index at depth t
+        const int tn = base + c;
+        if (admissible(&p.lo[size_t(s) * dim], &p.hi[size_t(s) * dim], &p.lo[size_t(tn) * dim],
+                       &p.hi[size_t(tn) * dim], dim, eta))
+          far[i].push_back(c);
+        else
+          keep[i].push_back(c);
+      };
+      if (t == 0) {
+        test(0);
+      } else {
+        for (int32_t q : inadm[i >> 1]) {
+          test(2 * q);
+          test(2 * q + 1);
+        }
+      }
+    });
+    flatten(far, p.far_ptr[t], p.far_idx[t]);
+    if (t == D) {
+      flatten(keep, p.near_ptr, p.near_idx);
+    } else {
+      inadm.swap(keep);
+    }
+  }
   return p;
 }
 

@@ -6,11 +6,13 @@
 // ceil(n / 2^d) <= leaf_size.  Nodes use heap numbering (children of i are
 // 2i+1, 2i+2); a node owns the contiguous slice [begin, end) of `perm`.
 //
-// The block partition comes from a recursive dual-tree traversal of
-// same-depth cluster pairs starting at (root, root): an admissible pair is a
-// far block (F_tau), an inadmissible pair at the leaf depth a dense block
-// (N_tau), otherwise the four child pairs are visited.  Lists are stored per
-// depth as CSR over local node indices, each row sorted ascending.
+// The block partition comes from the dual-tree traversal of same-depth
+// cluster pairs starting at (root, root): an admissible pair is a far block
+// (F_tau), an inadmissible pair at the leaf depth a dense block (N_tau),
+// otherwise the four child pairs are visited.  It is run breadth first, one
+// depth at a time and one cluster row at a time, on up to 16 host threads.
+// Lists are stored per depth as CSR over local node indices, each row
+// ascending.
 #pragma once
 
 #include <cstdint>

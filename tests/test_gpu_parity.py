@@ -242,3 +242,74 @@ def test_full_size_cube_sampled_parity(ctx):
     emv = np.linalg.norm(yh[rows] - kx) / np.linalg.norm(kx)
     _say(f"sampled-row matvec error {emv:.3e}")
     assert emv <= 10 * w.tol
+
+
+# ------------------------------------------------------------------ mixed precision
+# FP32 entries carry ~6e-8 relative error and FP32 partial sums are folded into
+# FP64 every 256 points, so each sketch column stays within ~1e-6 of its max;
+# bf16x3 products carry ~2^-16 relative error.  The bars below leave a factor
+# of ~10 over those estimates.
+MIXED_TOL = {1: 1e-5, 2: 2e-3}
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("n,dim,kind,length,ncols", [
+    (1000, 2, "exp", 0.1, 32), (3001, 3, "exp", 0.2, 48), (777, 3, "gauss", 0.15, 16), (129, 1, "exp", 0.3, 1),
+    (2500, 2, "gauss", 0.05, 80), (4096, 3, "exp", 0.2, 64),
+])
+def test_sketch_mixed_precision(ctx, precision, n, dim, kind, length, ncols):
+    import torch
+    _say(f"sketch precision={precision} n={n} dim={dim} kernel={kind} l={length} ncols={ncols}")
+    pts = uniform_points(n, dim, 10 + n)
+    om = np.random.default_rng(n).standard_normal((n, ncols))
+    y = _np(h2.sketch(ctx, torch.from_numpy(pts), kind, length, _colmajor_from(om), precision=precision))
+    ref = KernelOperator(pts, kind, length).sketch(om)
+    rel = (np.abs(y - ref).max(axis=0) / np.abs(ref).max(axis=0)).max()
+    _say(f"max column-relative error {rel:.3e}")
+    assert rel <= MIXED_TOL[precision]
+
+
+@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (2, 1e-4), (1, 1e-4)])
+def test_build_mixed_precision_meets_tol(ctx, precision, tol):
+    n, dim, kind, length = 6000, 3, "exp", 0.2
+    _say(f"build precision={precision} tol={tol} n={n}")
+    pts = uniform_points(n, dim, 77)
+    H = h2.build(ctx, pts, kind, length, tol=tol, leaf_size=64, eta=0.7, d0=32, d_inc=16, seed=5,
+                 precision=precision)
+    info = H.info()
+    _check_tree_lists(H, pts, 64, 0.7)
+    _check_identity_rows(H)
+    K = KernelOperator(pts, kind, length).dense()
+    KH = _dense_from_matvec(H, n)
+    eF = np.linalg.norm(K - KH) / np.linalg.norm(K)
+    _say(f"eF={eF:.3e} samples={info['samples']} ranks={info['rank_min']}..{info['rank_max']}")
+    assert eF <= 10 * tol
+
+
+def test_sketch_ahead_does_not_change_the_result(ctx):
+    """Columns sketched ahead of need are used exactly as if drawn lazily: the
+    construction is identical for any look-ahead (Omega is counter-based)."""
+    n = 6000
+    _say(f"sketch-ahead invariance n={n}")
+    pts = uniform_points(n, 3, 91)
+    outs = []
+    for ahead in (0, 16, 64):
+        H = h2.build(ctx, pts, "exp", 0.2, tol=1e-7, leaf_size=64, eta=0.7, d0=16, d_inc=16, seed=3,
+                     sketch_ahead=ahead)
+        info = H.info()
+        D, top = int(H.export("DEPTH")[0]), int(H.export("TOP")[0])
+        outs.append((info["samples"], info["rounds"],
+                     [H.export("RANKS", t) for t in range(top, D + 1)],
+                     [H.export("SKEL", t) for t in range(top, D + 1)],
+                     [H.export("BASIS", t) for t in range(top, D + 1)],
+                     [H.export("COUPLING", t) for t in range(top, D + 1)]))
+        _say(f"ahead={ahead}: samples={info['samples']} sketched={info['sketched']} rounds={info['rounds']}")
+    base = outs[0]
+    for o in outs[1:]:
+        assert o[0] == base[0] and o[1] == base[1]
+        for a, b in zip(o[2], base[2]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(o[3], base[3]):
+            np.testing.assert_array_equal(a, b)
+        for a, b in zip(o[4] + o[5], base[4] + base[5]):
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
