@@ -214,6 +214,53 @@ typedef struct {
 h2_status h2_query(const h2_matrix* h, h2_info* info);
 h2_status h2_free(h2_matrix* h);
 
+/* ---------------------------------------------------------------- batched */
+
+/* One problem of a batched build (a kernel matrix on its own point cloud). */
+typedef struct {
+  int64_t n;
+  int32_t dim;
+  const double* points;  /* DEVICE (dim x n) SoA, original order; borrowed for the call */
+  h2_kernel kernel;
+  double tol;
+  int32_t leaf_size;
+  double eta;
+  int32_t d0, d_inc;
+  uint64_t seed;
+  int32_t norm_mode;
+} h2_problem;
+
+typedef struct {
+  int32_t precision; /* h2_precision, common to the batch */
+  int32_t d_max;     /* columns sketched up front for every problem, 1..96 */
+  int32_t use_graph; /* 1: capture the whole build in one hipGraph and launch it once */
+} h2_batch_opts;
+
+typedef struct {
+  double t_total_ms;   /* wall time of the call */
+  double t_plan_ms;    /* host cluster trees and lists of all problems (threaded) */
+  double t_setup_ms;   /* host layout, device allocation and uploads */
+  double t_capture_ms; /* graph capture and instantiation (0 without a graph) */
+  double t_device_ms;  /* device work: graph launch (or first enqueue) to completion */
+  int32_t levels;      /* levels of the longest problem */
+  int32_t graph_nodes; /* nodes of the captured graph (0 without a graph) */
+  int64_t device_bytes;
+  double sketch_flops; /* algorithmic 2 * n^2 * d_max summed over problems */
+} h2_batch_info;
+
+/* Builds `count` independent H^2 matrices (Alg. 1 with adaptive sampling, Sec.
+ * III) in one launch sequence: every stage of a level is one kernel over the
+ * clusters of all problems, and with use_graph the whole sequence is captured
+ * in one hipGraph.  All d_max columns are sketched up front; the adaptive loop
+ * picks each problem's column count with one prefix QR per cluster, which
+ * gives the same count, and the same factors, as adding d_inc columns at a
+ * time.  A problem not converged within d_max makes the call fail with
+ * H2_ERR_SAMPLES.  out: array of `count` handles (each freed with h2_free;
+ * they share device storage, released with the last one).  info may be NULL.
+ * Synchronous. */
+h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
+                           h2_matrix** out, h2_batch_info* info);
+
 #ifdef __cplusplus
 }
 #endif

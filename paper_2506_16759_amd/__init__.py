@@ -18,7 +18,8 @@ import numpy as np
 from . import _lib
 from ._lib import BF16X3, FP32, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
 
-__all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "H2Matrix",
+__all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
+           "H2Matrix",
            "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "NORM_FRO_SCALED",
            "NORM_LITERAL"]
 
@@ -204,3 +205,36 @@ def build(ctx: Context, points, kernel="exp", length: float = 0.2, opts: _lib.Op
     _lib.check(_lib.load().h2_build(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), C.byref(k), C.byref(o),
                                     C.byref(h)), "h2_build")
     return H2Matrix(ctx, h, n)
+
+
+def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_graph: bool = True,
+                  return_info: bool = False):
+    """Many independent constructions in one launch sequence (h2_build_batched).
+
+    problems: sequence of dicts with keys points ((dim, n) array or tensor),
+    kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
+    norm_mode (defaults as h2_opts_default).  Returns a list of H2Matrix (and
+    the batch info dict when return_info)."""
+    torch = _torch()
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[precision]
+    d = opts_default()
+    arr = (_lib.Problem * len(problems))()
+    keep = []
+    for i, pr in enumerate(problems):
+        pts = torch.as_tensor(pr["points"]).to(device="cuda", dtype=torch.float64).contiguous()
+        keep.append(pts)
+        dim, n = pts.shape
+        nm = pr.get("norm_mode", d.norm_mode)
+        if isinstance(nm, str):
+            nm = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[nm]
+        arr[i] = _lib.Problem(n, dim, pts.data_ptr(), kernel_spec(pr.get("kernel", "exp"), pr.get("length", 0.2)),
+                              pr.get("tol", d.tol), pr.get("leaf_size", d.leaf_size), pr.get("eta", d.eta),
+                              pr.get("d0", d.d0), pr.get("d_inc", d.d_inc), pr.get("seed", d.seed), nm)
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0)
+    handles = (C.c_void_p * len(problems))()
+    info = _lib.BatchInfo()
+    _lib.check(_lib.load().h2_build_batched(ctx._h, len(problems), arr, C.byref(bo), handles, C.byref(info)),
+               "h2_build_batched")
+    mats = [H2Matrix(ctx, C.c_void_p(handles[i]), int(arr[i].n)) for i in range(len(problems))]
+    return (mats, info.as_dict()) if return_info else mats

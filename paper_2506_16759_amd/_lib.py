@@ -49,6 +49,25 @@ class Info(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("points", C.c_void_p), ("kernel", Kernel),
+                ("tol", C.c_double), ("leaf_size", C.c_int32), ("eta", C.c_double), ("d0", C.c_int32),
+                ("d_inc", C.c_int32), ("seed", C.c_uint64), ("norm_mode", C.c_int32)]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("d_max", C.c_int32), ("use_graph", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("t_total_ms", C.c_double), ("t_plan_ms", C.c_double), ("t_setup_ms", C.c_double),
+                ("t_capture_ms", C.c_double), ("t_device_ms", C.c_double), ("levels", C.c_int32),
+                ("graph_nodes", C.c_int32), ("device_bytes", C.c_int64), ("sketch_flops", C.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _P = C.c_void_p
 _SIGS = {
     "h2_opts_default": [C.POINTER(Opts)],
@@ -67,6 +86,8 @@ _SIGS = {
     "h2_export": [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)],
     "h2_query": [_P, C.POINTER(Info)],
     "h2_free": [_P],
+    "h2_build_batched": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(_P),
+                         C.POINTER(BatchInfo)],
 }
 EXPORTED = tuple(_SIGS)
 

@@ -17,207 +17,16 @@
 
 #include "h2.h"
 #include "h2_device.hpp"
+#include "h2_internal.hpp"
 #include "h2_plan.hpp"
 
-namespace {
-
+namespace h2i {
 thread_local std::string g_last_error;
+}  // namespace h2i
 
-struct Error : std::runtime_error {
-  h2_status status;
-  Error(h2_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
-};
+using namespace h2i;
 
-#define H2_HIP(expr)                                                                                    \
-  do {                                                                                                  \
-    hipError_t e_ = (expr);                                                                             \
-    if (e_ != hipSuccess)                                                                               \
-      throw Error(e_ == hipErrorOutOfMemory ? H2_ERR_OOM : H2_ERR_HIP,                                  \
-                  std::string(#expr) + ": " + hipGetErrorString(e_));                                   \
-  } while (0)
-
-#define H2_REQUIRE(cond, msg)                   \
-  do {                                          \
-    if (!(cond)) throw Error(H2_ERR_ARG, msg);  \
-  } while (0)
-
-template <typename F>
-h2_status guarded(F&& f) {
-  try {
-    f();
-    return H2_OK;
-  } catch (const Error& e) {
-    g_last_error = e.what();
-    return e.status;
-  } catch (const std::invalid_argument& e) {
-    g_last_error = e.what();
-    return H2_ERR_ARG;
-  } catch (const std::bad_alloc&) {
-    g_last_error = "host allocation failed";
-    return H2_ERR_OOM;
-  } catch (const std::exception& e) {
-    g_last_error = e.what();
-    return H2_ERR_HIP;
-  }
-}
-
-// Stream-ordered device array.
-template <typename T>
-class DevArray {
- public:
-  DevArray() = default;
-  DevArray(const DevArray&) = delete;
-  DevArray& operator=(const DevArray&) = delete;
-  DevArray(DevArray&& o) noexcept { *this = std::move(o); }
-  DevArray& operator=(DevArray&& o) noexcept {
-    if (this != &o) {
-      release();
-      p_ = o.p_;
-      n_ = o.n_;
-      s_ = o.s_;
-      o.p_ = nullptr;
-      o.n_ = 0;
-    }
-    return *this;
-  }
-  ~DevArray() { release(); }
-
-  void alloc(size_t n, hipStream_t s) {
-    release();
-    s_ = s;
-    n_ = n;
-    if (n == 0) return;
-    void* p = nullptr;
-    H2_HIP(hipMallocAsync(&p, n * sizeof(T), s));
-    p_ = static_cast<T*>(p);
-  }
-  void upload(const std::vector<T>& h, hipStream_t s) {
-    alloc(h.size(), s);
-    if (!h.empty()) H2_HIP(hipMemcpyAsync(p_, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-  }
-  void release() {
-    if (p_) (void)hipFreeAsync(p_, s_);
-    p_ = nullptr;
-    n_ = 0;
-  }
-  T* get() const { return p_; }
-  size_t size() const { return n_; }
-  size_t bytes() const { return n_ * sizeof(T); }
-
- private:
-  T* p_ = nullptr;
-  size_t n_ = 0;
-  hipStream_t s_ = nullptr;
-};
-
-template <typename T>
-std::vector<T> download(const T* d, size_t n, hipStream_t s) {
-  std::vector<T> h(n);
-  if (n) {
-    H2_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
-    H2_HIP(hipStreamSynchronize(s));
-  }
-  return h;
-}
-
-// Phase timer on HIP events: record pairs, resolve after the stream is synchronised.
-class PhaseTimer {
- public:
-  explicit PhaseTimer(hipStream_t s) : s_(s) {}
-  ~PhaseTimer() {
-    for (auto& r : recs_) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
-  }
-  int begin(int phase) {
-    Rec r{phase, nullptr, nullptr};
-    H2_HIP(hipEventCreate(&r.a));
-    H2_HIP(hipEventCreate(&r.b));
-    H2_HIP(hipEventRecord(r.a, s_));
-    recs_.push_back(r);
-    return static_cast<int>(recs_.size()) - 1;
-  }
-  void end(int h) { H2_HIP(hipEventRecord(recs_[h].b, s_)); }
-  void totals(double* out, int nphase) {
-    H2_HIP(hipStreamSynchronize(s_));
-    for (int p = 0; p < nphase; ++p) out[p] = 0;
-    for (auto& r : recs_) {
-      float ms = 0;
-      H2_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-      out[r.phase] += ms;
-    }
-  }
-
- private:
-  struct Rec {
-    int phase;
-    hipEvent_t a, b;
-  };
-  hipStream_t s_;
-  std::vector<Rec> recs_;
-};
-
-enum Phase { kTree, kSample, kNearGen, kSubtract, kConv, kId, kUpsweep, kCoupling, kMisc, kNumPhase };
-
-// Per-depth results of the construction.  Rows of depth t live in row space
-// R_t (in-rows, `rowoff`) and the skeleton rows in R_{t-1} (`koff`).
-struct Level {
-  int t = 0, nn = 0;
-  bool processed = false;
-  std::vector<int32_t> rowoff_h, k_h, koff_h;
-  std::vector<int64_t> joff_h, uoff_h;
-  int max_m = 0, max_k = 0;
-  DevArray<int32_t> rowoff, koff, J, pos_out;
-  DevArray<int64_t> joff, uoff;
-  DevArray<double> U, xs_out;
-  // far blocks at this depth
-  std::vector<int32_t> fptr_h, fidx_h;
-  std::vector<int64_t> boff_h;
-  DevArray<int32_t> fptr, fidx;
-  DevArray<int64_t> boff;
-  DevArray<double> B;
-  // sample buffers of row space R_t (capacity columns), only during a build
-  DevArray<double> om, y;
-  int64_t M = 0;
-};
-
-}  // namespace
-
-struct h2_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t lds_limit = 65536;
-};
-
-struct h2_plan {
-  h2::Plan plan;
-};
-
-struct h2_matrix {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  h2::Plan plan;
-  h2_kernel kernel{};
-  h2_opts opts{};
-  int top = 1;
-  double delta = 0, nu = 0;
-  int samples = 0, sketched = 0, rounds = 0;
-  double host_plan_ms = 0;
-  DevArray<int32_t> perm;
-  DevArray<double> X;  // tree-ordered SoA points
-  DevArray<int32_t> nptr, nidx, leafoff;
-  DevArray<int64_t> doff;
-  std::vector<int64_t> doff_h;
-  std::vector<int32_t> leafoff_h;
-  DevArray<double> Dblk;
-  std::vector<Level> lv;  // indexed by depth
-  double phase_ms[kNumPhase] = {};
-  double total_ms = 0;
-  double sketch_flops = 0, sketch_entries = 0;
-};
-
-namespace {
+namespace h2i {
 
 h2dev::KernelFn kernel_fn(const h2_kernel& k) {
   h2dev::KernelFn f;
@@ -231,6 +40,16 @@ void check_kernel(const h2_kernel* k) {
   H2_REQUIRE(k->kind == H2_K_EXP || k->kind == H2_K_GAUSS, "unknown kernel kind");
   H2_REQUIRE(k->length > 0.0 && std::isfinite(k->length), "kernel length must be finite and > 0");
 }
+
+int top_depth(const h2::Plan& p) {
+  for (int t = 1; t <= p.depth; ++t)
+    if (!p.far_idx[t].empty()) return t;
+  return p.depth + 1;
+}
+
+}  // namespace h2i
+
+namespace {
 
 void check_opts(const h2_opts* o) {
   H2_REQUIRE(o != nullptr, "opts is NULL");
@@ -246,18 +65,6 @@ void check_opts(const h2_opts* o) {
   H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 128, "sketch_ahead must be in [0, 128]");
 }
 
-int top_depth(const h2::Plan& p) {
-  for (int t = 1; t <= p.depth; ++t)
-    if (!p.far_idx[t].empty()) return t;
-  return p.depth + 1;
-}
-
-template <typename T>
-std::vector<T> prefix(const std::vector<T>& sizes) {
-  std::vector<T> off(sizes.size() + 1, 0);
-  for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + sizes[i];
-  return off;
-}
 
 class Builder {
  public:
@@ -701,6 +508,7 @@ h2_status h2_ctx_create(int device, void* stream, h2_ctx** out) {
     int lds = 0;
     H2_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
     c->lds_limit = lds > 2048 ? size_t(lds) - 1024 : size_t(lds);
+    H2_HIP(h2dev::prepare_kernels(c->lds_limit));
     // keep freed device memory in the stream-ordered pool between builds
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
@@ -925,7 +733,19 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
           copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
           return;
         }
-        copy_part(L.B.get(), L.B.bytes(), dst, dst_bytes, needed, true, s);
+        // packed k_s x k_b per far pair in CSR order (storage may hold gaps)
+        std::vector<double> all(L.B.size());
+        if (!all.empty()) {
+          H2_HIP(hipMemcpyAsync(all.data(), L.B.get(), all.size() * 8, hipMemcpyDeviceToHost, s));
+          H2_HIP(hipStreamSynchronize(s));
+        }
+        std::vector<double> packed;
+        for (int a = 0; a < L.nn; ++a)
+          for (int j = L.fptr_h[a]; j < L.fptr_h[a + 1]; ++j) {
+            const int64_t sz = int64_t(L.k_h[a]) * L.k_h[L.fidx_h[j]];
+            packed.insert(packed.end(), all.begin() + L.boff_h[j], all.begin() + L.boff_h[j] + sz);
+          }
+        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, s);
         return;
       }
       default:

@@ -1,0 +1,621 @@
+// Batched construction of many independent H^2 matrices (Alg. 1 with the
+// adaptive sampling of Sec. III-B) in one launch sequence.
+//
+// Problems are ordered by the number of levels they process (descending), so
+// the problems still active at any level are a prefix of that order and each
+// level's clusters and row space are contiguous.  Every stage of a level is one
+// kernel over the clusters of all active problems.  All d_max columns are
+// sketched up front; the adaptive loop then only picks each problem's column
+// count, from one prefix QR per cluster (qr_first_conv), so the device needs no
+// host decision.  Storage uses static per-cluster capacities (k <= min(m,
+// d_max)) except the compact skeleton rows, whose offsets come from a device
+// scan.  With use_graph the whole sequence is captured in one hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <string>
+#include <thread>
+
+#include "h2_internal.hpp"
+
+using namespace h2i;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+struct Prob {
+  int orig = 0;
+  h2_problem in{};
+  h2::Plan plan;
+  int D = 0, top = 1, L = 0;  // tree depth, coarsest processed depth, processed levels
+  int64_t base = 0;           // first global row
+  int leafbase = 0;           // first global leaf
+  int64_t dbase = 0;          // first dense-block entry
+};
+
+struct LevelB {
+  int G = 0;
+  std::vector<int32_t> nodeprob, childfirst, nodebase, mcap, kcap, fptr, fidx;
+  std::vector<int64_t> joff, uoff, boff;
+  int max_m = 0, max_k = 0;
+  int64_t rcap = 0;       // rows of R_l (this level's in-rows)
+  int64_t rcap_next = 0;  // rows of R_{l+1} (skeletons of this level)
+  DevArray<int32_t> d_nodeprob, d_childfirst, rowoff, k, koff, J, pos, d_fptr, d_fidx;
+  DevArray<int64_t> d_joff, d_uoff, d_boff, gws_off;
+  DevArray<double> U, B, xs, om, y, gws;
+  std::vector<int32_t> k_h, koff_h, rowoff_h;
+};
+
+struct BatchStore {
+  std::vector<LevelB> lv;  // index l-1
+  DevArray<double> Xo, Xt, Om0, Y0, Dblk;
+  DevArray<int32_t> perm_g, rowprob_o, rowlocal_o, leafoff, nptr, nidx, leafprob, kinds, dprob, incprob, exhausted;
+  DevArray<int64_t> doff;
+  DevArray<uint64_t> seeds;
+  DevArray<double> c2s, nu, delta;
+  DevArray<char> sjobs, tjobs;
+  DevArray<int32_t> tiles;
+  int64_t bytes = 0;
+};
+
+template <typename T>
+void up(DevArray<T>& a, const std::vector<T>& h, hipStream_t s, int64_t& bytes) {
+  a.upload(h, s);
+  bytes += static_cast<int64_t>(a.bytes());
+}
+template <typename T>
+void mk(DevArray<T>& a, size_t n, hipStream_t s, int64_t& bytes) {
+  a.alloc(n, s);
+  bytes += static_cast<int64_t>(a.bytes());
+}
+
+void check_problem(const h2_problem& p) {
+  H2_REQUIRE(p.points != nullptr, "problem points are NULL");
+  H2_REQUIRE(p.n >= 1 && p.n <= (int64_t{1} << 30), "problem n must be in [1, 2^30]");
+  H2_REQUIRE(p.dim >= 1 && p.dim <= 3, "problem dim must be 1..3");
+  check_kernel(&p.kernel);
+  H2_REQUIRE(p.tol > 0.0 && std::isfinite(p.tol), "problem tol must be finite and > 0");
+  H2_REQUIRE(p.leaf_size >= 2 && p.leaf_size <= 256, "problem leaf_size must be in [2, 256]");
+  H2_REQUIRE(p.eta > 0.0 && std::isfinite(p.eta), "problem eta must be finite and > 0");
+  H2_REQUIRE(p.d0 >= 1 && p.d_inc >= 1, "problem d0, d_inc must be >= 1");
+  H2_REQUIRE(p.norm_mode == H2_NORM_FRO_SCALED || p.norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
+}
+
+}  // namespace
+
+extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems,
+                                      const h2_batch_opts* bopts, h2_matrix** out, h2_batch_info* info) {
+  if (out && count > 0)
+    for (int i = 0; i < count; ++i) out[i] = nullptr;
+  return guarded([&] {
+    const auto t_start = Clock::now();
+    H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
+    H2_REQUIRE(count >= 1, "count must be >= 1");
+    const int prec = bopts->precision;
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3, "unknown precision");
+    const int dcap = bopts->d_max;
+    H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
+    for (int i = 0; i < count; ++i) {
+      check_problem(problems[i]);
+      H2_REQUIRE(problems[i].d0 <= dcap, "problem d0 exceeds d_max");
+    }
+    H2_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    auto store = std::make_shared<BatchStore>();
+    BatchStore& B = *store;
+    int64_t& bytes = B.bytes;
+
+    // ---- host plans (threaded over problems)
+    auto t0 = Clock::now();
+    std::vector<Prob> P(count);
+    std::vector<std::vector<double>> pts(count);
+    for (int i = 0; i < count; ++i) {
+      P[i].orig = i;
+      P[i].in = problems[i];
+      pts[i].resize(static_cast<size_t>(problems[i].n) * problems[i].dim);
+      H2_HIP(hipMemcpyAsync(pts[i].data(), problems[i].points, pts[i].size() * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    }
+    H2_HIP(hipStreamSynchronize(s));
+    {
+      std::vector<std::string> errs(count);
+      std::atomic<int> next{0};
+      const int nt = std::max(1, std::min(16, count));
+      std::vector<std::thread> pool;
+      for (int w = 0; w < nt; ++w)
+        pool.emplace_back([&] {
+          for (int i; (i = next.fetch_add(1)) < count;) {
+            try {
+              P[i].plan = h2::make_plan(P[i].in.n, P[i].in.dim, pts[i].data(), P[i].in.leaf_size, P[i].in.eta);
+            } catch (const std::exception& e) {
+              errs[i] = e.what();
+            }
+          }
+        });
+      for (auto& t : pool) t.join();
+      for (int i = 0; i < count; ++i)
+        if (!errs[i].empty()) throw Error(H2_ERR_ARG, "problem " + std::to_string(i) + ": " + errs[i]);
+    }
+    for (auto& p : P) {
+      p.D = p.plan.depth;
+      p.top = top_depth(p.plan);
+      p.L = p.top > p.D ? 0 : p.D - p.top + 1;
+    }
+    const double t_plan = ms_since(t0);
+
+    // ---- layout (problems ordered by processed levels, descending)
+    t0 = Clock::now();
+    std::stable_sort(P.begin(), P.end(), [](const Prob& a, const Prob& b) { return a.L > b.L; });
+    const int np = count;
+    int64_t NT = 0;
+    int nleaf_total = 0;
+    for (auto& p : P) {
+      p.base = NT;
+      NT += p.in.n;
+      p.leafbase = nleaf_total;
+      nleaf_total += 1 << p.D;
+    }
+    H2_REQUIRE(NT < (int64_t{1} << 31), "total points must be < 2^31");
+    // global tree order, original order maps
+    std::vector<int32_t> perm_g(NT), rowprob_o(NT), rowlocal_o(NT);
+    for (int q = 0; q < np; ++q) {
+      const auto& p = P[q];
+      for (int64_t r = 0; r < p.in.n; ++r) {
+        perm_g[p.base + r] = static_cast<int32_t>(p.base + p.plan.perm[r]);
+        rowprob_o[p.base + r] = q;
+        rowlocal_o[p.base + r] = static_cast<int32_t>(r);
+      }
+    }
+    // leaves and near field
+    std::vector<int32_t> leafoff(nleaf_total + 1), nptr(nleaf_total + 1, 0), nidx, leafprob(nleaf_total);
+    std::vector<int64_t> dsz;
+    int leaf_max = 0;
+    for (int q = 0; q < np; ++q) {
+      auto& p = P[q];
+      const int nl = 1 << p.D, lb = p.plan.level_begin(p.D);
+      for (int a = 0; a < nl; ++a) {
+        leafoff[p.leafbase + a] = static_cast<int32_t>(p.base + p.plan.begin[lb + a]);
+        leafprob[p.leafbase + a] = q;
+        leaf_max = std::max(leaf_max, p.plan.end[lb + a] - p.plan.begin[lb + a]);
+      }
+    }
+    leafoff[nleaf_total] = static_cast<int32_t>(NT);
+    int64_t dtot = 0;
+    for (int q = 0; q < np; ++q) {
+      auto& p = P[q];
+      p.dbase = dtot;
+      const int nl = 1 << p.D, lb = p.plan.level_begin(p.D);
+      for (int a = 0; a < nl; ++a) {
+        const int g = p.leafbase + a;
+        const int ma = p.plan.end[lb + a] - p.plan.begin[lb + a];
+        for (int j = p.plan.near_ptr[a]; j < p.plan.near_ptr[a + 1]; ++j) {
+          const int b = p.plan.near_idx[j];
+          nidx.push_back(p.leafbase + b);
+          const int64_t sz = int64_t(ma) * (p.plan.end[lb + b] - p.plan.begin[lb + b]);
+          dsz.push_back(sz);
+          dtot += sz;
+        }
+        nptr[g + 1] = static_cast<int32_t>(nidx.size());
+      }
+    }
+    const std::vector<int64_t> doff = prefix(dsz);
+
+    // levels
+    int Lmax = 0;
+    for (auto& p : P) Lmax = std::max(Lmax, p.L);
+    B.lv.resize(Lmax);
+    for (int l = 1; l <= Lmax; ++l) {
+      LevelB& V = B.lv[l - 1];
+      V.nodebase.assign(np, -1);
+      for (int q = 0; q < np && P[q].L >= l; ++q) {
+        const int t = P[q].D - l + 1;
+        V.nodebase[q] = V.G;
+        for (int a = 0; a < (1 << t); ++a) V.nodeprob.push_back(q);
+        V.G += 1 << t;
+      }
+      V.mcap.resize(V.G);
+      V.kcap.resize(V.G);
+      if (l == 1) {
+        V.rowoff_h.assign(leafoff.begin(), leafoff.begin() + V.G + 1);
+        for (int g = 0; g < V.G; ++g) V.mcap[g] = V.rowoff_h[g + 1] - V.rowoff_h[g];
+        V.rcap = NT;
+      } else {
+        const LevelB& C = B.lv[l - 2];
+        V.childfirst.resize(V.G + 1);
+        for (int q = 0; q < np && P[q].L >= l; ++q) {
+          const int t = P[q].D - l + 1;
+          for (int a = 0; a < (1 << t); ++a) {
+            const int g = V.nodebase[q] + a, c = C.nodebase[q] + 2 * a;
+            V.childfirst[g] = c;
+            V.mcap[g] = C.kcap[c] + C.kcap[c + 1];
+          }
+        }
+        // end of the last active cluster: the children of active problems are a prefix
+        int cend = 0;
+        for (int q = 0; q < np && P[q].L >= l; ++q) cend = C.nodebase[q] + (2 << (P[q].D - l + 1));
+        V.childfirst[V.G] = cend;
+        V.rcap = C.rcap_next;
+      }
+      for (int g = 0; g < V.G; ++g) {
+        V.kcap[g] = std::min(V.mcap[g], dcap);
+        V.max_m = std::max(V.max_m, V.mcap[g]);
+        V.max_k = std::max(V.max_k, V.kcap[g]);
+      }
+      std::vector<int64_t> jsz(V.G), usz(V.G);
+      for (int g = 0; g < V.G; ++g) {
+        jsz[g] = V.kcap[g];
+        usz[g] = int64_t(V.mcap[g]) * V.kcap[g];
+      }
+      V.joff = prefix(jsz);
+      V.uoff = prefix(usz);
+      V.rcap_next = V.joff.back();
+      // far lists at this level, global cluster indices; capacity offsets
+      V.fptr.assign(V.G + 1, 0);
+      std::vector<int64_t> bsz;
+      for (int q = 0; q < np && P[q].L >= l; ++q) {
+        const int t = P[q].D - l + 1;
+        const auto& fp = P[q].plan.far_ptr[t];
+        const auto& fi = P[q].plan.far_idx[t];
+        for (int a = 0; a < (1 << t); ++a) {
+          const int g = V.nodebase[q] + a;
+          for (int j = fp[a]; j < fp[a + 1]; ++j) {
+            const int b = V.nodebase[q] + fi[j];
+            V.fidx.push_back(b);
+            bsz.push_back(int64_t(V.kcap[g]) * V.kcap[b]);
+          }
+          V.fptr[g + 1] = static_cast<int32_t>(V.fidx.size());
+        }
+      }
+      V.boff = prefix(bsz);
+    }
+
+    // ---- device allocation and static uploads
+    H2_HIP(hipStreamSynchronize(s));
+    mk(B.Xo, size_t(3) * NT, s, bytes);
+    mk(B.Xt, size_t(3) * NT, s, bytes);
+    mk(B.Om0, size_t(NT) * dcap, s, bytes);
+    mk(B.Y0, size_t(NT) * dcap, s, bytes);
+    mk(B.Dblk, size_t(doff.back()), s, bytes);
+    up(B.perm_g, perm_g, s, bytes);
+    up(B.rowprob_o, rowprob_o, s, bytes);
+    up(B.rowlocal_o, rowlocal_o, s, bytes);
+    up(B.leafoff, leafoff, s, bytes);
+    up(B.nptr, nptr, s, bytes);
+    up(B.nidx, nidx, s, bytes);
+    up(B.doff, doff, s, bytes);
+    up(B.leafprob, leafprob, s, bytes);
+    std::vector<uint64_t> seeds(np);
+    std::vector<int32_t> kinds(np), incs(np);
+    std::vector<double> c2s(np);
+    std::vector<char> sj(h2dev::sketch_job_bytes() * np), tj(h2dev::threshold_job_bytes() * np);
+    std::vector<int32_t> tiles;
+    std::vector<std::pair<int64_t, int>> order(np);
+    for (int q = 0; q < np; ++q) {
+      const auto& p = P[q];
+      seeds[q] = p.in.seed;
+      kinds[q] = p.in.kernel.kind;
+      incs[q] = p.in.d_inc;
+      const h2dev::KernelFn kf = kernel_fn(p.in.kernel);
+      c2s[q] = -kf.scale * 1.4426950408889634;
+      h2dev::pack_sketch_job(sj.data() + q * h2dev::sketch_job_bytes(), p.in.n, p.base, kf.kind, kf.scale);
+      h2dev::pack_threshold_job(tj.data() + q * h2dev::threshold_job_bytes(), p.base, p.in.n, p.in.d0, 1 << p.D,
+                                p.in.norm_mode == H2_NORM_FRO_SCALED ? 0 : 1, p.in.tol);
+      order[q] = {p.in.n, q};
+    }
+    // sketch tiles, largest problems first
+    std::stable_sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
+    for (auto& o : order)
+      for (int64_t r0 = 0; r0 < o.first; r0 += 128) {
+        tiles.push_back(o.second);
+        tiles.push_back(static_cast<int32_t>(r0));
+      }
+    up(B.seeds, seeds, s, bytes);
+    up(B.kinds, kinds, s, bytes);
+    up(B.incprob, incs, s, bytes);
+    up(B.c2s, c2s, s, bytes);
+    up(B.sjobs, sj, s, bytes);
+    up(B.tjobs, tj, s, bytes);
+    up(B.tiles, tiles, s, bytes);
+    mk(B.nu, np, s, bytes);
+    mk(B.delta, np, s, bytes);
+    mk(B.dprob, np, s, bytes);
+    mk(B.exhausted, np, s, bytes);
+    for (int l = 1; l <= Lmax; ++l) {
+      LevelB& V = B.lv[l - 1];
+      up(V.d_nodeprob, V.nodeprob, s, bytes);
+      if (l == 1)
+        up(V.rowoff, V.rowoff_h, s, bytes);
+      else {
+        up(V.d_childfirst, V.childfirst, s, bytes);
+        mk(V.rowoff, V.G + 1, s, bytes);
+      }
+      mk(V.k, V.G, s, bytes);
+      mk(V.koff, V.G + 1, s, bytes);
+      up(V.d_joff, V.joff, s, bytes);
+      up(V.d_uoff, V.uoff, s, bytes);
+      mk(V.J, size_t(V.joff.back()), s, bytes);
+      mk(V.U, size_t(V.uoff.back()), s, bytes);
+      mk(V.pos, size_t(V.rcap_next), s, bytes);
+      mk(V.xs, size_t(3) * V.rcap_next, s, bytes);
+      up(V.d_fptr, V.fptr, s, bytes);
+      up(V.d_fidx, V.fidx, s, bytes);
+      up(V.d_boff, V.boff, s, bytes);
+      mk(V.B, size_t(V.boff.back()), s, bytes);
+      if (l >= 2) {
+        mk(V.om, size_t(V.rcap) * dcap, s, bytes);
+        mk(V.y, size_t(V.rcap) * dcap, s, bytes);
+      }
+      const size_t cbytes = size_t(3) * V.max_m * 8 + size_t(dcap | 1) * V.max_m * 8;
+      const size_t qbytes = size_t(V.max_m | 1) * dcap * 8;
+      if (std::max(cbytes, qbytes) > ctx->lds_limit) {
+        const int64_t per = int64_t((V.max_m | 1) + 1) * int64_t((dcap | 1) + 1);
+        std::vector<int64_t> off(V.G);
+        for (int g = 0; g < V.G; ++g) off[g] = per * g;
+        up(V.gws_off, off, s, bytes);
+        mk(V.gws, size_t(per) * V.G, s, bytes);
+      }
+    }
+    // level 1 works on the tree-ordered sketch itself
+    DevArray<double> Om1, Y1;  // tree-ordered Omega and Y (level 1 row space)
+    mk(Om1, size_t(NT) * dcap, s, bytes);
+    mk(Y1, size_t(NT) * dcap, s, bytes);
+    H2_HIP(hipStreamSynchronize(s));
+    const double t_setup = ms_since(t0);
+
+    // ---- the launch sequence
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const bool use_graph = bopts->use_graph != 0;
+    hipStream_t cs = nullptr;  // capture stream
+    if (use_graph) H2_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    auto enqueue = [&](hipStream_t s) {
+      // points: caller's arrays -> 3 x NT original order; then tree order
+      H2_HIP(h2dev::fill_zero(s, B.Xo.get(), 3 * NT));
+      for (const auto& p : P)
+        for (int a = 0; a < p.in.dim; ++a)
+          H2_HIP(hipMemcpyAsync(B.Xo.get() + a * NT + p.base, p.in.points + a * p.in.n, p.in.n * sizeof(double),
+                                hipMemcpyDeviceToDevice, s));
+      H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Xo.get(), NT, B.Xt.get(), NT, 3));
+      // sketch in original order (same evaluation as single builds), then tree order
+      H2_HIP(h2dev::gaussian_batched(s, NT, B.rowlocal_o.get(), B.rowprob_o.get(), B.seeds.get(), 0, dcap,
+                                     B.Om0.get(), NT));
+      H2_HIP(h2dev::sketch_batched(s, prec, static_cast<int>(tiles.size() / 2), B.sjobs.get(), B.tiles.get(),
+                                   B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT));
+      H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Om0.get(), NT, Om1.get(), NT, dcap));
+      H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Y0.get(), NT, Y1.get(), NT, dcap));
+      H2_HIP(h2dev::thresholds(s, np, B.tjobs.get(), Y1.get(), NT, B.nu.get(), B.delta.get(), B.dprob.get()));
+      H2_HIP(h2dev::fill_i32(s, B.exhausted.get(), np, 0));
+      // dense near field of every leaf, and its subtraction from the samples
+      H2_HIP(h2dev::gen_blocks_batched(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
+                                       B.Xt.get(), NT, B.leafprob.get(), B.kinds.get(), B.c2s.get(),
+                                       B.Dblk.get()));
+      H2_HIP(h2dev::bsr_gemm(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
+                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max, prec));
+      for (int l = 1; l <= Lmax; ++l) {
+        LevelB& V = B.lv[l - 1];
+        double* om = l == 1 ? Om1.get() : V.om.get();
+        double* y = l == 1 ? Y1.get() : V.y.get();
+        const int64_t ld = V.rcap;
+        if (l >= 2) {
+          LevelB& C = B.lv[l - 2];
+          H2_HIP(h2dev::gather_i32(s, V.G, V.d_childfirst.get(), C.koff.get(), V.rowoff.get()));
+          H2_HIP(h2dev::bsr_gemm(s, C.G, C.d_fptr.get(), C.d_fidx.get(), C.koff.get(), C.d_boff.get(), C.B.get(),
+                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), 0));
+        }
+        H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), V.d_nodeprob.get(),
+                                    B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m, ctx->lds_limit,
+                                    V.gws.get(), V.gws_off.get()));
+        H2_HIP(h2dev::cpqr_id(s, V.G, V.rowoff.get(), y, ld, dcap, 0.0, V.k.get(), V.J.get(), V.d_joff.get(),
+                              V.U.get(), V.d_uoff.get(), V.max_m, ctx->lds_limit, V.gws.get(), V.gws_off.get(),
+                              V.d_nodeprob.get(), B.dprob.get(), B.delta.get()));
+        H2_HIP(h2dev::scan_i32(s, V.G, V.k.get(), V.koff.get()));
+        if (l < Lmax) {
+          LevelB& N = B.lv[l];
+          H2_HIP(h2dev::shrink_up(s, V.G, V.rowoff.get(), V.koff.get(), V.J.get(), V.d_joff.get(), V.U.get(),
+                                  V.d_uoff.get(), y, ld, om, ld, N.y.get(), N.rcap, N.om.get(), N.rcap, dcap));
+        }
+        const int32_t* pos_in = l == 1 ? nullptr : B.lv[l - 2].pos.get();
+        H2_HIP(h2dev::skeleton(s, V.G, V.rowoff.get(), V.koff.get(), V.J.get(), V.d_joff.get(), pos_in,
+                               V.pos.get(), 3, B.Xt.get(), NT, V.xs.get(), V.rcap_next));
+        H2_HIP(h2dev::gen_blocks_batched(s, V.G, V.d_fptr.get(), V.d_fidx.get(), V.koff.get(), V.d_boff.get(),
+                                         V.xs.get(), V.rcap_next, V.d_nodeprob.get(), B.kinds.get(), B.c2s.get(),
+                                         V.B.get()));
+      }
+    };
+    double t_capture = 0;
+    size_t graph_nodes = 0;
+    hipEvent_t e0, e1;
+    H2_HIP(hipEventCreate(&e0));
+    H2_HIP(hipEventCreate(&e1));
+    try {
+      if (use_graph) {
+        t0 = Clock::now();
+        H2_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        try {
+          enqueue(cs);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cs, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        H2_HIP(hipStreamEndCapture(cs, &graph));
+        H2_HIP(hipGraphGetNodes(graph, nullptr, &graph_nodes));
+        H2_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        t_capture = ms_since(t0);
+        H2_HIP(hipEventRecord(e0, s));
+        H2_HIP(hipGraphLaunch(exec, s));
+        H2_HIP(hipEventRecord(e1, s));
+      } else {
+        H2_HIP(hipEventRecord(e0, s));
+        enqueue(s);
+        H2_HIP(hipEventRecord(e1, s));
+      }
+      H2_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (cs) (void)hipStreamDestroy(cs);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    float dev_ms = 0;
+    H2_HIP(hipEventElapsedTime(&dev_ms, e0, e1));
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+
+    // ---- results back to per-problem matrices (views into the batch storage)
+    const std::vector<int32_t> dprob = download(B.dprob.get(), np, s);
+    const std::vector<int32_t> exh = download(B.exhausted.get(), np, s);
+    const std::vector<double> nu = download(B.nu.get(), np, s);
+    const std::vector<double> delta = download(B.delta.get(), np, s);
+    for (int q = 0; q < np; ++q)
+      if (exh[q] && P[q].L > 0)
+        throw Error(H2_ERR_SAMPLES, "problem " + std::to_string(P[q].orig) + " not converged within d_max = " +
+                                        std::to_string(dcap) + " columns");
+    for (int l = 1; l <= Lmax; ++l) {
+      LevelB& V = B.lv[l - 1];
+      V.k_h = download(V.k.get(), V.G, s);
+      V.koff_h = download(V.koff.get(), V.G + 1, s);
+      if (l >= 2) V.rowoff_h = download(V.rowoff.get(), V.G + 1, s);
+    }
+    std::vector<std::unique_ptr<h2_matrix>> mats(np);
+    double sketch_flops = 0;
+    for (int q = 0; q < np; ++q) {
+      Prob& p = P[q];
+      auto h = std::make_unique<h2_matrix>();
+      h->device = ctx->device;
+      h->stream = s;
+      h->keep = store;
+      h->kernel = p.in.kernel;
+      h2_opts o{};
+      o.tol = p.in.tol;
+      o.leaf_size = p.in.leaf_size;
+      o.eta = p.in.eta;
+      o.d0 = p.in.d0;
+      o.d_inc = p.in.d_inc;
+      o.d_max = dcap;
+      o.seed = p.in.seed;
+      o.precision = prec;
+      o.norm_mode = p.in.norm_mode;
+      o.sketch_ahead = dcap - p.in.d0;
+      h->opts = o;
+      const int n = static_cast<int>(p.in.n);
+      const int D = p.D;
+      h->top = p.top;
+      h->delta = p.L > 0 ? delta[q] : 0.0;
+      h->nu = p.L > 0 ? nu[q] : 0.0;
+      h->samples = p.L > 0 ? dprob[q] : 0;
+      h->sketched = p.L > 0 ? dcap : 0;
+      h->rounds = p.L > 0 ? (dprob[q] - p.in.d0) / p.in.d_inc : 0;
+      h->perm.upload(p.plan.perm, s);
+      const int nl = 1 << D;
+      h->leafoff_h.resize(nl + 1);
+      for (int a = 0; a <= nl; ++a) h->leafoff_h[a] = leafoff[p.leafbase + a] - static_cast<int32_t>(p.base);
+      h->leafoff.upload(h->leafoff_h, s);
+      h->nptr.upload(p.plan.near_ptr, s);
+      h->nidx.upload(p.plan.near_idx, s);
+      const int j0 = nptr[p.leafbase], j1 = nptr[p.leafbase + nl];
+      h->doff_h.assign(doff.begin() + j0, doff.begin() + j1 + 1);
+      for (auto& v : h->doff_h) v -= doff[j0];
+      h->doff.upload(h->doff_h, s);
+      h->Dblk.borrow(B.Dblk.get() + doff[j0], size_t(doff[j1] - doff[j0]));
+      h->lv.resize(D + 1);
+      for (int t = 0; t <= D; ++t) {
+        h->lv[t].t = t;
+        h->lv[t].nn = 1 << t;
+      }
+      for (int l = 1; l <= p.L; ++l) {
+        LevelB& V = B.lv[l - 1];
+        const int t = D - l + 1;
+        Level& L = h->lv[t];
+        const int g0 = V.nodebase[q], nn = 1 << t;
+        L.processed = true;
+        L.rowoff_h.resize(nn + 1);
+        L.koff_h.resize(nn + 1);
+        for (int a = 0; a <= nn; ++a) {
+          L.rowoff_h[a] = V.rowoff_h[g0 + a] - V.rowoff_h[g0];
+          L.koff_h[a] = V.koff_h[g0 + a] - V.koff_h[g0];
+        }
+        L.k_h.assign(V.k_h.begin() + g0, V.k_h.begin() + g0 + nn);
+        L.joff_h.assign(V.joff.begin() + g0, V.joff.begin() + g0 + nn + 1);
+        L.uoff_h.assign(V.uoff.begin() + g0, V.uoff.begin() + g0 + nn + 1);
+        const int64_t jb = L.joff_h[0], ub = L.uoff_h[0];
+        for (auto& v : L.joff_h) v -= jb;
+        for (auto& v : L.uoff_h) v -= ub;
+        L.max_m = 0;
+        L.max_k = 0;
+        for (int a = 0; a < nn; ++a) {
+          L.max_m = std::max(L.max_m, L.rowoff_h[a + 1] - L.rowoff_h[a]);
+          L.max_k = std::max(L.max_k, L.k_h[a]);
+        }
+        L.rowoff.upload(L.rowoff_h, s);
+        L.koff.upload(L.koff_h, s);
+        L.joff.upload(L.joff_h, s);
+        L.uoff.upload(L.uoff_h, s);
+        L.J.borrow(V.J.get() + jb, size_t(L.joff_h.back()));
+        L.U.borrow(V.U.get() + ub, size_t(L.uoff_h.back()));
+        // skeleton tree positions, local to the problem
+        std::vector<int32_t> pos = download(V.pos.get() + V.koff_h[g0], size_t(L.koff_h.back()), s);
+        for (auto& v : pos) v -= static_cast<int32_t>(p.base);
+        L.pos_out.upload(pos, s);
+        L.fptr_h = p.plan.far_ptr[t];
+        L.fidx_h = p.plan.far_idx[t];
+        const int f0 = V.fptr[g0], f1 = V.fptr[g0 + nn];
+        L.boff_h.assign(V.boff.begin() + f0, V.boff.begin() + f1 + 1);
+        const int64_t bb = L.boff_h[0];
+        for (auto& v : L.boff_h) v -= bb;
+        L.fptr.upload(L.fptr_h, s);
+        L.fidx.upload(L.fidx_h, s);
+        L.boff.upload(L.boff_h, s);
+        L.B.borrow(V.B.get() + bb, size_t(L.boff_h.back()));
+      }
+      h->plan = std::move(p.plan);
+      if (p.L > 0) {
+        h->sketch_flops = 2.0 * double(n) * double(n) * dcap;
+        h->sketch_entries = double(n) * double(n);
+        sketch_flops += h->sketch_flops;
+      }
+      h->total_ms = dev_ms;
+      mats[q] = std::move(h);
+    }
+    // only the factors stay: dense blocks, bases, skeleton indices, couplings
+    for (auto& V : B.lv) {
+      V.om.release();
+      V.y.release();
+      V.gws.release();
+      V.xs.release();
+      V.pos.release();
+    }
+    B.Xo.release();
+    B.Xt.release();
+    B.Om0.release();
+    B.Y0.release();
+    H2_HIP(hipStreamSynchronize(s));
+    for (int q = 0; q < np; ++q) out[P[q].orig] = mats[q].release();
+    if (info) {
+      h2_batch_info r{};
+      r.t_total_ms = ms_since(t_start);
+      r.t_plan_ms = t_plan;
+      r.t_setup_ms = t_setup;
+      r.t_capture_ms = t_capture;
+      r.t_device_ms = dev_ms;
+      r.levels = Lmax;
+      r.graph_nodes = static_cast<int32_t>(graph_nodes);
+      r.device_bytes = bytes;
+      r.sketch_flops = sketch_flops;
+      *info = r;
+    }
+  });
+}

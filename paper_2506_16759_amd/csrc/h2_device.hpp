@@ -60,9 +60,13 @@ hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
 
 // Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
 // row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).
+// Batched use: nodeprob[i] names cluster i's problem, whose column count and
+// threshold are dprob[.] and deltaprob[.] (then d and delta are ignored).
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
                    double delta, int32_t* kout, int32_t* J, const int64_t* joff, double* U, const int64_t* uoff,
-                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off);
+                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off,
+                   const int32_t* nodeprob = nullptr, const int32_t* dprob = nullptr,
+                   const double* deltaprob = nullptr);
 
 // Shrink and upsweep (Alg. 1 batchedShrink + batchedGemm) on nc columns:
 //   Yout[koff[i] + r, :] = Yloc[rowoff[i] + J[r], :]           (skipped when Yloc == nullptr)
@@ -90,7 +94,54 @@ hipError_t permute_rows(hipStream_t s, int64_t n, const int32_t* idx, bool scatt
 hipError_t sumsq_partial(hipStream_t s, int64_t n, int nc, const double* A, int64_t lda, double* partial,
                          int nblocks);
 
+// Sets the dynamic-LDS limit of every kernel that can use more than 64 KB
+// (call once per device before launching or capturing).
+hipError_t prepare_kernels(size_t lds_limit);
+
 // Fill n doubles with zero (used instead of memset so the call is graph-capturable).
 hipError_t fill_zero(hipStream_t s, double* p, int64_t n);
+hipError_t fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+
+// ------------------------------------------------------------------ batched
+// Several independent problems share concatenated arrays: problem p owns
+// global rows [base_p, base_p + n_p) of the points (3 coordinates, unused
+// ones zero), of Omega and of Y; its clusters of a level are contiguous in
+// that level's node list.
+
+// Omega(rows[p], col0 + c) with the seed of problem rowprob[p].
+hipError_t gaussian_batched(hipStream_t s, int64_t nrows, const int32_t* rows, const int32_t* rowprob,
+                            const uint64_t* seeds, int64_t col0, int ncols, double* out, int64_t ldo);
+
+// y = K_p omega for every problem: workgroup b computes row tile tiles[2b+1]
+// (a multiple of 128) of problem tiles[2b].  jobs: device array of packed jobs.
+hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* jobs, const int32_t* tiles,
+                          const double* X, int64_t ldx, int ncols, const double* omega, int64_t ldo, double* y,
+                          int64_t ldy);
+size_t sketch_job_bytes();
+void pack_sketch_job(void* dst, int64_t n, int64_t base, int kind, double scale);
+
+// gen_blocks with per-block-row problem: kind kinds[rowprob[i]], exponent c2s[rowprob[i]]
+// (c2 = -scale * log2 e); X has 3 coordinate rows.
+hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                              const int64_t* blkoff, const double* X, int64_t ldx, const int32_t* rowprob,
+                              const int32_t* kinds, const double* c2s, double* out);
+
+// Prefix convergence test over all dsk sketched columns: raises dprob[p] to the
+// first column count on the grid dprob[p] + j*incprob[p] at which every cluster
+// of p is converged; sets exhausted[p] if some cluster is not converged within dsk.
+hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int dsk,
+                         const int32_t* incprob, const int32_t* nodeprob, int32_t* dprob, const double* deltaprob,
+                         int32_t* exhausted, int max_m, size_t lds_limit, double* gws, const int64_t* gws_off);
+
+// Exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total.
+hipError_t scan_i32(hipStream_t s, int n, const int32_t* in, int32_t* out);
+// dst[i] = src[map[i]], i = 0..n.
+hipError_t gather_i32(hipStream_t s, int n, const int32_t* map, const int32_t* src, int32_t* dst);
+
+// Per problem: nu = ||Y_p(:, 0:d0)||_F / sqrt(d0), delta from tol and mode, d = d0.
+size_t threshold_job_bytes();
+void pack_threshold_job(void* dst, int64_t base, int64_t n, int d0, int nleaves, int mode, double tol);
+hipError_t thresholds(hipStream_t s, int nprob, const void* jobs, const double* Y, int64_t ldy, double* nu,
+                      double* delta, int32_t* d);
 
 }  // namespace h2dev

@@ -1,0 +1,239 @@
+// Internal types shared by the C ABI translation units: error handling,
+// stream-ordered device arrays, per-depth level data and the matrix object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "h2.h"
+#include "h2_device.hpp"
+#include "h2_plan.hpp"
+
+namespace h2i {
+
+extern thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  h2_status status;
+  Error(h2_status s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+#define H2_HIP(expr)                                                                                    \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess)                                                                               \
+      throw ::h2i::Error(e_ == hipErrorOutOfMemory ? H2_ERR_OOM : H2_ERR_HIP,                           \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));                            \
+  } while (0)
+
+#define H2_REQUIRE(cond, msg)                          \
+  do {                                                 \
+    if (!(cond)) throw ::h2i::Error(H2_ERR_ARG, msg);  \
+  } while (0)
+
+template <typename F>
+h2_status guarded(F&& f) {
+  try {
+    f();
+    return H2_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::invalid_argument& e) {
+    g_last_error = e.what();
+    return H2_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return H2_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return H2_ERR_HIP;
+  }
+}
+
+// Stream-ordered device array; borrow() makes it a non-owning view.
+template <typename T>
+class DevArray {
+ public:
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  DevArray& operator=(const DevArray&) = delete;
+  DevArray(DevArray&& o) noexcept { *this = std::move(o); }
+  DevArray& operator=(DevArray&& o) noexcept {
+    if (this != &o) {
+      release();
+      p_ = o.p_;
+      n_ = o.n_;
+      s_ = o.s_;
+      owned_ = o.owned_;
+      o.p_ = nullptr;
+      o.n_ = 0;
+    }
+    return *this;
+  }
+  ~DevArray() { release(); }
+
+  void alloc(size_t n, hipStream_t s) {
+    release();
+    s_ = s;
+    n_ = n;
+    owned_ = true;
+    if (n == 0) return;
+    void* p = nullptr;
+    H2_HIP(hipMallocAsync(&p, n * sizeof(T), s));
+    p_ = static_cast<T*>(p);
+  }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size(), s);
+    if (!h.empty()) H2_HIP(hipMemcpyAsync(p_, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void borrow(T* p, size_t n) {
+    release();
+    p_ = n ? p : nullptr;
+    n_ = n;
+    owned_ = false;
+  }
+  void release() {
+    if (p_ && owned_) (void)hipFreeAsync(p_, s_);
+    p_ = nullptr;
+    n_ = 0;
+  }
+  T* get() const { return p_; }
+  size_t size() const { return n_; }
+  size_t bytes() const { return n_ * sizeof(T); }
+
+ private:
+  T* p_ = nullptr;
+  size_t n_ = 0;
+  hipStream_t s_ = nullptr;
+  bool owned_ = true;
+};
+
+template <typename T>
+std::vector<T> download(const T* d, size_t n, hipStream_t s) {
+  std::vector<T> h(n);
+  if (n) {
+    H2_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+  }
+  return h;
+}
+
+template <typename T>
+std::vector<T> prefix(const std::vector<T>& sizes) {
+  std::vector<T> off(sizes.size() + 1, 0);
+  for (size_t i = 0; i < sizes.size(); ++i) off[i + 1] = off[i] + sizes[i];
+  return off;
+}
+
+// Phase timer on HIP events: record pairs, resolve after the stream is synchronised.
+class PhaseTimer {
+ public:
+  explicit PhaseTimer(hipStream_t s) : s_(s) {}
+  ~PhaseTimer() {
+    for (auto& r : recs_) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+  int begin(int phase) {
+    Rec r{phase, nullptr, nullptr};
+    H2_HIP(hipEventCreate(&r.a));
+    H2_HIP(hipEventCreate(&r.b));
+    H2_HIP(hipEventRecord(r.a, s_));
+    recs_.push_back(r);
+    return static_cast<int>(recs_.size()) - 1;
+  }
+  void end(int h) { H2_HIP(hipEventRecord(recs_[h].b, s_)); }
+  void totals(double* out, int nphase) {
+    H2_HIP(hipStreamSynchronize(s_));
+    for (int p = 0; p < nphase; ++p) out[p] = 0;
+    for (auto& r : recs_) {
+      float ms = 0;
+      H2_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      out[r.phase] += ms;
+    }
+  }
+
+ private:
+  struct Rec {
+    int phase;
+    hipEvent_t a, b;
+  };
+  hipStream_t s_;
+  std::vector<Rec> recs_;
+};
+
+enum Phase { kTree, kSample, kNearGen, kSubtract, kConv, kId, kUpsweep, kCoupling, kMisc, kNumPhase };
+
+// Per-depth results of the construction.  Rows of depth t live in row space
+// R_t (in-rows, `rowoff`) and the skeleton rows in R_{t-1} (`koff`).  Block
+// and basis storage is addressed through the offset arrays (joff, uoff, boff),
+// which may leave gaps (batched builds reserve capacity per cluster).
+struct Level {
+  int t = 0, nn = 0;
+  bool processed = false;
+  std::vector<int32_t> rowoff_h, k_h, koff_h;
+  std::vector<int64_t> joff_h, uoff_h;
+  int max_m = 0, max_k = 0;
+  DevArray<int32_t> rowoff, koff, J, pos_out;
+  DevArray<int64_t> joff, uoff;
+  DevArray<double> U, xs_out;
+  // far blocks at this depth
+  std::vector<int32_t> fptr_h, fidx_h;
+  std::vector<int64_t> boff_h;
+  DevArray<int32_t> fptr, fidx;
+  DevArray<int64_t> boff;
+  DevArray<double> B;
+  // sample buffers of row space R_t (capacity columns), only during a build
+  DevArray<double> om, y;
+  int64_t M = 0;
+};
+
+h2dev::KernelFn kernel_fn(const h2_kernel& k);
+void check_kernel(const h2_kernel* k);
+int top_depth(const h2::Plan& p);
+
+}  // namespace h2i
+
+struct h2_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t lds_limit = 65536;
+};
+
+struct h2_plan {
+  h2::Plan plan;
+};
+
+struct h2_matrix {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  h2::Plan plan;
+  h2_kernel kernel{};
+  h2_opts opts{};
+  int top = 1;
+  double delta = 0, nu = 0;
+  int samples = 0, sketched = 0, rounds = 0;
+  double host_plan_ms = 0;
+  h2i::DevArray<int32_t> perm;
+  h2i::DevArray<double> X;  // tree-ordered SoA points (single builds)
+  h2i::DevArray<int32_t> nptr, nidx, leafoff;
+  h2i::DevArray<int64_t> doff;
+  std::vector<int64_t> doff_h;
+  std::vector<int32_t> leafoff_h;
+  h2i::DevArray<double> Dblk;
+  std::vector<h2i::Level> lv;  // indexed by depth
+  double phase_ms[h2i::kNumPhase] = {};
+  double total_ms = 0;
+  double sketch_flops = 0, sketch_entries = 0;
+  std::shared_ptr<void> keep;  // storage shared with other matrices of a batched build
+};

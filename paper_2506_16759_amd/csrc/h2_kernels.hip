@@ -64,13 +64,14 @@ __device__ __forceinline__ void philox_block(uint64_t& c0, uint64_t& c1, uint64_
 }
 
 __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, int64_t nrows, const int32_t* __restrict__ rows,
-                                                       int64_t col0, int ncols, double* __restrict__ out,
-                                                       int64_t ldo) {
+                                                       int64_t col0, int ncols, double* __restrict__ out, int64_t ldo,
+                                                       const int32_t* __restrict__ rowprob,
+                                                       const uint64_t* __restrict__ seeds) {
   const int64_t total = nrows * ncols;
   for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
     const int64_t p = e % nrows, c = e / nrows;
     uint64_t c0 = static_cast<uint64_t>(rows ? rows[p] : p), c1 = static_cast<uint64_t>(col0 + c), c2 = 0, c3 = 0;
-    philox_block(c0, c1, c2, c3, seed, 0);
+    philox_block(c0, c1, c2, c3, rowprob ? seeds[rowprob[p]] : seed, 0);
     const double u1 = (static_cast<double>(c0 >> 11) + 0.5) * 0x1p-53;
     const double u2 = (static_cast<double>(c1 >> 11) + 0.5) * 0x1p-53;
     out[p + c * ldo] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
@@ -89,17 +90,25 @@ constexpr int kSkK = 64;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+template <int DIM, int NC>
+struct SkF64Smem {
+  double xs[DIM][kSkK];
+  double om[kSkK][NC + 2];
+};
+
+// Rows [tile0, tile0 + 128) of y = K omega for one point set of n points.
 template <int DIM, int KIND, int NC>
-__global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                         double c2, int ncr, const double* __restrict__ omega,
-                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+__device__ __forceinline__ void sketch_f64_body(SkF64Smem<DIM, NC>& sm, int64_t tile0, int64_t n,
+                                                const double* __restrict__ X, int64_t ldx, double c2, int ncr,
+                                                const double* __restrict__ omega, int64_t ldo,
+                                                double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  __shared__ double xs[DIM][kSkK];
-  __shared__ double om[kSkK][NC + 2];
+  auto& xs = sm.xs;
+  auto& om = sm.om;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
 
   double xa[DIM], xb[DIM];
@@ -163,6 +172,41 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double
   }
 }
 
+// One problem of a batched sketch: its n points start at global row `base`
+// of the shared (point, Omega, y) arrays.
+struct SketchJob {
+  int64_t n;
+  int64_t base;
+  double c2;
+  int kind;
+  int pad;
+};
+
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                         double c2, int ncr, const double* __restrict__ omega,
+                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  __shared__ SkF64Smem<DIM, NC> sm;
+  sketch_f64_body<DIM, KIND, NC>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+}
+
+// Batched: workgroup b handles row tile tiles[2b+1] of job tiles[2b] (3-D
+// coordinates; lower-dimensional point sets carry zero coordinates).
+template <int NC>
+__global__ __launch_bounds__(256) void sketch_f64_batched(const SketchJob* __restrict__ jobs,
+                                                          const int32_t* __restrict__ tiles,
+                                                          const double* __restrict__ X, int64_t ldx, int ncr,
+                                                          const double* __restrict__ omega, int64_t ldo,
+                                                          double* __restrict__ y, int64_t ldy) {
+  __shared__ SkF64Smem<3, NC> sm;
+  const SketchJob J = jobs[tiles[2 * blockIdx.x]];
+  const int64_t t0 = tiles[2 * blockIdx.x + 1];
+  if (J.kind == kExp)
+    sketch_f64_body<3, kExp, NC>(sm, t0, J.n, X + J.base, ldx, J.c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+  else
+    sketch_f64_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, J.c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+}
+
 // --------------------------------------------- mixed-precision sketches
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -185,16 +229,23 @@ constexpr int kFlush = 4;
 
 // FP32 entries, v_mfma_f32_16x16x4_f32.  Same tiling as the FP64 kernel:
 // lane l supplies A[l%16][l/16], B[l/16][l%16] and holds D[4*(l/16)+q][l%16].
+template <int DIM, int NC>
+struct SkF32Smem {
+  float xs[DIM][kSkK];
+  float om[kSkK][NC + 4];
+};
+
 template <int DIM, int KIND, int NC>
-__global__ __launch_bounds__(256) void sketch_f32_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                         float c2, int ncr, const double* __restrict__ omega,
-                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+__device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t tile0, int64_t n,
+                                                const double* __restrict__ X, int64_t ldx, float c2, int ncr,
+                                                const double* __restrict__ omega, int64_t ldo,
+                                                double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  __shared__ float xs[DIM][kSkK];
-  __shared__ float om[kSkK][NC + 4];
+  auto& xs = sm.xs;
+  auto& om = sm.om;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
   float xa[DIM], xb[DIM];
   {
@@ -273,6 +324,30 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(int64_t n, const double
   }
 }
 
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_f32_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                         float c2, int ncr, const double* __restrict__ omega,
+                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  __shared__ SkF32Smem<DIM, NC> sm;
+  sketch_f32_body<DIM, KIND, NC>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void sketch_f32_batched(const SketchJob* __restrict__ jobs,
+                                                          const int32_t* __restrict__ tiles,
+                                                          const double* __restrict__ X, int64_t ldx, int ncr,
+                                                          const double* __restrict__ omega, int64_t ldo,
+                                                          double* __restrict__ y, int64_t ldy) {
+  __shared__ SkF32Smem<3, NC> sm;
+  const SketchJob J = jobs[tiles[2 * blockIdx.x]];
+  const int64_t t0 = tiles[2 * blockIdx.x + 1];
+  const float c2 = float(J.c2);
+  if (J.kind == kExp)
+    sketch_f32_body<3, kExp, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+  else
+    sketch_f32_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+}
+
 // Split a float into bf16 hi (truncated) and bf16 lo = bf16(x - hi) (truncated):
 // hi*hi + hi*lo + lo*hi reproduces the FP32 product to about 2^-16 relative.
 __device__ __forceinline__ void split_bf16(float v, uint32_t& hi, uint32_t& lo) {
@@ -289,18 +364,28 @@ __device__ __forceinline__ void split_bf16(float v, uint32_t& hi, uint32_t& lo) 
 // points with one 16-byte LDS load.
 constexpr int kBfK = 64;  // points per stage (two MFMA k-steps of 32)
 
+constexpr int kBfLdp = kBfK / 2 + 4;  // dwords per staged column (2 bf16 per dword)
+
+template <int DIM, int NC>
+struct SkBfSmem {
+  float xs[DIM][kBfK];
+  uint32_t omh[NC * kBfLdp];
+  uint32_t oml[NC * kBfLdp];
+};
+
 template <int DIM, int KIND, int NC>
-__global__ __launch_bounds__(256) void sketch_bf16x3_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                            float c2, int ncr, const double* __restrict__ omega,
-                                                            int64_t ldo, double* __restrict__ y, int64_t ldy) {
+__device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_t tile0, int64_t n,
+                                                   const double* __restrict__ X, int64_t ldx, float c2, int ncr,
+                                                   const double* __restrict__ omega, int64_t ldo,
+                                                   double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  constexpr int LDP = kBfK / 2 + 4;  // dwords per staged column (2 bf16 per dword)
-  __shared__ float xs[DIM][kBfK];
-  __shared__ uint32_t omh[NC * LDP];
-  __shared__ uint32_t oml[NC * LDP];
+  constexpr int LDP = kBfLdp;
+  auto& xs = sm.xs;
+  auto& omh = sm.omh;
+  auto& oml = sm.oml;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = int64_t(blockIdx.x) * kSkRows + wave * 32;
+  const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
   float xa[DIM], xb[DIM];
   {
@@ -417,6 +502,30 @@ __global__ __launch_bounds__(256) void sketch_bf16x3_kernel(int64_t n, const dou
   }
 }
 
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_bf16x3_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                            float c2, int ncr, const double* __restrict__ omega,
+                                                            int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  __shared__ SkBfSmem<DIM, NC> sm;
+  sketch_bf16x3_body<DIM, KIND, NC>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void sketch_bf16x3_batched(const SketchJob* __restrict__ jobs,
+                                                             const int32_t* __restrict__ tiles,
+                                                             const double* __restrict__ X, int64_t ldx, int ncr,
+                                                             const double* __restrict__ omega, int64_t ldo,
+                                                             double* __restrict__ y, int64_t ldy) {
+  __shared__ SkBfSmem<3, NC> sm;
+  const SketchJob J = jobs[tiles[2 * blockIdx.x]];
+  const int64_t t0 = tiles[2 * blockIdx.x + 1];
+  const float c2 = float(J.c2);
+  if (J.kind == kExp)
+    sketch_bf16x3_body<3, kExp, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+  else
+    sketch_bf16x3_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+}
+
 template <int P, int DIM, int KIND, int NC>
 void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
                        const double* omega, int64_t ldo, double* y, int64_t ldy) {
@@ -495,6 +604,54 @@ __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restri
         r2 += d * d;
       }
       o[e] = kernel_of_r2<KIND>(r2, c2);
+      r += dr;
+      c += dc;
+      if (r >= m) {
+        r -= m;
+        ++c;
+      }
+    }
+  }
+}
+
+// Batched form: block row i belongs to problem rowprob[i] with its own kernel
+// kind and exponent scale (points carry 3 coordinates, unused ones zero).
+__global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* __restrict__ ptr,
+                                                                 const int32_t* __restrict__ idx,
+                                                                 const int32_t* __restrict__ rowoff,
+                                                                 const int64_t* __restrict__ blkoff,
+                                                                 const double* __restrict__ X, int64_t ldx,
+                                                                 const int32_t* __restrict__ rowprob,
+                                                                 const int32_t* __restrict__ kinds,
+                                                                 const double* __restrict__ c2s,
+                                                                 double* __restrict__ out) {
+  __shared__ double xr[3][kGenMax];
+  __shared__ double xc[3][kGenMax];
+  const int i = blockIdx.x, tid = threadIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  if (ptr[i] == ptr[i + 1] || m == 0) return;
+  const int pr = rowprob[i];
+  const int kind = kinds[pr];
+  const double c2 = c2s[pr];
+  for (int e = tid; e < 3 * m; e += 256) xr[e / m][e % m] = X[(e / m) * ldx + r0 + e % m];
+  const int dr = 256 % m, dc = 256 / m;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
+    const int b = idx[j];
+    const int c0 = rowoff[b], mb = rowoff[b + 1] - c0;
+    __syncthreads();
+    for (int e = tid; e < 3 * mb; e += 256) xc[e / mb][e % mb] = X[(e / mb) * ldx + c0 + e % mb];
+    __syncthreads();
+    if (mb == 0) continue;
+    double* o = out + blkoff[j];
+    int r = tid % m, c = tid / m;
+    for (int e = tid; e < m * mb; e += 256) {
+      double r2 = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double d = xr[a][r] - xc[a][c];
+        r2 += d * d;
+      }
+      o[e] = kind == kExp ? kernel_of_r2<kExp>(r2, c2) : kernel_of_r2<kGauss>(r2, c2);
       r += dr;
       c += dc;
       if (r >= m) {
@@ -701,6 +858,175 @@ __global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double*
   }
 }
 
+// Prefix form of the convergence test.  The leading R_ii of a Householder QR
+// do not depend on later columns, so one QR over all dsk sketched columns
+// gives, for each cluster, the first column count d' = d + j*inc (d = its
+// problem's current count) at which it is converged: m <= d' or
+// min_{i < d'} |R_ii| < delta.  The problem's count is raised to the largest
+// d' over its clusters (atomic max).  A cluster that is not converged at any
+// admissible d' <= dsk sets *exhausted.
+template <bool kLds>
+__global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy,
+                                     int dsk, const int32_t* __restrict__ incprob, const int32_t* __restrict__ nodeprob,
+                                     int32_t* __restrict__ dprob, const double* __restrict__ deltaprob,
+                                     int32_t* __restrict__ exhausted, double* __restrict__ gws,
+                                     const int64_t* __restrict__ gws_off) {
+  extern __shared__ double smem[];
+  __shared__ double s_tau, s_beta;
+  const int i = blockIdx.x;
+  const int pr = nodeprob[i];
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int dcur = dprob[pr];
+  const int inc = incprob[pr];
+  const double delta = deltaprob[pr];
+  // first admissible count with m <= d'
+  int dfirst = -1;
+  if (m <= dcur) dfirst = dcur;
+  else if (inc > 0 && dcur + ((m - dcur + inc - 1) / inc) * inc <= dsk) dfirst = dcur + ((m - dcur + inc - 1) / inc) * inc;
+  const int ncols = min(m, dsk);  // R_ii exists for i < min(m, dsk)
+  if (dfirst == dcur || ncols == 0) {
+    if (tid == 0) {
+      if (dfirst < 0) atomicOr(&exhausted[pr], 1);
+      else atomicMax(&dprob[pr], dfirst);
+    }
+    return;
+  }
+  const int ldp = m | 1;
+  double* P = kLds ? smem : gws + gws_off[i];
+  for (int e = tid; e < m * ncols; e += nt) {
+    const int r = e % m, c = e / m;
+    P[c * ldp + r] = Y[int64_t(c) * ldy + r0 + r];
+  }
+  __syncthreads();
+  double mn = INFINITY;
+  int found = -1;
+  for (int j = 0; j < ncols; ++j) {
+    double* pj = P + j * ldp;
+    if (tid < kWave) {
+      double sg = 0.0;
+      for (int r = j + 1 + tid; r < m; r += kWave) sg += pj[r] * pj[r];
+      sg = wave_sum(sg);
+      const double alpha = pj[j];
+      double beta, tau, scal;
+      if (sg == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+        scal = 0.0;
+      } else {
+        const double nrm = sqrt(alpha * alpha + sg);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+      for (int r = j + 1 + tid; r < m; r += kWave) pj[r] *= scal;
+      if (tid == 0) {
+        s_tau = tau;
+        s_beta = beta;
+      }
+    }
+    __syncthreads();
+    mn = fmin(mn, fabs(s_beta));
+    // column count j+1 is a candidate if it lies on the grid
+    const int dd = j + 1;
+    if (dd >= dcur && (dd - dcur) % inc == 0 && mn < delta) {
+      found = dd;
+      break;
+    }
+    if (dfirst > 0 && dd >= dfirst) break;  // m <= d' reached first
+    const double tau = s_tau;
+    for (int c = j + 1 + tid; c < ncols; c += nt) {
+      double* pc = P + c * ldp;
+      double w0 = pc[j], w1 = 0.0;
+      int r = j + 1;
+      for (; r + 1 < m; r += 2) {
+        w0 += pj[r] * pc[r];
+        w1 += pj[r + 1] * pc[r + 1];
+      }
+      if (r < m) w0 += pj[r] * pc[r];
+      const double w = (w0 + w1) * tau;
+      pc[j] -= w;
+      for (int rr = j + 1; rr < m; ++rr) pc[rr] -= w * pj[rr];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int d = found;
+    if (d < 0 || (dfirst > 0 && dfirst < d)) d = dfirst;
+    if (d < 0) atomicOr(&exhausted[pr], 1);
+    else atomicMax(&dprob[pr], d);
+  }
+}
+
+// Exclusive scan of n int32 -> out[0..n] (out[n] = total), one workgroup.
+__global__ __launch_bounds__(1024) void scan_kernel(int n, const int32_t* __restrict__ in, int32_t* __restrict__ out) {
+  __shared__ int32_t part[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + threadIdx.x;
+    const int v = i < n ? in[i] : 0;
+    part[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const int t = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+      __syncthreads();
+      part[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < n) out[i] = carry + part[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 0) carry += part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+// dst[i] = src[map[i]] for i <= n (n + 1 entries).
+__global__ __launch_bounds__(256) void gather_i32_kernel(int n, const int32_t* __restrict__ map,
+                                                         const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= n) dst[i] = src[map[i]];
+}
+
+// Per problem p (one workgroup each): nu = ||Y[base, n rows, d0 cols]||_F / sqrt(d0),
+// delta = tol * nu / sqrt(#leaves) (mode 0) or tol * nu (mode 1); d = d0.
+struct ThresholdJob {
+  int64_t base, n;
+  int32_t d0, nleaves, mode, pad;
+  double tol;
+};
+
+__global__ __launch_bounds__(256) void threshold_kernel(const ThresholdJob* __restrict__ jobs,
+                                                        const double* __restrict__ Y, int64_t ldy,
+                                                        double* __restrict__ nu, double* __restrict__ delta,
+                                                        int32_t* __restrict__ d) {
+  __shared__ double red[4];
+  const ThresholdJob J = jobs[blockIdx.x];
+  double acc = 0.0;
+  const int64_t total = J.n * J.d0;
+  for (int64_t e = threadIdx.x; e < total; e += 256) {
+    const double v = Y[(e / J.n) * ldy + J.base + e % J.n];
+    acc += v * v;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double ss = (red[0] + red[1]) + (red[2] + red[3]);
+    const double v = sqrt(ss) / sqrt(double(J.d0));
+    nu[blockIdx.x] = v;
+    delta[blockIdx.x] = J.mode == 0 ? J.tol * v / sqrt(double(J.nleaves)) : J.tol * v;
+    d[blockIdx.x] = J.d0;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ p, int64_t n, int32_t v) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x)
+    p[e] = v;
+}
+
 // ---------------------------------------------------------------- CPQR / ID
 
 // Column-pivoted Householder QR of A = Y_loc^T (d x m) held in the panel with
@@ -736,7 +1062,14 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
                                                       int64_t ldy, int d, double delta, int32_t* __restrict__ kout,
                                                       int32_t* __restrict__ Jout, const int64_t* __restrict__ joff,
                                                       double* __restrict__ Uout, const int64_t* __restrict__ uoff,
-                                                      double* __restrict__ gws, const int64_t* __restrict__ gws_off) {
+                                                      double* __restrict__ gws, const int64_t* __restrict__ gws_off,
+                                                      const int32_t* __restrict__ nodeprob,
+                                                      const int32_t* __restrict__ dprob,
+                                                      const double* __restrict__ deltaprob) {
+  if (nodeprob) {  // batched: the column count and threshold of the cluster's problem
+    d = dprob[nodeprob[blockIdx.x]];
+    delta = deltaprob[nodeprob[blockIdx.x]];
+  }
   extern __shared__ double smem[];
   __shared__ PivotCand s_best[4];
   __shared__ double s_tau, s_scal;
@@ -1003,9 +1336,14 @@ unsigned grid_for(int64_t work, int64_t per_block = 256, unsigned cap = 65536) {
   return static_cast<unsigned>(g);
 }
 
+// Dynamic LDS above 64 KB needs the per-kernel attribute; prepare_kernels()
+// sets it once for every kernel that can ask for it, so launches (including
+// those recorded into a graph) make no further runtime calls.
+size_t g_lds_prepared = 0;
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
+  if (bytes <= 65536 || bytes <= g_lds_prepared) return hipSuccess;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                              static_cast<int>(bytes));
 }
@@ -1017,7 +1355,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* rows, int64_t col0, int ncols,
                     double* out, int64_t ldo) {
   if (nrows <= 0 || ncols <= 0) return hipSuccess;
-  gaussian_kernel<<<grid_for(nrows * ncols), 256, 0, s>>>(seed, nrows, rows, col0, ncols, out, ldo);
+  gaussian_kernel<<<grid_for(nrows * ncols), 256, 0, s>>>(seed, nrows, rows, col0, ncols, out, ldo, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1129,7 +1467,8 @@ hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
 
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
                    double delta, int32_t* kout, int32_t* J, const int64_t* joff, double* U, const int64_t* uoff,
-                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off) {
+                   int max_m, size_t lds_limit, double* gws, const int64_t* gws_off, const int32_t* nodeprob,
+                   const int32_t* dprob, const double* deltaprob) {
   if (nnodes <= 0) return hipSuccess;
   const int threads = max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256);
   const size_t small = size_t(3) * max_m * sizeof(double);
@@ -1138,13 +1477,13 @@ hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
     hipError_t e = allow_lds(cpqr_id_kernel<true>, bytes);
     if (e != hipSuccess) return e;
     cpqr_id_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, delta, kout, J, joff, U, uoff, gws,
-                                                        gws_off);
+                                                        gws_off, nodeprob, dprob, deltaprob);
   } else {
     if (!gws || !gws_off) return hipErrorInvalidValue;
     hipError_t e = allow_lds(cpqr_id_kernel<false>, small);
     if (e != hipSuccess) return e;
     cpqr_id_kernel<false><<<nnodes, threads, small, s>>>(rowoff, Y, ldy, d, delta, kout, J, joff, U, uoff, gws,
-                                                         gws_off);
+                                                         gws_off, nodeprob, dprob, deltaprob);
   }
   return hipGetLastError();
 }
@@ -1191,6 +1530,147 @@ hipError_t fill_zero(hipStream_t s, double* p, int64_t n) {
   if (n <= 0) return hipSuccess;
   fill_zero_kernel<<<grid_for(n, 256, 8192), 256, 0, s>>>(p, n);
   return hipGetLastError();
+}
+
+hipError_t gaussian_batched(hipStream_t s, int64_t nrows, const int32_t* rows, const int32_t* rowprob,
+                            const uint64_t* seeds, int64_t col0, int ncols, double* out, int64_t ldo) {
+  if (nrows <= 0 || ncols <= 0) return hipSuccess;
+  gaussian_kernel<<<grid_for(nrows * ncols), 256, 0, s>>>(0, nrows, rows, col0, ncols, out, ldo, rowprob, seeds);
+  return hipGetLastError();
+}
+
+hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* jobs, const int32_t* tiles,
+                          const double* X, int64_t ldx, int ncols, const double* omega, int64_t ldo, double* y,
+                          int64_t ldy) {
+  if (ntiles <= 0 || ncols <= 0) return hipSuccess;
+  const SketchJob* J = static_cast<const SketchJob*>(jobs);
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
+    const double* om = omega + int64_t(c0) * ldo;
+    double* yy = y + int64_t(c0) * ldy;
+#define H2_SKB(K, NCT) K<NCT><<<ntiles, 256, 0, s>>>(J, tiles, X, ldx, nc, om, ldo, yy, ldy)
+#define H2_SKB_NC(K)               \
+  if (nc <= 16) H2_SKB(K, 16);      \
+  else if (nc <= 32) H2_SKB(K, 32); \
+  else if (nc <= 48) H2_SKB(K, 48); \
+  else H2_SKB(K, 64);
+    if (precision == 0) {
+      H2_SKB_NC(sketch_f64_batched)
+    } else if (precision == 1) {
+      H2_SKB_NC(sketch_f32_batched)
+    } else {
+      H2_SKB_NC(sketch_bf16x3_batched)
+    }
+#undef H2_SKB_NC
+#undef H2_SKB
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t sketch_job_bytes() { return sizeof(SketchJob); }
+size_t threshold_job_bytes() { return sizeof(ThresholdJob); }
+
+void pack_sketch_job(void* dst, int64_t n, int64_t base, int kind, double scale) {
+  SketchJob j{};
+  j.n = n;
+  j.base = base;
+  j.c2 = -scale * kLog2e;
+  j.kind = kind;
+  *static_cast<SketchJob*>(dst) = j;
+}
+
+void pack_threshold_job(void* dst, int64_t base, int64_t n, int d0, int nleaves, int mode, double tol) {
+  ThresholdJob j{};
+  j.base = base;
+  j.n = n;
+  j.d0 = d0;
+  j.nleaves = nleaves;
+  j.mode = mode;
+  j.tol = tol;
+  *static_cast<ThresholdJob*>(dst) = j;
+}
+
+hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                              const int64_t* blkoff, const double* X, int64_t ldx, const int32_t* rowprob,
+                              const int32_t* kinds, const double* c2s, double* out) {
+  if (nrows <= 0) return hipSuccess;
+  gen_blocks_batched_kernel<<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, rowprob, kinds, c2s, out);
+  return hipGetLastError();
+}
+
+hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int dsk,
+                         const int32_t* incprob, const int32_t* nodeprob, int32_t* dprob, const double* deltaprob,
+                         int32_t* exhausted, int max_m, size_t lds_limit, double* gws, const int64_t* gws_off) {
+  if (nnodes <= 0) return hipSuccess;
+  const int threads = dsk <= 64 ? 64 : (dsk <= 128 ? 128 : 256);
+  const size_t bytes = size_t(max_m | 1) * size_t(dsk) * sizeof(double);
+  if (bytes <= lds_limit) {
+    hipError_t e = allow_lds(qr_first_conv_kernel<true>, bytes);
+    if (e != hipSuccess) return e;
+    qr_first_conv_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, dsk, incprob, nodeprob, dprob,
+                                                              deltaprob, exhausted, gws, gws_off);
+  } else {
+    if (!gws || !gws_off) return hipErrorInvalidValue;
+    qr_first_conv_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, dsk, incprob, nodeprob, dprob,
+                                                           deltaprob, exhausted, gws, gws_off);
+  }
+  return hipGetLastError();
+}
+
+hipError_t scan_i32(hipStream_t s, int n, const int32_t* in, int32_t* out) {
+  scan_kernel<<<1, 1024, 0, s>>>(n, in, out);
+  return hipGetLastError();
+}
+
+hipError_t gather_i32(hipStream_t s, int n, const int32_t* map, const int32_t* src, int32_t* dst) {
+  gather_i32_kernel<<<(n + 256) / 256, 256, 0, s>>>(n, map, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t thresholds(hipStream_t s, int nprob, const void* jobs, const double* Y, int64_t ldy, double* nu,
+                      double* delta, int32_t* d) {
+  if (nprob <= 0) return hipSuccess;
+  threshold_kernel<<<nprob, 256, 0, s>>>(static_cast<const ThresholdJob*>(jobs), Y, ldy, nu, delta, d);
+  return hipGetLastError();
+}
+
+hipError_t fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
+  if (n <= 0) return hipSuccess;
+  fill_i32_kernel<<<grid_for(n, 256, 1024), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t prepare_kernels(size_t lds_limit) {
+  const int b = static_cast<int>(lds_limit);
+  auto set = [b](const void* f) {
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  };
+  const void* ks[] = {
+      reinterpret_cast<const void*>(qr_test_kernel<true>),
+      reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
+      reinterpret_cast<const void*>(cpqr_id_kernel<true>),
+      reinterpret_cast<const void*>(cpqr_id_kernel<false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true>),
+  };
+  for (const void* f : ks) {
+    const hipError_t e = set(f);
+    if (e != hipSuccess) return e;
+  }
+  g_lds_prepared = lds_limit;
+  return hipSuccess;
 }
 
 }  // namespace h2dev

@@ -113,3 +113,17 @@ def test_export_size_query_and_small_buffer():
     buf = (ctypes.c_int32 * 10)()
     assert lib.h2_plan_export(p._h, _lib.PART["PERM"], 0, buf, 40, ctypes.byref(need)) == -1
     assert lib.h2_plan_export(p._h, _lib.PART["FAR_PTR"], 99, None, 0, ctypes.byref(need)) == -1
+
+
+def test_batched_build_rejects_bad_arguments_before_any_device_work():
+    import ctypes as C
+
+    from paper_2506_16759_amd import _lib
+    lib = _lib.load()
+    handles = (C.c_void_p * 1)()
+    bo = _lib.BatchOpts(0, 64, 1)
+    prob = (_lib.Problem * 1)()
+    # NULL context
+    assert lib.h2_build_batched(None, 1, prob, C.byref(bo), handles, None) == -1
+    assert "NULL" in lib.h2_last_error().decode()
+    assert handles[0] is None
