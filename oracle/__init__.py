@@ -13,7 +13,10 @@ Plain, slow and meant to be checked by eye against the paper:
                                                              [Sec. II-B, Sec. III-B]
   kernels  -- covariance kernels and dense products          [Sec. V-A]
   build    -- Algorithm 1 with the adaptive sampling loop    [Alg. 1, Sec. III]
-  h2       -- the H^2 container, matvec, dense reconstruction, error measures
+  h2       -- the H^2 container, matvec (and transposed), dense reconstruction,
+              entries from the format's definition, error measures
+  update   -- two-sided construction of non-symmetric matrices and the H^2
+              low-rank update A = K_H + U V^T          [Sec. II-A, Sec. III, Sec. V]
 
 Every function cites the passage it follows.  Readings of points the paper
 leaves open are the ones listed in the design notes; each is restated where it
