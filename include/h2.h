@@ -145,7 +145,14 @@ typedef enum {
   H2_PART_DENSE = 12,    /* float64: D_{s,b} for the near pairs in CSR order, each
                             m_s x m_b column-major (rows/cols in tree order) */
   H2_PART_TOP = 13,      /* int32[1]: coarsest processed depth */
-  H2_PART_SKEL_POS = 14  /* int32[sum k]: skeleton tree positions, node by node */
+  H2_PART_SKEL_POS = 14, /* int32[sum k]: skeleton tree positions, node by node */
+  /* column side of a two-sided matrix (h2_build_update); for a symmetric
+     matrix these equal RANKS, SKEL, BASIS and SKEL_POS.  COUPLING blocks of a
+     two-sided matrix are k_s (row rank) x k_b (column rank). */
+  H2_PART_RANKS_C = 15,
+  H2_PART_SKEL_C = 16,
+  H2_PART_BASIS_C = 17,
+  H2_PART_SKEL_POS_C = 18
 } h2_part;
 
 /* Copies a part into host memory dst (dst_bytes large).  dst == NULL only
@@ -260,6 +267,29 @@ typedef struct {
  * Synchronous. */
 h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
                            h2_matrix** out, h2_batch_info* info);
+
+/* ------------------------------------------------------------ low-rank update */
+
+/* H^2 approximation of A = H + U V^T on the partition of H (same points,
+ * tree and lists), built with the two-sided form of Algorithm 1 and adaptive
+ * sampling: row bases from Y = A Omega, column bases from Z = A^T Omega'
+ * (Omega' keyed by seed + 1), one shared sample count d, delta from the row
+ * sketch.  The black box is the H^2 product of H plus U (V^T Omega) (Sec. V
+ * uses an existing H^2 matrix as the sampler); coupling entries at the new
+ * skeletons come from H's own format (the nested basis of H evaluated at the
+ * skeleton rows) plus U V^T.  The near blocks stay those of H plus the
+ * factors U_s V_b^T, which is exact; h2_export(DENSE) writes them out.
+ *   old:   a symmetric matrix from h2_build or h2_build_batched; its dense
+ *          blocks become shared with the result and live until both are freed.
+ *   U, V:  DEVICE n x rank (ld >= n), ORIGINAL point order, borrowed for the
+ *          call; 0 <= rank <= 128 (NULL allowed when rank = 0).
+ *   opts:  tol, d0, d_inc, d_max, seed, norm_mode and sketch_ahead are used;
+ *          leaf_size and eta are taken from old; precision must be H2_FP64
+ *          (else H2_ERR_UNSUPPORTED).
+ * The result is two-sided: h2_matvec applies A, the *_C parts export its
+ * column side.  Synchronous. */
+h2_status h2_build_update(h2_ctx* ctx, h2_matrix* old, int32_t rank, const double* U, int64_t ldu,
+                          const double* V, int64_t ldv, const h2_opts* opts, h2_matrix** out);
 
 #ifdef __cplusplus
 }

@@ -206,15 +206,17 @@ class H2Matrix:
         lr = np.searchsorted(leaf_begin, pr, side="right") - 1
         lc = np.searchsorted(leaf_begin, pc, side="right") - 1
         out = np.zeros((rows.size, cols.size))
-        near = {(s, int(b)) for s in range(1 << D)
-                for b in self.lists.near_idx[self.lists.near_ptr[s]:self.lists.near_ptr[s + 1]]}
-        far = {}
-        for t in range(1, D + 1):
-            fp, fi = self.lists.far_ptr[t], self.lists.far_idx[t]
-            for s in range(1 << t):
-                for j in range(fp[s], fp[s + 1]):
-                    far[(t, s, int(fi[j]))] = True
-        bases = {}
+        if getattr(self, "_blocks", None) is None:   # lookup tables, built once per matrix
+            near = {(s, int(b)) for s in range(1 << D)
+                    for b in self.lists.near_idx[self.lists.near_ptr[s]:self.lists.near_ptr[s + 1]]}
+            far = set()
+            for t in range(1, D + 1):
+                fp, fi = self.lists.far_ptr[t], self.lists.far_idx[t]
+                for s in range(1 << t):
+                    for j in range(fp[s], fp[s + 1]):
+                        far.add((t, s, int(fi[j])))
+            self._blocks = (near, far, {})
+        near, far, bases = self._blocks
 
         def basis_rows(t, s, pos, col):
             key = (t, s, col)

@@ -19,6 +19,7 @@ from . import _lib
 from ._lib import BF16X3, FP32, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
+           "build_update",
            "H2Matrix",
            "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "NORM_FRO_SCALED",
            "NORM_LITERAL"]
@@ -238,3 +239,30 @@ def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_g
                "h2_build_batched")
     mats = [H2Matrix(ctx, C.c_void_p(handles[i]), int(arr[i].n)) for i in range(len(problems))]
     return (mats, info.as_dict()) if return_info else mats
+
+
+def build_update(ctx: Context, old: H2Matrix, U=None, V=None, opts: _lib.Opts | None = None,
+                 **opt_over) -> H2Matrix:
+    """H^2 approximation of old + U V^T on old's partition (h2_build_update).
+
+    U, V: (n, r) arrays or tensors in original point order (None for r = 0).
+    Options as for build (leaf_size and eta come from old); seed keys Omega,
+    seed + 1 keys Omega'."""
+    torch = _torch()
+    o = opts if opts is not None else opts_default(**opt_over)
+    n = old.n
+    if U is None:
+        r, up, vp, keep = 0, None, None, ()
+    else:
+        Ut = torch.as_tensor(U).to(device="cuda", dtype=torch.float64)
+        Vt = torch.as_tensor(V).to(device="cuda", dtype=torch.float64)
+        if Ut.shape != Vt.shape or Ut.shape[0] != n:
+            raise ValueError("U and V must both be (n, r)")
+        r = Ut.shape[1]
+        Uc, Vc = Ut.T.contiguous(), Vt.T.contiguous()   # (r, n) C-order = column-major n x r
+        up, vp, keep = C.c_void_p(Uc.data_ptr()), C.c_void_p(Vc.data_ptr()), (Uc, Vc)
+    h = C.c_void_p()
+    _lib.check(_lib.load().h2_build_update(ctx._h, old._h, r, up, n, vp, n, C.byref(o), C.byref(h)),
+               "h2_build_update")
+    del keep
+    return H2Matrix(ctx, h, n)

@@ -16,10 +16,11 @@ FP64, FP32, BF16X3 = 0, 1, 2
 NORM_FRO_SCALED, NORM_LITERAL = 0, 1
 
 PART = dict(DEPTH=0, PERM=1, NODES=2, BOXES=3, NEAR_PTR=4, NEAR_IDX=5, FAR_PTR=6, FAR_IDX=7, RANKS=8,
-            SKEL=9, BASIS=10, COUPLING=11, DENSE=12, TOP=13, SKEL_POS=14)
+            SKEL=9, BASIS=10, COUPLING=11, DENSE=12, TOP=13, SKEL_POS=14, RANKS_C=15, SKEL_C=16, BASIS_C=17,
+            SKEL_POS_C=18)
 PART_DTYPE = dict(DEPTH="i4", PERM="i4", NODES="i4", BOXES="f8", NEAR_PTR="i4", NEAR_IDX="i4", FAR_PTR="i4",
                   FAR_IDX="i4", RANKS="i4", SKEL="i4", BASIS="f8", COUPLING="f8", DENSE="f8", TOP="i4",
-                  SKEL_POS="i4")
+                  SKEL_POS="i4", RANKS_C="i4", SKEL_C="i4", BASIS_C="f8", SKEL_POS_C="i4")
 
 
 class Opts(C.Structure):
@@ -88,6 +89,7 @@ _SIGS = {
     "h2_free": [_P],
     "h2_build_batched": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(_P),
                          C.POINTER(BatchInfo)],
+    "h2_build_update": [_P, _P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.POINTER(Opts), C.POINTER(_P)],
 }
 EXPORTED = tuple(_SIGS)
 

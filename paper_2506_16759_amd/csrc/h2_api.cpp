@@ -47,6 +47,58 @@ int top_depth(const h2::Plan& p) {
   return p.depth + 1;
 }
 
+void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt,
+                 int nc) {
+  const int64_t n = h.plan.n;
+  const int D = h.plan.depth;
+  const int nleaves = 1 << D;
+  if (nc <= 0) return;
+  if (nc > 64) throw Error(H2_ERR_ARG, "matvec_tree: at most 64 columns");
+  const std::vector<Level>& up = h.col_levels();  // column bases: x_hat = V^T x
+  const std::vector<Level>& dn = h.lv;            // row bases: y += U y_hat
+  if (h.top <= D) {
+    std::vector<DevArray<double>> xh(D + 1), yh(D + 1);
+    for (int t = h.top; t <= D; ++t) {
+      xh[t].alloc(size_t(up[t].koff_h.back()) * nc, s);
+      yh[t].alloc(size_t(dn[t].koff_h.back()) * nc, s);
+    }
+    for (int t = D; t >= h.top; --t) {  // upsweep
+      const Level& L = up[t];
+      const int64_t M = L.koff_h.back();
+      const double* src = t == D ? xt : xh[t + 1].get();
+      const int64_t lds = t == D ? ldxt : up[t + 1].koff_h.back();
+      H2_HIP(h2dev::shrink_up(s, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(),
+                              L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t].get(), M, nc));
+      H2_HIP(h2dev::fill_zero(s, yh[t].get(), dn[t].koff_h.back() * nc));
+    }
+    for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b
+      const Level& L = dn[t];
+      const Level& C = up[t];
+      H2_HIP(h2dev::bsr_gemm2(s, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), C.koff.get(), nullptr,
+                              L.boff.get(), L.B.get(), xh[t].get(), C.koff_h.back(), yh[t].get(), L.koff_h.back(), nc,
+                              1.0, std::max({L.max_k, C.max_k, 1})));
+    }
+    for (int t = h.top; t <= D; ++t) {  // downsweep
+      const Level& L = dn[t];
+      double* dst = t == D ? yt : yh[t + 1].get();
+      const int64_t ldd = t == D ? ldyt : dn[t + 1].koff_h.back();
+      H2_HIP(h2dev::expand(s, L.nn, L.rowoff.get(), L.koff.get(), L.U.get(), L.uoff.get(), yh[t].get(),
+                           L.koff_h.back(), dst, ldd, nc));
+    }
+  }
+  int leaf_max = 0;
+  for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
+  H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,
+                         ldxt, yt, ldyt, nc, 1.0, leaf_max));
+  if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b
+    DevArray<double> W;
+    W.alloc(size_t(nleaves) * h.lr_rank * nc, s);
+    H2_HIP(h2dev::lr_leaf_project(s, nleaves, h.leafoff.get(), h.lrV.get(), n, h.lr_rank, xt, ldxt, nc, W.get()));
+    H2_HIP(h2dev::lr_apply(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), n, h.lrU.get(), n, h.lr_rank,
+                           W.get(), nc, yt, ldyt, 1.0));
+  }
+}
+
 }  // namespace h2i
 
 namespace {
@@ -612,51 +664,15 @@ h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t nrhs, const double
     H2_REQUIRE(ldx >= n && ldy >= n, "ld < n");
     H2_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    const int D = h.plan.depth;
-    const int nleaves = 1 << D;
-    int leaf_max = 0;
-    for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
     const int chunk = 64;
     DevArray<double> xt, yt;
     xt.alloc(size_t(n) * chunk, s);
     yt.alloc(size_t(n) * chunk, s);
-    std::vector<DevArray<double>> xh(D + 1), yh(D + 1);  // per depth t: R_{t-1} rows
-    for (int t = h.top; t <= D; ++t) {
-      const int64_t M = h.lv[t].koff_h.back();
-      xh[t].alloc(size_t(M) * chunk, s);
-      yh[t].alloc(size_t(M) * chunk, s);
-    }
     for (int c0 = 0; c0 < nrhs; c0 += chunk) {
       const int nc = std::min(chunk, nrhs - c0);
       H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), false, x + int64_t(c0) * ldx, ldx, xt.get(), n, nc));
       H2_HIP(h2dev::fill_zero(s, yt.get(), n * nc));
-      if (h.top <= D) {
-        for (int t = D; t >= h.top; --t) {  // upsweep x_hat = U^T x, E^T x_hat
-          const Level& L = h.lv[t];
-          const int64_t M = L.koff_h.back();
-          const double* src = t == D ? xt.get() : xh[t + 1].get();
-          const int64_t lds = t == D ? n : h.lv[t + 1].koff_h.back();
-          H2_HIP(h2dev::shrink_up(s, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(),
-                                  L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t].get(), M, nc));
-          H2_HIP(h2dev::fill_zero(s, yh[t].get(), M * nc));
-        }
-        for (int t = h.top; t <= D; ++t) {  // coupling y_hat_s = sum B_{s,b} x_hat_b
-          const Level& L = h.lv[t];
-          const int64_t M = L.koff_h.back();
-          H2_HIP(h2dev::bsr_gemm(s, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), L.boff.get(), L.B.get(),
-                                 xh[t].get(), M, yh[t].get(), M, nc, 1.0, std::max(L.max_k, 1)));
-        }
-        for (int t = h.top; t <= D; ++t) {  // downsweep y_hat_child += E y_hat, y += U y_hat
-          const Level& L = h.lv[t];
-          const int64_t M = L.koff_h.back();
-          double* dst = t == D ? yt.get() : yh[t + 1].get();
-          const int64_t ldd = t == D ? n : h.lv[t + 1].koff_h.back();
-          H2_HIP(h2dev::expand(s, L.nn, L.rowoff.get(), L.koff.get(), L.U.get(), L.uoff.get(), yh[t].get(), M, dst,
-                               ldd, nc));
-        }
-      }
-      H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
-                             xt.get(), n, yt.get(), n, nc, 1.0, leaf_max));
+      matvec_tree(h, s, xt.get(), n, yt.get(), n, nc);
       H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), true, yt.get(), n, y + int64_t(c0) * ldy, ldy, nc));
     }
     // temporaries are released stream-ordered; inputs stay valid until the stream passes this point
@@ -679,11 +695,26 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
       return;
     }
     if (part == H2_PART_DENSE) {
-      copy_part(h.Dblk.get(), h.Dblk.bytes(), dst, dst_bytes, needed, true, s);
+      if (h.lr_rank == 0 || !dst) {
+        copy_part(h.Dblk.get(), h.Dblk.bytes(), dst, dst_bytes, needed, true, s);
+        return;
+      }
+      // an update keeps D_old and the factors of U V^T: write the blocks out
+      DevArray<double> tmp;
+      tmp.alloc(h.Dblk.size(), s);
+      H2_HIP(h2dev::dense_lowrank(s, 1 << p.depth, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(),
+                                  h.Dblk.get(), h.lrU.get(), p.n, h.lrV.get(), p.n, h.lr_rank, tmp.get()));
+      copy_part(tmp.get(), tmp.bytes(), dst, dst_bytes, needed, true, s);
       return;
     }
     H2_REQUIRE(depth >= 0 && depth <= p.depth, "depth out of range");
-    const Level& L = h.lv[depth];
+    const bool col = part >= H2_PART_RANKS_C && part <= H2_PART_SKEL_POS_C;
+    if (col) part = part == H2_PART_RANKS_C  ? H2_PART_RANKS
+                    : part == H2_PART_SKEL_C ? H2_PART_SKEL
+                    : part == H2_PART_BASIS_C ? H2_PART_BASIS
+                                              : H2_PART_SKEL_POS;
+    const Level& L = col ? h.col_levels()[depth] : h.lv[depth];
+    const Level& Lc = h.col_levels()[depth];
     const bool have = L.processed;
     switch (part) {
       case H2_PART_RANKS: {
@@ -742,7 +773,7 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
         std::vector<double> packed;
         for (int a = 0; a < L.nn; ++a)
           for (int j = L.fptr_h[a]; j < L.fptr_h[a + 1]; ++j) {
-            const int64_t sz = int64_t(L.k_h[a]) * L.k_h[L.fidx_h[j]];
+            const int64_t sz = int64_t(L.k_h[a]) * Lc.k_h[L.fidx_h[j]];
             packed.insert(packed.end(), all.begin() + L.boff_h[j], all.begin() + L.boff_h[j] + sz);
           }
         copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, s);
@@ -783,6 +814,15 @@ h2_status h2_query(const h2_matrix* hm, h2_info* info) {
       r.bytes_coupling += static_cast<int64_t>(L.B.bytes());
       r.bytes_basis += static_cast<int64_t>(L.U.bytes());
     }
+    for (const Level& L : h.lvc) {  // column side of a two-sided matrix
+      if (!L.processed) continue;
+      for (int k : L.k_h) {
+        r.rank_min = std::min(r.rank_min, k);
+        r.rank_max = std::max(r.rank_max, k);
+      }
+      r.bytes_basis += static_cast<int64_t>(L.U.bytes());
+    }
+    r.bytes_dense += static_cast<int64_t>(h.lrU.bytes() + h.lrV.bytes());
     if (r.rank_max == 0 && r.rank_min == (1 << 30)) r.rank_min = 0;
     r.t_total = h.total_ms;
     r.t_tree = h.phase_ms[kTree];

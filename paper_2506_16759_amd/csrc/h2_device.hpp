@@ -50,6 +50,15 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
                     int64_t ldy, int nc, double alpha, int max_m, int precision = 0);
 
+// Two-sided form: block row i has rows [rowoff[i], rowoff[i+1]) of Y, block
+// column b rows [coloff[b], coloff[b+1]) of X; with tpos != nullptr the block of
+// entry j is the transpose of stored block tpos[j] (which is stored
+// (coloff height) x (rowoff height), column-major).  max_m bounds both heights.
+hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                     const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
+                     int precision = 0);
+
 // Adaptive convergence test (Sec. III-B): per cluster, unpivoted Householder QR of its samples
 // Y[rowoff[i]..rowoff[i+1]) x [0,d); conv[i] = 1 if m <= d or min |R_jj| < delta.
 // minr[i] receives the smallest |R_jj| seen (0 when m <= d).  *unconverged counts clusters
@@ -70,7 +79,7 @@ hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
 
 // Shrink and upsweep (Alg. 1 batchedShrink + batchedGemm) on nc columns:
 //   Yout[koff[i] + r, :] = Yloc[rowoff[i] + J[r], :]           (skipped when Yloc == nullptr)
-//   Wout[koff[i] + r, :] = sum_q U[q, r] Win[rowoff[i] + q, :]
+//   Wout[koff[i] + r, :] = sum_q U[q, r] Win[rowoff[i] + q, :]    (skipped when Win == nullptr)
 hipError_t shrink_up(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
                      const int64_t* joff, const double* U, const int64_t* uoff, const double* Yloc, int64_t ldyl,
                      const double* Win, int64_t ldwi, double* Yout, int64_t ldyo, double* Wout, int64_t ldwo,
@@ -143,5 +152,39 @@ size_t threshold_job_bytes();
 void pack_threshold_job(void* dst, int64_t base, int64_t n, int d0, int nleaves, int mode, double tol);
 hipError_t thresholds(hipStream_t s, int nprob, const void* jobs, const double* Y, int64_t ldy, double* nu,
                       double* delta, int32_t* d);
+
+// ------------------------------------------------------- low-rank update
+// A = H + U V^T with U, V (n x r, column-major, tree order).
+
+// W_b = V(leaf b rows, :)^T X(leaf b rows, :) for every leaf b: r x nc blocks,
+// column-major with ld r, block b at W + b*r*nc.
+hipError_t lr_leaf_project(hipStream_t s, int nleaves, const int32_t* leafoff, const double* V, int64_t ldv, int r,
+                           const double* X, int64_t ldx, int nc, double* W);
+// out (len) = sum_b W_b in a fixed order; partial holds lr_sum_scratch doubles.
+size_t lr_sum_scratch(int nleaves, int len);
+hipError_t lr_sum(hipStream_t s, int nleaves, int len, const double* W, double* partial, double* out);
+// Y(leaf s rows, :) += alpha U(leaf s rows, :) sum_{b in ptr/idx row s} W_b   (ptr != nullptr), or
+// Y(0..n, :) += alpha U W                                                 (ptr == nullptr).
+// Requires r * nc <= 8192.
+hipError_t lr_apply(hipStream_t s, int nleaves, const int32_t* ptr, const int32_t* idx, const int32_t* leafoff,
+                    int64_t n, const double* U, int64_t ldu, int r, const double* W, int nc, double* Y, int64_t ldy,
+                    double alpha);
+// Rows of the old nested basis at the new skeletons (see the kernel's comment).
+hipError_t basis_rows(hipStream_t s, int nnodes, bool leaf, const int32_t* koff, const int32_t* J,
+                      const int64_t* joff, const int32_t* kold_off, const int32_t* kold_child_off,
+                      const int32_t* leafoff, const double* Uold, const int64_t* uoff_old, const int32_t* koff_child,
+                      const double* Rc, int64_t ldrc, double* R, int64_t ldr);
+// B_new(s, b) = R_r_s B_old(s, b) R_c_b^T + U(pos_r of s) V(pos_c of b)^T over a far list.
+// Old ranks must be <= 128.
+hipError_t coupling_update(hipStream_t s, int nnodes, const int32_t* fptr, const int32_t* fidx,
+                           const int32_t* koff_r, const int32_t* koff_c, const int32_t* kold_off, int max_kold,
+                           const double* Bold, const int64_t* boff_old, const double* Rr, int64_t ldrr,
+                           const double* Rc, int64_t ldrc, const int32_t* pos_r, const int32_t* pos_c,
+                           const double* U, int64_t ldu, const double* V, int64_t ldv, int r, double* Bnew,
+                           const int64_t* boff_new);
+// out_j = D_j + U(rows s) V(rows b)^T for the near blocks (explicit dense blocks of an update).
+hipError_t dense_lowrank(hipStream_t s, int nleaves, const int32_t* ptr, const int32_t* idx,
+                         const int32_t* leafoff, const int64_t* blkoff, const double* Din, const double* U,
+                         int64_t ldu, const double* V, int64_t ldv, int r, double* out);
 
 }  // namespace h2dev

@@ -204,6 +204,14 @@ int top_depth(const h2::Plan& p);
 
 }  // namespace h2i
 
+struct h2_matrix;
+namespace h2i {
+// yt += A xt for nc <= 64 columns, both in TREE order (ld >= n): the standard
+// H^2 product (upsweep through the column bases, couplings, downsweep through
+// the row bases) plus the near field.  Stream-ordered on s.
+void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt, int nc);
+}  // namespace h2i
+
 struct h2_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -235,5 +243,14 @@ struct h2_matrix {
   double phase_ms[h2i::kNumPhase] = {};
   double total_ms = 0;
   double sketch_flops = 0, sketch_entries = 0;
-  std::shared_ptr<void> keep;  // storage shared with other matrices of a batched build
+  std::shared_ptr<void> keep;    // storage shared with other matrices of a batched build
+  std::shared_ptr<void> keep_d;  // owner of Dblk when it is shared with an update
+  // Two-sided matrices (low-rank updates): column-side levels, empty when the
+  // matrix is symmetric (column bases = row bases).
+  std::vector<h2i::Level> lvc;
+  // Near blocks of an update are Dblk + U_s V_b^T: factors n x lr_rank, tree order.
+  int lr_rank = 0;
+  h2i::DevArray<double> lrU, lrV;
+  bool two_sided() const { return !lvc.empty(); }
+  const std::vector<h2i::Level>& col_levels() const { return lvc.empty() ? lv : lvc; }
 };

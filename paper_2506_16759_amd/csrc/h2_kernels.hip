@@ -670,9 +670,11 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 // block are staged in LDS ([q][c], shared by the 4 waves); the blocks stream
 // from HBM straight into the MFMA A operand (lane l reads row l%16 of column
 // l/16 of a 16x4 slice: four 128-byte runs per load).
-template <int NB, int RT, bool F32>
+template <int NB, int RT, bool F32, bool TR>
 __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rowoff,
+                                                       const int32_t* __restrict__ coloff,
+                                                       const int64_t* __restrict__ tpos,
                                                        const int64_t* __restrict__ blkoff,
                                                        const double* __restrict__ blocks, const double* __restrict__ X,
                                                        int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
@@ -693,10 +695,13 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
+  // Two-sided use: block columns index the row space `coloff`, and with TR
+  // the block of entry j is the transpose of the stored block tpos[j]
+  // (stored mb x m, column-major).
   for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
     const int b = idx[j];
-    const int q0b = rowoff[b], mb = rowoff[b + 1] - q0b, mb4 = (mb + 3) & ~3;
-    const double* blk = blocks + blkoff[j];
+    const int q0b = coloff[b], mb = coloff[b + 1] - q0b, mb4 = (mb + 3) & ~3;
+    const double* blk = blocks + blkoff[TR ? tpos[j] : j];
     __syncthreads();
     for (int q = lane; q < mb4; q += 64)
       for (int c = wave; c < LDB; c += 4) {
@@ -720,7 +725,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int row = (wave + 4 * t) * 16 + li;
-          a[t] = (row < m && q < mb) ? float(blk[int64_t(q) * m + row]) : 0.0f;
+          a[t] = (row < m && q < mb) ? float(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0f;
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -745,7 +750,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int row = (wave + 4 * t) * 16 + li;
-          a[t] = (row < m && q < mb) ? blk[int64_t(q) * m + row] : 0.0;
+          a[t] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -1247,6 +1252,7 @@ __global__ __launch_bounds__(256) void shrink_up_kernel(const int32_t* __restric
   for (int e = threadIdx.x; e < k * nc; e += blockDim.x) {
     const int r = e % k, c = e / k;
     if (Yloc) Yout[int64_t(c) * ldyo + k0 + r] = Yloc[int64_t(c) * ldyl + r0 + Ji[r]];
+    if (!Win) continue;
     const double* u = Ui + int64_t(r) * m;
     const double* w = Win + int64_t(c) * ldwi + r0;
     double s0 = 0.0, s1 = 0.0;
@@ -1329,6 +1335,209 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(double* __restrict__ p, 
     p[e] = 0.0;
 }
 
+// ------------------------------------------------ low-rank update A = H + U V^T
+// The update keeps the dense leaf blocks of H and adds the low-rank term
+// U_s V_b^T of each near pair through these factored products; all row
+// indices are tree positions.
+
+// W_b (r x nc, column-major, ld r, at b*r*nc) = V(leaf b rows, :)^T X(leaf b rows, :).
+__global__ __launch_bounds__(256) void lr_leaf_project_kernel(const int32_t* __restrict__ leafoff,
+                                                              const double* __restrict__ V, int64_t ldv, int r,
+                                                              const double* __restrict__ X, int64_t ldx, int nc,
+                                                              double* __restrict__ W) {
+  const int b = blockIdx.x;
+  const int r0 = leafoff[b], m = leafoff[b + 1] - r0;
+  double* Wb = W + int64_t(b) * r * nc;
+  for (int e = threadIdx.x; e < r * nc; e += blockDim.x) {
+    const int q = e % r, c = e / r;
+    const double* v = V + int64_t(q) * ldv + r0;
+    const double* x = X + int64_t(c) * ldx + r0;
+    double s0 = 0.0, s1 = 0.0;
+    int p = 0;
+    for (; p + 1 < m; p += 2) {
+      s0 += v[p] * x[p];
+      s1 += v[p + 1] * x[p + 1];
+    }
+    if (p < m) s0 += v[p] * x[p];
+    Wb[e] = s0 + s1;
+  }
+}
+
+// partial[g][e] = sum of W_b[e] over the 64 leaves b of group g (fixed order).
+__global__ __launch_bounds__(256) void lr_sum_partial_kernel(int nleaves, int len, const double* __restrict__ W,
+                                                             double* __restrict__ partial) {
+  const int g = blockIdx.y;
+  const int b0 = g * 64, b1 = min(nleaves, b0 + 64);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) acc += W[int64_t(b) * len + e];
+    partial[int64_t(g) * len + e] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void lr_sum_final_kernel(int ngroups, int len, const double* __restrict__ partial,
+                                                           double* __restrict__ out) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < len; e += gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int g = 0; g < ngroups; ++g) acc += partial[int64_t(g) * len + e];
+    out[e] = acc;
+  }
+}
+
+// Near-field low-rank term: Y(leaf s rows, :) += alpha U(leaf s rows, :) sum_{b in N_s} W_b.
+// Global form (ptr == nullptr): Y(all n rows) += alpha U W_0, rows split over workgroups.
+__global__ __launch_bounds__(256) void lr_apply_kernel(const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ leafoff, int64_t n,
+                                                       const double* __restrict__ U, int64_t ldu, int r,
+                                                       const double* __restrict__ W, int nc, double* __restrict__ Y,
+                                                       int64_t ldy, double alpha) {
+  extern __shared__ double S[];  // r x nc
+  const int len = r * nc;
+  int64_t r0, m;
+  if (ptr) {
+    const int s = blockIdx.x;
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+      double acc = 0.0;
+      for (int j = ptr[s]; j < ptr[s + 1]; ++j) acc += W[int64_t(idx[j]) * len + e];
+      S[e] = acc;
+    }
+    r0 = leafoff[s];
+    m = leafoff[s + 1] - r0;
+  } else {
+    for (int e = threadIdx.x; e < len; e += blockDim.x) S[e] = W[e];
+    r0 = int64_t(blockIdx.x) * 256;
+    m = min(int64_t(256), n - r0);
+  }
+  __syncthreads();
+  for (int64_t e = threadIdx.x; e < m * nc; e += blockDim.x) {
+    const int64_t row = e % m;
+    const int c = static_cast<int>(e / m);
+    double acc = 0.0;
+    for (int q = 0; q < r; ++q) acc += U[int64_t(q) * ldu + r0 + row] * S[q + c * r];
+    Y[int64_t(c) * ldy + r0 + row] += alpha * acc;
+  }
+}
+
+// Rows of the old nested basis at the new skeletons (basis-row extraction):
+//   R_i = U_old_i(J_i, :)                                   at the leaves,
+//   R_i(a, :) = R_nu(jj, :) U_old_i(off_nu + (0..ko_nu-1), :)   at inner clusters,
+// where the in-row J_i[a] of the new ID lies in child nu at its row jj, and
+// off_nu is the first row of nu's block in the old transfer matrix
+// [E_nu1; E_nu2].  R_i has k_i rows at koff[i] (ld ldr) and ko_i columns.
+__global__ __launch_bounds__(256) void basis_rows_kernel(int leaf, const int32_t* __restrict__ koff,
+                                                         const int32_t* __restrict__ J,
+                                                         const int64_t* __restrict__ joff,
+                                                         const int32_t* __restrict__ kold_off,
+                                                         const int32_t* __restrict__ kold_child_off,
+                                                         const int32_t* __restrict__ leafoff,
+                                                         const double* __restrict__ Uold,
+                                                         const int64_t* __restrict__ uoff_old,
+                                                         const int32_t* __restrict__ koff_child,
+                                                         const double* __restrict__ Rc, int64_t ldrc,
+                                                         double* __restrict__ R, int64_t ldr) {
+  const int i = blockIdx.x;
+  const int k0 = koff[i], k = koff[i + 1] - k0;
+  const int ko = kold_off[i + 1] - kold_off[i];
+  const int* Ji = J + joff[i];
+  const double* Ui = Uold + uoff_old[i];
+  if (leaf) {
+    const int m = leafoff[i + 1] - leafoff[i];
+    for (int e = threadIdx.x; e < k * ko; e += blockDim.x) {
+      const int a = e % k, c = e / k;
+      R[int64_t(c) * ldr + k0 + a] = Ui[int64_t(c) * m + Ji[a]];
+    }
+    return;
+  }
+  const int c1 = 2 * i, c2 = 2 * i + 1;
+  const int kn1 = koff_child[c2] - koff_child[c1];
+  const int ko1 = kold_child_off[c2] - kold_child_off[c1];
+  const int ko2 = kold_child_off[c2 + 1] - kold_child_off[c2];
+  const int mo = ko1 + ko2;
+  for (int e = threadIdx.x; e < k * ko; e += blockDim.x) {
+    const int a = e % k, c = e / k;
+    const int row = Ji[a];
+    const bool first = row < kn1;
+    const int nu = first ? c1 : c2, jj = first ? row : row - kn1, off = first ? 0 : ko1, kon = first ? ko1 : ko2;
+    const double* rc = Rc + koff_child[nu] + jj;
+    const double* u = Ui + int64_t(c) * mo + off;
+    double acc = 0.0;
+    for (int q = 0; q < kon; ++q) acc += rc[int64_t(q) * ldrc] * u[q];
+    R[int64_t(c) * ldr + k0 + a] = acc;
+  }
+}
+
+// Coupling of the update at an admissible pair (s, b):
+//   B_new = R_r_s B_old(s, b) R_c_b^T + U(skel_r_s, :) V(skel_c_b, :)^T
+// (k_r_s x k_c_b, column-major at boff_new[j]).  One workgroup per block row;
+// B_old R_c_b^T is formed 32 columns at a time in LDS.
+constexpr int kCuCols = 32;
+constexpr int kCuMaxK = 128;
+__global__ __launch_bounds__(256) void coupling_update_kernel(
+    const int32_t* __restrict__ fptr, const int32_t* __restrict__ fidx, const int32_t* __restrict__ koff_r,
+    const int32_t* __restrict__ koff_c, const int32_t* __restrict__ kold_off, const double* __restrict__ Bold,
+    const int64_t* __restrict__ boff_old, const double* __restrict__ Rr, int64_t ldrr,
+    const double* __restrict__ Rc, int64_t ldrc, const int32_t* __restrict__ pos_r,
+    const int32_t* __restrict__ pos_c, const double* __restrict__ U, int64_t ldu, const double* __restrict__ V,
+    int64_t ldv, int r, double* __restrict__ Bnew, const int64_t* __restrict__ boff_new) {
+  __shared__ double T[kCuMaxK * kCuCols];
+  const int s = blockIdx.x;
+  const int kr0 = koff_r[s], kr = koff_r[s + 1] - kr0;
+  const int kos = kold_off[s + 1] - kold_off[s];
+  for (int j = fptr[s]; j < fptr[s + 1]; ++j) {
+    const int b = fidx[j];
+    const int kc0 = koff_c[b], kc = koff_c[b + 1] - kc0;
+    const int kob = kold_off[b + 1] - kold_off[b];
+    const double* bo = Bold + boff_old[j];
+    double* out = Bnew + boff_new[j];
+    for (int c0 = 0; c0 < kc; c0 += kCuCols) {
+      const int w = min(kCuCols, kc - c0);
+      __syncthreads();
+      for (int e = threadIdx.x; e < kos * w; e += blockDim.x) {
+        const int p = e % kos, cc = e / kos;
+        const double* rc = Rc + kc0 + c0 + cc;
+        double acc = 0.0;
+        for (int q = 0; q < kob; ++q) acc += bo[int64_t(q) * kos + p] * rc[int64_t(q) * ldrc];
+        T[cc * kCuMaxK + p] = acc;
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < kr * w; e += blockDim.x) {
+        const int a = e % kr, cc = e / kr;
+        const double* rr = Rr + kr0 + a;
+        double acc = 0.0;
+        for (int p = 0; p < kos; ++p) acc += rr[int64_t(p) * ldrr] * T[cc * kCuMaxK + p];
+        const int64_t pr = pos_r[kr0 + a], pc = pos_c[kc0 + c0 + cc];
+        double lr = 0.0;
+        for (int q = 0; q < r; ++q) lr += U[int64_t(q) * ldu + pr] * V[int64_t(q) * ldv + pc];
+        out[int64_t(c0 + cc) * kr + a] = acc + lr;
+      }
+    }
+  }
+}
+
+// Dense blocks of the update, written out: out_j = D_j + U(rows s, :) V(rows b, :)^T.
+__global__ __launch_bounds__(256) void dense_lowrank_kernel(const int32_t* __restrict__ ptr,
+                                                            const int32_t* __restrict__ idx,
+                                                            const int32_t* __restrict__ leafoff,
+                                                            const int64_t* __restrict__ blkoff,
+                                                            const double* __restrict__ Din,
+                                                            const double* __restrict__ U, int64_t ldu,
+                                                            const double* __restrict__ V, int64_t ldv, int r,
+                                                            double* __restrict__ out) {
+  const int s = blockIdx.x;
+  const int r0 = leafoff[s], m = leafoff[s + 1] - r0;
+  for (int j = ptr[s]; j < ptr[s + 1]; ++j) {
+    const int b = idx[j];
+    const int q0 = leafoff[b], mb = leafoff[b + 1] - q0;
+    for (int e = threadIdx.x; e < m * mb; e += blockDim.x) {
+      const int row = e % m, c = e / m;
+      double lr = 0.0;
+      for (int q = 0; q < r; ++q) lr += U[int64_t(q) * ldu + r0 + row] * V[int64_t(q) * ldv + q0 + c];
+      out[blkoff[j] + e] = Din[blkoff[j] + e] + lr;
+    }
+  }
+}
+
 unsigned grid_for(int64_t work, int64_t per_block = 256, unsigned cap = 65536) {
   int64_t g = (work + per_block - 1) / per_block;
   if (g < 1) g = 1;
@@ -1399,52 +1608,71 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
   return hipGetLastError();
 }
 
-template <int NB, bool F32>
+template <int NB, bool F32, bool TR>
 hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
-                         const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                         int64_t ldy, int nc, double alpha, int max_m) {
+                         const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                         const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
   const size_t lds = size_t((max_m + 3) & ~3) * NB * 16 * sizeof(double);
   hipError_t e = hipSuccess;
+#define H2_BSR_RT(RT)                                                                                    \
+  if ((e = allow_lds(bsr_gemm_kernel<NB, RT, F32, TR>, lds)) != hipSuccess) return e;                    \
+  bsr_gemm_kernel<NB, RT, F32, TR><<<grid, 256, lds, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, \
+                                                          ldx, Y, ldy, nc, alpha)
   if (max_m <= 64) {
-    if ((e = allow_lds(bsr_gemm_kernel<NB, 1, F32>, lds)) != hipSuccess) return e;
-    bsr_gemm_kernel<NB, 1, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+    H2_BSR_RT(1);
   } else if (max_m <= 128) {
-    if ((e = allow_lds(bsr_gemm_kernel<NB, 2, F32>, lds)) != hipSuccess) return e;
-    bsr_gemm_kernel<NB, 2, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+    H2_BSR_RT(2);
   } else if (max_m <= 256) {
-    if ((e = allow_lds(bsr_gemm_kernel<NB, 4, F32>, lds)) != hipSuccess) return e;
-    bsr_gemm_kernel<NB, 4, F32><<<grid, 256, lds, s>>>(ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha);
+    H2_BSR_RT(4);
   } else {
     return hipErrorInvalidValue;
   }
+#undef H2_BSR_RT
   return hipGetLastError();
 }
 
 template <bool F32>
 hipError_t bsr_gemm_p(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
-                      const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                      int64_t ldy, int nc, double alpha, int max_m) {
+                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   // at most 64 columns per workgroup, and at most 64 KB of staged X
   int nb = (nc + 15) / 16;
   if (nb > 4) nb = 4;
   while (nb > 1 && size_t((max_m + 3) & ~3) * nb * 16 * sizeof(double) > 65536) --nb;
+#define H2_BSR_NB(NB)                                                                                         \
+  (tpos ? launch_bsr_nb<NB, false, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy,   \
+                                         nc, alpha, max_m)                                                          \
+        : launch_bsr_nb<NB, F32, false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, \
+                                        alpha, max_m))
   switch (nb) {
-    case 1: return launch_bsr_nb<1, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
-    case 2: return launch_bsr_nb<2, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
-    case 3: return launch_bsr_nb<3, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
-    default:
-      return launch_bsr_nb<4, F32>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+    case 1: return H2_BSR_NB(1);
+    case 2: return H2_BSR_NB(2);
+    case 3: return H2_BSR_NB(3);
+    default: return H2_BSR_NB(4);
   }
+#undef H2_BSR_NB
+}
+
+hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                     const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
+                     int precision) {
+  if (nrows <= 0 || nc <= 0) return hipSuccess;
+  if (max_m < 1) max_m = 1;
+  if (precision == 0)
+    return bsr_gemm_p<false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha,
+                             max_m);
+  if (tpos) return hipErrorInvalidValue;  // transposed blocks: FP64 only
+  return bsr_gemm_p<true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha,
+                          max_m);
 }
 
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
                     int64_t ldy, int nc, double alpha, int max_m, int precision) {
-  if (nrows <= 0 || nc <= 0) return hipSuccess;
-  if (max_m < 1) max_m = 1;
-  if (precision == 0) return bsr_gemm_p<false>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
-  return bsr_gemm_p<true>(s, nrows, ptr, idx, rowoff, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+  return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m,
+                   precision);
 }
 
 hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
@@ -1652,18 +1880,24 @@ hipError_t prepare_kernels(size_t lds_limit) {
       reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true, false>),
   };
   for (const void* f : ks) {
     const hipError_t e = set(f);
@@ -1671,6 +1905,70 @@ hipError_t prepare_kernels(size_t lds_limit) {
   }
   g_lds_prepared = lds_limit;
   return hipSuccess;
+}
+
+// ------------------------------------------------ low-rank update launchers
+
+hipError_t lr_leaf_project(hipStream_t s, int nleaves, const int32_t* leafoff, const double* V, int64_t ldv, int r,
+                           const double* X, int64_t ldx, int nc, double* W) {
+  if (nleaves <= 0 || r <= 0 || nc <= 0) return hipSuccess;
+  lr_leaf_project_kernel<<<nleaves, 256, 0, s>>>(leafoff, V, ldv, r, X, ldx, nc, W);
+  return hipGetLastError();
+}
+
+size_t lr_sum_scratch(int nleaves, int len) { return size_t((nleaves + 63) / 64) * size_t(len); }
+
+hipError_t lr_sum(hipStream_t s, int nleaves, int len, const double* W, double* partial, double* out) {
+  if (len <= 0) return hipSuccess;
+  const int ng = (nleaves + 63) / 64;
+  if (ng == 0) return fill_zero(s, out, len);
+  const dim3 grid(grid_for(len, 256, 64), ng);
+  lr_sum_partial_kernel<<<grid, 256, 0, s>>>(nleaves, len, W, partial);
+  lr_sum_final_kernel<<<grid_for(len, 256, 64), 256, 0, s>>>(ng, len, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t lr_apply(hipStream_t s, int nleaves, const int32_t* ptr, const int32_t* idx, const int32_t* leafoff,
+                    int64_t n, const double* U, int64_t ldu, int r, const double* W, int nc, double* Y, int64_t ldy,
+                    double alpha) {
+  if (r <= 0 || nc <= 0) return hipSuccess;
+  const size_t lds = size_t(r) * nc * sizeof(double);
+  if (lds > 65536) return hipErrorInvalidValue;
+  const unsigned grid = ptr ? static_cast<unsigned>(nleaves) : static_cast<unsigned>((n + 255) / 256);
+  if (grid == 0) return hipSuccess;
+  lr_apply_kernel<<<grid, 256, lds, s>>>(ptr, idx, leafoff, n, U, ldu, r, W, nc, Y, ldy, alpha);
+  return hipGetLastError();
+}
+
+hipError_t basis_rows(hipStream_t s, int nnodes, bool leaf, const int32_t* koff, const int32_t* J,
+                      const int64_t* joff, const int32_t* kold_off, const int32_t* kold_child_off,
+                      const int32_t* leafoff, const double* Uold, const int64_t* uoff_old, const int32_t* koff_child,
+                      const double* Rc, int64_t ldrc, double* R, int64_t ldr) {
+  if (nnodes <= 0) return hipSuccess;
+  basis_rows_kernel<<<nnodes, 256, 0, s>>>(leaf ? 1 : 0, koff, J, joff, kold_off, kold_child_off, leafoff, Uold,
+                                           uoff_old, koff_child, Rc, ldrc, R, ldr);
+  return hipGetLastError();
+}
+
+hipError_t coupling_update(hipStream_t s, int nnodes, const int32_t* fptr, const int32_t* fidx,
+                           const int32_t* koff_r, const int32_t* koff_c, const int32_t* kold_off, int max_kold,
+                           const double* Bold, const int64_t* boff_old, const double* Rr, int64_t ldrr,
+                           const double* Rc, int64_t ldrc, const int32_t* pos_r, const int32_t* pos_c,
+                           const double* U, int64_t ldu, const double* V, int64_t ldv, int r, double* Bnew,
+                           const int64_t* boff_new) {
+  if (nnodes <= 0) return hipSuccess;
+  if (max_kold > kCuMaxK) return hipErrorInvalidValue;
+  coupling_update_kernel<<<nnodes, 256, 0, s>>>(fptr, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
+                                                ldrc, pos_r, pos_c, U, ldu, V, ldv, r, Bnew, boff_new);
+  return hipGetLastError();
+}
+
+hipError_t dense_lowrank(hipStream_t s, int nleaves, const int32_t* ptr, const int32_t* idx,
+                         const int32_t* leafoff, const int64_t* blkoff, const double* Din, const double* U,
+                         int64_t ldu, const double* V, int64_t ldv, int r, double* out) {
+  if (nleaves <= 0) return hipSuccess;
+  dense_lowrank_kernel<<<nleaves, 256, 0, s>>>(ptr, idx, leafoff, blkoff, Din, U, ldu, V, ldv, r, out);
+  return hipGetLastError();
 }
 
 }  // namespace h2dev

@@ -88,3 +88,35 @@ def batch_problems(count: int = 64, seed: int = 4):
                             length=length, leaf_size=64, eta=0.7, tol=1e-6,
                             omega_seed=2000 + i))
     return out
+
+
+@dataclass
+class UpdateWorkload:
+    """Low-rank update of an H^2 matrix: A = H + U V^T, with H the H^2
+    matrix of ``base`` and U, V = gaussian_factors(n, rank, factor_seed).
+    Omega of the update is keyed by ``omega_seed`` (Omega' by omega_seed + 1)."""
+    name: str
+    base: Workload
+    rank: int = 64
+    factor_seed: int = 3
+    omega_seed: int = 1002
+    tol: float = 1e-6
+    d0: int = 32
+    d_inc: int = 16
+    d_max: int = 128
+
+    @property
+    def n(self) -> int:
+        return self.base.n
+
+    def factors(self):
+        return gaussian_factors(self.base.n, self.rank, self.factor_seed)
+
+
+def cube_update(n: int) -> UpdateWorkload:
+    """The update workload on n uniform points in the unit cube (points seed 2):
+    H built like the timed workload (exp(-r/0.2), leaf 64, eta 0.7, tol 1e-6),
+    rank-64 Gaussian update."""
+    base = Workload(f"exp3d_n{n}_seed2", n=n, dim=3, point_seed=2, kernel="exp", length=0.2, leaf_size=64,
+                    eta=0.7, tol=1e-6, omega_seed=1001)
+    return UpdateWorkload(f"update_exp3d_n{n}_r64", base=base)

@@ -1,0 +1,239 @@
+"""Low-rank update A = H + U V^T of an H^2 matrix (two-sided construction).
+
+Parity bars:
+  * small problem: the GPU update against the oracle's update of the oracle's
+    own H on the same seeded inputs -- both are randomized constructions of the
+    same matrix up to rounding, so the bar is the accuracy bound (10 tol) plus
+    rank agreement, as for the symmetric build;
+  * the 2^14 update workload: against stored oracle results
+    (tests/golden/update_exp3d_n16384_r64.json, written by
+    tests/golden/make_update_golden.py, which runs only the oracle);
+  * larger sizes: the property that holds at any size,
+    ||(A_H2 - (H + U V^T)) x|| <= 10 tol ||(H + U V^T) x||, with H's own matvec;
+  * exact parts: the dense blocks are H's plus U_s V_b^T (rounding only), the
+    partition is H's, and U(J, :) = I on both sides.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_16759_amd as h2
+from paper_2506_16759_amd.workloads import cube_update, gaussian_factors, gaussian_vectors, uniform_points
+from oracle.build import build_h2
+from oracle.kernels import KernelOperator
+from oracle.update import update_h2
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "update_exp3d_n16384_r64.json")
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return h2.Context(0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _colmajor_from(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).cuda().T
+
+
+def _dense_from_matvec(H, n):
+    import torch
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    return _np(H.matvec(eye.T.contiguous().T))
+
+
+def _check_identity_rows(H, col):
+    sfx = "_C" if col else ""
+    D = int(H.export("DEPTH")[0])
+    top = int(H.export("TOP")[0])
+    nodes = H.export("NODES").reshape(-1, 2)
+    for t in range(top, D + 1):
+        ranks = H.export("RANKS" + sfx, t)
+        basis = H.export("BASIS" + sfx, t)
+        skel = H.export("SKEL_POS" + sfx, t)
+        if t == D:
+            m = np.array([nodes[(1 << D) - 1 + i, 1] - nodes[(1 << D) - 1 + i, 0] for i in range(1 << D)])
+            rows_of = [np.arange(nodes[(1 << D) - 1 + i, 0], nodes[(1 << D) - 1 + i, 1]) for i in range(1 << D)]
+        else:
+            kc = H.export("RANKS" + sfx, t + 1)
+            sk_c = H.export("SKEL_POS" + sfx, t + 1)
+            offc = np.concatenate([[0], np.cumsum(kc)])
+            m = kc[0::2] + kc[1::2]
+            rows_of = [sk_c[offc[2 * i]:offc[2 * i + 2]] for i in range(1 << t)]
+        off_b = off_s = 0
+        for i in range(1 << t):
+            k = int(ranks[i])
+            U = basis[off_b:off_b + m[i] * k].reshape(k, m[i]).T
+            sk = skel[off_s:off_s + k]
+            J = np.array([np.nonzero(rows_of[i] == s)[0][0] for s in sk], dtype=int)
+            np.testing.assert_array_equal(U[J], np.eye(k))
+            off_b += m[i] * k
+            off_s += k
+
+
+def test_update_matches_oracle_small(ctx):
+    n, tol, r = 3000, 1e-7, 8
+    _say(f"update parity n={n} tol={tol} rank={r}")
+    pts = uniform_points(n, 3, 51)
+    H = h2.build(ctx, pts, "exp", 0.2, tol=tol, leaf_size=32, eta=0.7, d0=16, d_inc=16, seed=7)
+    U, V = gaussian_factors(n, r, 52)
+    U = 30.0 * U          # an update that matters at this tolerance
+    Hu = h2.build_update(ctx, H, U, V, tol=tol, d0=16, d_inc=16, d_max=128, seed=9)
+    info = Hu.info()
+    _say(f"gpu update: samples={info['samples']} rounds={info['rounds']} ranks={info['rank_min']}..{info['rank_max']}")
+    # partition and exact parts
+    for part in ("PERM", "NEAR_PTR", "NEAR_IDX", "TOP"):
+        np.testing.assert_array_equal(Hu.export(part), H.export(part))
+    Dold, Dnew = H.export("DENSE"), Hu.export("DENSE")
+    D = int(H.export("DEPTH")[0])
+    nodes = H.export("NODES").reshape(-1, 2)
+    perm = H.export("PERM")
+    Ut, Vt = U[perm], V[perm]
+    npp, ni = H.export("NEAR_PTR"), H.export("NEAR_IDX")
+    off = 0
+    for s_ in range(1 << D):
+        rs = np.arange(*nodes[(1 << D) - 1 + s_])
+        for j in range(npp[s_], npp[s_ + 1]):
+            cb = np.arange(*nodes[(1 << D) - 1 + ni[j]])
+            sz = rs.size * cb.size
+            ref = Dold[off:off + sz].reshape(cb.size, rs.size).T + Ut[rs] @ Vt[cb].T
+            got = Dnew[off:off + sz].reshape(cb.size, rs.size).T
+            np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14 * max(1.0, np.abs(ref).max()))
+            off += sz
+    _check_identity_rows(Hu, col=False)
+    _check_identity_rows(Hu, col=True)
+    # accuracy against the matrix it approximates (GPU H + U V^T) and the oracle's update
+    A_gpu = _dense_from_matvec(H, n) + U @ V.T
+    Au = _dense_from_matvec(Hu, n)
+    e_self = np.linalg.norm(Au - A_gpu) / np.linalg.norm(A_gpu)
+    op = KernelOperator(pts, "exp", 0.2)
+    ho = build_h2(op, pts, 32, 0.7, tol, 16, 16, 128, 7)
+    hou = update_h2(ho, pts, U, V, 32, 0.7, tol, 16, 16, 128, 9)
+    A_or = ho.dense() + U @ V.T
+    e_or = np.linalg.norm(Au - hou.dense()) / np.linalg.norm(A_or)
+    e_ref = np.linalg.norm(Au - A_or) / np.linalg.norm(A_or)
+    _say(f"errors: vs GPU H+UV^T {e_self:.3e}, vs oracle update {e_or:.3e}, vs oracle H+UV^T {e_ref:.3e}; "
+         f"oracle samples {hou.samples}")
+    assert e_self <= 10 * tol and e_or <= 10 * tol and e_ref <= 10 * tol
+    assert abs(info["samples"] - hou.samples) <= 16
+    agree = []
+    for t in range(hou.top, D + 1):
+        for col in (False, True):
+            kg = Hu.export("RANKS_C" if col else "RANKS", t)
+            ko = np.array([hou.rank_c(t, i) if col else hou.rank(t, i) for i in range(1 << t)])
+            agree.append(np.mean(kg == ko))
+            assert np.abs(kg - ko).max() <= 4
+    _say(f"rank agreement per depth/side {np.round(agree, 3).tolist()}")
+    assert np.mean(agree) >= 0.8
+    # matvec of a two-sided matrix equals its dense reconstruction applied to x
+    x = np.random.default_rng(3).standard_normal((n, 3))
+    np.testing.assert_allclose(_np(Hu.matvec(_colmajor_from(x))), Au @ x, rtol=0,
+                               atol=1e-12 * np.abs(Au @ x).max())
+
+
+def test_update_rank_zero_recompresses(ctx):
+    n, tol = 2500, 1e-7
+    _say(f"rank-0 update n={n}")
+    pts = uniform_points(n, 2, 61)
+    H = h2.build(ctx, pts, "gauss", 0.1, tol=tol, leaf_size=40, d0=16, d_inc=16, seed=1)
+    Hu = h2.build_update(ctx, H, None, None, tol=tol, d0=16, d_inc=16, seed=2)
+    A = _dense_from_matvec(H, n)
+    e = np.linalg.norm(_dense_from_matvec(Hu, n) - A) / np.linalg.norm(A)
+    _say(f"rank-0 error {e:.3e} samples {Hu.info()['samples']}")
+    assert e <= 10 * tol
+
+
+def test_update_workload_n16384_against_oracle_golden(ctx):
+    g = json.load(open(GOLDEN))
+    w = cube_update(g["n"])
+    b = w.base
+    _say(f"update workload {w.name}: GPU H then update, against the stored oracle results")
+    pts = b.points()
+    H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
+                 d_inc=b.d_inc, seed=b.omega_seed)
+    U, V = w.factors()
+    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+    info = Hu.info()
+    _say(f"gpu: old samples {H.info()['samples']} update samples {info['samples']} ({info['t_total']:.1f} ms); "
+         f"oracle: {g['old_samples']} / {g['samples']}")
+    assert abs(H.info()["samples"] - g["old_samples"]) <= 16
+    assert abs(info["samples"] - g["samples"]) <= 16
+    assert int(Hu.export("TOP")[0]) == g["top"]
+    agree = []
+    for t, ko in g["ranks"].items():
+        kg = Hu.export("RANKS", int(t))
+        agree.append(np.mean(kg == np.array(ko)))
+        assert np.abs(kg - np.array(ko)).max() <= 4
+    for t, ko in g["ranks_c"].items():
+        kg = Hu.export("RANKS_C", int(t))
+        agree.append(np.mean(kg == np.array(ko)))
+        assert np.abs(kg - np.array(ko)).max() <= 4
+    _say(f"rank agreement {np.round(agree, 3).tolist()}")
+    assert np.mean(agree) >= 0.8
+    x = gaussian_vectors(w.n, 2, g["x_seed"])
+    rows = np.array(g["rows"])
+    y = _np(Hu.matvec(_colmajor_from(x)))[rows]
+    y_or, y_ref = np.array(g["y_update"]), np.array(g["y_reference"])
+    e1 = np.linalg.norm(y - y_or) / np.linalg.norm(y_ref)
+    e2 = np.linalg.norm(y - y_ref) / np.linalg.norm(y_ref)
+    _say(f"sampled rows: vs oracle update {e1:.3e}, vs oracle H + UV^T {e2:.3e}")
+    assert e1 <= 10 * w.tol and e2 <= 10 * w.tol
+
+
+@pytest.mark.parametrize("n", [1 << 16])
+def test_update_workload_any_size_property(ctx, n):
+    w = cube_update(n)
+    b = w.base
+    _say(f"update workload {w.name}: accuracy property with H's own matvec")
+    pts = b.points()
+    H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
+                 d_inc=b.d_inc, seed=b.omega_seed)
+    U, V = w.factors()
+    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+    info = Hu.info()
+    _say(f"update built in {info['t_total']:.1f} ms, samples {info['samples']}, ranks {info['rank_min']}.."
+         f"{info['rank_max']}")
+    x = gaussian_vectors(n, 4, 5)
+    xc = _colmajor_from(x)
+    ref = _np(H.matvec(xc)) + U @ (V.T @ x)
+    e = np.linalg.norm(_np(Hu.matvec(xc)) - ref) / np.linalg.norm(ref)
+    _say(f"||(A_H2 - (H + UV^T)) x|| / ||(H + UV^T) x|| = {e:.3e}")
+    assert e <= 10 * w.tol
+
+
+def test_update_error_paths(ctx):
+    _say("update error paths")
+    pts = uniform_points(800, 2, 71)
+    H = h2.build(ctx, pts, "exp", 0.2, leaf_size=32)
+    U, V = gaussian_factors(800, 4, 1)
+    with pytest.raises(h2.H2Error) as ei:
+        h2.build_update(ctx, H, U, V, precision="fp32")
+    assert ei.value.status == -7
+    Hu = h2.build_update(ctx, H, U, V)
+    with pytest.raises(h2.H2Error) as ei:
+        h2.build_update(ctx, Hu, U, V)
+    assert ei.value.status == -7
+    # the old matrix stays usable after the update and after the update is freed
+    x = _colmajor_from(np.ones((800, 1)))
+    y0 = _np(H.matvec(x))
+    Hu.close()
+    np.testing.assert_array_equal(_np(H.matvec(x)), y0)
+    # the update stays usable after the old matrix is freed (shared dense blocks)
+    Hu2 = h2.build_update(ctx, H, U, V)
+    y1 = _np(Hu2.matvec(x))
+    H.close()
+    np.testing.assert_array_equal(_np(Hu2.matvec(x)), y1)
