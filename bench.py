@@ -79,6 +79,89 @@ def cpu_baseline(w, samples_used: int, rows: int = 2048):
     }
 
 
+def bench_batched(h2, ctx, steps: int = 2):
+    """The 64-problem covariance batch: batched FP64 and FP32 builds (one
+    hipGraph each) against 64 sequential single FP64 builds."""
+    import torch
+
+    from paper_2506_16759_amd.workloads import batch_problems
+    ws = batch_problems()
+    probs = [dict(points=torch.from_numpy(w.points()).cuda(), kernel=w.kernel, length=w.length,
+                  leaf_size=w.leaf_size, tol=w.tol, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed)
+             for w in ws]
+    res = {"problems": len(ws), "total_n": int(sum(w.n for w in ws)),
+           "sum_n2": float(sum(float(w.n) ** 2 for w in ws))}
+    for name, prec in (("fp64", h2.FP64), ("fp32", h2.FP32)):
+        times, info = [], None
+        for i in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                mats, info = h2.build_batched(ctx, probs, precision=prec, d_max=96, return_info=True)
+            except h2.H2Error as exc:
+                res[name] = {"error": str(exc)}
+                break
+            torch.cuda.synchronize()
+            if i > 0:
+                times.append((time.perf_counter() - t0) * 1e3)
+            samples = [m.info()["samples"] for m in mats]
+            for m in mats:
+                m.close()
+            print(f"[bench] batched {name} {times[-1] if times else 0:.1f} ms", file=sys.stderr, flush=True)
+        else:
+            res[name] = {"ms_per_batch": statistics.median(times), "device_ms": info["t_device_ms"],
+                         "plan_ms": info["t_plan_ms"], "setup_ms": info["t_setup_ms"],
+                         "capture_ms": info["t_capture_ms"], "graph_nodes": info["graph_nodes"],
+                         "device_gb": info["device_bytes"] / 1e9,
+                         "samples_range": [min(samples), max(samples)]}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        H = h2.build(ctx, p["points"], p["kernel"], p["length"], tol=p["tol"], leaf_size=p["leaf_size"],
+                     eta=p["eta"], d0=p["d0"], d_inc=p["d_inc"], seed=p["seed"])
+        H.close()
+    torch.cuda.synchronize()
+    res["sequential_fp64_ms"] = (time.perf_counter() - t0) * 1e3
+    if "ms_per_batch" in res.get("fp64", {}):
+        res["batched_vs_sequential_speedup"] = res["sequential_fp64_ms"] / res["fp64"]["ms_per_batch"]
+        if "ms_per_batch" in res.get("fp32", {}):
+            res["mixed_vs_fp64_batched_speedup"] = res["fp64"]["ms_per_batch"] / res["fp32"]["ms_per_batch"]
+    return res
+
+
+def bench_update(h2, ctx, n: int = 1 << 16):
+    """Low-rank update of an H^2 matrix (rank 64) on n points: build H, then
+    the two-sided update with H's matvec as the black box."""
+    import torch
+
+    from paper_2506_16759_amd.workloads import cube_update
+    w = cube_update(n)
+    b = w.base
+    pts = torch.from_numpy(b.points()).cuda()
+    H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
+                 d_inc=b.d_inc, seed=b.omega_seed)
+    U, V = w.factors()
+    Ut, Vt = torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda()
+    times = []
+    for i in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Hu = h2.build_update(ctx, H, Ut, Vt, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        info = Hu.info()
+        if i == 0:
+            Hu.close()
+    print(f"[bench] update n={n} {times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    out = {"workload": w.name, "n": n, "rank": w.rank, "ms_per_update": times[-1],
+           "old_build_ms": H.info()["t_total"], "samples": info["samples"], "rounds": info["rounds"],
+           "rank_range": [info["rank_min"], info["rank_max"]],
+           "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
+    Hu.close()
+    H.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +170,8 @@ def main():
     ap.add_argument("--tol", type=float, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sketch-launches", type=int, default=5)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 64-problem batched build and the low-rank update measurements")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
@@ -212,6 +297,9 @@ def main():
             "traffic": measured_traffic("sketch_f64_kernel<3,exp,32>"),
         },
     }
+    if not args.no_extras:
+        out["batched"] = bench_batched(h2, ctx)
+        out["update"] = bench_update(h2, ctx)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, info["samples"])

@@ -229,9 +229,21 @@ constexpr int kFlush = 4;
 
 // FP32 entries, v_mfma_f32_16x16x4_f32.  Same tiling as the FP64 kernel:
 // lane l supplies A[l%16][l/16], B[l/16][l%16] and holds D[4*(l/16)+q][l%16].
+// Coordinates are held as float pairs hi + lo (hi = x rounded to FP32, lo =
+// the remainder rounded to FP32), and differences are formed as
+// (hi_i - hi_j) + (lo_i - lo_j): for close points the first difference is
+// exact, so distances keep ~FP32 relative accuracy instead of absolute
+// 2^-24 errors of the coordinates, which would dominate the entry error of
+// close pairs.
+__device__ __forceinline__ void split_f32(double v, float& h, float& l) {
+  h = float(v);
+  l = float(v - double(h));
+}
+
 template <int DIM, int NC>
 struct SkF32Smem {
-  float xs[DIM][kSkK];
+  float xsh[DIM][kSkK];
+  float xsl[DIM][kSkK];
   float om[kSkK][NC + 4];
 };
 
@@ -241,19 +253,20 @@ __device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t 
                                                 const double* __restrict__ omega, int64_t ldo,
                                                 double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  auto& xs = sm.xs;
+  auto& xsh = sm.xsh;
+  auto& xsl = sm.xsl;
   auto& om = sm.om;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  float xa[DIM], xb[DIM];
+  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
   {
     const int64_t ia = row0 + li, ib = row0 + 16 + li;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      xa[a] = ia < n ? float(X[a * ldx + ia]) : 0.0f;
-      xb[a] = ib < n ? float(X[a * ldx + ib]) : 0.0f;
+      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
+      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
     }
   }
   flt4 acc0[NB], acc1[NB];
@@ -270,7 +283,7 @@ __device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t 
     __syncthreads();
     for (int e = tid; e < DIM * kSkK; e += 256) {
       const int a = e / kSkK, jj = e % kSkK;
-      xs[a][jj] = (j0 + jj < n) ? float(X[a * ldx + j0 + jj]) : 0.0f;
+      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
     }
     for (int e = tid; e < NC * kSkK; e += 256) {
       const int c = e / kSkK, jj = e % kSkK;
@@ -283,8 +296,8 @@ __device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t 
       float ra = 0.f, rb = 0.f;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const float xj = xs[a][jj];
-        const float da = xa[a] - xj, db = xb[a] - xj;
+        const float jh = xsh[a][jj], jl = xsl[a][jj];
+        const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
         ra += da * da;
         rb += db * db;
       }
@@ -368,7 +381,8 @@ constexpr int kBfLdp = kBfK / 2 + 4;  // dwords per staged column (2 bf16 per dw
 
 template <int DIM, int NC>
 struct SkBfSmem {
-  float xs[DIM][kBfK];
+  float xsh[DIM][kBfK];
+  float xsl[DIM][kBfK];
   uint32_t omh[NC * kBfLdp];
   uint32_t oml[NC * kBfLdp];
 };
@@ -380,20 +394,21 @@ __device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_
                                                    double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
   constexpr int LDP = kBfLdp;
-  auto& xs = sm.xs;
+  auto& xsh = sm.xsh;
+  auto& xsl = sm.xsl;
   auto& omh = sm.omh;
   auto& oml = sm.oml;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  float xa[DIM], xb[DIM];
+  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
   {
     const int64_t ia = row0 + li, ib = row0 + 16 + li;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      xa[a] = ia < n ? float(X[a * ldx + ia]) : 0.0f;
-      xb[a] = ib < n ? float(X[a * ldx + ib]) : 0.0f;
+      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
+      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
     }
   }
   flt4 acc0[NB], acc1[NB];
@@ -410,7 +425,7 @@ __device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_
     __syncthreads();
     for (int e = tid; e < DIM * kBfK; e += 256) {
       const int a = e / kBfK, jj = e % kBfK;
-      xs[a][jj] = (j0 + jj < n) ? float(X[a * ldx + j0 + jj]) : 0.0f;
+      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
     }
     // pairs of points per thread: dword (c, p) holds points 2p, 2p+1 of column c
     for (int e = tid; e < NC * (kBfK / 2); e += 256) {
@@ -441,8 +456,8 @@ __device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_
           float ra = 0.f, rb = 0.f;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
-            const float xj = xs[a][jj];
-            const float da = xa[a] - xj, db = xb[a] - xj;
+            const float jh = xsh[a][jj], jl = xsl[a][jj];
+            const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
             ra += da * da;
             rb += db * db;
           }
