@@ -78,25 +78,29 @@ typedef struct {
   double tol;         /* relative compression tolerance epsilon, > 0 (Alg. 1 input) */
   int32_t leaf_size;  /* KD-tree leaf size m0, 2..256 */
   double eta;         /* general admissibility parameter (Sec. II-A), > 0 */
-  int32_t d0;         /* initial sample columns (Alg. 1 "sample block size"), 1..128 */
+  int32_t d0;         /* initial sample columns (Alg. 1 "sample block size"), 1..256 */
   int32_t d_inc;      /* columns added per adaptive round (Sec. III-B), 1..128 */
-  int32_t d_max;      /* cap on total columns, <= 128; exceeding it -> H2_ERR_SAMPLES */
+  int32_t d_max;      /* cap on total columns, <= 256; exceeding it -> H2_ERR_SAMPLES */
   uint64_t seed;      /* key of the counter-based Gaussian test matrix */
   int32_t precision;  /* h2_precision */
   int32_t norm_mode;  /* h2_norm_mode */
-  int32_t sketch_ahead; /* extra columns sketched whenever a sketch pass runs (0..128).  The
+  int32_t sketch_ahead; /* extra columns sketched whenever a sketch pass runs (0..256).  The
                          * adaptive loop still grows d by d_inc; columns already sketched
                          * are used without another pass.  Results are identical for any
                          * value (Omega is counter-based); only the number of passes over
                          * the O(n^2) black box changes. */
+  int32_t oversample;   /* p, 0..64: the convergence test looks at the leading d - p sample
+                         * columns only (a cluster with m + p <= d is converged), so the ID
+                         * always has p samples beyond the rank it detects (Sec. III-A's
+                         * oversampling).  p = 0 is the bare test of Sec. III-B. */
 } h2_opts;
 
 typedef struct h2_ctx h2_ctx;
 typedef struct h2_matrix h2_matrix;
 typedef struct h2_plan h2_plan;
 
-/* Fills defaults: tol 1e-6, leaf 64, eta 0.7, d0 32, d_inc 16, d_max 128,
- * seed 1000, FP64, FRO_SCALED, sketch_ahead 32. */
+/* Fills defaults: tol 1e-6, leaf 64, eta 0.7, d0 32, d_inc 16, d_max 256,
+ * seed 1000, FP64, FRO_SCALED, sketch_ahead 32, oversample 5. */
 h2_status h2_opts_default(h2_opts* opts);
 
 const char* h2_status_string(h2_status s);
@@ -235,6 +239,7 @@ typedef struct {
   int32_t d0, d_inc;
   uint64_t seed;
   int32_t norm_mode;
+  int32_t oversample;    /* as h2_opts.oversample */
 } h2_problem;
 
 typedef struct {

@@ -72,17 +72,29 @@ def top_depth(lists, D: int) -> int:
     return D + 1
 
 
-def converged(Yloc: np.ndarray, delta: float) -> bool:
-    """Adaptive convergence test of one cluster (Sec. III-B)."""
+def converged(Yloc: np.ndarray, delta: float, oversample: int = 0) -> bool:
+    """Adaptive convergence test of one cluster (Sec. III-B): the samples suffice
+    when the QR of Y_loc shows a diagonal entry below delta.
+
+    Reading: the test looks only at the leading d - p columns, keeping p
+    samples of oversampling (the margin of the fixed-rank scheme, Sec. III-A)
+    for the ID: the trailing diagonal entries of a nearly square Gaussian
+    sketch are small even for a full-rank block, and without the margin such a
+    block is truncated wrongly.  A cluster with m + p <= d has all its rows
+    resolved and is converged."""
     m, d = Yloc.shape
-    if m <= d:
+    if m + oversample <= d:
         return True
-    return bool(qr_r_diag(Yloc).min() < delta)
+    q = d - oversample
+    if q <= 0:
+        return False
+    return bool(qr_r_diag(Yloc[:, :q]).min() < delta)
 
 
 class _Builder:
-    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, norm_mode):
+    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, norm_mode, oversample=0):
         self.op = op
+        self.oversample = oversample
         self.tree = build_tree(points, leaf_size)
         self.lists = build_lists(self.tree, eta)
         self.tol, self.d0, self.d_inc, self.d_max = tol, d0, d_inc, d_max
@@ -197,7 +209,7 @@ class _Builder:
             om_in, y_in = self.level_inputs(t, om0, y0, child_om, child_y)
             yloc = self.subtract(t, y_in, om_in, child_om)
             rounds = 0
-            while not all(converged(yl, h.delta) for yl in yloc):
+            while not all(converged(yl, h.delta, self.oversample) for yl in yloc):
                 om_b, yloc_b = self.update_samples(t)
                 om_in = [np.hstack([a, b]) for a, b in zip(om_in, om_b)]
                 yloc = [np.hstack([a, b]) for a, b in zip(yloc, yloc_b)]
@@ -231,6 +243,6 @@ class _Builder:
 
 def build_h2(op, points: np.ndarray, leaf_size: int = 64, eta: float = 0.7, tol: float = 1e-6,
              d0: int = 32, d_inc: int = 16, d_max: int = 1024, seed: int = 1000,
-             norm_mode: str = "fro_scaled") -> H2Matrix:
+             norm_mode: str = "fro_scaled", oversample: int = 5) -> H2Matrix:
     """Build the H^2 matrix of ``op`` on ``points`` (dim, n) with Alg. 1 + adaptive sampling."""
-    return _Builder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, norm_mode).run()
+    return _Builder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, norm_mode, oversample).run()

@@ -71,8 +71,9 @@ class _Side:
 
 
 class _TwoSidedBuilder:
-    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, seed_c, norm_mode):
+    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, seed_c, norm_mode, oversample=5):
         self.op = op
+        self.oversample = oversample
         self.tree = build_tree(points, leaf_size)
         self.lists = build_lists(self.tree, eta)
         self.tol, self.d0, self.d_inc, self.d_max = tol, d0, d_inc, d_max
@@ -203,7 +204,8 @@ class _TwoSidedBuilder:
         for t in range(D, h.top - 1, -1):
             res = self._sweep_level(t, om0, y0, omc0, z0, child)
             rounds = 0
-            while not all(converged(yl, h.delta) for side in (self.r, self.c) for yl in res[id(side)][1]):
+            while not all(converged(yl, h.delta, self.oversample)
+                          for side in (self.r, self.c) for yl in res[id(side)][1]):
                 more = self.update_samples(t)
                 for side in (self.r, self.c):
                     om_in, yloc = res[id(side)]
@@ -245,21 +247,23 @@ class _TwoSidedBuilder:
 
 def build_h2_two_sided(op, points: np.ndarray, leaf_size: int = 64, eta: float = 0.7, tol: float = 1e-6,
                        d0: int = 32, d_inc: int = 16, d_max: int = 1024, seed: int = 1000,
-                       seed_c: int | None = None, norm_mode: str = "fro_scaled") -> H2Matrix:
+                       seed_c: int | None = None, norm_mode: str = "fro_scaled", oversample: int = 5) -> H2Matrix:
     """Two-sided Alg. 1 + adaptive sampling for a non-symmetric ``op`` (needs
     op.sketch, op.sketch_t and op.entries).  seed_c defaults to seed + 1."""
     sc = seed + 1 if seed_c is None else seed_c
-    return _TwoSidedBuilder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, sc, norm_mode).run()
+    return _TwoSidedBuilder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, sc, norm_mode,
+                            oversample).run()
 
 
 def update_h2(h_old: H2Matrix, points: np.ndarray, U: np.ndarray, V: np.ndarray, leaf_size: int = 64,
               eta: float = 0.7, tol: float = 1e-6, d0: int = 32, d_inc: int = 16, d_max: int = 1024,
-              seed: int = 1002, seed_c: int | None = None, norm_mode: str = "fro_scaled") -> H2Matrix:
+              seed: int = 1002, seed_c: int | None = None, norm_mode: str = "fro_scaled",
+              oversample: int = 5) -> H2Matrix:
     """H^2 approximation of K_H + U V^T, built two-sided from the H^2 black box on
     the partition of ``h_old`` (same points, leaf size and eta)."""
     op = LowRankUpdateOperator(h_old, U, V)
     b = _TwoSidedBuilder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed,
-                         seed + 1 if seed_c is None else seed_c, norm_mode)
+                         seed + 1 if seed_c is None else seed_c, norm_mode, oversample)
     if not (np.array_equal(b.tree.perm, h_old.tree.perm)
             and all(np.array_equal(a, c) for a, c in zip(b.lists.far_idx, h_old.lists.far_idx))):
         raise ValueError("h_old was built on another partition")

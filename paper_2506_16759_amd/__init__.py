@@ -214,7 +214,7 @@ def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_g
 
     problems: sequence of dicts with keys points ((dim, n) array or tensor),
     kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
-    norm_mode (defaults as h2_opts_default).  Returns a list of H2Matrix (and
+    norm_mode, oversample (defaults as h2_opts_default).  Returns a list of H2Matrix (and
     the batch info dict when return_info)."""
     torch = _torch()
     if isinstance(precision, str):
@@ -231,7 +231,8 @@ def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_g
             nm = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[nm]
         arr[i] = _lib.Problem(n, dim, pts.data_ptr(), kernel_spec(pr.get("kernel", "exp"), pr.get("length", 0.2)),
                               pr.get("tol", d.tol), pr.get("leaf_size", d.leaf_size), pr.get("eta", d.eta),
-                              pr.get("d0", d.d0), pr.get("d_inc", d.d_inc), pr.get("seed", d.seed), nm)
+                              pr.get("d0", d.d0), pr.get("d_inc", d.d_inc), pr.get("seed", d.seed), nm,
+                              pr.get("oversample", d.oversample))
     bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0)
     handles = (C.c_void_p * len(problems))()
     info = _lib.BatchInfo()

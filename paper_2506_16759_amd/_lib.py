@@ -26,7 +26,7 @@ PART_DTYPE = dict(DEPTH="i4", PERM="i4", NODES="i4", BOXES="f8", NEAR_PTR="i4", 
 class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("leaf_size", C.c_int32), ("eta", C.c_double), ("d0", C.c_int32),
                 ("d_inc", C.c_int32), ("d_max", C.c_int32), ("seed", C.c_uint64), ("precision", C.c_int32),
-                ("norm_mode", C.c_int32), ("sketch_ahead", C.c_int32)]
+                ("norm_mode", C.c_int32), ("sketch_ahead", C.c_int32), ("oversample", C.c_int32)]
 
 
 class Kernel(C.Structure):
@@ -53,7 +53,7 @@ class Info(C.Structure):
 class Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("dim", C.c_int32), ("points", C.c_void_p), ("kernel", Kernel),
                 ("tol", C.c_double), ("leaf_size", C.c_int32), ("eta", C.c_double), ("d0", C.c_int32),
-                ("d_inc", C.c_int32), ("seed", C.c_uint64), ("norm_mode", C.c_int32)]
+                ("d_inc", C.c_int32), ("seed", C.c_uint64), ("norm_mode", C.c_int32), ("oversample", C.c_int32)]
 
 
 class BatchOpts(C.Structure):

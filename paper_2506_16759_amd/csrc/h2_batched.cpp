@@ -55,7 +55,8 @@ struct LevelB {
 struct BatchStore {
   std::vector<LevelB> lv;  // index l-1
   DevArray<double> Xo, Xt, Om0, Y0, Dblk;
-  DevArray<int32_t> perm_g, rowprob_o, rowlocal_o, leafoff, nptr, nidx, leafprob, kinds, dprob, incprob, exhausted;
+  DevArray<int32_t> perm_g, rowprob_o, rowlocal_o, leafoff, nptr, nidx, leafprob, kinds, dprob, incprob, ovprob,
+      exhausted;
   DevArray<int64_t> doff;
   DevArray<uint64_t> seeds;
   DevArray<double> c2s, nu, delta;
@@ -85,6 +86,7 @@ void check_problem(const h2_problem& p) {
   H2_REQUIRE(p.eta > 0.0 && std::isfinite(p.eta), "problem eta must be finite and > 0");
   H2_REQUIRE(p.d0 >= 1 && p.d_inc >= 1, "problem d0, d_inc must be >= 1");
   H2_REQUIRE(p.norm_mode == H2_NORM_FRO_SCALED || p.norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
+  H2_REQUIRE(p.oversample >= 0 && p.oversample <= 64, "problem oversample must be in [0, 64]");
 }
 
 }  // namespace
@@ -291,7 +293,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     up(B.doff, doff, s, bytes);
     up(B.leafprob, leafprob, s, bytes);
     std::vector<uint64_t> seeds(np);
-    std::vector<int32_t> kinds(np), incs(np);
+    std::vector<int32_t> kinds(np), incs(np), ovs(np);
     std::vector<double> c2s(np);
     std::vector<char> sj(h2dev::sketch_job_bytes() * np), tj(h2dev::threshold_job_bytes() * np);
     std::vector<int32_t> tiles;
@@ -301,6 +303,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       seeds[q] = p.in.seed;
       kinds[q] = p.in.kernel.kind;
       incs[q] = p.in.d_inc;
+      ovs[q] = p.in.oversample;
       const h2dev::KernelFn kf = kernel_fn(p.in.kernel);
       c2s[q] = -kf.scale * 1.4426950408889634;
       h2dev::pack_sketch_job(sj.data() + q * h2dev::sketch_job_bytes(), p.in.n, p.base, kf.kind, kf.scale);
@@ -318,6 +321,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     up(B.seeds, seeds, s, bytes);
     up(B.kinds, kinds, s, bytes);
     up(B.incprob, incs, s, bytes);
+    up(B.ovprob, ovs, s, bytes);
     up(B.c2s, c2s, s, bytes);
     up(B.sjobs, sj, s, bytes);
     up(B.tjobs, tj, s, bytes);
@@ -408,9 +412,9 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
           H2_HIP(h2dev::bsr_gemm(s, C.G, C.d_fptr.get(), C.d_fidx.get(), C.koff.get(), C.d_boff.get(), C.B.get(),
                                  om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), 0));
         }
-        H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), V.d_nodeprob.get(),
-                                    B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m, ctx->lds_limit,
-                                    V.gws.get(), V.gws_off.get()));
+        H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), B.ovprob.get(),
+                                    V.d_nodeprob.get(), B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m,
+                                    ctx->lds_limit, V.gws.get(), V.gws_off.get()));
         H2_HIP(h2dev::cpqr_id(s, V.G, V.rowoff.get(), y, ld, dcap, 0.0, V.k.get(), V.J.get(), V.d_joff.get(),
                               V.U.get(), V.d_uoff.get(), V.max_m, ctx->lds_limit, V.gws.get(), V.gws_off.get(),
                               V.d_nodeprob.get(), B.dprob.get(), B.delta.get()));
@@ -510,6 +514,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       o.precision = prec;
       o.norm_mode = p.in.norm_mode;
       o.sketch_ahead = dcap - p.in.d0;
+      o.oversample = p.in.oversample;
       h->opts = o;
       const int n = static_cast<int>(p.in.n);
       const int D = p.D;

@@ -59,11 +59,12 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
                      int precision = 0);
 
-// Adaptive convergence test (Sec. III-B): per cluster, unpivoted Householder QR of its samples
-// Y[rowoff[i]..rowoff[i+1]) x [0,d); conv[i] = 1 if m <= d or min |R_jj| < delta.
-// minr[i] receives the smallest |R_jj| seen (0 when m <= d).  *unconverged counts clusters
-// with conv 0 (must be zeroed by the caller).  Panels larger than lds_limit bytes use gws.
-hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+// Adaptive convergence test (Sec. III-B) with an oversampling margin p: per cluster,
+// unpivoted Householder QR of its samples Y[rowoff[i]..rowoff[i+1]) x [0, d-p);
+// conv[i] = 1 if m + p <= d or min |R_jj| < delta.  minr[i] receives the smallest |R_jj|
+// seen (0 when m + p <= d).  *unconverged counts clusters with conv 0 (must be zeroed by
+// the caller).  Panels larger than lds_limit bytes use gws.
+hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d, int p,
                    double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m,
                    size_t lds_limit, double* gws, const int64_t* gws_off);
 
@@ -137,10 +138,12 @@ hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, cons
 
 // Prefix convergence test over all dsk sketched columns: raises dprob[p] to the
 // first column count on the grid dprob[p] + j*incprob[p] at which every cluster
-// of p is converged; sets exhausted[p] if some cluster is not converged within dsk.
+// of p is converged (test of qr_test with margin ovprob[p]); sets exhausted[p] if
+// some cluster is not converged within dsk.
 hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int dsk,
-                         const int32_t* incprob, const int32_t* nodeprob, int32_t* dprob, const double* deltaprob,
-                         int32_t* exhausted, int max_m, size_t lds_limit, double* gws, const int64_t* gws_off);
+                         const int32_t* incprob, const int32_t* ovprob, const int32_t* nodeprob, int32_t* dprob,
+                         const double* deltaprob, int32_t* exhausted, int max_m, size_t lds_limit, double* gws,
+                         const int64_t* gws_off);
 
 // Exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total.
 hipError_t scan_i32(hipStream_t s, int n, const int32_t* in, int32_t* out);

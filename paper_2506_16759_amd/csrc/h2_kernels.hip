@@ -8,6 +8,8 @@
 // one thread per panel column and wave shuffles for norms and the pivot argmax.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <cmath>
 #include <cstdint>
 
@@ -685,6 +687,14 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 // block are staged in LDS ([q][c], shared by the 4 waves); the blocks stream
 // from HBM straight into the MFMA A operand (lane l reads row l%16 of column
 // l/16 of a 16x4 slice: four 128-byte runs per load).
+// Block-sparse product, one workgroup per block row i and 16*NB columns:
+//   Y[rows_i, c0:c0+16NB] += alpha * sum_j Blk_j X[rows_b, c0:c0+16NB].
+// Wave w owns row tiles w, w+4, .. (RT of them, 16 rows each).  The X rows of
+// block j+1 are fetched into registers while block j runs on the matrix cores
+// from the other LDS buffer (double buffering, one barrier per block), and the
+// block's A operands are loaded 16/RT k-steps at a time.
+// F32: blocks and X are rounded to FP32 at load, the products run on the FP32
+// matrix cores and each block's FP32 partial sums are folded into FP64.
 template <int NB, int RT, bool F32, bool TR>
 __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rowoff,
@@ -694,87 +704,108 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
                                                        const double* __restrict__ blocks, const double* __restrict__ X,
                                                        int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
                                                        double alpha) {
-  // F32: blocks and X are rounded to FP32 at load, the products run on the
-  // FP32 matrix cores and each block's FP32 partial sums are folded into FP64.
+  using T = typename std::conditional<F32, float, double>::type;
   constexpr int LDB = NB * 16;
-  extern __shared__ double xb[];
-  float* xbf = reinterpret_cast<float*>(xb);
+  constexpr int MAXQ = 64 * RT;      // rows of a staged X tile (block heights <= 64 RT)
+  constexpr int QI = RT, CI = LDB / 4;  // staged values per thread: rows lane + 64 qi, columns wave + 4 ci
+  constexpr int KC = 16 / RT;        // k-steps per batch of A loads
+  extern __shared__ double smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);  // two buffers of MAXQ x LDB
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
   const int c0 = blockIdx.y * LDB;
   const int ncl = min(LDB, nc - c0);
+  const int jb = ptr[i], je = ptr[i + 1];
+  if (m == 0 || jb == je) return;  // uniform over the workgroup
+
+  // Two-sided use: block columns index the row space `coloff`, and with TR
+  // the block of entry j is the transpose of the stored block tpos[j]
+  // (stored mb x m, column-major).
+  T xv[QI][CI];
+  auto fetch = [&](int j) {
+    const int b = idx[j];
+    const int q0 = coloff[b], mb = coloff[b + 1] - q0;
+#pragma unroll
+    for (int qi = 0; qi < QI; ++qi)
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) {
+        const int q = lane + 64 * qi, c = wave + 4 * ci;
+        xv[qi][ci] = (q < mb && c < ncl) ? T(X[int64_t(c0 + c) * ldx + q0 + q]) : T(0);
+      }
+  };
+  auto stash = [&](int slot) {
+    T* bs = buf + slot * (MAXQ * LDB);
+#pragma unroll
+    for (int qi = 0; qi < QI; ++qi)
+#pragma unroll
+      for (int ci = 0; ci < CI; ++ci) bs[(lane + 64 * qi) * LDB + wave + 4 * ci] = xv[qi][ci];
+  };
+
   dbl4 acc[RT][NB];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  // Two-sided use: block columns index the row space `coloff`, and with TR
-  // the block of entry j is the transpose of the stored block tpos[j]
-  // (stored mb x m, column-major).
-  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
+  fetch(jb);
+  stash(0);
+  __syncthreads();
+  for (int j = jb; j < je; ++j) {
+    const int cur = (j - jb) & 1;
+    const bool more = j + 1 < je;
+    if (more) fetch(j + 1);  // in flight while block j computes
     const int b = idx[j];
-    const int q0b = coloff[b], mb = coloff[b + 1] - q0b, mb4 = (mb + 3) & ~3;
+    const int mb = coloff[b + 1] - coloff[b], mb4 = (mb + 3) & ~3;
     const double* blk = blocks + blkoff[TR ? tpos[j] : j];
-    __syncthreads();
-    for (int q = lane; q < mb4; q += 64)
-      for (int c = wave; c < LDB; c += 4) {
-        const double v = (q < mb && c < ncl) ? X[int64_t(c0 + c) * ldx + q0b + q] : 0.0;
-        if constexpr (F32)
-          xbf[q * LDB + c] = float(v);
-        else
-          xb[q * LDB + c] = v;
-      }
-    __syncthreads();
+    const T* bs = buf + cur * (MAXQ * LDB);
+    using V4 = typename std::conditional<F32, flt4, dbl4>::type;
+    V4 part[RT][NB];
     if constexpr (F32) {
-      flt4 part[RT][NB];
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
-        for (int c = 0; c < NB; ++c) part[t][c] = flt4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-      for (int k = 0; k < mb4; k += 4) {
-        const int q = k + lk;
-        float a[RT];
+        for (int c = 0; c < NB; ++c) part[t][c] = V4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
+      T a[RT][KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int q = k0 + 4 * kc + lk;
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int row = (wave + 4 * t) * 16 + li;
-          a[t] = (row < m && q < mb) ? float(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0f;
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const float bv = xbf[q * LDB + c * 16 + li];
-#pragma unroll
-          for (int t = 0; t < RT; ++t) part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], bv, part[t][c], 0, 0, 0);
+          a[t][kc] = (row < m && q < mb) ? T(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : T(0);
         }
       }
-      // FP32 layout D[4*(l/16)+q][l%16] -> FP64 layout D[l/16+4q][l%16]: keep the
-      // FP32 layout in the FP64 accumulators (the store below follows F32).
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        if (k0 + 4 * kc >= mb4) break;
+        const int q = k0 + 4 * kc + lk;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const T bv = bs[q * LDB + c * 16 + li];
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            if constexpr (F32)
+              part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][kc], bv, part[t][c], 0, 0, 0);
+            else
+              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if constexpr (F32) {
+      // FP32 layout D[4*(l/16)+q][l%16] is kept in the FP64 accumulators (the store follows it)
 #pragma unroll
       for (int t = 0; t < RT; ++t)
 #pragma unroll
         for (int c = 0; c < NB; ++c)
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[t][c][q] += double(part[t][c][q]);
-    } else {
-#pragma unroll 4
-      for (int k = 0; k < mb4; k += 4) {
-        const int q = k + lk;
-        double a[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int row = (wave + 4 * t) * 16 + li;
-          a[t] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const double bv = xb[q * LDB + c * 16 + li];
-#pragma unroll
-          for (int t = 0; t < RT; ++t) acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv, acc[t][c], 0, 0, 0);
-        }
-      }
     }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
   }
 #pragma unroll
   for (int t = 0; t < RT; ++t)
@@ -801,7 +832,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 // applies it on its own.  Stops at the first |R_jj| < delta.
 template <bool kLds>
 __global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy, int d,
-                               double delta, int32_t* __restrict__ conv, double* __restrict__ minr,
+                               int p, double delta, int32_t* __restrict__ conv, double* __restrict__ minr,
                                int32_t* __restrict__ unconverged, double* __restrict__ gws,
                                const int64_t* __restrict__ gws_off) {
   extern __shared__ double smem[];
@@ -810,10 +841,20 @@ __global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double*
   const int i = blockIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (m <= d) {  // as many samples as rows: nothing left to resolve
+  if (m + p <= d) {  // every row resolved with p samples to spare
     if (tid == 0) {
       conv[i] = 1;
       minr[i] = 0.0;
+    }
+    return;
+  }
+  // only the leading d - p columns are tested; the last p are the ID's oversampling
+  d -= p;
+  if (d <= 0) {
+    if (tid == 0) {
+      conv[i] = 0;
+      minr[i] = INFINITY;
+      atomicAdd(unconverged, 1);
     }
     return;
   }
@@ -887,10 +928,10 @@ __global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double*
 // admissible d' <= dsk sets *exhausted.
 template <bool kLds>
 __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy,
-                                     int dsk, const int32_t* __restrict__ incprob, const int32_t* __restrict__ nodeprob,
-                                     int32_t* __restrict__ dprob, const double* __restrict__ deltaprob,
-                                     int32_t* __restrict__ exhausted, double* __restrict__ gws,
-                                     const int64_t* __restrict__ gws_off) {
+                                     int dsk, const int32_t* __restrict__ incprob, const int32_t* __restrict__ ovprob,
+                                     const int32_t* __restrict__ nodeprob, int32_t* __restrict__ dprob,
+                                     const double* __restrict__ deltaprob, int32_t* __restrict__ exhausted,
+                                     double* __restrict__ gws, const int64_t* __restrict__ gws_off) {
   extern __shared__ double smem[];
   __shared__ double s_tau, s_beta;
   const int i = blockIdx.x;
@@ -899,13 +940,18 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
   const int tid = threadIdx.x, nt = blockDim.x;
   const int dcur = dprob[pr];
   const int inc = incprob[pr];
+  const int p = ovprob[pr];
   const double delta = deltaprob[pr];
-  // first admissible count with m <= d'
-  int dfirst = -1;
-  if (m <= dcur) dfirst = dcur;
-  else if (inc > 0 && dcur + ((m - dcur + inc - 1) / inc) * inc <= dsk) dfirst = dcur + ((m - dcur + inc - 1) / inc) * inc;
-  const int ncols = min(m, dsk);  // R_ii exists for i < min(m, dsk)
-  if (dfirst == dcur || ncols == 0) {
+  // smallest admissible count d' >= x (grid dcur + j*inc), or -1 beyond dsk
+  auto grid_at_least = [&](int x) {
+    if (x <= dcur) return dcur;
+    const int g = dcur + ((x - dcur + inc - 1) / inc) * inc;
+    return g <= dsk ? g : -1;
+  };
+  // first admissible count with every row resolved (m + p <= d')
+  const int dfirst = grid_at_least(m + p);
+  const int ncols = min(m, dsk - p);  // R_ii tested for i < d' - p <= dsk - p
+  if (dfirst == dcur || ncols <= 0) {
     if (tid == 0) {
       if (dfirst < 0) atomicOr(&exhausted[pr], 1);
       else atomicMax(&dprob[pr], dfirst);
@@ -947,13 +993,12 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
     }
     __syncthreads();
     mn = fmin(mn, fabs(s_beta));
-    // column count j+1 is a candidate if it lies on the grid
-    const int dd = j + 1;
-    if (dd >= dcur && (dd - dcur) % inc == 0 && mn < delta) {
-      found = dd;
+    // a diagonal below delta among the first j+1: converged at the first grid count >= j + 1 + p
+    if (mn < delta) {
+      found = grid_at_least(j + 1 + p);
       break;
     }
-    if (dfirst > 0 && dd >= dfirst) break;  // m <= d' reached first
+    if (dfirst > 0 && j + 1 + p >= dfirst) break;  // m + p <= d' reached first
     const double tau = s_tau;
     for (int c = j + 1 + tid; c < ncols; c += nt) {
       double* pc = P + c * ldp;
@@ -1628,7 +1673,9 @@ hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int
                          const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
-  const size_t lds = size_t((max_m + 3) & ~3) * NB * 16 * sizeof(double);
+  const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
+  if (rt * NB > 4) return hipErrorInvalidValue;
+  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * (F32 ? sizeof(float) : sizeof(double));
   hipError_t e = hipSuccess;
 #define H2_BSR_RT(RT)                                                                                    \
   if ((e = allow_lds(bsr_gemm_kernel<NB, RT, F32, TR>, lds)) != hipSuccess) return e;                    \
@@ -1651,10 +1698,11 @@ template <bool F32>
 hipError_t bsr_gemm_p(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                       const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
-  // at most 64 columns per workgroup, and at most 64 KB of staged X
+  // at most 64 columns per workgroup; RT * NB <= 4 keeps the two staged X
+  // tiles within 64 KB and the per-thread staging within 16 values
   int nb = (nc + 15) / 16;
-  if (nb > 4) nb = 4;
-  while (nb > 1 && size_t((max_m + 3) & ~3) * nb * 16 * sizeof(double) > 65536) --nb;
+  const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
+  if (nb > 4 / rt) nb = 4 / rt;
 #define H2_BSR_NB(NB)                                                                                         \
   (tpos ? launch_bsr_nb<NB, false, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy,   \
                                          nc, alpha, max_m)                                                          \
@@ -1690,20 +1738,22 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
                    precision);
 }
 
-hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
+hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d, int p,
                    double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m, size_t lds_limit,
                    double* gws, const int64_t* gws_off) {
   if (nnodes <= 0) return hipSuccess;
+  if (p < 0) return hipErrorInvalidValue;
   const int threads = d <= 64 ? 64 : (d <= 128 ? 128 : 256);
   const size_t bytes = size_t(max_m | 1) * size_t(d) * sizeof(double);
   if (bytes <= lds_limit) {
     hipError_t e = allow_lds(qr_test_kernel<true>, bytes);
     if (e != hipSuccess) return e;
-    qr_test_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, delta, conv, minr, unconverged, gws,
+    qr_test_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, p, delta, conv, minr, unconverged, gws,
                                                         gws_off);
   } else {
     if (!gws || !gws_off) return hipErrorInvalidValue;
-    qr_test_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, d, delta, conv, minr, unconverged, gws, gws_off);
+    qr_test_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, d, p, delta, conv, minr, unconverged, gws,
+                                                     gws_off);
   }
   return hipGetLastError();
 }
@@ -1844,20 +1894,21 @@ hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, cons
 }
 
 hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int dsk,
-                         const int32_t* incprob, const int32_t* nodeprob, int32_t* dprob, const double* deltaprob,
-                         int32_t* exhausted, int max_m, size_t lds_limit, double* gws, const int64_t* gws_off) {
+                         const int32_t* incprob, const int32_t* ovprob, const int32_t* nodeprob, int32_t* dprob,
+                         const double* deltaprob, int32_t* exhausted, int max_m, size_t lds_limit, double* gws,
+                         const int64_t* gws_off) {
   if (nnodes <= 0) return hipSuccess;
   const int threads = dsk <= 64 ? 64 : (dsk <= 128 ? 128 : 256);
   const size_t bytes = size_t(max_m | 1) * size_t(dsk) * sizeof(double);
   if (bytes <= lds_limit) {
     hipError_t e = allow_lds(qr_first_conv_kernel<true>, bytes);
     if (e != hipSuccess) return e;
-    qr_first_conv_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, dsk, incprob, nodeprob, dprob,
-                                                              deltaprob, exhausted, gws, gws_off);
+    qr_first_conv_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob,
+                                                              dprob, deltaprob, exhausted, gws, gws_off);
   } else {
     if (!gws || !gws_off) return hipErrorInvalidValue;
-    qr_first_conv_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, dsk, incprob, nodeprob, dprob,
-                                                           deltaprob, exhausted, gws, gws_off);
+    qr_first_conv_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob,
+                                                           dprob, deltaprob, exhausted, gws, gws_off);
   }
   return hipGetLastError();
 }

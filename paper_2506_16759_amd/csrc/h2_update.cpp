@@ -347,8 +347,9 @@ class UpdateBuilder {
       for (Level* L : {&Lr, &Lc}) {
         const size_t qbytes = size_t(L->max_m | 1) * size_t(d_) * sizeof(double);
         if (qbytes > ctx_->lds_limit) ensure_gws(L->nn, L->max_m, d_);
-        H2_HIP(h2dev::qr_test(s_, L->nn, L->rowoff.get(), L->y.get(), L->M, d_, h.delta, conv_.get(), minr_.get(),
-                              counter_.get(), L->max_m, ctx_->lds_limit, gws_.get(), gws_off_.get()));
+        H2_HIP(h2dev::qr_test(s_, L->nn, L->rowoff.get(), L->y.get(), L->M, d_, h.opts.oversample, h.delta,
+                              conv_.get(), minr_.get(), counter_.get(), L->max_m, ctx_->lds_limit, gws_.get(),
+                              gws_off_.get()));
       }
       const int32_t unconv = download(counter_.get(), 1, s_)[0];
       timer_.end(ph);
@@ -452,11 +453,12 @@ class UpdateBuilder {
 void check_update_opts(const h2_opts* o) {
   H2_REQUIRE(o != nullptr, "opts is NULL");
   H2_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be finite and > 0");
-  H2_REQUIRE(o->d0 >= 1 && o->d0 <= 128, "d0 must be in [1, 128]");
+  H2_REQUIRE(o->d0 >= 1 && o->d0 <= 256, "d0 must be in [1, 256]");
   H2_REQUIRE(o->d_inc >= 1 && o->d_inc <= 128, "d_inc must be in [1, 128]");
-  H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 128, "d_max must be in [d0, 128]");
+  H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 256, "d_max must be in [d0, 256]");
   H2_REQUIRE(o->norm_mode == H2_NORM_FRO_SCALED || o->norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
-  H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 128, "sketch_ahead must be in [0, 128]");
+  H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 256, "sketch_ahead must be in [0, 256]");
+  H2_REQUIRE(o->oversample >= 0 && o->oversample <= 64, "oversample must be in [0, 64]");
   if (o->precision != H2_FP64) throw Error(H2_ERR_UNSUPPORTED, "updates are built in FP64 only");
 }
 

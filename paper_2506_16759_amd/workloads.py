@@ -103,7 +103,7 @@ class UpdateWorkload:
     tol: float = 1e-6
     d0: int = 32
     d_inc: int = 16
-    d_max: int = 128
+    d_max: int = 256
 
     @property
     def n(self) -> int:

@@ -34,7 +34,8 @@ def test_status_strings_and_defaults():
     lib = _lib.load()
     assert lib.h2_status_string(-5).decode() == "adaptive sampling reached d_max"
     o = h2.opts_default()
-    assert (o.tol, o.leaf_size, o.eta, o.d0, o.d_inc, o.d_max) == (1e-6, 64, 0.7, 32, 16, 128)
+    assert (o.tol, o.leaf_size, o.eta, o.d0, o.d_inc, o.d_max) == (1e-6, 64, 0.7, 32, 16, 256)
+    assert (o.sketch_ahead, o.oversample) == (32, 5)
 
 
 def _compare_plan(pts, leaf, eta):

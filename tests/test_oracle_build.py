@@ -156,3 +156,21 @@ def test_degenerate_inputs():
     h = build_h2(op, pts, leaf_size=16, eta=1e-12)       # nothing admissible
     np.testing.assert_array_equal(h.dense(), op.dense())
     assert h.samples == 0
+
+
+def test_convergence_test_keeps_an_oversampling_margin():
+    from oracle.build import converged
+    rng = np.random.default_rng(0)
+    m = 20
+    A = rng.standard_normal((m, 300))               # full rank block row
+    for d in (20, 22, 24):
+        Y = A @ rng.standard_normal((300, d))
+        assert converged(Y, 1e-8, 0) == (m <= d)    # bare test: converged once d >= m
+        assert not converged(Y, 1e-8, 5)            # margin 5: needs d >= m + 5
+    Y = A @ rng.standard_normal((300, 25))
+    assert converged(Y, 1e-8, 5)
+    # a rank-6 block row converges as soon as a diagonal below delta appears
+    # among the leading d - p columns
+    B = rng.standard_normal((m, 6)) @ rng.standard_normal((6, 300))
+    Y = B @ rng.standard_normal((300, 12))
+    assert converged(Y, 1e-8, 5) and not converged(Y[:, :11], 1e-8, 5)

@@ -117,3 +117,18 @@ def test_update_of_h2_matrix(small):
     np.testing.assert_array_equal(hu.tree.perm, hs.tree.perm)
     with pytest.raises(ValueError):
         update_h2(hs, pts, U, V, 16, 0.7, tol, 16, 8)
+
+
+def test_update_with_full_rank_leaves_meets_tolerance():
+    """A rank-64 update makes every 64-point leaf block row full rank: the
+    convergence test must keep an oversampling margin, or nearly square
+    Gaussian sketches truncate such blocks (error ~70 tol without the margin)."""
+    from paper_2506_16759_amd.workloads import gaussian_factors
+    n, tol = 4096, 1e-6
+    pts = uniform_points(n, 3, 2)
+    op = KernelOperator(pts, "exp", 0.2)
+    h = build_h2(op, pts, 64, 0.7, tol, 32, 16, 256, 1001)
+    U, V = gaussian_factors(n, 64, 3)
+    hu = update_h2(h, pts, U, V, 64, 0.7, tol, 32, 16, 256, 1002)
+    A = h.dense() + U @ V.T
+    assert np.linalg.norm(A - hu.dense()) / np.linalg.norm(A) <= 10 * tol
