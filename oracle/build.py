@@ -12,9 +12,10 @@ One level does:
   1. subtract the part already represented at this level (Alg. 1):
        leaf : Y_loc = Y^1_tau - sum_{b in N_tau} D_{tau,b} Omega^1_b, D_{tau,b} = K(I_tau, I_b)
        inner: Y_loc = Y^l_tau - [sum_{b in F_nu1} B_{nu1,b} Omega^l_b ; sum_{b in F_nu2} B_{nu2,b} Omega^l_b]
-  2. adaptive test (Sec. III-B): a cluster is converged when m_tau <= d or the
-     smallest |R_ii| of the unpivoted QR of Y_loc is below the absolute threshold
-     delta.  While some cluster is not converged, d_inc new columns are drawn,
+  2. adaptive test (Sec. III-B): a cluster is converged when the smallest |R_ii|
+     of the unpivoted QR of the leading d - p columns of Y_loc is below the
+     absolute threshold delta, or when m_tau + p <= d (p = oversampling margin,
+     see ``converged``).  While some cluster is not converged, d_inc new columns are drawn,
      sketched and swept up through the levels already finished with the stored
      factors (updateSamples), then appended to Y_loc and Omega^l of this level.
   3. row ID of Y_loc (Sec. II-B):  Y_loc ~= U Y_loc(J, :)   (leaf U_tau, or the
