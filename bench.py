@@ -91,6 +91,12 @@ def bench_batched(h2, ctx, steps: int = 2):
              for w in ws]
     res = {"problems": len(ws), "total_n": int(sum(w.n for w in ws)),
            "sum_n2": float(sum(float(w.n) ** 2 for w in ws))}
+    t0 = time.perf_counter()
+    leaves = h2.autotune_leaf(ctx, probs, candidates=(32, 64, 128), d_max=96)
+    res["autotune_ms"] = (time.perf_counter() - t0) * 1e3
+    res["leaf_sizes"] = {str(c): leaves.count(c) for c in (32, 64, 128)}
+    for p, leaf in zip(probs, leaves):
+        p["leaf_size"] = leaf
     for name, prec in (("fp64", h2.FP64), ("fp32", h2.FP32)):
         times, info = [], None
         for i in range(steps + 1):

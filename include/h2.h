@@ -273,6 +273,17 @@ typedef struct {
 h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
                            h2_matrix** out, h2_batch_info* info);
 
+/* Leaf-size autotuner for h2_build_batched: problems are grouped by (dim,
+ * kernel kind, floor(log2 n)); the median-n problem of each group is built
+ * alone with every candidate leaf size (twice; the second build's device time
+ * counts) and the fastest candidate is written to best[i] for every problem i
+ * of the group.  problems' own leaf_size is ignored; opts as for
+ * h2_build_batched.  candidates: HOST int32[ncand], each in [2, 256]; best:
+ * HOST int32[count].  Candidates that reach d_max are skipped; if none
+ * converges the call fails with H2_ERR_SAMPLES.  Synchronous. */
+h2_status h2_autotune_leaf(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
+                           const int32_t* candidates, int32_t ncand, int32_t* best);
+
 /* ------------------------------------------------------------ low-rank update */
 
 /* H^2 approximation of A = H + U V^T on the partition of H (same points,

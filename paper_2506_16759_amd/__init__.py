@@ -19,7 +19,7 @@ from . import _lib
 from ._lib import BF16X3, FP32, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
-           "build_update",
+           "build_update", "autotune_leaf",
            "H2Matrix",
            "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "NORM_FRO_SCALED",
            "NORM_LITERAL"]
@@ -208,17 +208,8 @@ def build(ctx: Context, points, kernel="exp", length: float = 0.2, opts: _lib.Op
     return H2Matrix(ctx, h, n)
 
 
-def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_graph: bool = True,
-                  return_info: bool = False):
-    """Many independent constructions in one launch sequence (h2_build_batched).
-
-    problems: sequence of dicts with keys points ((dim, n) array or tensor),
-    kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
-    norm_mode, oversample (defaults as h2_opts_default).  Returns a list of H2Matrix (and
-    the batch info dict when return_info)."""
+def _problem_array(problems):
     torch = _torch()
-    if isinstance(precision, str):
-        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[precision]
     d = opts_default()
     arr = (_lib.Problem * len(problems))()
     keep = []
@@ -233,6 +224,34 @@ def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_g
                               pr.get("tol", d.tol), pr.get("leaf_size", d.leaf_size), pr.get("eta", d.eta),
                               pr.get("d0", d.d0), pr.get("d_inc", d.d_inc), pr.get("seed", d.seed), nm,
                               pr.get("oversample", d.oversample))
+    return arr, keep
+
+
+def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP64, d_max: int = 96):
+    """Leaf size per problem from h2_autotune_leaf (problems as for build_batched)."""
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[precision]
+    arr, keep = _problem_array(problems)
+    cand = (C.c_int32 * len(candidates))(*candidates)
+    best = (C.c_int32 * len(problems))()
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1)
+    _lib.check(_lib.load().h2_autotune_leaf(ctx._h, len(problems), arr, C.byref(bo), cand, len(candidates), best),
+               "h2_autotune_leaf")
+    del keep
+    return [int(b) for b in best]
+
+
+def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_graph: bool = True,
+                  return_info: bool = False):
+    """Many independent constructions in one launch sequence (h2_build_batched).
+
+    problems: sequence of dicts with keys points ((dim, n) array or tensor),
+    kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
+    norm_mode, oversample (defaults as h2_opts_default).  Returns a list of H2Matrix (and
+    the batch info dict when return_info)."""
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}[precision]
+    arr, keep = _problem_array(problems)
     bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0)
     handles = (C.c_void_p * len(problems))()
     info = _lib.BatchInfo()

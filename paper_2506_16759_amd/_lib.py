@@ -90,6 +90,8 @@ _SIGS = {
     "h2_build_batched": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(_P),
                          C.POINTER(BatchInfo)],
     "h2_build_update": [_P, _P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.POINTER(Opts), C.POINTER(_P)],
+    "h2_autotune_leaf": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(C.c_int32), C.c_int32,
+                         C.POINTER(C.c_int32)],
 }
 EXPORTED = tuple(_SIGS)
 

@@ -15,8 +15,11 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
+#include <map>
 #include <string>
 #include <thread>
+#include <tuple>
 
 #include "h2_internal.hpp"
 
@@ -621,6 +624,59 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       r.device_bytes = bytes;
       r.sketch_flops = sketch_flops;
       *info = r;
+    }
+  });
+}
+
+// Leaf-size autotuner for batched builds.  Problems are grouped by (dim,
+// kernel kind, floor(log2 n)); for each group the problem of median n is built
+// alone (as a one-problem batch, graph launch) with every candidate leaf size,
+// twice, and the candidate with the smallest device time of the second build
+// is assigned to every problem of the group.  Candidates whose build fails
+// (e.g. the sample cap is reached) are skipped.
+extern "C" h2_status h2_autotune_leaf(h2_ctx* ctx, int32_t count, const h2_problem* problems,
+                                      const h2_batch_opts* opts, const int32_t* candidates, int32_t ncand,
+                                      int32_t* best) {
+  return guarded([&] {
+    H2_REQUIRE(ctx && problems && opts && candidates && best, "NULL argument");
+    H2_REQUIRE(count >= 1 && ncand >= 1, "count and ncand must be >= 1");
+    for (int c = 0; c < ncand; ++c)
+      H2_REQUIRE(candidates[c] >= 2 && candidates[c] <= 256, "candidate leaf sizes must be in [2, 256]");
+    for (int i = 0; i < count; ++i) check_problem(problems[i]);
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < count; ++i) {
+      const auto& p = problems[i];
+      const int lg = static_cast<int>(std::floor(std::log2(double(p.n))));
+      groups[{p.dim, p.kernel.kind, lg}].push_back(i);
+    }
+    for (auto& [key, members] : groups) {
+      std::vector<int> ord = members;
+      std::sort(ord.begin(), ord.end(), [&](int a, int b) { return problems[a].n < problems[b].n; });
+      h2_problem rep = problems[ord[ord.size() / 2]];
+      int choice = -1;
+      double tbest = 0;
+      for (int c = 0; c < ncand; ++c) {
+        rep.leaf_size = candidates[c];
+        double t = -1;
+        for (int rep_i = 0; rep_i < 2; ++rep_i) {
+          h2_matrix* m = nullptr;
+          h2_batch_info info{};
+          const h2_status st = h2_build_batched(ctx, 1, &rep, opts, &m, &info);
+          if (st != H2_OK) {
+            if (st != H2_ERR_SAMPLES) throw Error(st, std::string("autotune build: ") + h2_last_error());
+            t = -1;
+            break;
+          }
+          h2_free(m);
+          t = info.t_device_ms;
+        }
+        if (t >= 0 && (choice < 0 || t < tbest)) {
+          choice = candidates[c];
+          tbest = t;
+        }
+      }
+      if (choice < 0) throw Error(H2_ERR_SAMPLES, "autotune: no candidate leaf size converged within d_max");
+      for (int i : members) best[i] = choice;
     }
   });
 }

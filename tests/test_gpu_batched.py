@@ -193,3 +193,30 @@ def test_batched_covariance_workload_sampled(ctx):
         assert e <= 10 * w.tol
     for H in mats:
         H.close()
+
+
+def test_autotuned_leaf_sizes(ctx):
+    """The autotuner returns one of the candidates for every problem, the same
+    one within a (dim, kernel, log2 n) group, and the tuned batch is accurate."""
+    ws = batch_problems(count=10, seed=11)
+    probs = [dict(points=w.points(), kernel=w.kernel, length=w.length, tol=w.tol, eta=w.eta, d0=w.d0,
+                  d_inc=w.d_inc, seed=w.omega_seed) for w in ws]
+    _say(f"autotune leaf sizes for n={[w.n for w in ws]}")
+    leaves = h2.autotune_leaf(ctx, probs, candidates=(32, 64, 128), d_max=96)
+    _say(f"tuned leaves {leaves}")
+    assert all(l in (32, 64, 128) for l in leaves)
+    groups = {}
+    for w, l in zip(ws, leaves):
+        groups.setdefault((w.dim, w.kernel, int(np.floor(np.log2(w.n)))), set()).add(l)
+    assert all(len(v) == 1 for v in groups.values())
+    for p, l in zip(probs, leaves):
+        p["leaf_size"] = l
+    mats = h2.build_batched(ctx, probs, d_max=96)
+    for w, p, H in zip(ws, probs, mats):
+        op = KernelOperator(p["points"], w.kernel, w.length)
+        rows = np.random.default_rng(w.n).choice(w.n, 16, replace=False)
+        x = np.random.default_rng(1).standard_normal((w.n, 2))
+        y = _np(H.matvec(_colmajor_from(x)))
+        kx = op.entries(rows, np.arange(w.n)) @ x
+        assert np.linalg.norm(y[rows] - kx) / np.linalg.norm(kx) <= 10 * w.tol
+        H.close()

@@ -128,3 +128,15 @@ def test_batched_build_rejects_bad_arguments_before_any_device_work():
     assert lib.h2_build_batched(None, 1, prob, C.byref(bo), handles, None) == -1
     assert "NULL" in lib.h2_last_error().decode()
     assert handles[0] is None
+
+
+def test_autotune_rejects_bad_arguments_before_any_device_work():
+    import ctypes as C
+
+    from paper_2506_16759_amd import _lib
+    lib = _lib.load()
+    prob = (_lib.Problem * 1)()
+    bo = _lib.BatchOpts(0, 64, 1)
+    cand = (C.c_int32 * 1)(64)
+    best = (C.c_int32 * 1)()
+    assert lib.h2_autotune_leaf(None, 1, prob, C.byref(bo), cand, 1, best) == -1
