@@ -152,7 +152,8 @@ def bench_update(h2, ctx, n: int = 1 << 16):
     for i in range(2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Hu = h2.build_update(ctx, H, Ut, Vt, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+        Hu = h2.build_update(ctx, H, Ut, Vt, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed,
+                             oversample=w.oversample)
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) * 1e3)
         info = Hu.info()

@@ -92,7 +92,11 @@ typedef struct {
   int32_t oversample;   /* p, 0..64: the convergence test looks at the leading d - p sample
                          * columns only (a cluster with m + p <= d is converged), so the ID
                          * always has p samples beyond the rank it detects (Sec. III-A's
-                         * oversampling).  p = 0 is the bare test of Sec. III-B. */
+                         * oversampling).  p = 0 is the bare test of Sec. III-B, enough for
+                         * kernel matrices (fast singular-value decay); operators with flat
+                         * spectra such as low-rank updates need p >= 4: with p = 0 the
+                         * nearly square sketch of a full-rank block shows a spuriously
+                         * small trailing diagonal and the block is truncated. */
 } h2_opts;
 
 typedef struct h2_ctx h2_ctx;
@@ -100,7 +104,7 @@ typedef struct h2_matrix h2_matrix;
 typedef struct h2_plan h2_plan;
 
 /* Fills defaults: tol 1e-6, leaf 64, eta 0.7, d0 32, d_inc 16, d_max 256,
- * seed 1000, FP64, FRO_SCALED, sketch_ahead 32, oversample 5. */
+ * seed 1000, FP64, FRO_SCALED, sketch_ahead 32, oversample 0. */
 h2_status h2_opts_default(h2_opts* opts);
 
 const char* h2_status_string(h2_status s);
@@ -299,9 +303,10 @@ h2_status h2_autotune_leaf(h2_ctx* ctx, int32_t count, const h2_problem* problem
  *          blocks become shared with the result and live until both are freed.
  *   U, V:  DEVICE n x rank (ld >= n), ORIGINAL point order, borrowed for the
  *          call; 0 <= rank <= 128 (NULL allowed when rank = 0).
- *   opts:  tol, d0, d_inc, d_max, seed, norm_mode and sketch_ahead are used;
- *          leaf_size and eta are taken from old; precision must be H2_FP64
- *          (else H2_ERR_UNSUPPORTED).
+ *   opts:  tol, d0, d_inc, d_max, seed, norm_mode, sketch_ahead and oversample
+ *          are used (use oversample >= 4: the update's block rows have flat
+ *          spectra); leaf_size and eta are taken from old; precision must be
+ *          H2_FP64 (else H2_ERR_UNSUPPORTED).
  * The result is two-sided: h2_matvec applies A, the *_C parts export its
  * column side.  Synchronous. */
 h2_status h2_build_update(h2_ctx* ctx, h2_matrix* old, int32_t rank, const double* U, int64_t ldu,

@@ -244,6 +244,6 @@ class _Builder:
 
 def build_h2(op, points: np.ndarray, leaf_size: int = 64, eta: float = 0.7, tol: float = 1e-6,
              d0: int = 32, d_inc: int = 16, d_max: int = 1024, seed: int = 1000,
-             norm_mode: str = "fro_scaled", oversample: int = 5) -> H2Matrix:
+             norm_mode: str = "fro_scaled", oversample: int = 0) -> H2Matrix:
     """Build the H^2 matrix of ``op`` on ``points`` (dim, n) with Alg. 1 + adaptive sampling."""
     return _Builder(op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, norm_mode, oversample).run()

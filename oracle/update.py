@@ -71,7 +71,7 @@ class _Side:
 
 
 class _TwoSidedBuilder:
-    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, seed_c, norm_mode, oversample=5):
+    def __init__(self, op, points, leaf_size, eta, tol, d0, d_inc, d_max, seed, seed_c, norm_mode, oversample=0):
         self.op = op
         self.oversample = oversample
         self.tree = build_tree(points, leaf_size)
@@ -247,7 +247,7 @@ class _TwoSidedBuilder:
 
 def build_h2_two_sided(op, points: np.ndarray, leaf_size: int = 64, eta: float = 0.7, tol: float = 1e-6,
                        d0: int = 32, d_inc: int = 16, d_max: int = 1024, seed: int = 1000,
-                       seed_c: int | None = None, norm_mode: str = "fro_scaled", oversample: int = 5) -> H2Matrix:
+                       seed_c: int | None = None, norm_mode: str = "fro_scaled", oversample: int = 0) -> H2Matrix:
     """Two-sided Alg. 1 + adaptive sampling for a non-symmetric ``op`` (needs
     op.sketch, op.sketch_t and op.entries).  seed_c defaults to seed + 1."""
     sc = seed + 1 if seed_c is None else seed_c
@@ -258,7 +258,7 @@ def build_h2_two_sided(op, points: np.ndarray, leaf_size: int = 64, eta: float =
 def update_h2(h_old: H2Matrix, points: np.ndarray, U: np.ndarray, V: np.ndarray, leaf_size: int = 64,
               eta: float = 0.7, tol: float = 1e-6, d0: int = 32, d_inc: int = 16, d_max: int = 1024,
               seed: int = 1002, seed_c: int | None = None, norm_mode: str = "fro_scaled",
-              oversample: int = 5) -> H2Matrix:
+              oversample: int = 0) -> H2Matrix:
     """H^2 approximation of K_H + U V^T, built two-sided from the H^2 black box on
     the partition of ``h_old`` (same points, leaf size and eta)."""
     op = LowRankUpdateOperator(h_old, U, V)

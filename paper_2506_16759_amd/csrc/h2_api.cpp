@@ -528,7 +528,7 @@ h2_status h2_opts_default(h2_opts* o) {
     o->precision = H2_FP64;
     o->norm_mode = H2_NORM_FRO_SCALED;
     o->sketch_ahead = 32;
-    o->oversample = 5;
+    o->oversample = 0;
   });
 }
 

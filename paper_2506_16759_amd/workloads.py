@@ -104,6 +104,7 @@ class UpdateWorkload:
     d0: int = 32
     d_inc: int = 16
     d_max: int = 256
+    oversample: int = 5   # flat spectra of the update's block rows need a sampling margin
 
     @property
     def n(self) -> int:

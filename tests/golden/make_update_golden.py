@@ -30,7 +30,8 @@ def main():
     h = build_h2(KernelOperator(pts, b.kernel, b.length), pts, b.leaf_size, b.eta, b.tol, b.d0, b.d_inc, 128,
                  b.omega_seed)
     U, V = w.factors()
-    hu = update_h2(h, pts, U, V, b.leaf_size, b.eta, w.tol, w.d0, w.d_inc, w.d_max, w.omega_seed)
+    hu = update_h2(h, pts, U, V, b.leaf_size, b.eta, w.tol, w.d0, w.d_inc, w.d_max, w.omega_seed,
+                   oversample=w.oversample)
     x = gaussian_vectors(w.n, 2, 21)
     rows = np.sort(np.random.default_rng(22).choice(w.n, 64, replace=False))
     y_upd = hu.matvec(x)[rows]

@@ -92,7 +92,7 @@ def test_update_matches_oracle_small(ctx):
     H = h2.build(ctx, pts, "exp", 0.2, tol=tol, leaf_size=32, eta=0.7, d0=16, d_inc=16, seed=7)
     U, V = gaussian_factors(n, r, 52)
     U = 30.0 * U          # an update that matters at this tolerance
-    Hu = h2.build_update(ctx, H, U, V, tol=tol, d0=16, d_inc=16, d_max=128, seed=9)
+    Hu = h2.build_update(ctx, H, U, V, tol=tol, d0=16, d_inc=16, d_max=128, seed=9, oversample=5)
     info = Hu.info()
     _say(f"gpu update: samples={info['samples']} rounds={info['rounds']} ranks={info['rank_min']}..{info['rank_max']}")
     # partition and exact parts
@@ -122,7 +122,7 @@ def test_update_matches_oracle_small(ctx):
     e_self = np.linalg.norm(Au - A_gpu) / np.linalg.norm(A_gpu)
     op = KernelOperator(pts, "exp", 0.2)
     ho = build_h2(op, pts, 32, 0.7, tol, 16, 16, 128, 7)
-    hou = update_h2(ho, pts, U, V, 32, 0.7, tol, 16, 16, 128, 9)
+    hou = update_h2(ho, pts, U, V, 32, 0.7, tol, 16, 16, 128, 9, oversample=5)
     A_or = ho.dense() + U @ V.T
     e_or = np.linalg.norm(Au - hou.dense()) / np.linalg.norm(A_or)
     e_ref = np.linalg.norm(Au - A_or) / np.linalg.norm(A_or)
@@ -150,7 +150,7 @@ def test_update_rank_zero_recompresses(ctx):
     _say(f"rank-0 update n={n}")
     pts = uniform_points(n, 2, 61)
     H = h2.build(ctx, pts, "gauss", 0.1, tol=tol, leaf_size=40, d0=16, d_inc=16, seed=1)
-    Hu = h2.build_update(ctx, H, None, None, tol=tol, d0=16, d_inc=16, seed=2)
+    Hu = h2.build_update(ctx, H, None, None, tol=tol, d0=16, d_inc=16, seed=2, oversample=5)
     A = _dense_from_matvec(H, n)
     e = np.linalg.norm(_dense_from_matvec(Hu, n) - A) / np.linalg.norm(A)
     _say(f"rank-0 error {e:.3e} samples {Hu.info()['samples']}")
@@ -166,7 +166,8 @@ def test_update_workload_n16384_against_oracle_golden(ctx):
     H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
                  d_inc=b.d_inc, seed=b.omega_seed)
     U, V = w.factors()
-    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed,
+                         oversample=w.oversample)
     info = Hu.info()
     _say(f"gpu: old samples {H.info()['samples']} update samples {info['samples']} ({info['t_total']:.1f} ms); "
          f"oracle: {g['old_samples']} / {g['samples']}")
@@ -203,7 +204,8 @@ def test_update_workload_any_size_property(ctx, n):
     H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
                  d_inc=b.d_inc, seed=b.omega_seed)
     U, V = w.factors()
-    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed)
+    Hu = h2.build_update(ctx, H, U, V, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed,
+                         oversample=w.oversample)
     info = Hu.info()
     _say(f"update built in {info['t_total']:.1f} ms, samples {info['samples']}, ranks {info['rank_min']}.."
          f"{info['rank_max']}")
@@ -223,7 +225,7 @@ def test_update_error_paths(ctx):
     with pytest.raises(h2.H2Error) as ei:
         h2.build_update(ctx, H, U, V, precision="fp32")
     assert ei.value.status == -7
-    Hu = h2.build_update(ctx, H, U, V)
+    Hu = h2.build_update(ctx, H, U, V, oversample=5)
     with pytest.raises(h2.H2Error) as ei:
         h2.build_update(ctx, Hu, U, V)
     assert ei.value.status == -7
@@ -233,7 +235,7 @@ def test_update_error_paths(ctx):
     Hu.close()
     np.testing.assert_array_equal(_np(H.matvec(x)), y0)
     # the update stays usable after the old matrix is freed (shared dense blocks)
-    Hu2 = h2.build_update(ctx, H, U, V)
+    Hu2 = h2.build_update(ctx, H, U, V, oversample=5)
     y1 = _np(Hu2.matvec(x))
     H.close()
     np.testing.assert_array_equal(_np(Hu2.matvec(x)), y1)

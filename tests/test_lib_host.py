@@ -35,7 +35,7 @@ def test_status_strings_and_defaults():
     assert lib.h2_status_string(-5).decode() == "adaptive sampling reached d_max"
     o = h2.opts_default()
     assert (o.tol, o.leaf_size, o.eta, o.d0, o.d_inc, o.d_max) == (1e-6, 64, 0.7, 32, 16, 256)
-    assert (o.sketch_ahead, o.oversample) == (32, 5)
+    assert (o.sketch_ahead, o.oversample) == (32, 0)
 
 
 def _compare_plan(pts, leaf, eta):

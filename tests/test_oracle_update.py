@@ -129,6 +129,9 @@ def test_update_with_full_rank_leaves_meets_tolerance():
     op = KernelOperator(pts, "exp", 0.2)
     h = build_h2(op, pts, 64, 0.7, tol, 32, 16, 256, 1001)
     U, V = gaussian_factors(n, 64, 3)
-    hu = update_h2(h, pts, U, V, 64, 0.7, tol, 32, 16, 256, 1002)
+    hu = update_h2(h, pts, U, V, 64, 0.7, tol, 32, 16, 256, 1002, oversample=5)
     A = h.dense() + U @ V.T
     assert np.linalg.norm(A - hu.dense()) / np.linalg.norm(A) <= 10 * tol
+    # without the margin the full-rank leaves are truncated
+    hu0 = update_h2(h, pts, U, V, 64, 0.7, tol, 32, 16, 256, 1002, oversample=0)
+    assert np.linalg.norm(A - hu0.dense()) / np.linalg.norm(A) > 10 * tol
