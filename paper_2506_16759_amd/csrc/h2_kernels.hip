@@ -1529,49 +1529,98 @@ __global__ __launch_bounds__(256) void basis_rows_kernel(int leaf, const int32_t
 
 // Coupling of the update at an admissible pair (s, b):
 //   B_new = R_r_s B_old(s, b) R_c_b^T + U(skel_r_s, :) V(skel_c_b, :)^T
-// (k_r_s x k_c_b, column-major at boff_new[j]).  One workgroup per block row;
-// B_old R_c_b^T is formed 32 columns at a time in LDS.
+// (k_r_s x k_c_b, column-major at boff_new[j]).  One workgroup per pair, on the
+// FP64 matrix cores, 32 output columns at a time:
+//   T      = B_old(s, b) R_c_b(cols)^T              (k_old_s x 32, in LDS)
+//   B_new  = [R_r_s | U_r] [T ; V_c(cols)^T]          (inner dim k_old_s + r)
+// Wave w owns output column tile (w & 1) and every other group of four 16-row
+// tiles (w >> 1), so each B operand it loads feeds four MFMAs.
+// f64 16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16]; D[l/16 + 4q][l%16].
 constexpr int kCuCols = 32;
 constexpr int kCuMaxK = 128;
+constexpr int kCuLdt = kCuCols + 8;
 __global__ __launch_bounds__(256) void coupling_update_kernel(
-    const int32_t* __restrict__ fptr, const int32_t* __restrict__ fidx, const int32_t* __restrict__ koff_r,
+    const int32_t* __restrict__ frow, const int32_t* __restrict__ fidx, const int32_t* __restrict__ koff_r,
     const int32_t* __restrict__ koff_c, const int32_t* __restrict__ kold_off, const double* __restrict__ Bold,
     const int64_t* __restrict__ boff_old, const double* __restrict__ Rr, int64_t ldrr,
     const double* __restrict__ Rc, int64_t ldrc, const int32_t* __restrict__ pos_r,
     const int32_t* __restrict__ pos_c, const double* __restrict__ U, int64_t ldu, const double* __restrict__ V,
     int64_t ldv, int r, double* __restrict__ Bnew, const int64_t* __restrict__ boff_new) {
-  __shared__ double T[kCuMaxK * kCuCols];
-  const int s = blockIdx.x;
+  __shared__ double T[kCuMaxK * kCuLdt];
+  const int j = blockIdx.x;
+  const int s = frow[j], b = fidx[j];
   const int kr0 = koff_r[s], kr = koff_r[s + 1] - kr0;
+  const int kc0 = koff_c[b], kc = koff_c[b + 1] - kc0;
   const int kos = kold_off[s + 1] - kold_off[s];
-  for (int j = fptr[s]; j < fptr[s + 1]; ++j) {
-    const int b = fidx[j];
-    const int kc0 = koff_c[b], kc = koff_c[b + 1] - kc0;
-    const int kob = kold_off[b + 1] - kold_off[b];
-    const double* bo = Bold + boff_old[j];
-    double* out = Bnew + boff_new[j];
-    for (int c0 = 0; c0 < kc; c0 += kCuCols) {
-      const int w = min(kCuCols, kc - c0);
-      __syncthreads();
-      for (int e = threadIdx.x; e < kos * w; e += blockDim.x) {
-        const int p = e % kos, cc = e / kos;
-        const double* rc = Rc + kc0 + c0 + cc;
-        double acc = 0.0;
-        for (int q = 0; q < kob; ++q) acc += bo[int64_t(q) * kos + p] * rc[int64_t(q) * ldrc];
-        T[cc * kCuMaxK + p] = acc;
+  const int kob = kold_off[b + 1] - kold_off[b];
+  if (kr == 0 || kc == 0) return;  // uniform
+  const double* bo = Bold + boff_old[j];
+  double* out = Bnew + boff_new[j];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tn = wave & 1, half = wave >> 1;
+  const int kin = kos + r;
+  const int mt1 = (kos + 15) / 16, mt2 = (kr + 15) / 16;
+  for (int c0 = 0; c0 < kc; c0 += kCuCols) {
+    const int w = min(kCuCols, kc - c0);
+    const int ncol = tn * 16 + li;  // this lane's B column within the chunk
+    // ---- T = B_old R_c^T for the chunk's columns
+    for (int tm0 = 4 * half; tm0 < mt1; tm0 += 8) {
+      dbl4 acc[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < kob; k0 += 4) {
+        const int k = k0 + lk;
+        const double bv = (ncol < w && k < kob) ? Rc[(kc0 + c0 + ncol) + int64_t(k) * ldrc] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int m = (tm0 + u) * 16 + li;
+          const double a = (m < kos && k < kob) ? bo[m + int64_t(k) * kos] : 0.0;
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+        }
       }
-      __syncthreads();
-      for (int e = threadIdx.x; e < kr * w; e += blockDim.x) {
-        const int a = e % kr, cc = e / kr;
-        const double* rr = Rr + kr0 + a;
-        double acc = 0.0;
-        for (int p = 0; p < kos; ++p) acc += rr[int64_t(p) * ldrr] * T[cc * kCuMaxK + p];
-        const int64_t pr = pos_r[kr0 + a], pc = pos_c[kc0 + c0 + cc];
-        double lr = 0.0;
-        for (int q = 0; q < r; ++q) lr += U[int64_t(q) * ldu + pr] * V[int64_t(q) * ldv + pc];
-        out[int64_t(c0 + cc) * kr + a] = acc + lr;
-      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = (tm0 + u) * 16 + lk + 4 * q;
+          if (row < kos) T[row * kCuLdt + tn * 16 + li] = acc[u][q];
+        }
     }
+    __syncthreads();
+    // ---- B_new(:, chunk) = [R_r | U_r] [T ; V_c^T]
+    const int64_t pc = ncol < w ? pos_c[kc0 + c0 + ncol] : 0;
+    for (int tm0 = 4 * half; tm0 < mt2; tm0 += 8) {
+      dbl4 acc[4];
+      int64_t pr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+        const int m = (tm0 + u) * 16 + li;
+        pr[u] = m < kr ? pos_r[kr0 + m] : 0;
+      }
+      for (int k0 = 0; k0 < kin; k0 += 4) {
+        const int k = k0 + lk;
+        double bv = 0.0;
+        if (ncol < w && k < kin) bv = k < kos ? T[k * kCuLdt + ncol] : V[int64_t(k - kos) * ldv + pc];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int m = (tm0 + u) * 16 + li;
+          double a = 0.0;
+          if (m < kr && k < kin) a = k < kos ? Rr[(kr0 + m) + int64_t(k) * ldrr] : U[int64_t(k - kos) * ldu + pr[u]];
+          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = (tm0 + u) * 16 + lk + 4 * q;
+          const int col = tn * 16 + li;
+          if (row < kr && col < w) out[int64_t(c0 + col) * kr + row] = acc[u][q];
+        }
+    }
+    __syncthreads();
   }
 }
 
@@ -2016,15 +2065,15 @@ hipError_t basis_rows(hipStream_t s, int nnodes, bool leaf, const int32_t* koff,
   return hipGetLastError();
 }
 
-hipError_t coupling_update(hipStream_t s, int nnodes, const int32_t* fptr, const int32_t* fidx,
+hipError_t coupling_update(hipStream_t s, int npairs, const int32_t* frow, const int32_t* fidx,
                            const int32_t* koff_r, const int32_t* koff_c, const int32_t* kold_off, int max_kold,
                            const double* Bold, const int64_t* boff_old, const double* Rr, int64_t ldrr,
                            const double* Rc, int64_t ldrc, const int32_t* pos_r, const int32_t* pos_c,
                            const double* U, int64_t ldu, const double* V, int64_t ldv, int r, double* Bnew,
                            const int64_t* boff_new) {
-  if (nnodes <= 0) return hipSuccess;
+  if (npairs <= 0) return hipSuccess;
   if (max_kold > kCuMaxK) return hipErrorInvalidValue;
-  coupling_update_kernel<<<nnodes, 256, 0, s>>>(fptr, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
+  coupling_update_kernel<<<npairs, 256, 0, s>>>(frow, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
                                                 ldrc, pos_r, pos_c, U, ldu, V, ldv, r, Bnew, boff_new);
   return hipGetLastError();
 }

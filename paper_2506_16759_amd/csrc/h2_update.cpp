@@ -437,7 +437,13 @@ class UpdateBuilder {
     // the column-side level carries the same lists (export and matvec read the row side's)
     Lc.fptr_h = Lr.fptr_h;
     Lc.fidx_h = Lr.fidx_h;
-    H2_HIP(h2dev::coupling_update(s_, Lr.nn, Lr.fptr.get(), Lr.fidx.get(), Lr.koff.get(), Lc.koff.get(),
+    std::vector<int32_t> frow(Lr.fidx_h.size());
+    for (int a = 0; a < Lr.nn; ++a)
+      for (int j = Lr.fptr_h[a]; j < Lr.fptr_h[a + 1]; ++j) frow[j] = a;
+    DevArray<int32_t> frow_d;
+    frow_d.upload(frow, s_);
+    H2_HIP(h2dev::coupling_update(s_, static_cast<int>(frow.size()), frow_d.get(), Lr.fidx.get(), Lr.koff.get(),
+                                  Lc.koff.get(),
                                   Ho.koff.get(), Ho.max_k, Ho.B.get(), Ho.boff.get(), Rr_[t].get(),
                                   std::max<int64_t>(Lr.koff_h.back(), 1), Rc_[t].get(),
                                   std::max<int64_t>(Lc.koff_h.back(), 1), Lr.pos_out.get(), Lc.pos_out.get(),
