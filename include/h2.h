@@ -56,16 +56,22 @@ typedef struct {
   double length;  /* correlation length l > 0 */
 } h2_kernel;
 
-/* Arithmetic of the dense sketch (and, in later versions, the near-field
- * products).  Kernel blocks D and B are always evaluated and stored in FP64;
- * the stopping test, CPQR norm downdating and interpolation solve are FP64.
+/* Arithmetic of the dense sketch and of the leaf near-field product.  Kernel
+ * blocks D and B are always evaluated and stored in FP64; the stopping test,
+ * CPQR norm downdating and interpolation solve are FP64.
  *   H2_FP64:   FP64 entries, FP64 matrix cores.
  *   H2_FP32:   FP32 entries, FP32 matrix cores (FP32 partial sums folded into
- *              FP64 every 256 points).
+ *              FP64 every 256 points); near-field product on FP32 matrix cores.
+ *              The FP32 accumulation leaves ~1e-6 relative noise in the
+ *              samples, so tolerances near 1e-6 need extra samples.
  *   H2_BF16X3: FP32 entries split into bf16 hi + lo, three bf16 products
  *              (hi*hi + hi*lo + lo*hi) with FP32 accumulation, folded into FP64
- *              likewise; about 2^-16 relative error per product. */
-typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2 } h2_precision;
+ *              likewise; about 2^-16 relative error per product (tol >= ~1e-4).
+ *   H2_FP32E:  FP32 entries (the transcendental work), converted to FP64 and
+ *              contracted with the FP64 Omega on the FP64 matrix cores with FP64
+ *              accumulation; ~1e-7 relative entry noise, no accumulated
+ *              rounding; near-field product in FP64. */
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2, H2_FP32E = 3 } h2_precision;
 
 /* How the absolute ID/stopping threshold delta is derived from tol
  * (Sec. III-B: "an approximate norm of the matrix ... via sketching"):
@@ -262,6 +268,9 @@ typedef struct {
   int32_t graph_nodes; /* nodes of the captured graph (0 without a graph) */
   int64_t device_bytes;
   double sketch_flops; /* algorithmic 2 * n^2 * d_max summed over problems */
+  double t_layout_ms;  /* part of t_setup_ms: host layout of the batch */
+  double t_alloc_ms;   /* part of t_setup_ms: device allocation and uploads */
+  double t_results_ms; /* per-problem result objects after the device work */
 } h2_batch_info;
 
 /* Builds `count` independent H^2 matrices (Alg. 1 with adaptive sampling, Sec.

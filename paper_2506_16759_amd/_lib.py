@@ -12,7 +12,7 @@ STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_HIP", -3: "H2_ERR_OOM", -4: 
           -5: "H2_ERR_SAMPLES", -6: "H2_ERR_STATE", -7: "H2_ERR_UNSUPPORTED"}
 
 K_EXP, K_GAUSS = 1, 2
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, FP32E = 0, 1, 2, 3
 NORM_FRO_SCALED, NORM_LITERAL = 0, 1
 
 PART = dict(DEPTH=0, PERM=1, NODES=2, BOXES=3, NEAR_PTR=4, NEAR_IDX=5, FAR_PTR=6, FAR_IDX=7, RANKS=8,
@@ -63,7 +63,8 @@ class BatchOpts(C.Structure):
 class BatchInfo(C.Structure):
     _fields_ = [("t_total_ms", C.c_double), ("t_plan_ms", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_capture_ms", C.c_double), ("t_device_ms", C.c_double), ("levels", C.c_int32),
-                ("graph_nodes", C.c_int32), ("device_bytes", C.c_int64), ("sketch_flops", C.c_double)]
+                ("graph_nodes", C.c_int32), ("device_bytes", C.c_int64), ("sketch_flops", C.c_double),
+                ("t_layout_ms", C.c_double), ("t_alloc_ms", C.c_double), ("t_results_ms", C.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

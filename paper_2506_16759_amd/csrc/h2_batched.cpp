@@ -103,7 +103,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
     H2_REQUIRE(count >= 1, "count must be >= 1");
     const int prec = bopts->precision;
-    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3, "unknown precision");
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E,
+               "unknown precision");
     const int dcap = bopts->d_max;
     H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
     for (int i = 0; i < count; ++i) {
@@ -282,6 +283,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
 
     // ---- device allocation and static uploads
     H2_HIP(hipStreamSynchronize(s));
+    const double t_layout = ms_since(t0);
+    const auto t_alloc0 = Clock::now();
     mk(B.Xo, size_t(3) * NT, s, bytes);
     mk(B.Xt, size_t(3) * NT, s, bytes);
     mk(B.Om0, size_t(NT) * dcap, s, bytes);
@@ -374,6 +377,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     mk(Y1, size_t(NT) * dcap, s, bytes);
     H2_HIP(hipStreamSynchronize(s));
     const double t_setup = ms_since(t0);
+    const double t_alloc = ms_since(t_alloc0);
 
     // ---- the launch sequence
     hipGraph_t graph = nullptr;
@@ -403,7 +407,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
                                        B.Xt.get(), NT, B.leafprob.get(), B.kinds.get(), B.c2s.get(),
                                        B.Dblk.get()));
       H2_HIP(h2dev::bsr_gemm(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
-                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max, prec));
+                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max,
+                             prec == H2_FP32 || prec == H2_BF16X3 ? 1 : 0));
       for (int l = 1; l <= Lmax; ++l) {
         LevelB& V = B.lv[l - 1];
         double* om = l == 1 ? Om1.get() : V.om.get();
@@ -483,6 +488,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     (void)hipEventDestroy(e1);
 
     // ---- results back to per-problem matrices (views into the batch storage)
+    const auto t_res0 = Clock::now();
     const std::vector<int32_t> dprob = download(B.dprob.get(), np, s);
     const std::vector<int32_t> exh = download(B.exhausted.get(), np, s);
     const std::vector<double> nu = download(B.nu.get(), np, s);
@@ -617,6 +623,9 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       r.t_total_ms = ms_since(t_start);
       r.t_plan_ms = t_plan;
       r.t_setup_ms = t_setup;
+      r.t_layout_ms = t_layout;
+      r.t_alloc_ms = t_alloc;
+      r.t_results_ms = ms_since(t_res0);
       r.t_capture_ms = t_capture;
       r.t_device_ms = dev_ms;
       r.levels = Lmax;

@@ -543,6 +543,116 @@ __global__ __launch_bounds__(256) void sketch_bf16x3_batched(const SketchJob* __
     sketch_bf16x3_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
 }
 
+// FP32 kernel entries, FP64 contraction: entries are evaluated in FP32 (hi/lo
+// coordinates, hardware exp2/sqrt), converted to FP64 and contracted with the
+// FP64 Omega on the FP64 matrix cores with FP64 accumulation.  The entry error
+// (~1e-7 relative) enters the samples as independent noise, not accumulated
+// rounding, so the samples stay within ~1e-7 of K Omega at about a third of
+// the FP64 entry cost.  Same tiling and lane layout as the FP64 kernel.
+template <int DIM, int NC>
+struct SkE32Smem {
+  float xsh[DIM][kSkK];
+  float xsl[DIM][kSkK];
+  double om[kSkK][NC + 2];
+};
+
+template <int DIM, int KIND, int NC>
+__device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t tile0, int64_t n,
+                                                const double* __restrict__ X, int64_t ldx, float c2, int ncr,
+                                                const double* __restrict__ omega, int64_t ldo,
+                                                double* __restrict__ y, int64_t ldy) {
+  constexpr int NB = NC / 16;
+  auto& xsh = sm.xsh;
+  auto& xsl = sm.xsl;
+  auto& om = sm.om;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = tile0 + wave * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
+  {
+    const int64_t ia = row0 + li, ib = row0 + 16 + li;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
+      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
+    }
+  }
+  dbl4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    acc0[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    acc1[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
+    __syncthreads();
+    for (int e = tid; e < DIM * kSkK; e += 256) {
+      const int a = e / kSkK, jj = e % kSkK;
+      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
+    }
+    for (int e = tid; e < NC * kSkK; e += 256) {
+      const int c = e / kSkK, jj = e % kSkK;
+      om[jj][c] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kSkK / 4; ++kk) {
+      const int jj = kk * 4 + lk;
+      float ra = 0.f, rb = 0.f;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a) {
+        const float jh = xsh[a][jj], jl = xsl[a][jj];
+        const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
+        ra += da * da;
+        rb += db * db;
+      }
+      const double ka = double(kernel_of_r2_f32<KIND>(ra, c2));
+      const double kb = double(kernel_of_r2_f32<KIND>(rb, c2));
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double bv = om[jj][c * 16 + li];
+        acc0[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, bv, acc0[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, bv, acc1[c], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = c * 16 + li;
+    if (col >= ncr) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ra = row0 + lk + 4 * q, rb = row0 + 16 + lk + 4 * q;
+      if (ra < n) y[col * ldy + ra] = acc0[c][q];
+      if (rb < n) y[col * ldy + rb] = acc1[c][q];
+    }
+  }
+}
+
+template <int DIM, int KIND, int NC>
+__global__ __launch_bounds__(256) void sketch_e32_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                         float c2, int ncr, const double* __restrict__ omega,
+                                                         int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  __shared__ SkE32Smem<DIM, NC> sm;
+  sketch_e32_body<DIM, KIND, NC>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+}
+
+template <int NC>
+__global__ __launch_bounds__(256) void sketch_e32_batched(const SketchJob* __restrict__ jobs,
+                                                          const int32_t* __restrict__ tiles,
+                                                          const double* __restrict__ X, int64_t ldx, int ncr,
+                                                          const double* __restrict__ omega, int64_t ldo,
+                                                          double* __restrict__ y, int64_t ldy) {
+  __shared__ SkE32Smem<3, NC> sm;
+  const SketchJob J = jobs[tiles[2 * blockIdx.x]];
+  const int64_t t0 = tiles[2 * blockIdx.x + 1];
+  const float c2 = float(J.c2);
+  if (J.kind == kExp)
+    sketch_e32_body<3, kExp, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+  else
+    sketch_e32_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+}
+
 template <int P, int DIM, int KIND, int NC>
 void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
                        const double* omega, int64_t ldo, double* y, int64_t ldy) {
@@ -550,8 +660,10 @@ void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int
     sketch_f64_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else if constexpr (P == 1)
     sketch_f32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
-  else
+  else if constexpr (P == 2)
     sketch_bf16x3_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+  else
+    sketch_e32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
 }
 
 template <int P, int DIM, int KIND>
@@ -1692,6 +1804,8 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
       e = launch_sketch_p<1>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
     else if (precision == 2)
       e = launch_sketch_p<2>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+    else if (precision == 3)
+      e = launch_sketch_p<3>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
     else
       return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
@@ -1900,8 +2014,10 @@ hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* 
       H2_SKB_NC(sketch_f64_batched)
     } else if (precision == 1) {
       H2_SKB_NC(sketch_f32_batched)
-    } else {
+    } else if (precision == 2) {
       H2_SKB_NC(sketch_bf16x3_batched)
+    } else {
+      H2_SKB_NC(sketch_e32_batched)
     }
 #undef H2_SKB_NC
 #undef H2_SKB
