@@ -129,17 +129,37 @@ __device__ __forceinline__ void sketch_f64_body(SkF64Smem<DIM, NC>& sm, int64_t 
     acc1[c] = dbl4{0.0, 0.0, 0.0, 0.0};
   }
 
+  // The next stage's points and Omega rows are fetched into registers while
+  // the current stage computes, then written to LDS between two barriers.
+  constexpr int PX = (DIM * kSkK + 255) / 256, PO = NC * kSkK / 256;
+  double rx[PX], ro[PO];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u, a = e / kSkK, jj = e % kSkK;
+      rx[u] = (e < DIM * kSkK && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u, c = e / kSkK, jj = e % kSkK;
+      ro[u] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+    }
+  };
+  fetch(0);
   for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
     __syncthreads();
-    for (int e = tid; e < DIM * kSkK; e += 256) {
-      const int a = e / kSkK, jj = e % kSkK;
-      xs[a][jj] = (j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u;
+      if (e < DIM * kSkK) xs[e / kSkK][e % kSkK] = rx[u];
     }
-    for (int e = tid; e < NC * kSkK; e += 256) {
-      const int c = e / kSkK, jj = e % kSkK;
-      om[jj][c] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u;
+      om[e % kSkK][e / kSkK] = ro[u];
     }
     __syncthreads();
+    if (j0 + kSkK < n) fetch(j0 + kSkK);
 #pragma unroll 4
     for (int kk = 0; kk < kSkK / 4; ++kk) {
       const int jj = kk * 4 + lk;
@@ -584,17 +604,35 @@ __device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t 
     acc0[c] = dbl4{0.0, 0.0, 0.0, 0.0};
     acc1[c] = dbl4{0.0, 0.0, 0.0, 0.0};
   }
+  constexpr int PX = (DIM * kSkK + 255) / 256, PO = NC * kSkK / 256;
+  double rx[PX], ro[PO];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u, a = e / kSkK, jj = e % kSkK;
+      rx[u] = (e < DIM * kSkK && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u, c = e / kSkK, jj = e % kSkK;
+      ro[u] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+    }
+  };
+  fetch(0);
   for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
     __syncthreads();
-    for (int e = tid; e < DIM * kSkK; e += 256) {
-      const int a = e / kSkK, jj = e % kSkK;
-      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u;
+      if (e < DIM * kSkK) split_f32(rx[u], xsh[e / kSkK][e % kSkK], xsl[e / kSkK][e % kSkK]);
     }
-    for (int e = tid; e < NC * kSkK; e += 256) {
-      const int c = e / kSkK, jj = e % kSkK;
-      om[jj][c] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u;
+      om[e % kSkK][e / kSkK] = ro[u];
     }
     __syncthreads();
+    if (j0 + kSkK < n) fetch(j0 + kSkK);
 #pragma unroll 4
     for (int kk = 0; kk < kSkK / 4; ++kk) {
       const int jj = kk * 4 + lk;
