@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -39,6 +41,47 @@ void check_kernel(const h2_kernel* k) {
   H2_REQUIRE(k != nullptr, "kernel is NULL");
   H2_REQUIRE(k->kind == H2_K_EXP || k->kind == H2_K_GAUSS, "unknown kernel kind");
   H2_REQUIRE(k->length > 0.0 && std::isfinite(k->length), "kernel length must be finite and > 0");
+}
+
+hipMemPool_t large_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  H2_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  H2_HIP(hipMemPoolCreate(&pool, &props));
+  uint64_t thr = UINT64_MAX;  // keep freed blocks for the next build
+  H2_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  pools[dev] = pool;
+  return pool;
+}
+
+void* pool_alloc(size_t bytes, hipStream_t s) {
+  const bool large = bytes >= kLargeBytes;
+  auto once = [&](void** p) {
+    return large ? hipMallocFromPoolAsync(p, bytes, large_pool(), s) : hipMallocAsync(p, bytes, s);
+  };
+  void* p = nullptr;
+  hipError_t e = once(&p);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    H2_HIP(hipStreamSynchronize(s));
+    int dev = 0;
+    H2_HIP(hipGetDevice(&dev));
+    hipMemPool_t def = nullptr;
+    if (hipDeviceGetDefaultMemPool(&def, dev) == hipSuccess) (void)hipMemPoolTrimTo(def, 0);
+    (void)hipMemPoolTrimTo(large_pool(), 0);
+    e = once(&p);
+  }
+  H2_HIP(e);
+  return p;
 }
 
 int top_depth(const h2::Plan& p) {

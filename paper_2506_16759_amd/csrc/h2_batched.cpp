@@ -16,6 +16,7 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <string>
 #include <thread>
@@ -31,6 +32,46 @@ using Clock = std::chrono::steady_clock;
 double ms_since(Clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
+
+// One device block carved into 256-byte aligned arrays.  A batch uses two:
+// the factors the matrices keep (dense blocks, IDs, couplings) and the
+// build's working set, released after the build.  Equal-sized blocks on
+// repeated builds come straight back from the stream-ordered pool.
+struct Arena {
+  struct Item {
+    size_t off, bytes;
+    std::function<void(char*)> bind;
+    const void* src;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  DevArray<char> block;
+  template <typename T>
+  void want(DevArray<T>& a, size_t n) {
+    add(a, n, nullptr);
+  }
+  template <typename T>
+  void want(DevArray<T>& a, const std::vector<T>& h) {
+    add(a, h.size(), h.data());
+  }
+  template <typename T>
+  void add(DevArray<T>& a, size_t n, const void* src) {
+    const size_t b = n * sizeof(T);
+    DevArray<T>* pa = &a;
+    items.push_back({total, b, [pa, n](char* p) { pa->borrow(reinterpret_cast<T*>(p), n); }, src});
+    total += (b + 255) & ~size_t(255);
+  }
+  // allocate, bind every array and enqueue the uploads (host sources must stay
+  // alive until the stream is synchronised)
+  void commit(hipStream_t s) {
+    block.alloc(std::max<size_t>(total, 256), s);
+    for (auto& it : items) {
+      it.bind(block.get() + it.off);
+      if (it.src && it.bytes)
+        H2_HIP(hipMemcpyAsync(block.get() + it.off, it.src, it.bytes, hipMemcpyHostToDevice, s));
+    }
+  }
+};
 
 struct Prob {
   int orig = 0;
@@ -53,6 +94,7 @@ struct LevelB {
   DevArray<int64_t> d_joff, d_uoff, d_boff, gws_off;
   DevArray<double> U, B, xs, om, y, gws;
   std::vector<int32_t> k_h, koff_h, rowoff_h;
+  std::vector<int64_t> gws_off_h;
 };
 
 struct BatchStore {
@@ -65,19 +107,9 @@ struct BatchStore {
   DevArray<double> c2s, nu, delta;
   DevArray<char> sjobs, tjobs;
   DevArray<int32_t> tiles;
+  Arena keep, work;  // factors kept by the matrices; the build's working set
   int64_t bytes = 0;
 };
-
-template <typename T>
-void up(DevArray<T>& a, const std::vector<T>& h, hipStream_t s, int64_t& bytes) {
-  a.upload(h, s);
-  bytes += static_cast<int64_t>(a.bytes());
-}
-template <typename T>
-void mk(DevArray<T>& a, size_t n, hipStream_t s, int64_t& bytes) {
-  a.alloc(n, s);
-  bytes += static_cast<int64_t>(a.bytes());
-}
 
 void check_problem(const h2_problem& p) {
   H2_REQUIRE(p.points != nullptr, "problem points are NULL");
@@ -285,19 +317,19 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     H2_HIP(hipStreamSynchronize(s));
     const double t_layout = ms_since(t0);
     const auto t_alloc0 = Clock::now();
-    mk(B.Xo, size_t(3) * NT, s, bytes);
-    mk(B.Xt, size_t(3) * NT, s, bytes);
-    mk(B.Om0, size_t(NT) * dcap, s, bytes);
-    mk(B.Y0, size_t(NT) * dcap, s, bytes);
-    mk(B.Dblk, size_t(doff.back()), s, bytes);
-    up(B.perm_g, perm_g, s, bytes);
-    up(B.rowprob_o, rowprob_o, s, bytes);
-    up(B.rowlocal_o, rowlocal_o, s, bytes);
-    up(B.leafoff, leafoff, s, bytes);
-    up(B.nptr, nptr, s, bytes);
-    up(B.nidx, nidx, s, bytes);
-    up(B.doff, doff, s, bytes);
-    up(B.leafprob, leafprob, s, bytes);
+    B.work.want(B.Xo, size_t(3) * NT);
+    B.work.want(B.Xt, size_t(3) * NT);
+    B.work.want(B.Om0, size_t(NT) * dcap);
+    B.work.want(B.Y0, size_t(NT) * dcap);
+    B.keep.want(B.Dblk, size_t(doff.back()));
+    B.work.want(B.perm_g, perm_g);
+    B.work.want(B.rowprob_o, rowprob_o);
+    B.work.want(B.rowlocal_o, rowlocal_o);
+    B.work.want(B.leafoff, leafoff);
+    B.work.want(B.nptr, nptr);
+    B.work.want(B.nidx, nidx);
+    B.work.want(B.doff, doff);
+    B.work.want(B.leafprob, leafprob);
     std::vector<uint64_t> seeds(np);
     std::vector<int32_t> kinds(np), incs(np), ovs(np);
     std::vector<double> c2s(np);
@@ -324,57 +356,60 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
         tiles.push_back(o.second);
         tiles.push_back(static_cast<int32_t>(r0));
       }
-    up(B.seeds, seeds, s, bytes);
-    up(B.kinds, kinds, s, bytes);
-    up(B.incprob, incs, s, bytes);
-    up(B.ovprob, ovs, s, bytes);
-    up(B.c2s, c2s, s, bytes);
-    up(B.sjobs, sj, s, bytes);
-    up(B.tjobs, tj, s, bytes);
-    up(B.tiles, tiles, s, bytes);
-    mk(B.nu, np, s, bytes);
-    mk(B.delta, np, s, bytes);
-    mk(B.dprob, np, s, bytes);
-    mk(B.exhausted, np, s, bytes);
+    B.work.want(B.seeds, seeds);
+    B.work.want(B.kinds, kinds);
+    B.work.want(B.incprob, incs);
+    B.work.want(B.ovprob, ovs);
+    B.work.want(B.c2s, c2s);
+    B.work.want(B.sjobs, sj);
+    B.work.want(B.tjobs, tj);
+    B.work.want(B.tiles, tiles);
+    B.work.want(B.nu, np);
+    B.work.want(B.delta, np);
+    B.work.want(B.dprob, np);
+    B.work.want(B.exhausted, np);
     for (int l = 1; l <= Lmax; ++l) {
       LevelB& V = B.lv[l - 1];
-      up(V.d_nodeprob, V.nodeprob, s, bytes);
+      B.work.want(V.d_nodeprob, V.nodeprob);
       if (l == 1)
-        up(V.rowoff, V.rowoff_h, s, bytes);
+        B.work.want(V.rowoff, V.rowoff_h);
       else {
-        up(V.d_childfirst, V.childfirst, s, bytes);
-        mk(V.rowoff, V.G + 1, s, bytes);
+        B.work.want(V.d_childfirst, V.childfirst);
+        B.work.want(V.rowoff, V.G + 1);
       }
-      mk(V.k, V.G, s, bytes);
-      mk(V.koff, V.G + 1, s, bytes);
-      up(V.d_joff, V.joff, s, bytes);
-      up(V.d_uoff, V.uoff, s, bytes);
-      mk(V.J, size_t(V.joff.back()), s, bytes);
-      mk(V.U, size_t(V.uoff.back()), s, bytes);
-      mk(V.pos, size_t(V.rcap_next), s, bytes);
-      mk(V.xs, size_t(3) * V.rcap_next, s, bytes);
-      up(V.d_fptr, V.fptr, s, bytes);
-      up(V.d_fidx, V.fidx, s, bytes);
-      up(V.d_boff, V.boff, s, bytes);
-      mk(V.B, size_t(V.boff.back()), s, bytes);
+      B.work.want(V.k, V.G);
+      B.work.want(V.koff, V.G + 1);
+      B.work.want(V.d_joff, V.joff);
+      B.work.want(V.d_uoff, V.uoff);
+      B.keep.want(V.J, size_t(V.joff.back()));
+      B.keep.want(V.U, size_t(V.uoff.back()));
+      B.work.want(V.pos, size_t(V.rcap_next));
+      B.work.want(V.xs, size_t(3) * V.rcap_next);
+      B.work.want(V.d_fptr, V.fptr);
+      B.work.want(V.d_fidx, V.fidx);
+      B.work.want(V.d_boff, V.boff);
+      B.keep.want(V.B, size_t(V.boff.back()));
       if (l >= 2) {
-        mk(V.om, size_t(V.rcap) * dcap, s, bytes);
-        mk(V.y, size_t(V.rcap) * dcap, s, bytes);
+        B.work.want(V.om, size_t(V.rcap) * dcap);
+        B.work.want(V.y, size_t(V.rcap) * dcap);
       }
       const size_t cbytes = size_t(3) * V.max_m * 8 + size_t(dcap | 1) * V.max_m * 8;
       const size_t qbytes = size_t(V.max_m | 1) * dcap * 8;
       if (std::max(cbytes, qbytes) > ctx->lds_limit) {
         const int64_t per = int64_t((V.max_m | 1) + 1) * int64_t((dcap | 1) + 1);
-        std::vector<int64_t> off(V.G);
-        for (int g = 0; g < V.G; ++g) off[g] = per * g;
-        up(V.gws_off, off, s, bytes);
-        mk(V.gws, size_t(per) * V.G, s, bytes);
+        V.gws_off_h.resize(V.G);
+        for (int g = 0; g < V.G; ++g) V.gws_off_h[g] = per * g;
+        B.work.want(V.gws_off, V.gws_off_h);
+        B.work.want(V.gws, size_t(per) * V.G);
       }
     }
     // level 1 works on the tree-ordered sketch itself
     DevArray<double> Om1, Y1;  // tree-ordered Omega and Y (level 1 row space)
-    mk(Om1, size_t(NT) * dcap, s, bytes);
-    mk(Y1, size_t(NT) * dcap, s, bytes);
+    B.work.want(Om1, size_t(NT) * dcap);
+    B.work.want(Y1, size_t(NT) * dcap);
+    B.keep.commit(s);
+    B.work.commit(s);
+    bytes = static_cast<int64_t>(B.keep.total + B.work.total);
     H2_HIP(hipStreamSynchronize(s));
     const double t_setup = ms_since(t0);
     const double t_alloc = ms_since(t_alloc0);
@@ -605,18 +640,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       mats[q] = std::move(h);
     }
     // only the factors stay: dense blocks, bases, skeleton indices, couplings
-    for (auto& V : B.lv) {
-      V.om.release();
-      V.y.release();
-      V.gws.release();
-      V.xs.release();
-      V.pos.release();
-    }
-    B.Xo.release();
-    B.Xt.release();
-    B.Om0.release();
-    B.Y0.release();
     H2_HIP(hipStreamSynchronize(s));
+    B.work.block.release();
     for (int q = 0; q < np; ++q) out[P[q].orig] = mats[q].release();
     if (info) {
       h2_batch_info r{};

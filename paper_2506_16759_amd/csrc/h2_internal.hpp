@@ -59,6 +59,16 @@ h2_status guarded(F&& f) {
   }
 }
 
+// Stream-ordered pool of the current device for large arrays (>= 64 MB).
+// Keeping them apart from the small per-level arrays stops the small ones from
+// splitting a freed large block, so a repeated build of the same size gets its
+// large blocks back without mapping new memory.
+hipMemPool_t large_pool();
+constexpr size_t kLargeBytes = size_t(64) << 20;
+// Stream-ordered allocation from the matching pool; on exhaustion the pools'
+// cached free blocks are released (after the stream drains) and it retries once.
+void* pool_alloc(size_t bytes, hipStream_t s);
+
 // Stream-ordered device array; borrow() makes it a non-owning view.
 template <typename T>
 class DevArray {
@@ -87,9 +97,7 @@ class DevArray {
     n_ = n;
     owned_ = true;
     if (n == 0) return;
-    void* p = nullptr;
-    H2_HIP(hipMallocAsync(&p, n * sizeof(T), s));
-    p_ = static_cast<T*>(p);
+    p_ = static_cast<T*>(pool_alloc(n * sizeof(T), s));
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
     alloc(h.size(), s);
