@@ -47,6 +47,16 @@ def opts_default(**over) -> _lib.Opts:
     return o
 
 
+def _release(obj, fname: str):
+    """Free obj's handle through the library object it was created with (module
+    globals may already be gone when this runs at interpreter exit)."""
+    h = getattr(obj, "_h", None)
+    lib = getattr(obj, "_lib_ref", None)
+    obj._h = None
+    if h and lib is not None:
+        getattr(lib, fname)(h)
+
+
 def _export(fn, handle, name: str, depth: int = 0) -> np.ndarray:
     part = _lib.PART[name]
     need = C.c_size_t(0)
@@ -66,7 +76,7 @@ class Plan:
         pts = np.ascontiguousarray(points, dtype=np.float64)
         dim, n = pts.shape
         h = C.c_void_p()
-        lib = _lib.load()
+        lib = self._lib_ref = _lib.load()
         _lib.check(lib.h2_plan_create(n, dim, pts.ctypes.data_as(C.c_void_p), leaf_size, float(eta), C.byref(h)),
                    "h2_plan_create")
         self._h = h
@@ -76,9 +86,7 @@ class Plan:
         return _export(_lib.load().h2_plan_export, self._h, name, depth)
 
     def close(self):
-        if getattr(self, "_h", None):
-            _lib.load().h2_plan_free(self._h)
-            self._h = None
+        _release(self, "h2_plan_free")
 
     __del__ = close
 
@@ -92,6 +100,7 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None):
         self._h = None
+        self._lib_ref = _lib.load()
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library needs an MI355X")
@@ -107,9 +116,7 @@ class Context:
         self.stream.synchronize()
 
     def close(self):
-        if getattr(self, "_h", None):
-            _lib.load().h2_ctx_destroy(self._h)
-            self._h = None
+        _release(self, "h2_ctx_destroy")
 
     __del__ = close
 
@@ -165,6 +172,7 @@ class H2Matrix:
 
     def __init__(self, ctx: Context, handle, n: int):
         self.ctx, self._h, self.n = ctx, handle, n
+        self._lib_ref = _lib.load()
 
     def matvec(self, x):
         """K_H x for x an (n, c) column-major cuda tensor (or an (n,) vector)."""
@@ -187,9 +195,7 @@ class H2Matrix:
         return inf.as_dict()
 
     def close(self):
-        if getattr(self, "_h", None):
-            _lib.load().h2_free(self._h)
-            self._h = None
+        _release(self, "h2_free")
 
     __del__ = close
 
