@@ -180,6 +180,8 @@ def main():
     ap.add_argument("--sketch-launches", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-problem batched build and the low-rank update measurements")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="only the 64-problem batched build and the low-rank update (printed as one JSON line)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
@@ -210,6 +212,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"profile_kernels": "done", "copy_bytes": a.numel() * 8}), flush=True)
+        return
+    if args.only_extras:
+        ctx = h2.Context(0)
+        print(json.dumps({"batched": bench_batched(h2, ctx), "update": bench_update(h2, ctx)}), flush=True)
         return
     print(f"[bench] workload {w.name} n={w.n} tol={tol}", file=sys.stderr, flush=True)
     ctx = h2.Context(0)
