@@ -845,6 +845,8 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 // block's A operands are loaded 16/RT k-steps at a time.
 // F32: blocks and X are rounded to FP32 at load, the products run on the FP32
 // matrix cores and each block's FP32 partial sums are folded into FP64.
+constexpr int kBsrMeta = 1024;  // blocks per row whose metadata is cached in LDS
+
 template <int NB, int RT, bool F32, bool TR>
 __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rowoff,
@@ -869,13 +871,33 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
   const int jb = ptr[i], je = ptr[i + 1];
   if (m == 0 || jb == je) return;  // uniform over the workgroup
 
+  // Each block's column offset, height and storage offset are gathered into
+  // LDS once per row (rows of up to kBsrMeta blocks), so the per-block chain
+  // idx -> coloff -> X is not a sequence of dependent global loads.
+  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (MAXQ * LDB));
+  int* s_mb = s_q0 + kBsrMeta;
+  int64_t* s_bo = reinterpret_cast<int64_t*>(s_mb + kBsrMeta);
+  const bool meta = je - jb <= kBsrMeta;
+  if (meta) {
+    for (int e = tid; e < je - jb; e += 256) {
+      const int b = idx[jb + e];
+      const int q0 = coloff[b];
+      s_q0[e] = q0;
+      s_mb[e] = coloff[b + 1] - q0;
+      s_bo[e] = blkoff[TR ? tpos[jb + e] : jb + e];
+    }
+    __syncthreads();
+  }
+  auto col0 = [&](int j) { return meta ? s_q0[j - jb] : coloff[idx[j]]; };
+  auto height = [&](int j) { return meta ? s_mb[j - jb] : coloff[idx[j] + 1] - coloff[idx[j]]; };
+  auto boff = [&](int j) { return meta ? s_bo[j - jb] : blkoff[TR ? tpos[j] : j]; };
+
   // Two-sided use: block columns index the row space `coloff`, and with TR
   // the block of entry j is the transpose of the stored block tpos[j]
   // (stored mb x m, column-major).
   T xv[QI][CI];
   auto fetch = [&](int j) {
-    const int b = idx[j];
-    const int q0 = coloff[b], mb = coloff[b + 1] - q0;
+    const int q0 = col0(j), mb = height(j);
 #pragma unroll
     for (int qi = 0; qi < QI; ++qi)
 #pragma unroll
@@ -905,9 +927,8 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
     const int cur = (j - jb) & 1;
     const bool more = j + 1 < je;
     if (more) fetch(j + 1);  // in flight while block j computes
-    const int b = idx[j];
-    const int mb = coloff[b + 1] - coloff[b], mb4 = (mb + 3) & ~3;
-    const double* blk = blocks + blkoff[TR ? tpos[j] : j];
+    const int mb = height(j), mb4 = (mb + 3) & ~3;
+    const double* blk = blocks + boff(j);
     const T* bs = buf + cur * (MAXQ * LDB);
     using V4 = typename std::conditional<F32, flt4, dbl4>::type;
     V4 part[RT][NB];
@@ -1876,7 +1897,8 @@ hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int
   const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
   const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
   if (rt * NB > 4) return hipErrorInvalidValue;
-  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * (F32 ? sizeof(float) : sizeof(double));
+  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * (F32 ? sizeof(float) : sizeof(double)) +
+                     size_t(kBsrMeta) * (2 * sizeof(int) + sizeof(int64_t));
   hipError_t e = hipSuccess;
 #define H2_BSR_RT(RT)                                                                                    \
   if ((e = allow_lds(bsr_gemm_kernel<NB, RT, F32, TR>, lds)) != hipSuccess) return e;                    \
