@@ -920,34 +920,15 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  // A operands of a block's first 4*KC k-steps (rows of the block in the
-  // MFMA A layout); the next block's are loaded while the current computes.
-  auto load_a = [&](T (&a)[RT][KC], int j, int k0) {
-    const int mb = height(j);
-    const double* blk = blocks + boff(j);
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc) {
-      const int q = k0 + 4 * kc + lk;
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int row = (wave + 4 * t) * 16 + li;
-        a[t][kc] = (row < m && q < mb) ? T(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : T(0);
-      }
-    }
-  };
-  T a_cur[RT][KC], a_nxt[RT][KC];
   fetch(jb);
-  load_a(a_cur, jb, 0);
   stash(0);
   __syncthreads();
   for (int j = jb; j < je; ++j) {
     const int cur = (j - jb) & 1;
     const bool more = j + 1 < je;
-    if (more) {  // in flight while block j computes
-      fetch(j + 1);
-      load_a(a_nxt, j + 1, 0);
-    }
-    const int mb4 = (height(j) + 3) & ~3;
+    if (more) fetch(j + 1);  // in flight while block j computes
+    const int mb = height(j), mb4 = (mb + 3) & ~3;
+    const double* blk = blocks + boff(j);
     const T* bs = buf + cur * (MAXQ * LDB);
     using V4 = typename std::conditional<F32, flt4, dbl4>::type;
     V4 part[RT][NB];
@@ -958,7 +939,16 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
         for (int c = 0; c < NB; ++c) part[t][c] = V4{0.f, 0.f, 0.f, 0.f};
     }
     for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
-      if (k0 > 0) load_a(a_cur, j, k0);  // blocks taller than 4*KC rows
+      T a[RT][KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        const int q = k0 + 4 * kc + lk;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int row = (wave + 4 * t) * 16 + li;
+          a[t][kc] = (row < m && q < mb) ? T(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : T(0);
+        }
+      }
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         if (k0 + 4 * kc >= mb4) break;
@@ -969,9 +959,9 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
           for (int t = 0; t < RT; ++t) {
             if constexpr (F32)
-              part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a_cur[t][kc], bv, part[t][c], 0, 0, 0);
+              part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][kc], bv, part[t][c], 0, 0, 0);
             else
-              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[t][kc], bv, acc[t][c], 0, 0, 0);
+              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
           }
         }
       }
@@ -985,13 +975,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[t][c][q] += double(part[t][c][q]);
     }
-    if (more) {
-      stash(cur ^ 1);
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) a_cur[t][kc] = a_nxt[t][kc];
-    }
+    if (more) stash(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
