@@ -47,14 +47,26 @@ def opts_default(**over) -> _lib.Opts:
     return o
 
 
-def _release(obj, fname: str):
-    """Free obj's handle through the library object it was created with (module
-    globals may already be gone when this runs at interpreter exit)."""
-    h = getattr(obj, "_h", None)
-    lib = getattr(obj, "_lib_ref", None)
-    obj._h = None
-    if h and lib is not None:
-        getattr(lib, fname)(h)
+class _Handle:
+    """Owner of one library handle, freed through the library object it was
+    created with: close() reads nothing but the instance, since module globals
+    may already be gone when it runs at interpreter exit."""
+
+    _free = ""
+    _h = None
+    _lib_ref = None
+
+    def close(self):
+        h, lib = self._h, self._lib_ref
+        self._h = None
+        if h and lib is not None:
+            getattr(lib, self._free)(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _export(fn, handle, name: str, depth: int = 0) -> np.ndarray:
@@ -68,8 +80,10 @@ def _export(fn, handle, name: str, depth: int = 0) -> np.ndarray:
     return out
 
 
-class Plan:
+class Plan(_Handle):
     """Host-only cluster tree + interaction lists (h2_plan_*)."""
+
+    _free = "h2_plan_free"
 
     def __init__(self, points: np.ndarray, leaf_size: int, eta: float):
         self._h = None
@@ -85,18 +99,15 @@ class Plan:
     def export(self, name: str, depth: int = 0) -> np.ndarray:
         return _export(_lib.load().h2_plan_export, self._h, name, depth)
 
-    def close(self):
-        _release(self, "h2_plan_free")
-
-    __del__ = close
-
 
 def plan_create(points: np.ndarray, leaf_size: int = 64, eta: float = 0.7) -> Plan:
     return Plan(points, leaf_size, eta)
 
 
-class Context:
+class Context(_Handle):
     """h2_ctx bound to a device and (by default) torch's current stream."""
+
+    _free = "h2_ctx_destroy"
 
     def __init__(self, device: int = 0, stream=None):
         self._h = None
@@ -114,11 +125,6 @@ class Context:
 
     def synchronize(self):
         self.stream.synchronize()
-
-    def close(self):
-        _release(self, "h2_ctx_destroy")
-
-    __del__ = close
 
 
 def _colmajor(t, rows: int):
@@ -167,8 +173,10 @@ def sketch(ctx: Context, points, kernel, length: float, omega, precision: int = 
     return y
 
 
-class H2Matrix:
+class H2Matrix(_Handle):
     """A built H^2 matrix (h2_matrix): matvec, export, query."""
+
+    _free = "h2_free"
 
     def __init__(self, ctx: Context, handle, n: int):
         self.ctx, self._h, self.n = ctx, handle, n
@@ -193,11 +201,6 @@ class H2Matrix:
         inf = _lib.Info()
         _lib.check(_lib.load().h2_query(self._h, C.byref(inf)), "h2_query")
         return inf.as_dict()
-
-    def close(self):
-        _release(self, "h2_free")
-
-    __del__ = close
 
 
 def build(ctx: Context, points, kernel="exp", length: float = 0.2, opts: _lib.Opts | None = None,

@@ -209,6 +209,8 @@ class Builder {
   const double* points_ = nullptr;  // caller's points, original order (borrowed for the build)
   DevArray<double> gws_;
   DevArray<int64_t> gws_off_;
+  int64_t gws_per_ = 0;
+  int gws_nn_ = 0;
   DevArray<int32_t> conv_, counter_;
   DevArray<double> minr_;
 
@@ -362,10 +364,17 @@ class Builder {
                             P.y.get() + int64_t(c0) * P.M, P.M, P.om.get() + int64_t(c0) * P.M, P.M, nc));
   }
 
+  // Per-cluster panels (stride gws_per_ doubles) for the kernels whose panel
+  // exceeds LDS.  The offsets are laid out again whenever a call needs a larger
+  // stride or more clusters: a buffer that is large enough in total but laid
+  // out with a smaller stride would hand overlapping panels to the clusters of
+  // a later level (fewer, larger clusters).
   void ensure_gws(int nn, int max_m, int d) {
     const int64_t per = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
-    if (gws_.size() >= size_t(per) * nn) return;
-    gws_.alloc(size_t(per) * nn, s_);
+    if (per <= gws_per_ && nn <= gws_nn_) return;
+    if (gws_.size() < size_t(per) * nn) gws_.alloc(size_t(per) * nn, s_);
+    gws_per_ = per;
+    gws_nn_ = nn;
     std::vector<int64_t> off(nn);
     for (int i = 0; i < nn; ++i) off[i] = per * i;
     gws_off_.upload(off, s_);

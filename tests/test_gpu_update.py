@@ -195,7 +195,7 @@ def test_update_workload_n16384_against_oracle_golden(ctx):
     assert e1 <= 10 * w.tol and e2 <= 10 * w.tol
 
 
-@pytest.mark.parametrize("n", [1 << 16])
+@pytest.mark.parametrize("n", [1 << 16, 1 << 17])
 def test_update_workload_any_size_property(ctx, n):
     w = cube_update(n)
     b = w.base
