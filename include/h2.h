@@ -56,22 +56,29 @@ typedef struct {
   double length;  /* correlation length l > 0 */
 } h2_kernel;
 
-/* Arithmetic of the dense sketch and of the leaf near-field product.  Kernel
- * blocks D and B are always evaluated and stored in FP64; the stopping test,
- * CPQR norm downdating and interpolation solve are FP64.
+/* Arithmetic of the dense on-the-fly sketch.  Kernel blocks D and B are
+ * always evaluated and stored in FP64 and multiplied on the FP64 matrix cores
+ * (the leaf near-field product is bound by block traffic and latency, so an
+ * FP32 form gains nothing); the stopping test, CPQR and interpolation solve
+ * are FP64.  In the reduced modes an entry is evaluated from the FP64 squared
+ * distance with the FP32 square root and exponential (~1e-7 relative error).
  *   H2_FP64:   FP64 entries, FP64 matrix cores.
- *   H2_FP32:   FP32 entries, FP32 matrix cores (FP32 partial sums folded into
- *              FP64 every 256 points); near-field product on FP32 matrix cores.
- *              The FP32 accumulation leaves ~1e-6 relative noise in the
- *              samples, so tolerances near 1e-6 need extra samples.
- *   H2_BF16X3: FP32 entries split into bf16 hi + lo, three bf16 products
- *              (hi*hi + hi*lo + lo*hi) with FP32 accumulation, folded into FP64
- *              likewise; about 2^-16 relative error per product (tol >= ~1e-4).
- *   H2_FP32E:  FP32 entries (the transcendental work), converted to FP64 and
- *              contracted with the FP64 Omega on the FP64 matrix cores with FP64
- *              accumulation; ~1e-7 relative entry noise, no accumulated
- *              rounding; near-field product in FP64. */
-typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2, H2_FP32E = 3 } h2_precision;
+ *   H2_FP32:   FP32 entries and Omega, FP32 matrix cores; the FP32 partial
+ *              sums are folded into FP64 every 64 points, which keeps their
+ *              rounding below the entry error (same sample counts as FP64 at
+ *              tol 1e-6 on the 131072-point covariance matrix).
+ *   H2_BF16X3: FP32 entries and Omega split into round-to-nearest bf16
+ *              hi + lo, three bf16 products (hi*hi + hi*lo + lo*hi) with FP32
+ *              accumulation, folded into FP64 likewise; about 2^-17 relative
+ *              error per product (tol >= ~1e-4).
+ *   H2_FP32E:  FP32 entries converted to FP64 and contracted with the FP64
+ *              Omega on the FP64 matrix cores with FP64 accumulation.
+ *   H2_BF16X6: FP32 entries and Omega each split into three round-to-nearest
+ *              bf16 terms; the six products whose split orders add up to at
+ *              most 2 run on the bf16 matrix cores with FP32 accumulation,
+ *              folded into FP64 every 64 points: FP32-accurate products at a
+ *              fraction of the FP32 matrix-core cycles. */
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2, H2_FP32E = 3, H2_BF16X6 = 4 } h2_precision;
 
 /* How the absolute ID/stopping threshold delta is derived from tol
  * (Sec. III-B: "an approximate norm of the matrix ... via sketching"):

@@ -16,12 +16,12 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BF16X3, FP32, FP32E, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
+from ._lib import BF16X3, BF16X6, FP32, FP32E, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
            "build_update", "autotune_leaf",
            "H2Matrix",
-           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "FP32E", "NORM_FRO_SCALED",
+           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "FP32E", "BF16X6", "NORM_FRO_SCALED",
            "NORM_LITERAL"]
 
 
@@ -42,7 +42,7 @@ def opts_default(**over) -> _lib.Opts:
         if k == "norm_mode" and isinstance(v, str):
             v = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[v]
         if k == "precision" and isinstance(v, str):
-            v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E}[v]
+            v = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[v]
         setattr(o, k, v)
     return o
 
@@ -239,7 +239,7 @@ def _problem_array(problems):
 def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP64, d_max: int = 96):
     """Leaf size per problem from h2_autotune_leaf (problems as for build_batched)."""
     if isinstance(precision, str):
-        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E}[precision]
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
     arr, keep = _problem_array(problems)
     cand = (C.c_int32 * len(candidates))(*candidates)
     best = (C.c_int32 * len(problems))()
@@ -259,7 +259,7 @@ def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_g
     norm_mode, oversample (defaults as h2_opts_default).  Returns a list of H2Matrix (and
     the batch info dict when return_info)."""
     if isinstance(precision, str):
-        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E}[precision]
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
     arr, keep = _problem_array(problems)
     bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0)
     handles = (C.c_void_p * len(problems))()

@@ -146,10 +146,6 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
 
 namespace {
 
-// The leaf near-field product runs on FP32 matrix cores only in the FP32 and
-// bf16x3 modes; FP32E keeps it in FP64.
-int near_precision(int precision) { return precision == H2_FP32 || precision == H2_BF16X3 ? 1 : 0; }
-
 void check_opts(const h2_opts* o) {
   H2_REQUIRE(o != nullptr, "opts is NULL");
   H2_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be finite and > 0");
@@ -159,7 +155,7 @@ void check_opts(const h2_opts* o) {
   H2_REQUIRE(o->d_inc >= 1 && o->d_inc <= 128, "d_inc must be in [1, 128]");
   H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 256, "d_max must be in [d0, 256]");
   H2_REQUIRE(o->precision == H2_FP64 || o->precision == H2_FP32 || o->precision == H2_BF16X3 ||
-                 o->precision == H2_FP32E,
+                 o->precision == H2_FP32E || o->precision == H2_BF16X6,
              "unknown precision");
   H2_REQUIRE(o->norm_mode == H2_NORM_FRO_SCALED || o->norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
   H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 256, "sketch_ahead must be in [0, 256]");
@@ -345,7 +341,7 @@ class Builder {
     if (t == D) {
       H2_HIP(h2dev::bsr_gemm(s_, L.nn, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             L.max_m, near_precision(h.opts.precision)));
+                             L.max_m));
     } else {
       Level& C = h.lv[t + 1];
       H2_HIP(h2dev::bsr_gemm(s_, C.nn, C.fptr.get(), C.fidx.get(), C.koff.get(), C.boff.get(), C.B.get(),
@@ -678,7 +674,8 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
   return guarded([&] {
     H2_REQUIRE(ctx != nullptr, "ctx is NULL");
     check_kernel(kernel);
-    H2_REQUIRE(precision == H2_FP64 || precision == H2_FP32 || precision == H2_BF16X3 || precision == H2_FP32E,
+    H2_REQUIRE(precision == H2_FP64 || precision == H2_FP32 || precision == H2_BF16X3 || precision == H2_FP32E ||
+                 precision == H2_BF16X6,
                "unknown precision");
     H2_REQUIRE(n >= 0 && n < (int64_t{1} << 31), "n out of range");
     H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");

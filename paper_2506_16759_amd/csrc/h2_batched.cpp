@@ -135,7 +135,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
     H2_REQUIRE(count >= 1, "count must be >= 1");
     const int prec = bopts->precision;
-    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E,
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E || prec == H2_BF16X6,
                "unknown precision");
     const int dcap = bopts->d_max;
     H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
@@ -442,8 +442,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
                                        B.Xt.get(), NT, B.leafprob.get(), B.kinds.get(), B.c2s.get(),
                                        B.Dblk.get()));
       H2_HIP(h2dev::bsr_gemm(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
-                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max,
-                             prec == H2_FP32 || prec == H2_BF16X3 ? 1 : 0));
+                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max));
       for (int l = 1; l <= Lmax; ++l) {
         LevelB& V = B.lv[l - 1];
         double* om = l == 1 ? Om1.get() : V.om.get();
@@ -453,7 +452,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
           LevelB& C = B.lv[l - 2];
           H2_HIP(h2dev::gather_i32(s, V.G, V.d_childfirst.get(), C.koff.get(), V.rowoff.get()));
           H2_HIP(h2dev::bsr_gemm(s, C.G, C.d_fptr.get(), C.d_fidx.get(), C.koff.get(), C.d_boff.get(), C.B.get(),
-                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), 0));
+                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1)));
         }
         H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), B.ovprob.get(),
                                     V.d_nodeprob.get(), B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m,

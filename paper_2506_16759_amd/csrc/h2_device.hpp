@@ -42,13 +42,11 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out);
 
-// Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc columns.
-// max_m bounds every block-row height (<= 256).  precision 0: FP64 matrix
-// cores; otherwise blocks and X are rounded to FP32, multiplied on the FP32
-// matrix cores and each block's partial sums folded into FP64.
+// Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc
+// columns, on the FP64 matrix cores.  max_m bounds every block-row height (<= 256).
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m, int precision = 0);
+                    int64_t ldy, int nc, double alpha, int max_m);
 
 // Two-sided form: block row i has rows [rowoff[i], rowoff[i+1]) of Y, block
 // column b rows [coloff[b], coloff[b+1]) of X; with tpos != nullptr the block of
@@ -56,8 +54,7 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
 // (coloff height) x (rowoff height), column-major).  max_m bounds both heights.
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     int precision = 0);
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m);
 
 // Adaptive convergence test (Sec. III-B) with an oversampling margin p: per cluster,
 // unpivoted Householder QR of its samples Y[rowoff[i]..rowoff[i+1]) x [0, d-p);

@@ -246,26 +246,23 @@ __device__ __forceinline__ float kernel_of_r2_f32(float r2, float c2) {
 }
 
 // FP32 partial sums are folded into FP64 accumulators every kFlush stages of
-// kSkK points, so the FP32 rounding error never grows with n.
-constexpr int kFlush = 4;
+// kSkK points.  Over 256 points the FP32 rounding of the running sums already
+// lifts the noise of the samples above the adaptive threshold at tol 1e-6 (16
+// extra samples on the 131072-point covariance matrix); every 64 points it does
+// not.
+constexpr int kFlush = 1;
 
 // FP32 entries, v_mfma_f32_16x16x4_f32.  Same tiling as the FP64 kernel:
 // lane l supplies A[l%16][l/16], B[l/16][l%16] and holds D[4*(l/16)+q][l%16].
-// Coordinates are held as float pairs hi + lo (hi = x rounded to FP32, lo =
-// the remainder rounded to FP32), and differences are formed as
-// (hi_i - hi_j) + (lo_i - lo_j): for close points the first difference is
-// exact, so distances keep ~FP32 relative accuracy instead of absolute
-// 2^-24 errors of the coordinates, which would dominate the entry error of
-// close pairs.
-__device__ __forceinline__ void split_f32(double v, float& h, float& l) {
-  h = float(v);
-  l = float(v - double(h));
-}
-
+// Squared distances are formed in FP64 (without packed FP32 arithmetic an FP64
+// add or FMA issues at the FP32 rate) and rounded once to FP32; the square
+// root and exponential are the hardware FP32 ones.  Omega is staged in LDS as
+// FP32; the next stage's points and Omega rows are fetched into registers
+// while the current one computes.  Waves of one SIMD overlap their entry
+// generation (VALU) with each other's FP32 MFMAs.
 template <int DIM, int NC>
 struct SkF32Smem {
-  float xsh[DIM][kSkK];
-  float xsl[DIM][kSkK];
+  double xs[DIM][kSkK];
   float om[kSkK][NC + 4];
 };
 
@@ -275,20 +272,19 @@ __device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t 
                                                 const double* __restrict__ omega, int64_t ldo,
                                                 double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  auto& xsh = sm.xsh;
-  auto& xsl = sm.xsl;
+  auto& xs = sm.xs;
   auto& om = sm.om;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
+  double xa[DIM], xb[DIM];
   {
     const int64_t ia = row0 + li, ib = row0 + 16 + li;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
-      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
+      xa[a] = ia < n ? X[a * ldx + ia] : 0.0;
+      xb[a] = ib < n ? X[a * ldx + ib] : 0.0;
     }
   }
   flt4 acc0[NB], acc1[NB];
@@ -300,31 +296,50 @@ __device__ __forceinline__ void sketch_f32_body(SkF32Smem<DIM, NC>& sm, int64_t 
 #pragma unroll
     for (int q = 0; q < 4; ++q) ya[c][q] = yb[c][q] = 0.0;
   }
+  constexpr int PX = (DIM * kSkK + 255) / 256, PO = NC * kSkK / 256;
+  double rx[PX];
+  float ro[PO];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u, a = e / kSkK, jj = e % kSkK;
+      rx[u] = (e < DIM * kSkK && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u, c = e / kSkK, jj = e % kSkK;
+      ro[u] = (j0 + jj < n && c < ncr) ? float(omega[c * ldo + j0 + jj]) : 0.0f;
+    }
+  };
+  fetch(0);
   int stage = 0;
   for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
     __syncthreads();
-    for (int e = tid; e < DIM * kSkK; e += 256) {
-      const int a = e / kSkK, jj = e % kSkK;
-      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u;
+      if (e < DIM * kSkK) xs[e / kSkK][e % kSkK] = rx[u];
     }
-    for (int e = tid; e < NC * kSkK; e += 256) {
-      const int c = e / kSkK, jj = e % kSkK;
-      om[jj][c] = (j0 + jj < n && c < ncr) ? float(omega[c * ldo + j0 + jj]) : 0.0f;
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u;
+      om[e % kSkK][e / kSkK] = ro[u];
     }
     __syncthreads();
-#pragma unroll 4
+    if (j0 + kSkK < n) fetch(j0 + kSkK);
+#pragma unroll
     for (int kk = 0; kk < kSkK / 4; ++kk) {
       const int jj = kk * 4 + lk;
-      float ra = 0.f, rb = 0.f;
+      double ra = 0.0, rb = 0.0;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const float jh = xsh[a][jj], jl = xsl[a][jj];
-        const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
+        const double xj = xs[a][jj];
+        const double da = xa[a] - xj, db = xb[a] - xj;
         ra += da * da;
         rb += db * db;
       }
-      const float ka = kernel_of_r2_f32<KIND>(ra, c2);
-      const float kb = kernel_of_r2_f32<KIND>(rb, c2);
+      const float ka = kernel_of_r2_f32<KIND>(float(ra), c2);
+      const float kb = kernel_of_r2_f32<KIND>(float(rb), c2);
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const float bv = om[jj][c * 16 + li];
@@ -383,54 +398,69 @@ __global__ __launch_bounds__(256) void sketch_f32_batched(const SketchJob* __res
     sketch_f32_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
 }
 
-// Split a float into bf16 hi (truncated) and bf16 lo = bf16(x - hi) (truncated):
-// hi*hi + hi*lo + lo*hi reproduces the FP32 product to about 2^-16 relative.
-__device__ __forceinline__ void split_bf16(float v, uint32_t& hi, uint32_t& lo) {
-  const uint32_t b = __float_as_uint(v);
-  const uint32_t h = b & 0xffff0000u;
-  hi = h >> 16;
-  lo = __float_as_uint(v - __uint_as_float(h)) >> 16;
+// Split bf16 products.  A pair of FP32 values (a, b) is split into S packed
+// bf16x2 words, each the round-to-nearest bf16 of what the earlier words left
+// (the remainders are exact in FP32).  With S = 2 the products
+// hi*hi + hi*lo + lo*hi keep about 2^-17 relative accuracy; with S = 3 the six
+// products whose split orders add up to at most 2 (hh, hm, mh, hl, lh, mm)
+// keep about 2^-24, the accuracy of FP32 products, on the bf16 matrix cores.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+template <int S>
+__device__ __forceinline__ void split_pair(float a, float b, uint32_t (&w)[S]) {
+#pragma unroll
+  for (int t = 0; t < S; ++t) {
+    const bf16x2 p = {__bf16(a), __bf16(b)};
+    const uint32_t u = __builtin_bit_cast(uint32_t, p);
+    w[t] = u;
+    if (t + 1 < S) {
+      a -= __uint_as_float(u << 16);
+      b -= __uint_as_float(u & 0xffff0000u);
+    }
+  }
 }
 
-// Entries in FP32 split into bf16 pairs, v_mfma_f32_16x16x32_bf16 (three
-// products per tile).  Lane l supplies A[l%16][8*(l/16)+e] and
-// B[8*(l/16)+e][l%16], e = 0..7, and holds D[4*(l/16)+q][l%16].  The Omega
-// tile is staged pre-split as [column][point] bf16 so each lane reads its 8
-// points with one 16-byte LDS load.
+// Entries in FP32 split into S bf16 terms, v_mfma_f32_16x16x32_bf16.  Lane l
+// supplies A[l%16][8*(l/16)+e] and B[8*(l/16)+e][l%16], e = 0..7, and holds
+// D[4*(l/16)+q][l%16].  Entries as in the FP32 kernel (FP64 squared distance,
+// FP32 exp2/sqrt).  The Omega tile is staged pre-split as [term][column][point]
+// bf16 so each lane reads its 8 points of a term with one 16-byte LDS load.
+// FP32 partial sums are folded into FP64 every kFlush stages.
 constexpr int kBfK = 64;  // points per stage (two MFMA k-steps of 32)
 
 constexpr int kBfLdp = kBfK / 2 + 4;  // dwords per staged column (2 bf16 per dword)
 
-template <int DIM, int NC>
+template <int DIM, int NC, int S>
 struct SkBfSmem {
-  float xsh[DIM][kBfK];
-  float xsl[DIM][kBfK];
-  uint32_t omh[NC * kBfLdp];
-  uint32_t oml[NC * kBfLdp];
+  double xs[DIM][kBfK];
+  uint32_t om[S][NC * kBfLdp];
 };
 
-template <int DIM, int KIND, int NC>
-__device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_t tile0, int64_t n,
-                                                   const double* __restrict__ X, int64_t ldx, float c2, int ncr,
-                                                   const double* __restrict__ omega, int64_t ldo,
-                                                   double* __restrict__ y, int64_t ldy) {
+template <int DIM, int KIND, int NC, int S>
+__device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64_t tile0, int64_t n,
+                                                 const double* __restrict__ X, int64_t ldx, float c2, int ncr,
+                                                 const double* __restrict__ omega, int64_t ldo,
+                                                 double* __restrict__ y, int64_t ldy) {
+  static_assert(S == 2 || S == 3, "two or three bf16 terms");
   constexpr int NB = NC / 16;
   constexpr int LDP = kBfLdp;
-  auto& xsh = sm.xsh;
-  auto& xsl = sm.xsl;
-  auto& omh = sm.omh;
-  auto& oml = sm.oml;
+  // products (term of K, term of Omega) with split orders adding up to < S
+  constexpr int NP = S == 2 ? 3 : 6;
+  constexpr int PI[6] = {0, 0, 1, 0, 2, 1};
+  constexpr int PJ[6] = {0, 1, 0, 2, 0, 1};
+  auto& xs = sm.xs;
+  auto& om = sm.om;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
+  double xa[DIM], xb[DIM];
   {
     const int64_t ia = row0 + li, ib = row0 + 16 + li;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
-      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
+      xa[a] = ia < n ? X[a * ldx + ia] : 0.0;
+      xb[a] = ib < n ? X[a * ldx + ib] : 0.0;
     }
   }
   flt4 acc0[NB], acc1[NB];
@@ -442,74 +472,88 @@ __device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_
 #pragma unroll
     for (int q = 0; q < 4; ++q) ya[c][q] = yb[c][q] = 0.0;
   }
+  // The next stage's points and Omega rows are fetched into registers while
+  // the current stage computes; a thread stages pairs of points (2p, 2p+1) of
+  // one column, which form one dword of each split Omega term.
+  constexpr int PX = (DIM * kBfK + 255) / 256, PP = NC * (kBfK / 2) / 256;
+  double rx[PX];
+  float ro0[PP], ro1[PP];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u, a = e / kBfK, jj = e % kBfK;
+      rx[u] = (e < DIM * kBfK && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int e = tid + 256 * u, c = e / (kBfK / 2), pp = e % (kBfK / 2);
+      const int64_t j = j0 + 2 * pp;
+      ro0[u] = (c < ncr && j < n) ? float(omega[c * ldo + j]) : 0.0f;
+      ro1[u] = (c < ncr && j + 1 < n) ? float(omega[c * ldo + j + 1]) : 0.0f;
+    }
+  };
+  fetch(0);
   int stage = 0;
   for (int64_t j0 = 0; j0 < n; j0 += kBfK) {
     __syncthreads();
-    for (int e = tid; e < DIM * kBfK; e += 256) {
-      const int a = e / kBfK, jj = e % kBfK;
-      split_f32((j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0, xsh[a][jj], xsl[a][jj]);
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u;
+      if (e < DIM * kBfK) xs[e / kBfK][e % kBfK] = rx[u];
     }
-    // pairs of points per thread: dword (c, p) holds points 2p, 2p+1 of column c
-    for (int e = tid; e < NC * (kBfK / 2); e += 256) {
-      const int c = e / (kBfK / 2), pp = e % (kBfK / 2);
-      const int64_t j = j0 + 2 * pp;
-      float v0 = 0.f, v1 = 0.f;
-      if (c < ncr) {
-        if (j < n) v0 = float(omega[c * ldo + j]);
-        if (j + 1 < n) v1 = float(omega[c * ldo + j + 1]);
-      }
-      uint32_t h0, l0, h1, l1;
-      split_bf16(v0, h0, l0);
-      split_bf16(v1, h1, l1);
-      omh[c * LDP + pp] = h0 | (h1 << 16);
-      oml[c * LDP + pp] = l0 | (l1 << 16);
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int e = tid + 256 * u, c = e / (kBfK / 2), pp = e % (kBfK / 2);
+      uint32_t w[S];
+      split_pair<S>(ro0[u], ro1[u], w);
+#pragma unroll
+      for (int t = 0; t < S; ++t) om[t][c * LDP + pp] = w[t];
     }
     __syncthreads();
+    if (j0 + kBfK < n) fetch(j0 + kBfK);
 #pragma unroll
     for (int ks = 0; ks < kBfK; ks += 32) {
       const int jb = ks + 8 * lk;  // first of this lane's 8 points
-      u32x4 ah0, al0, ah1, al1;
+      u32x4 a0[S], a1[S];
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         float kv[2][2];
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int jj = jb + 2 * w + e;
-          float ra = 0.f, rb = 0.f;
+          double ra = 0.0, rb = 0.0;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
-            const float jh = xsh[a][jj], jl = xsl[a][jj];
-            const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
+            const double xj = xs[a][jj];
+            const double da = xa[a] - xj, db = xb[a] - xj;
             ra += da * da;
             rb += db * db;
           }
-          kv[0][e] = kernel_of_r2_f32<KIND>(ra, c2);
-          kv[1][e] = kernel_of_r2_f32<KIND>(rb, c2);
+          kv[0][e] = kernel_of_r2_f32<KIND>(float(ra), c2);
+          kv[1][e] = kernel_of_r2_f32<KIND>(float(rb), c2);
         }
-        uint32_t h0, l0, h1, l1;
-        split_bf16(kv[0][0], h0, l0);
-        split_bf16(kv[0][1], h1, l1);
-        ah0[w] = h0 | (h1 << 16);
-        al0[w] = l0 | (l1 << 16);
-        split_bf16(kv[1][0], h0, l0);
-        split_bf16(kv[1][1], h1, l1);
-        ah1[w] = h0 | (h1 << 16);
-        al1[w] = l0 | (l1 << 16);
+        uint32_t w0[S], w1[S];
+        split_pair<S>(kv[0][0], kv[0][1], w0);
+        split_pair<S>(kv[1][0], kv[1][1], w1);
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          a0[t][w] = w0[t];
+          a1[t][w] = w1[t];
+        }
       }
-      const bf16x8 Ah0 = __builtin_bit_cast(bf16x8, ah0), Al0 = __builtin_bit_cast(bf16x8, al0);
-      const bf16x8 Ah1 = __builtin_bit_cast(bf16x8, ah1), Al1 = __builtin_bit_cast(bf16x8, al1);
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const int col = c * 16 + li;
-        const u32x4 bh = *reinterpret_cast<const u32x4*>(&omh[col * LDP + jb / 2]);
-        const u32x4 bl = *reinterpret_cast<const u32x4*>(&oml[col * LDP + jb / 2]);
-        const bf16x8 Bh = __builtin_bit_cast(bf16x8, bh), Bl = __builtin_bit_cast(bf16x8, bl);
-        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah0, Bh, acc0[c], 0, 0, 0);
-        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah0, Bl, acc0[c], 0, 0, 0);
-        acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al0, Bh, acc0[c], 0, 0, 0);
-        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah1, Bh, acc1[c], 0, 0, 0);
-        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah1, Bl, acc1[c], 0, 0, 0);
-        acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al1, Bh, acc1[c], 0, 0, 0);
+        bf16x8 B[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          B[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&om[t][col * LDP + jb / 2]));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          const bf16x8 A0 = __builtin_bit_cast(bf16x8, a0[PI[p]]), A1 = __builtin_bit_cast(bf16x8, a1[PI[p]]);
+          acc0[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B[PJ[p]], acc0[c], 0, 0, 0);
+          acc1[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B[PJ[p]], acc1[c], 0, 0, 0);
+        }
       }
     }
     if (++stage == kFlush || j0 + kBfK >= n) {
@@ -539,40 +583,39 @@ __device__ __forceinline__ void sketch_bf16x3_body(SkBfSmem<DIM, NC>& sm, int64_
   }
 }
 
-template <int DIM, int KIND, int NC>
-__global__ __launch_bounds__(256) void sketch_bf16x3_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                            float c2, int ncr, const double* __restrict__ omega,
-                                                            int64_t ldo, double* __restrict__ y, int64_t ldy) {
-  __shared__ SkBfSmem<DIM, NC> sm;
-  sketch_bf16x3_body<DIM, KIND, NC>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+template <int DIM, int KIND, int NC, int S>
+__global__ __launch_bounds__(256) void sketch_bf16_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+                                                          float c2, int ncr, const double* __restrict__ omega,
+                                                          int64_t ldo, double* __restrict__ y, int64_t ldy) {
+  __shared__ SkBfSmem<DIM, NC, S> sm;
+  sketch_bf16_body<DIM, KIND, NC, S>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
 }
 
-template <int NC>
-__global__ __launch_bounds__(256) void sketch_bf16x3_batched(const SketchJob* __restrict__ jobs,
-                                                             const int32_t* __restrict__ tiles,
-                                                             const double* __restrict__ X, int64_t ldx, int ncr,
-                                                             const double* __restrict__ omega, int64_t ldo,
-                                                             double* __restrict__ y, int64_t ldy) {
-  __shared__ SkBfSmem<3, NC> sm;
+template <int NC, int S>
+__global__ __launch_bounds__(256) void sketch_bf16_batched(const SketchJob* __restrict__ jobs,
+                                                           const int32_t* __restrict__ tiles,
+                                                           const double* __restrict__ X, int64_t ldx, int ncr,
+                                                           const double* __restrict__ omega, int64_t ldo,
+                                                           double* __restrict__ y, int64_t ldy) {
+  __shared__ SkBfSmem<3, NC, S> sm;
   const SketchJob J = jobs[tiles[2 * blockIdx.x]];
   const int64_t t0 = tiles[2 * blockIdx.x + 1];
   const float c2 = float(J.c2);
   if (J.kind == kExp)
-    sketch_bf16x3_body<3, kExp, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+    sketch_bf16_body<3, kExp, NC, S>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
   else
-    sketch_bf16x3_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+    sketch_bf16_body<3, kGauss, NC, S>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
 }
 
-// FP32 kernel entries, FP64 contraction: entries are evaluated in FP32 (hi/lo
-// coordinates, hardware exp2/sqrt), converted to FP64 and contracted with the
+// FP32 kernel entries, FP64 contraction: entries are evaluated in FP32 (FP64
+// squared distance, hardware exp2/sqrt), converted to FP64 and contracted with the
 // FP64 Omega on the FP64 matrix cores with FP64 accumulation.  The entry error
 // (~1e-7 relative) enters the samples as independent noise, not accumulated
 // rounding, so the samples stay within ~1e-7 of K Omega at about a third of
 // the FP64 entry cost.  Same tiling and lane layout as the FP64 kernel.
 template <int DIM, int NC>
 struct SkE32Smem {
-  float xsh[DIM][kSkK];
-  float xsl[DIM][kSkK];
+  double xs[DIM][kSkK];
   double om[kSkK][NC + 2];
 };
 
@@ -582,20 +625,19 @@ __device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t 
                                                 const double* __restrict__ omega, int64_t ldo,
                                                 double* __restrict__ y, int64_t ldy) {
   constexpr int NB = NC / 16;
-  auto& xsh = sm.xsh;
-  auto& xsl = sm.xsl;
+  auto& xs = sm.xs;
   auto& om = sm.om;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = tile0 + wave * 32;
   const int li = lane & 15, lk = lane >> 4;
-  float xah[DIM], xal[DIM], xbh[DIM], xbl[DIM];
+  double xa[DIM], xb[DIM];
   {
     const int64_t ia = row0 + li, ib = row0 + 16 + li;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-      split_f32(ia < n ? X[a * ldx + ia] : 0.0, xah[a], xal[a]);
-      split_f32(ib < n ? X[a * ldx + ib] : 0.0, xbh[a], xbl[a]);
+      xa[a] = ia < n ? X[a * ldx + ia] : 0.0;
+      xb[a] = ib < n ? X[a * ldx + ib] : 0.0;
     }
   }
   dbl4 acc0[NB], acc1[NB];
@@ -624,7 +666,7 @@ __device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t 
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
       const int e = tid + 256 * u;
-      if (e < DIM * kSkK) split_f32(rx[u], xsh[e / kSkK][e % kSkK], xsl[e / kSkK][e % kSkK]);
+      if (e < DIM * kSkK) xs[e / kSkK][e % kSkK] = rx[u];
     }
 #pragma unroll
     for (int u = 0; u < PO; ++u) {
@@ -636,16 +678,16 @@ __device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t 
 #pragma unroll 4
     for (int kk = 0; kk < kSkK / 4; ++kk) {
       const int jj = kk * 4 + lk;
-      float ra = 0.f, rb = 0.f;
+      double ra = 0.0, rb = 0.0;
 #pragma unroll
       for (int a = 0; a < DIM; ++a) {
-        const float jh = xsh[a][jj], jl = xsl[a][jj];
-        const float da = (xah[a] - jh) + (xal[a] - jl), db = (xbh[a] - jh) + (xbl[a] - jl);
+        const double xj = xs[a][jj];
+        const double da = xa[a] - xj, db = xb[a] - xj;
         ra += da * da;
         rb += db * db;
       }
-      const double ka = double(kernel_of_r2_f32<KIND>(ra, c2));
-      const double kb = double(kernel_of_r2_f32<KIND>(rb, c2));
+      const double ka = double(kernel_of_r2_f32<KIND>(float(ra), c2));
+      const double kb = double(kernel_of_r2_f32<KIND>(float(rb), c2));
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         const double bv = om[jj][c * 16 + li];
@@ -699,9 +741,11 @@ void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int
   else if constexpr (P == 1)
     sketch_f32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
   else if constexpr (P == 2)
-    sketch_bf16x3_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
-  else
+    sketch_bf16_kernel<DIM, KIND, NC, 2><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+  else if constexpr (P == 3)
     sketch_e32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+  else
+    sketch_bf16_kernel<DIM, KIND, NC, 3><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
 }
 
 template <int P, int DIM, int KIND>
@@ -831,23 +875,18 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 
 // ------------------------------------------------------- block-sparse GEMM
 
-// Y[rows_i, c] += alpha * sum_j Blk_j X[rows_b, c] on the FP64 matrix cores.
-// One workgroup (4 waves) per block row and 16*NB columns; wave w owns the
-// 16-row tiles w, w+4, ... (RT of them).  The X rows of the current column
-// block are staged in LDS ([q][c], shared by the 4 waves); the blocks stream
-// from HBM straight into the MFMA A operand (lane l reads row l%16 of column
-// l/16 of a 16x4 slice: four 128-byte runs per load).
-// Block-sparse product, one workgroup per block row i and 16*NB columns:
+// Block-sparse product on the FP64 matrix cores, one workgroup per block row i
+// and 16*NB columns:
 //   Y[rows_i, c0:c0+16NB] += alpha * sum_j Blk_j X[rows_b, c0:c0+16NB].
 // Wave w owns row tiles w, w+4, .. (RT of them, 16 rows each).  The X rows of
 // block j+1 are fetched into registers while block j runs on the matrix cores
-// from the other LDS buffer (double buffering, one barrier per block), and the
-// block's A operands are loaded 16/RT k-steps at a time.
-// F32: blocks and X are rounded to FP32 at load, the products run on the FP32
-// matrix cores and each block's FP32 partial sums are folded into FP64.
+// from the other LDS buffer (double buffering, one barrier per block); the
+// blocks stream from HBM straight into the MFMA A operand (lane l reads row
+// l%16 of column l/16 of a 16x4 slice: four 128-byte runs per load), 16/RT
+// k-steps at a time.
 constexpr int kBsrMeta = 1024;  // blocks per row whose metadata is cached in LDS
 
-template <int NB, int RT, bool F32, bool TR>
+template <int NB, int RT, bool TR>
 __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                                                        const int32_t* __restrict__ rowoff,
                                                        const int32_t* __restrict__ coloff,
@@ -856,13 +895,12 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
                                                        const double* __restrict__ blocks, const double* __restrict__ X,
                                                        int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
                                                        double alpha) {
-  using T = typename std::conditional<F32, float, double>::type;
   constexpr int LDB = NB * 16;
   constexpr int MAXQ = 64 * RT;      // rows of a staged X tile (block heights <= 64 RT)
   constexpr int QI = RT, CI = LDB / 4;  // staged values per thread: rows lane + 64 qi, columns wave + 4 ci
   constexpr int KC = 16 / RT;        // k-steps per batch of A loads
   extern __shared__ double smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);  // two buffers of MAXQ x LDB
+  double* buf = smem_raw;  // two buffers of MAXQ x LDB
   const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
@@ -895,7 +933,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
   // Two-sided use: block columns index the row space `coloff`, and with TR
   // the block of entry j is the transpose of the stored block tpos[j]
   // (stored mb x m, column-major).
-  T xv[QI][CI];
+  double xv[QI][CI];
   auto fetch = [&](int j) {
     const int q0 = col0(j), mb = height(j);
 #pragma unroll
@@ -903,11 +941,11 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 #pragma unroll
       for (int ci = 0; ci < CI; ++ci) {
         const int q = lane + 64 * qi, c = wave + 4 * ci;
-        xv[qi][ci] = (q < mb && c < ncl) ? T(X[int64_t(c0 + c) * ldx + q0 + q]) : T(0);
+        xv[qi][ci] = (q < mb && c < ncl) ? X[int64_t(c0 + c) * ldx + q0 + q] : 0.0;
       }
   };
   auto stash = [&](int slot) {
-    T* bs = buf + slot * (MAXQ * LDB);
+    double* bs = buf + slot * (MAXQ * LDB);
 #pragma unroll
     for (int qi = 0; qi < QI; ++qi)
 #pragma unroll
@@ -929,24 +967,16 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
     if (more) fetch(j + 1);  // in flight while block j computes
     const int mb = height(j), mb4 = (mb + 3) & ~3;
     const double* blk = blocks + boff(j);
-    const T* bs = buf + cur * (MAXQ * LDB);
-    using V4 = typename std::conditional<F32, flt4, dbl4>::type;
-    V4 part[RT][NB];
-    if constexpr (F32) {
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) part[t][c] = V4{0.f, 0.f, 0.f, 0.f};
-    }
+    const double* bs = buf + cur * (MAXQ * LDB);
     for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
-      T a[RT][KC];
+      double a[RT][KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
         const int q = k0 + 4 * kc + lk;
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
           const int row = (wave + 4 * t) * 16 + li;
-          a[t][kc] = (row < m && q < mb) ? T(TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : T(0);
+          a[t][kc] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
         }
       }
 #pragma unroll
@@ -955,25 +985,13 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
         const int q = k0 + 4 * kc + lk;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
-          const T bv = bs[q * LDB + c * 16 + li];
+          const double bv = bs[q * LDB + c * 16 + li];
 #pragma unroll
           for (int t = 0; t < RT; ++t) {
-            if constexpr (F32)
-              part[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][kc], bv, part[t][c], 0, 0, 0);
-            else
-              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
+            acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
           }
         }
       }
-    }
-    if constexpr (F32) {
-      // FP32 layout D[4*(l/16)+q][l%16] is kept in the FP64 accumulators (the store follows it)
-#pragma unroll
-      for (int t = 0; t < RT; ++t)
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[t][c][q] += double(part[t][c][q]);
     }
     if (more) stash(cur ^ 1);
     __syncthreads();
@@ -986,7 +1004,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
       if (col >= ncl) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = (wave + 4 * t) * 16 + (F32 ? 4 * lk + q : lk + 4 * q);
+        const int row = (wave + 4 * t) * 16 + lk + 4 * q;
         if (row < m) {
           double* yp = Y + int64_t(c0 + col) * ldy + r0 + row;
           *yp += alpha * acc[t][c][q];
@@ -1865,6 +1883,8 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
       e = launch_sketch_p<2>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
     else if (precision == 3)
       e = launch_sketch_p<3>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+    else if (precision == 4)
+      e = launch_sketch_p<4>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
     else
       return hipErrorInvalidValue;
     if (e != hipSuccess) return e;
@@ -1890,19 +1910,19 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
   return hipGetLastError();
 }
 
-template <int NB, bool F32, bool TR>
+template <int NB, bool TR>
 hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                          const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
   const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
   if (rt * NB > 4) return hipErrorInvalidValue;
-  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * (F32 ? sizeof(float) : sizeof(double)) +
+  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * sizeof(double) +
                      size_t(kBsrMeta) * (2 * sizeof(int) + sizeof(int64_t));
   hipError_t e = hipSuccess;
 #define H2_BSR_RT(RT)                                                                                    \
-  if ((e = allow_lds(bsr_gemm_kernel<NB, RT, F32, TR>, lds)) != hipSuccess) return e;                    \
-  bsr_gemm_kernel<NB, RT, F32, TR><<<grid, 256, lds, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, \
+  if ((e = allow_lds(bsr_gemm_kernel<NB, RT, TR>, lds)) != hipSuccess) return e;                    \
+  bsr_gemm_kernel<NB, RT, TR><<<grid, 256, lds, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, \
                                                           ldx, Y, ldy, nc, alpha)
   if (max_m <= 64) {
     H2_BSR_RT(1);
@@ -1917,20 +1937,21 @@ hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int
   return hipGetLastError();
 }
 
-template <bool F32>
-hipError_t bsr_gemm_p(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
-                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
+hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                     const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
+  if (nrows <= 0 || nc <= 0) return hipSuccess;
+  if (max_m < 1) max_m = 1;
   // at most 64 columns per workgroup; RT * NB <= 4 keeps the two staged X
   // tiles within 64 KB and the per-thread staging within 16 values
   int nb = (nc + 15) / 16;
   const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
   if (nb > 4 / rt) nb = 4 / rt;
-#define H2_BSR_NB(NB)                                                                                         \
-  (tpos ? launch_bsr_nb<NB, false, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy,   \
-                                         nc, alpha, max_m)                                                          \
-        : launch_bsr_nb<NB, F32, false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, \
-                                        alpha, max_m))
+#define H2_BSR_NB(NB)                                                                                              \
+  (tpos ? launch_bsr_nb<NB, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, \
+                                  max_m)                                                                             \
+        : launch_bsr_nb<NB, false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc,       \
+                                   alpha, max_m))
   switch (nb) {
     case 1: return H2_BSR_NB(1);
     case 2: return H2_BSR_NB(2);
@@ -1940,25 +1961,10 @@ hipError_t bsr_gemm_p(hipStream_t s, int nrows, const int32_t* ptr, const int32_
 #undef H2_BSR_NB
 }
 
-hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
-                     const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     int precision) {
-  if (nrows <= 0 || nc <= 0) return hipSuccess;
-  if (max_m < 1) max_m = 1;
-  if (precision == 0)
-    return bsr_gemm_p<false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha,
-                             max_m);
-  if (tpos) return hipErrorInvalidValue;  // transposed blocks: FP64 only
-  return bsr_gemm_p<true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha,
-                          max_m);
-}
-
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m, int precision) {
-  return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m,
-                   precision);
+                    int64_t ldy, int nc, double alpha, int max_m) {
+  return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
 }
 
 hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d, int p,
@@ -2065,6 +2071,12 @@ hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* 
     const double* om = omega + int64_t(c0) * ldo;
     double* yy = y + int64_t(c0) * ldy;
 #define H2_SKB(K, NCT) K<NCT><<<ntiles, 256, 0, s>>>(J, tiles, X, ldx, nc, om, ldo, yy, ldy)
+#define H2_SKB_S(NCT, S) sketch_bf16_batched<NCT, S><<<ntiles, 256, 0, s>>>(J, tiles, X, ldx, nc, om, ldo, yy, ldy)
+#define H2_SKB_NC_S(S)                 \
+  if (nc <= 16) H2_SKB_S(16, S);      \
+  else if (nc <= 32) H2_SKB_S(32, S); \
+  else if (nc <= 48) H2_SKB_S(48, S); \
+  else H2_SKB_S(64, S);
 #define H2_SKB_NC(K)               \
   if (nc <= 16) H2_SKB(K, 16);      \
   else if (nc <= 32) H2_SKB(K, 32); \
@@ -2075,10 +2087,16 @@ hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* 
     } else if (precision == 1) {
       H2_SKB_NC(sketch_f32_batched)
     } else if (precision == 2) {
-      H2_SKB_NC(sketch_bf16x3_batched)
-    } else {
+      H2_SKB_NC_S(2)
+    } else if (precision == 3) {
       H2_SKB_NC(sketch_e32_batched)
+    } else if (precision == 4) {
+      H2_SKB_NC_S(3)
+    } else {
+      return hipErrorInvalidValue;
     }
+#undef H2_SKB_NC_S
+#undef H2_SKB_S
 #undef H2_SKB_NC
 #undef H2_SKB
     const hipError_t e = hipGetLastError();
@@ -2171,24 +2189,18 @@ hipError_t prepare_kernels(size_t lds_limit) {
       reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false>),
+      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false>),
   };
   for (const void* f : ks) {
     const hipError_t e = set(f);

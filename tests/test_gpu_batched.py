@@ -155,7 +155,7 @@ def test_batched_sample_limit_is_reported(ctx):
     assert ei.value.status == -5
 
 
-@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (1, 1e-4), (2, 1e-4)])
+@pytest.mark.parametrize("precision,tol", [(1, 1e-6), (1, 1e-4), (2, 1e-4), (4, 1e-6)])
 def test_batched_mixed_precision_meets_tol(ctx, precision, tol):
     spec = [(4000, 3, "exp", 0.2, 64, tol, 32, 16, 8), (2500, 2, "gauss", 0.1, 64, tol, 32, 16, 9)]
     probs = _problems(spec)
