@@ -97,7 +97,7 @@ def bench_batched(h2, ctx, steps: int = 2):
     res["leaf_sizes"] = {str(c): leaves.count(c) for c in (32, 64, 128)}
     for p, leaf in zip(probs, leaves):
         p["leaf_size"] = leaf
-    for name, prec in (("fp64", h2.FP64), ("fp32e", h2.FP32E)):
+    for name, prec in (("fp64", h2.FP64), ("bf16x6", h2.BF16X6)):
         times, info = [], None
         for i in range(steps + 1):
             torch.cuda.synchronize()
@@ -131,14 +131,15 @@ def bench_batched(h2, ctx, steps: int = 2):
     res["sequential_fp64_ms"] = (time.perf_counter() - t0) * 1e3
     if "ms_per_batch" in res.get("fp64", {}):
         res["batched_vs_sequential_speedup"] = res["sequential_fp64_ms"] / res["fp64"]["ms_per_batch"]
-        if "ms_per_batch" in res.get("fp32e", {}):
-            res["mixed_vs_fp64_batched_speedup"] = res["fp64"]["ms_per_batch"] / res["fp32e"]["ms_per_batch"]
+        if "ms_per_batch" in res.get("bf16x6", {}):
+            res["mixed_vs_fp64_batched_speedup"] = res["fp64"]["ms_per_batch"] / res["bf16x6"]["ms_per_batch"]
     return res
 
 
-def bench_update(h2, ctx, n: int = 1 << 16):
+def bench_update(h2, ctx, n: int = 1 << 17):
     """Low-rank update of an H^2 matrix (rank 64) on n points: build H, then
-    the two-sided update with H's matvec as the black box."""
+    the two-sided update with H's matvec as the black box.  The error is
+    measured against that black box, (H + U V^T) x, on two Gaussian vectors."""
     import torch
 
     from paper_2506_16759_amd.workloads import cube_update
@@ -160,8 +161,11 @@ def bench_update(h2, ctx, n: int = 1 << 16):
         info = Hu.info()
         if i == 0:
             Hu.close()
-    print(f"[bench] update n={n} {times[-1]:.1f} ms", file=sys.stderr, flush=True)
-    out = {"workload": w.name, "n": n, "rank": w.rank, "ms_per_update": times[-1],
+    x = torch.randn(2, n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5)).T
+    ref = H.matvec(x) + Ut @ (Vt.T @ x)
+    err = float(torch.linalg.norm(Hu.matvec(x) - ref) / torch.linalg.norm(ref))
+    print(f"[bench] update n={n} {times[-1]:.1f} ms error {err:.2e}", file=sys.stderr, flush=True)
+    out = {"workload": w.name, "n": n, "rank": w.rank, "ms_per_update": times[-1], "error_vs_sampler": err,
            "old_build_ms": H.info()["t_total"], "samples": info["samples"], "rounds": info["rounds"],
            "rank_range": [info["rank_min"], info["rank_max"]],
            "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
@@ -183,7 +187,7 @@ def main():
     ap.add_argument("--only-extras", action="store_true",
                     help="only the 64-problem batched build and the low-rank update (printed as one JSON line)")
     ap.add_argument("--profile-kernels", action="store_true",
-                    help="only run the sketch (FP64, FP32, bf16x3; 32 columns) twice each and a 1 GiB copy of "
+                    help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -203,7 +207,7 @@ def main():
         ctx = h2.Context(0)
         pts = torch.from_numpy(w.points()).cuda()
         omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, w.d0)
-        for prec in (h2.FP64, h2.FP32, h2.BF16X3, h2.FP32E):
+        for prec in (h2.FP64, h2.FP32, h2.BF16X3, h2.FP32E, h2.BF16X6):
             for _ in range(2):
                 h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=prec)
         # calibration: a plain device copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
@@ -215,7 +219,8 @@ def main():
         return
     if args.only_extras:
         ctx = h2.Context(0)
-        print(json.dumps({"batched": bench_batched(h2, ctx), "update": bench_update(h2, ctx)}), flush=True)
+        upd = bench_update(h2, ctx)
+        print(json.dumps({"update": upd, "batched": bench_batched(h2, ctx)}), flush=True)
         return
     print(f"[bench] workload {w.name} n={w.n} tol={tol}", file=sys.stderr, flush=True)
     ctx = h2.Context(0)
@@ -245,13 +250,13 @@ def main():
 
     ms_per_step, times, info = timed_builds(opts, "fp64", args.steps, args.warmup)
 
-    # mixed precision on the same points: FP32 entries contracted in FP64
-    # (fp32e) and FP32 matrix cores (fp32) at the same tolerance; bf16x3 at
-    # tol 1e-4 (its products carry ~2^-16 relative error), with FP64 at 1e-4
-    # for comparison
+    # mixed precision on the same points at the same tolerance: three-term
+    # split bf16 products (bf16x6), FP32 matrix cores (fp32), FP32 entries
+    # contracted in FP64 (fp32e); bf16x3 at tol 1e-4 (its products carry
+    # ~2^-17 relative error), with FP64 at 1e-4 for comparison
     mixed = {}
-    for name, prec, mtol in (("fp32e", h2.FP32E, tol), ("fp32", h2.FP32, tol), ("fp64_tol1e-4", h2.FP64, 1e-4),
-                             ("bf16x3_tol1e-4", h2.BF16X3, 1e-4)):
+    for name, prec, mtol in (("bf16x6", h2.BF16X6, tol), ("fp32", h2.FP32, tol), ("fp32e", h2.FP32E, tol),
+                             ("fp64_tol1e-4", h2.FP64, 1e-4), ("bf16x3_tol1e-4", h2.BF16X3, 1e-4)):
         o = h2.opts_default(tol=mtol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed,
                             precision=prec)
         try:
@@ -278,6 +283,14 @@ def main():
     ev1.record(ctx.stream)
     ev1.synchronize()
     sk_ms = ev0.elapsed_time(ev1) / args.sketch_launches
+    # the same sketch with three-term split bf16 products
+    h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=h2.BF16X6)
+    ev0.record(ctx.stream)
+    for _ in range(args.sketch_launches):
+        h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=h2.BF16X6)
+    ev1.record(ctx.stream)
+    ev1.synchronize()
+    sk6_ms = ev0.elapsed_time(ev1) / args.sketch_launches
     entries = float(w.n) * w.n
     achieved = sketch_flops_per_entry(w.dim, nc) * entries / (sk_ms * 1e-3) / 1e12
     sketch_tflops = 2.0 * entries * nc / (sk_ms * 1e-3) / 1e12
@@ -302,7 +315,9 @@ def main():
         "sketch_tflops": sketch_tflops,
         "sketch_entries_per_s": entries / (sk_ms * 1e-3),
         "sketch_kernel_ms": sk_ms,
-        "mixed_vs_fp64_speedup": mixed.get("fp32e", {}).get("speedup_vs_fp64"),
+        "sketch_bf16x6_kernel_ms": sk6_ms,
+        "sketch_bf16x6_tflops": 2.0 * entries * nc / (sk6_ms * 1e-3) / 1e12,
+        "mixed_vs_fp64_speedup": mixed.get("bf16x6", {}).get("speedup_vs_fp64"),
         "mixed": mixed,
         "samples": info["samples"],
         "adaptive_rounds": info["rounds"],
@@ -320,8 +335,10 @@ def main():
         },
     }
     if not args.no_extras:
-        out["batched"] = bench_batched(h2, ctx)
+        # the update first: its 27 GB of couplings would otherwise wait for the
+        # memory pool to map new pages past what the batched builds left cached
         out["update"] = bench_update(h2, ctx)
+        out["batched"] = bench_batched(h2, ctx)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, info["samples"])
