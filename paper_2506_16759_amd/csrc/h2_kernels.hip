@@ -968,7 +968,10 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
     const int mb = height(j), mb4 = (mb + 3) & ~3;
     const double* blk = blocks + boff(j);
     const double* bs = buf + cur * (MAXQ * LDB);
-    for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
+    // with one row tile per wave, a wave whose tile lies past the block row's
+    // height has only zero products: it only stages X (uniform over the wave)
+    const int kend = (RT == 1 && wave * 16 >= m) ? 0 : mb4;
+    for (int k0 = 0; k0 < kend; k0 += 4 * KC) {
       double a[RT][KC];
 #pragma unroll
       for (int kc = 0; kc < KC; ++kc) {
