@@ -84,6 +84,26 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
+// A stream of default priority for work that may overlap the build stream;
+// join() makes another stream wait for everything enqueued on it so far.
+struct SideStream {
+  hipStream_t s = nullptr;
+  SideStream() { H2_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+  ~SideStream() {
+    if (s) (void)hipStreamDestroy(s);
+  }
+  SideStream(const SideStream&) = delete;
+  SideStream& operator=(const SideStream&) = delete;
+  void join(hipStream_t other) {
+    hipEvent_t e = nullptr;
+    H2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    hipError_t r = hipEventRecord(e, s);
+    if (r == hipSuccess) r = hipStreamWaitEvent(other, e, 0);
+    (void)hipEventDestroy(e);
+    H2_HIP(r);
+  }
+};
+
 int top_depth(const h2::Plan& p) {
   for (int t = 1; t <= p.depth; ++t)
     if (!p.far_idx[t].empty()) return t;
@@ -245,14 +265,6 @@ class Builder {
     h.host_plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - th0).count();
     const h2::Plan& p = h.plan;
     const int D = p.depth;
-    ph = timer_.begin(kTree);
-    h.perm.upload(p.perm, s_);
-    h.X.alloc(static_cast<size_t>(n) * dim, s_);
-    H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
-    timer_.end(ph);
-
-    // ---- dense near-field blocks D_{tau,b} = K(I_tau, I_b)  (Alg. 1 batchedGen)
-    ph = timer_.begin(kNearGen);
     const int nleaves = 1 << D;
     h.leafoff_h.assign(nleaves + 1, 0);
     for (int i = 0; i < nleaves; ++i) h.leafoff_h[i] = p.begin[p.level_begin(D) + i];
@@ -266,14 +278,44 @@ class Builder {
       }
     }
     h.doff_h = prefix(dsz);
-    h.nptr.upload(p.near_ptr, s_);
-    h.nidx.upload(p.near_idx, s_);
-    h.leafoff.upload(h.leafoff_h, s_);
-    h.doff.upload(h.doff_h, s_);
-    h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), s_);
-    H2_HIP(h2dev::gen_blocks(s_, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim, h.X.get(), n,
-                             kf_, h.Dblk.get()));
-    timer_.end(ph);
+
+    // ---- tree-ordered points and the dense near-field blocks
+    // D_{tau,b} = K(I_tau, I_b) (Alg. 1 batchedGen) depend on the tree only:
+    // they are produced on a side stream while the first sketch still runs on
+    // the build stream, which then waits for them.  Their arrays are handed to
+    // the build stream, which orders their later release.
+    SideStream side;
+    auto adopt_all = [&] {
+      h.perm.adopt(s_);
+      h.X.adopt(s_);
+      h.nptr.adopt(s_);
+      h.nidx.adopt(s_);
+      h.leafoff.adopt(s_);
+      h.doff.adopt(s_);
+      h.Dblk.adopt(s_);
+    };
+    try {
+      ph = timer_.begin(kTree, side.s);
+      h.perm.upload(p.perm, side.s);
+      h.X.alloc(static_cast<size_t>(n) * dim, side.s);
+      H2_HIP(h2dev::permute_rows(side.s, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
+      timer_.end(ph, side.s);
+      ph = timer_.begin(kNearGen, side.s);
+      h.nptr.upload(p.near_ptr, side.s);
+      h.nidx.upload(p.near_idx, side.s);
+      h.leafoff.upload(h.leafoff_h, side.s);
+      h.doff.upload(h.doff_h, side.s);
+      h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), side.s);
+      H2_HIP(h2dev::gen_blocks(side.s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim,
+                               h.X.get(), n, kf_, h.Dblk.get()));
+      timer_.end(ph, side.s);
+      side.join(s_);
+    } catch (...) {
+      (void)hipStreamSynchronize(side.s);
+      adopt_all();
+      throw;
+    }
+    adopt_all();
 
     h.lv.clear();
     h.lv.resize(D + 1);

@@ -114,6 +114,9 @@ class DevArray {
     p_ = nullptr;
     n_ = 0;
   }
+  // Later releases are ordered on stream s; the caller has made s wait for
+  // every use of the array on the stream it was allocated on.
+  void adopt(hipStream_t s) { s_ = s; }
   T* get() const { return p_; }
   size_t size() const { return n_; }
   size_t bytes() const { return n_ * sizeof(T); }
@@ -152,15 +155,17 @@ class PhaseTimer {
       (void)hipEventDestroy(r.b);
     }
   }
-  int begin(int phase) {
+  // A phase is timed on the timer's stream or on another stream `on`, which
+  // must have been joined into the timer's stream before totals().
+  int begin(int phase, hipStream_t on = nullptr) {
     Rec r{phase, nullptr, nullptr};
     H2_HIP(hipEventCreate(&r.a));
     H2_HIP(hipEventCreate(&r.b));
-    H2_HIP(hipEventRecord(r.a, s_));
+    H2_HIP(hipEventRecord(r.a, on ? on : s_));
     recs_.push_back(r);
     return static_cast<int>(recs_.size()) - 1;
   }
-  void end(int h) { H2_HIP(hipEventRecord(recs_[h].b, s_)); }
+  void end(int h, hipStream_t on = nullptr) { H2_HIP(hipEventRecord(recs_[h].b, on ? on : s_)); }
   void totals(double* out, int nphase) {
     H2_HIP(hipStreamSynchronize(s_));
     for (int p = 0; p < nphase; ++p) out[p] = 0;
