@@ -84,6 +84,43 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
+void PanelWorkspace::ensure(int nodes, int max_m, int d, hipStream_t s) {
+  const int64_t want = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
+  if (want <= per && nodes <= nn) return;
+  if (buf.size() < size_t(want) * nodes) buf.alloc(size_t(want) * nodes, s);
+  per = want;
+  nn = nodes;
+  std::vector<int64_t> o(nodes);
+  for (int i = 0; i < nodes; ++i) o[i] = want * i;
+  off.upload(o, s);
+}
+
+void PrefixConvTest::init(hipStream_t s, int max_nodes, int inc, int oversample, double delta, size_t lds_limit) {
+  inc_ = inc;
+  ov_ = oversample;
+  lds_ = lds_limit;
+  zeros_.alloc(size_t(std::max(max_nodes, 1)), s);
+  H2_HIP(h2dev::fill_i32(s, zeros_.get(), std::max(max_nodes, 1), 0));
+  state_.alloc(4, s);
+  delta_.upload(std::vector<double>{delta}, s);
+}
+
+int PrefixConvTest::first_converged(hipStream_t s, std::initializer_list<const Level*> levels, int d, int dsk,
+                                    PanelWorkspace& ws) {
+  int32_t* st = state_.get();
+  H2_HIP(h2dev::fill_i32(s, st, 1, d));
+  H2_HIP(h2dev::fill_i32(s, st + 1, 1, inc_));
+  H2_HIP(h2dev::fill_i32(s, st + 2, 1, ov_));
+  H2_HIP(h2dev::fill_i32(s, st + 3, 1, 0));
+  for (const Level* L : levels) {
+    if (size_t(L->max_m | 1) * size_t(dsk) * sizeof(double) > lds_) ws.ensure(L->nn, L->max_m, dsk, s);
+    H2_HIP(h2dev::qr_first_conv(s, L->nn, L->rowoff.get(), L->y.get(), L->M, dsk, st + 1, st + 2, zeros_.get(), st,
+                                delta_.get(), st + 3, L->max_m, lds_, ws.buf.get(), ws.off.get()));
+  }
+  const std::vector<int32_t> r = download(st, 4, s);
+  return r[3] ? -1 : r[0];
+}
+
 // A stream of default priority for work that may overlap the build stream;
 // join() makes another stream wait for everything enqueued on it so far.
 struct SideStream {
@@ -223,12 +260,8 @@ class Builder {
   h2dev::KernelFn kf_{};
   int dcap_ = 0, d_ = 0, dsk_ = 0, ahead_ = 0;
   const double* points_ = nullptr;  // caller's points, original order (borrowed for the build)
-  DevArray<double> gws_;
-  DevArray<int64_t> gws_off_;
-  int64_t gws_per_ = 0;
-  int gws_nn_ = 0;
-  DevArray<int32_t> conv_, counter_;
-  DevArray<double> minr_;
+  PanelWorkspace ws_;
+  PrefixConvTest conv_;
 
   void run_inner(int64_t n, int dim, const double* points) {
     h2_matrix& h = *h_;
@@ -348,9 +381,7 @@ class Builder {
     d_ = o.d0;
     timer_.end(ph);
 
-    conv_.alloc(static_cast<size_t>(nleaves), s_);
-    minr_.alloc(static_cast<size_t>(nleaves), s_);
-    counter_.alloc(1, s_);
+    conv_.init(s_, nleaves, h.opts.d_inc, h.opts.oversample, h.delta, ctx_->lds_limit);
 
     for (int t = D; t >= h.top; --t) level(t);
     h.samples = d_;
@@ -402,21 +433,6 @@ class Builder {
                             P.y.get() + int64_t(c0) * P.M, P.M, P.om.get() + int64_t(c0) * P.M, P.M, nc));
   }
 
-  // Per-cluster panels (stride gws_per_ doubles) for the kernels whose panel
-  // exceeds LDS.  The offsets are laid out again whenever a call needs a larger
-  // stride or more clusters: a buffer that is large enough in total but laid
-  // out with a smaller stride would hand overlapping panels to the clusters of
-  // a later level (fewer, larger clusters).
-  void ensure_gws(int nn, int max_m, int d) {
-    const int64_t per = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
-    if (per <= gws_per_ && nn <= gws_nn_) return;
-    if (gws_.size() < size_t(per) * nn) gws_.alloc(size_t(per) * nn, s_);
-    gws_per_ = per;
-    gws_nn_ = nn;
-    std::vector<int64_t> off(nn);
-    for (int i = 0; i < nn; ++i) off[i] = per * i;
-    gws_off_.upload(off, s_);
-  }
 
   void level(int t) {
     h2_matrix& h = *h_;
@@ -441,21 +457,27 @@ class Builder {
     subtract(t, 0, dsk_);  // every sketched column, used or not yet
     timer_.end(ph);
 
-    // adaptive sampling (Sec. III-B)
+    // adaptive sampling (Sec. III-B): the counts d_, d_ + d_inc, ... are
+    // tested together on every sketched column (prefix test), then more
+    // columns are sketched if none of them converges
+    const int inc = h.opts.d_inc;
     while (true) {
       ph = timer_.begin(kConv);
-      H2_HIP(hipMemsetAsync(counter_.get(), 0, sizeof(int32_t), s_));
-      const size_t qbytes = size_t(L.max_m | 1) * size_t(d_) * sizeof(double);
-      if (qbytes > ctx_->lds_limit) ensure_gws(L.nn, L.max_m, d_);
-      H2_HIP(h2dev::qr_test(s_, L.nn, L.rowoff.get(), L.y.get(), L.M, d_, h.opts.oversample, h.delta, conv_.get(),
-                            minr_.get(), counter_.get(), L.max_m, ctx_->lds_limit, gws_.get(), gws_off_.get()));
-      const int32_t unconv = download(counter_.get(), 1, s_)[0];
+      const int dconv = conv_.first_converged(s_, {&L}, d_, dsk_, ws_);
       timer_.end(ph);
-      if (unconv == 0) break;
-      if (d_ + h.opts.d_inc > h.opts.d_max)
+      if (dconv > 0) {
+        h.rounds += (dconv - d_) / inc;
+        d_ = dconv;
+        break;
+      }
+      // every count up to the sketched columns fails: continue from the last one
+      const int gmax = d_ + ((dsk_ - d_) / inc) * inc;
+      h.rounds += (gmax - d_) / inc;
+      d_ = gmax;
+      if (d_ + inc > h.opts.d_max)
         throw Error(H2_ERR_SAMPLES, "adaptive sampling did not converge within d_max = " +
                                         std::to_string(h.opts.d_max) + " columns at depth " + std::to_string(t));
-      const int need = d_ + h.opts.d_inc;
+      const int need = d_ + inc;
       if (need > dsk_) {
         // sketch the missing columns plus the look-ahead, then updateSamples:
         // sweep them up through the finished levels
@@ -496,9 +518,9 @@ class Builder {
     DevArray<int32_t> kdev;
     kdev.alloc(L.nn, s_);
     const size_t cbytes = size_t(3) * L.max_m * sizeof(double) + size_t(d_ | 1) * L.max_m * sizeof(double);
-    if (cbytes > ctx_->lds_limit) ensure_gws(L.nn, L.max_m, d_);
+    if (cbytes > ctx_->lds_limit) ws_.ensure(L.nn, L.max_m, d_, s_);
     H2_HIP(h2dev::cpqr_id(s_, L.nn, L.rowoff.get(), L.y.get(), L.M, d_, h.delta, kdev.get(), L.J.get(), L.joff.get(),
-                          L.U.get(), L.uoff.get(), L.max_m, ctx_->lds_limit, gws_.get(), gws_off_.get()));
+                          L.U.get(), L.uoff.get(), L.max_m, ctx_->lds_limit, ws_.buf.get(), ws_.off.get()));
     L.k_h = download(kdev.get(), L.nn, s_);
     L.koff_h = prefix(L.k_h);
     L.koff.upload(L.koff_h, s_);

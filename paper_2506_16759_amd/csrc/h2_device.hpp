@@ -56,15 +56,6 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m);
 
-// Adaptive convergence test (Sec. III-B) with an oversampling margin p: per cluster,
-// unpivoted Householder QR of its samples Y[rowoff[i]..rowoff[i+1]) x [0, d-p);
-// conv[i] = 1 if m + p <= d or min |R_jj| < delta.  minr[i] receives the smallest |R_jj|
-// seen (0 when m + p <= d).  *unconverged counts clusters with conv 0 (must be zeroed by
-// the caller).  Panels larger than lds_limit bytes use gws.
-hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d, int p,
-                   double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m,
-                   size_t lds_limit, double* gws, const int64_t* gws_off);
-
 // Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
 // row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).
 // Batched use: nodeprob[i] names cluster i's problem, whose column count and
@@ -133,10 +124,13 @@ hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, cons
                               const int64_t* blkoff, const double* X, int64_t ldx, const int32_t* rowprob,
                               const int32_t* kinds, const double* c2s, double* out);
 
-// Prefix convergence test over all dsk sketched columns: raises dprob[p] to the
-// first column count on the grid dprob[p] + j*incprob[p] at which every cluster
-// of p is converged (test of qr_test with margin ovprob[p]); sets exhausted[p] if
-// some cluster is not converged within dsk.
+// Adaptive convergence test (Sec. III-B) over all dsk sketched columns, with
+// an oversampling margin: a cluster of m rows is converged at count d if
+// m + ovprob[p] <= d or min |R_jj| < delta over j < d - ovprob[p] (unpivoted
+// Householder QR of its samples).  Raises dprob[p] to the first count on the
+// grid dprob[p] + j*incprob[p] at which every cluster of problem p is
+// converged; sets exhausted[p] if some cluster is not converged within dsk.
+// Panels larger than lds_limit bytes use gws.
 hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int dsk,
                          const int32_t* incprob, const int32_t* ovprob, const int32_t* nodeprob, int32_t* dprob,
                          const double* deltaprob, int32_t* exhausted, int max_m, size_t lds_limit, double* gws,

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <initializer_list>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -214,6 +215,38 @@ struct Level {
 h2dev::KernelFn kernel_fn(const h2_kernel& k);
 void check_kernel(const h2_kernel* k);
 int top_depth(const h2::Plan& p);
+
+// Per-cluster panels for the kernels whose panel (QR test, CPQR) exceeds LDS:
+// one panel of `per` doubles per cluster.  The offsets are laid out again
+// whenever a call needs a larger stride or more clusters: a buffer that is
+// large enough in total but laid out with a smaller stride would hand
+// overlapping panels to the clusters of a later level (fewer, larger clusters).
+struct PanelWorkspace {
+  DevArray<double> buf;
+  DevArray<int64_t> off;
+  int64_t per = 0;
+  int nn = 0;
+  void ensure(int nodes, int max_m, int d, hipStream_t s);
+};
+
+// Adaptive stopping test (Sec. III-B) on every sketched column at once: the
+// smallest count d' on the grid d, d + inc, ... (d' <= dsk) at which every
+// cluster of the given levels is converged, or -1 if some cluster is not
+// converged within the dsk sketched columns.  The leading diagonal entries of
+// a cluster's QR do not depend on later columns, so a converged count stays
+// converged and the result equals testing d, d + inc, ... one at a time.
+class PrefixConvTest {
+ public:
+  void init(hipStream_t s, int max_nodes, int inc, int oversample, double delta, size_t lds_limit);
+  int first_converged(hipStream_t s, std::initializer_list<const Level*> levels, int d, int dsk,
+                      PanelWorkspace& ws);
+
+ private:
+  DevArray<int32_t> zeros_, state_;  // state: d (raised in place), inc, oversample, exhausted
+  DevArray<double> delta_;
+  int inc_ = 16, ov_ = 0;
+  size_t lds_ = 0;
+};
 
 }  // namespace h2i
 

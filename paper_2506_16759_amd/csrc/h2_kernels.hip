@@ -1018,99 +1018,6 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
 
 // ------------------------------------------------- adaptive convergence test
 
-// Unpivoted Householder QR of a cluster's samples P (m x d, column-major in the
-// panel with odd leading dimension ldp).  Thread c owns column c.  The
-// reflector of step j is formed by wave 0 from column j; every other column
-// applies it on its own.  Stops at the first |R_jj| < delta.
-template <bool kLds>
-__global__ void qr_test_kernel(const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy, int d,
-                               int p, double delta, int32_t* __restrict__ conv, double* __restrict__ minr,
-                               int32_t* __restrict__ unconverged, double* __restrict__ gws,
-                               const int64_t* __restrict__ gws_off) {
-  extern __shared__ double smem[];
-  __shared__ double s_tau, s_beta;
-  __shared__ int s_stop;
-  const int i = blockIdx.x;
-  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (m + p <= d) {  // every row resolved with p samples to spare
-    if (tid == 0) {
-      conv[i] = 1;
-      minr[i] = 0.0;
-    }
-    return;
-  }
-  // only the leading d - p columns are tested; the last p are the ID's oversampling
-  d -= p;
-  if (d <= 0) {
-    if (tid == 0) {
-      conv[i] = 0;
-      minr[i] = INFINITY;
-      atomicAdd(unconverged, 1);
-    }
-    return;
-  }
-  const int ldp = m | 1;
-  double* P = kLds ? smem : gws + gws_off[i];
-  for (int e = tid; e < m * d; e += nt) {
-    const int r = e % m, c = e / m;
-    P[c * ldp + r] = Y[int64_t(c) * ldy + r0 + r];
-  }
-  if (tid == 0) s_stop = 0;
-  __syncthreads();
-  double mn = INFINITY;
-  for (int j = 0; j < d; ++j) {
-    double* pj = P + j * ldp;
-    if (tid < kWave) {
-      double sg = 0.0;
-      for (int r = j + 1 + tid; r < m; r += kWave) sg += pj[r] * pj[r];
-      sg = wave_sum(sg);
-      const double alpha = pj[j];
-      double beta, tau, scal;
-      if (sg == 0.0) {
-        beta = alpha;
-        tau = 0.0;
-        scal = 0.0;
-      } else {
-        const double nrm = sqrt(alpha * alpha + sg);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      for (int r = j + 1 + tid; r < m; r += kWave) pj[r] *= scal;
-      if (tid == 0) {
-        s_tau = tau;
-        s_beta = beta;
-        if (fabs(beta) < delta) s_stop = 1;
-      }
-    }
-    __syncthreads();
-    mn = fmin(mn, fabs(s_beta));
-    if (s_stop) break;
-    const double tau = s_tau;
-    for (int c = j + 1 + tid; c < d; c += nt) {
-      double* pc = P + c * ldp;
-      double w0 = pc[j], w1 = 0.0;
-      int r = j + 1;
-      for (; r + 1 < m; r += 2) {
-        w0 += pj[r] * pc[r];
-        w1 += pj[r + 1] * pc[r + 1];
-      }
-      if (r < m) w0 += pj[r] * pc[r];
-      const double w = (w0 + w1) * tau;
-      pc[j] -= w;
-      for (int rr = j + 1; rr < m; ++rr) pc[rr] -= w * pj[rr];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    const int ok = mn < delta ? 1 : 0;
-    conv[i] = ok;
-    minr[i] = mn;
-    if (!ok) atomicAdd(unconverged, 1);
-  }
-}
-
 // Prefix form of the convergence test.  The leading R_ii of a Householder QR
 // do not depend on later columns, so one QR over all dsk sketched columns
 // gives, for each cluster, the first column count d' = d + j*inc (d = its
@@ -1970,26 +1877,6 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
   return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
 }
 
-hipError_t qr_test(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d, int p,
-                   double delta, int32_t* conv, double* minr, int32_t* unconverged, int max_m, size_t lds_limit,
-                   double* gws, const int64_t* gws_off) {
-  if (nnodes <= 0) return hipSuccess;
-  if (p < 0) return hipErrorInvalidValue;
-  const int threads = d <= 64 ? 64 : (d <= 128 ? 128 : 256);
-  const size_t bytes = size_t(max_m | 1) * size_t(d) * sizeof(double);
-  if (bytes <= lds_limit) {
-    hipError_t e = allow_lds(qr_test_kernel<true>, bytes);
-    if (e != hipSuccess) return e;
-    qr_test_kernel<true><<<nnodes, threads, bytes, s>>>(rowoff, Y, ldy, d, p, delta, conv, minr, unconverged, gws,
-                                                        gws_off);
-  } else {
-    if (!gws || !gws_off) return hipErrorInvalidValue;
-    qr_test_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, d, p, delta, conv, minr, unconverged, gws,
-                                                     gws_off);
-  }
-  return hipGetLastError();
-}
-
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
                    double delta, int32_t* kout, int32_t* J, const int64_t* joff, double* U, const int64_t* uoff,
                    int max_m, size_t lds_limit, double* gws, const int64_t* gws_off, const int32_t* nodeprob,
@@ -2188,7 +2075,6 @@ hipError_t prepare_kernels(size_t lds_limit) {
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, b);
   };
   const void* ks[] = {
-      reinterpret_cast<const void*>(qr_test_kernel<true>),
       reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<false>),

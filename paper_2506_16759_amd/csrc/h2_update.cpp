@@ -75,28 +75,10 @@ class UpdateBuilder {
   std::vector<DevArray<int64_t>> tpos_;  // per depth: CSR position of the mirrored far pair
   std::vector<DevArray<double>> Rr_, Rc_;  // per depth: rows of H's basis at the new skeletons
   std::vector<int> maxko_;
-  DevArray<double> gws_, lrW_, lrPart_, lrSum_;
-  DevArray<int64_t> gws_off_;
-  int64_t gws_per_ = 0;
-  int gws_nn_ = 0;
-  DevArray<int32_t> conv_, counter_;
-  DevArray<double> minr_;
+  DevArray<double> lrW_, lrPart_, lrSum_;
+  PanelWorkspace ws_;
+  PrefixConvTest conv_;
 
-  // Per-cluster panels (stride gws_per_ doubles) for the kernels whose panel
-  // exceeds LDS.  The offsets are laid out again whenever a call needs a larger
-  // stride or more clusters: a buffer that is large enough in total but laid
-  // out with a smaller stride would hand overlapping panels to the clusters of
-  // a later level (fewer, larger clusters).
-  void ensure_gws(int nn, int max_m, int d) {
-    const int64_t per = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
-    if (per <= gws_per_ && nn <= gws_nn_) return;
-    if (gws_.size() < size_t(per) * nn) gws_.alloc(size_t(per) * nn, s_);
-    gws_per_ = per;
-    gws_nn_ = nn;
-    std::vector<int64_t> off(nn);
-    for (int i = 0; i < nn; ++i) off[i] = per * i;
-    gws_off_.upload(off, s_);
-  }
 
   void run_inner(const double* U, int64_t ldu, const double* V, int64_t ldv) {
     h2_matrix& h = *h_;
@@ -179,9 +161,7 @@ class UpdateBuilder {
     d_ = o.d0;
     timer_.end(ph);
 
-    conv_.alloc(size_t(nleaves), s_);
-    minr_.alloc(size_t(nleaves), s_);
-    counter_.alloc(1, s_);
+    conv_.init(s_, nleaves, o.d_inc, o.oversample, h.delta, ctx_->lds_limit);
     Rr_.resize(D + 2);
     Rc_.resize(D + 2);
     maxko_.assign(D + 2, 0);
@@ -325,10 +305,10 @@ class UpdateBuilder {
     DevArray<int32_t> kdev;
     kdev.alloc(L.nn, s_);
     const size_t cbytes = size_t(3) * L.max_m * sizeof(double) + size_t(d_ | 1) * L.max_m * sizeof(double);
-    if (cbytes > ctx_->lds_limit) ensure_gws(L.nn, L.max_m, d_);
+    if (cbytes > ctx_->lds_limit) ws_.ensure(L.nn, L.max_m, d_, s_);
     H2_HIP(h2dev::cpqr_id(s_, L.nn, L.rowoff.get(), L.y.get(), L.M, d_, h.delta, kdev.get(), L.J.get(),
-                          L.joff.get(), L.U.get(), L.uoff.get(), L.max_m, ctx_->lds_limit, gws_.get(),
-                          gws_off_.get()));
+                          L.joff.get(), L.U.get(), L.uoff.get(), L.max_m, ctx_->lds_limit, ws_.buf.get(),
+                          ws_.off.get()));
     L.k_h = download(kdev.get(), L.nn, s_);
     L.koff_h = prefix(L.k_h);
     L.koff.upload(L.koff_h, s_);
@@ -349,24 +329,26 @@ class UpdateBuilder {
     subtract(t, 0, dsk_);
     timer_.end(ph);
 
-    // adaptive sampling: both sides share d
+    // adaptive sampling: both sides share d; the counts d_, d_ + d_inc, ...
+    // are tested together on every sketched column (prefix test)
+    const int inc = h.opts.d_inc;
     while (true) {
       ph = timer_.begin(kConv);
-      H2_HIP(h2dev::fill_i32(s_, counter_.get(), 1, 0));
-      for (Level* L : {&Lr, &Lc}) {
-        const size_t qbytes = size_t(L->max_m | 1) * size_t(d_) * sizeof(double);
-        if (qbytes > ctx_->lds_limit) ensure_gws(L->nn, L->max_m, d_);
-        H2_HIP(h2dev::qr_test(s_, L->nn, L->rowoff.get(), L->y.get(), L->M, d_, h.opts.oversample, h.delta,
-                              conv_.get(), minr_.get(), counter_.get(), L->max_m, ctx_->lds_limit, gws_.get(),
-                              gws_off_.get()));
-      }
-      const int32_t unconv = download(counter_.get(), 1, s_)[0];
+      const int dconv = conv_.first_converged(s_, {&Lr, &Lc}, d_, dsk_, ws_);
       timer_.end(ph);
-      if (unconv == 0) break;
-      if (d_ + h.opts.d_inc > h.opts.d_max)
+      if (dconv > 0) {
+        h.rounds += (dconv - d_) / inc;
+        d_ = dconv;
+        break;
+      }
+      // every count up to the sketched columns fails: continue from the last one
+      const int gmax = d_ + ((dsk_ - d_) / inc) * inc;
+      h.rounds += (gmax - d_) / inc;
+      d_ = gmax;
+      if (d_ + inc > h.opts.d_max)
         throw Error(H2_ERR_SAMPLES, "adaptive sampling did not converge within d_max = " +
                                         std::to_string(h.opts.d_max) + " columns at depth " + std::to_string(t));
-      const int need = d_ + h.opts.d_inc;
+      const int need = d_ + inc;
       if (need > dsk_) {
         const int c0 = dsk_, nc = std::min(need - dsk_ + ahead_, dcap_ - dsk_);
         ph = timer_.begin(kSample);
