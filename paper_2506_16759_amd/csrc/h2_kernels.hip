@@ -886,46 +886,23 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 // k-steps at a time.
 constexpr int kBsrMeta = 1024;  // blocks per row whose metadata is cached in LDS
 
-template <int NB, int RT, bool TR>
-__global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                                       const int32_t* __restrict__ rowoff,
-                                                       const int32_t* __restrict__ coloff,
-                                                       const int64_t* __restrict__ tpos,
-                                                       const int64_t* __restrict__ blkoff,
-                                                       const double* __restrict__ blocks, const double* __restrict__ X,
-                                                       int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
-                                                       double alpha) {
+// The block row's products for a wave with L live row tiles (L <= RT): the
+// wave's row tiles w + 4t with t >= L lie past the block row's height, hold
+// zeros and are neither loaded nor multiplied.  Every wave stages its share of
+// X and takes part in every barrier whatever its L.
+template <int NB, int RT, bool TR, int L>
+__device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const int32_t* __restrict__ coloff,
+                                        const int64_t* __restrict__ tpos, const int64_t* __restrict__ blkoff,
+                                        const double* __restrict__ blocks, const double* __restrict__ X, int64_t ldx,
+                                        double* __restrict__ Y, int64_t ldy, double alpha, double* buf,
+                                        const int* s_q0, const int* s_mb, const int64_t* s_bo, bool meta, int jb,
+                                        int je, int r0, int m, int c0, int ncl) {
   constexpr int LDB = NB * 16;
-  constexpr int MAXQ = 64 * RT;      // rows of a staged X tile (block heights <= 64 RT)
+  constexpr int MAXQ = 64 * RT;         // rows of a staged X tile (block heights <= 64 RT)
   constexpr int QI = RT, CI = LDB / 4;  // staged values per thread: rows lane + 64 qi, columns wave + 4 ci
-  constexpr int KC = 16 / RT;        // k-steps per batch of A loads
-  extern __shared__ double smem_raw[];
-  double* buf = smem_raw;  // two buffers of MAXQ x LDB
-  const int i = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int KC = 16 / RT;           // k-steps per batch of A loads
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  const int c0 = blockIdx.y * LDB;
-  const int ncl = min(LDB, nc - c0);
-  const int jb = ptr[i], je = ptr[i + 1];
-  if (m == 0 || jb == je) return;  // uniform over the workgroup
-
-  // Each block's column offset, height and storage offset are gathered into
-  // LDS once per row (rows of up to kBsrMeta blocks), so the per-block chain
-  // idx -> coloff -> X is not a sequence of dependent global loads.
-  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (MAXQ * LDB));
-  int* s_mb = s_q0 + kBsrMeta;
-  int64_t* s_bo = reinterpret_cast<int64_t*>(s_mb + kBsrMeta);
-  const bool meta = je - jb <= kBsrMeta;
-  if (meta) {
-    for (int e = tid; e < je - jb; e += 256) {
-      const int b = idx[jb + e];
-      const int q0 = coloff[b];
-      s_q0[e] = q0;
-      s_mb[e] = coloff[b + 1] - q0;
-      s_bo[e] = blkoff[TR ? tpos[jb + e] : jb + e];
-    }
-    __syncthreads();
-  }
   auto col0 = [&](int j) { return meta ? s_q0[j - jb] : coloff[idx[j]]; };
   auto height = [&](int j) { return meta ? s_mb[j - jb] : coloff[idx[j] + 1] - coloff[idx[j]]; };
   auto boff = [&](int j) { return meta ? s_bo[j - jb] : blkoff[TR ? tpos[j] : j]; };
@@ -952,9 +929,9 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
       for (int ci = 0; ci < CI; ++ci) bs[(lane + 64 * qi) * LDB + wave + 4 * ci] = xv[qi][ci];
   };
 
-  dbl4 acc[RT][NB];
+  dbl4 acc[L > 0 ? L : 1][NB];
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+  for (int t = 0; t < L; ++t)
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
@@ -965,33 +942,31 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
     const int cur = (j - jb) & 1;
     const bool more = j + 1 < je;
     if (more) fetch(j + 1);  // in flight while block j computes
-    const int mb = height(j), mb4 = (mb + 3) & ~3;
-    const double* blk = blocks + boff(j);
-    const double* bs = buf + cur * (MAXQ * LDB);
-    // with one row tile per wave, a wave whose tile lies past the block row's
-    // height has only zero products: it only stages X (uniform over the wave)
-    const int kend = (RT == 1 && wave * 16 >= m) ? 0 : mb4;
-    for (int k0 = 0; k0 < kend; k0 += 4 * KC) {
-      double a[RT][KC];
+    if constexpr (L > 0) {
+      const int mb = height(j), mb4 = (mb + 3) & ~3;
+      const double* blk = blocks + boff(j);
+      const double* bs = buf + cur * (MAXQ * LDB);
+      for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
+        double a[L][KC];
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        const int q = k0 + 4 * kc + lk;
+        for (int kc = 0; kc < KC; ++kc) {
+          const int q = k0 + 4 * kc + lk;
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int row = (wave + 4 * t) * 16 + li;
-          a[t][kc] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
+          for (int t = 0; t < L; ++t) {
+            const int row = (wave + 4 * t) * 16 + li;
+            a[t][kc] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
+          }
         }
-      }
 #pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        if (k0 + 4 * kc >= mb4) break;
-        const int q = k0 + 4 * kc + lk;
+        for (int kc = 0; kc < KC; ++kc) {
+          if (k0 + 4 * kc >= mb4) break;
+          const int q = k0 + 4 * kc + lk;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const double bv = bs[q * LDB + c * 16 + li];
+          for (int c = 0; c < NB; ++c) {
+            const double bv = bs[q * LDB + c * 16 + li];
 #pragma unroll
-          for (int t = 0; t < RT; ++t) {
-            acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
+            for (int t = 0; t < L; ++t)
+              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
           }
         }
       }
@@ -1000,7 +975,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < RT; ++t)
+  for (int t = 0; t < L; ++t)
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       const int col = c * 16 + li;
@@ -1014,6 +989,65 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
         }
       }
     }
+}
+
+template <int NB, int RT, bool TR>
+__global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                                                       const int32_t* __restrict__ rowoff,
+                                                       const int32_t* __restrict__ coloff,
+                                                       const int64_t* __restrict__ tpos,
+                                                       const int64_t* __restrict__ blkoff,
+                                                       const double* __restrict__ blocks, const double* __restrict__ X,
+                                                       int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
+                                                       double alpha) {
+  constexpr int LDB = NB * 16;
+  constexpr int MAXQ = 64 * RT;
+  extern __shared__ double smem_raw[];
+  double* buf = smem_raw;  // two buffers of MAXQ x LDB
+  const int i = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int c0 = blockIdx.y * LDB;
+  const int ncl = min(LDB, nc - c0);
+  const int jb = ptr[i], je = ptr[i + 1];
+  if (m == 0 || jb == je) return;  // uniform over the workgroup
+
+  // Each block's column offset, height and storage offset are gathered into
+  // LDS once per row (rows of up to kBsrMeta blocks), so the per-block chain
+  // idx -> coloff -> X is not a sequence of dependent global loads.
+  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (MAXQ * LDB));
+  int* s_mb = s_q0 + kBsrMeta;
+  int64_t* s_bo = reinterpret_cast<int64_t*>(s_mb + kBsrMeta);
+  const bool meta = je - jb <= kBsrMeta;
+  if (meta) {
+    for (int e = tid; e < je - jb; e += 256) {
+      const int b = idx[jb + e];
+      const int q0 = coloff[b];
+      s_q0[e] = q0;
+      s_mb[e] = coloff[b + 1] - q0;
+      s_bo[e] = blkoff[TR ? tpos[jb + e] : jb + e];
+    }
+    __syncthreads();
+  }
+  // live row tiles of this wave: t with (wave + 4 t) * 16 < m (uniform over the wave)
+  const int live = min(RT, max(0, (m - 16 * wave + 63) / 64));
+#define H2_BSR_ROW(L)                                                                                          \
+  bsr_row<NB, RT, TR, L>(idx, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, alpha, buf, s_q0, s_mb, s_bo, meta, \
+                         jb, je, r0, m, c0, ncl)
+  if (live == 0) {
+    H2_BSR_ROW(0);
+  } else if (RT == 1 || live == 1) {
+    H2_BSR_ROW(1);
+  } else if constexpr (RT >= 2) {
+    if (live == 2 || RT == 2) {
+      H2_BSR_ROW(2);
+    } else if constexpr (RT >= 4) {
+      if (live == 3)
+        H2_BSR_ROW(3);
+      else
+        H2_BSR_ROW(4);
+    }
+  }
+#undef H2_BSR_ROW
 }
 
 // ------------------------------------------------- adaptive convergence test
