@@ -8,6 +8,7 @@
 // one thread per panel column and wave shuffles for norms and the pivot argmax.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include <cmath>
@@ -879,17 +880,21 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 // and 16*NB columns:
 //   Y[rows_i, c0:c0+16NB] += alpha * sum_j Blk_j X[rows_b, c0:c0+16NB].
 // Wave w owns row tiles w, w+4, .. (RT of them, 16 rows each).  The X rows of
-// block j+1 are fetched into registers while block j runs on the matrix cores
-// from the other LDS buffer (double buffering, one barrier per block); the
-// blocks stream from HBM straight into the MFMA A operand (lane l reads row
-// l%16 of column l/16 of a 16x4 slice: four 128-byte runs per load), 16/RT
-// k-steps at a time.
+// the next block chunk are fetched into registers while the current one runs
+// on the matrix cores from the other LDS buffer (double buffering, one barrier
+// per chunk of up to 64 rows); the blocks stream from HBM straight into the
+// MFMA A operand (lane l reads row l%16 of column l/16 of a 16x4 slice: four
+// 128-byte runs per load), 16/RT k-steps at a time.
 constexpr int kBsrMeta = 1024;  // blocks per row whose metadata is cached in LDS
 
 // The block row's products for a wave with L live row tiles (L <= RT): the
 // wave's row tiles w + 4t with t >= L lie past the block row's height, hold
 // zeros and are neither loaded nor multiplied.  Every wave stages its share of
-// X and takes part in every barrier whatever its L.
+// X and takes part in every barrier whatever its L.  X is staged in chunks of
+// kBsrQ rows of a block (a block of height mb takes ceil(mb / kBsrQ) chunks),
+// so the LDS tile does not grow with the block height.
+constexpr int kBsrQ = 64;
+
 template <int NB, int RT, bool TR, int L>
 __device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const int32_t* __restrict__ coloff,
                                         const int64_t* __restrict__ tpos, const int64_t* __restrict__ blkoff,
@@ -898,9 +903,8 @@ __device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const i
                                         const int* s_q0, const int* s_mb, const int64_t* s_bo, bool meta, int jb,
                                         int je, int r0, int m, int c0, int ncl) {
   constexpr int LDB = NB * 16;
-  constexpr int MAXQ = 64 * RT;         // rows of a staged X tile (block heights <= 64 RT)
-  constexpr int QI = RT, CI = LDB / 4;  // staged values per thread: rows lane + 64 qi, columns wave + 4 ci
-  constexpr int KC = 16 / RT;           // k-steps per batch of A loads
+  constexpr int CI = LDB / 4;   // staged values per thread: row lane, columns wave + 4 ci
+  constexpr int KC = 16 / RT;   // k-steps per batch of A loads
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   auto col0 = [&](int j) { return meta ? s_q0[j - jb] : coloff[idx[j]]; };
@@ -910,23 +914,19 @@ __device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const i
   // Two-sided use: block columns index the row space `coloff`, and with TR
   // the block of entry j is the transpose of the stored block tpos[j]
   // (stored mb x m, column-major).
-  double xv[QI][CI];
-  auto fetch = [&](int j) {
-    const int q0 = col0(j), mb = height(j);
+  double xv[CI];
+  auto fetch = [&](int j, int qlo) {
+    const int q0 = col0(j) + qlo, qn = height(j) - qlo;
 #pragma unroll
-    for (int qi = 0; qi < QI; ++qi)
-#pragma unroll
-      for (int ci = 0; ci < CI; ++ci) {
-        const int q = lane + 64 * qi, c = wave + 4 * ci;
-        xv[qi][ci] = (q < mb && c < ncl) ? X[int64_t(c0 + c) * ldx + q0 + q] : 0.0;
-      }
+    for (int ci = 0; ci < CI; ++ci) {
+      const int c = wave + 4 * ci;
+      xv[ci] = (lane < qn && c < ncl) ? X[int64_t(c0 + c) * ldx + q0 + lane] : 0.0;
+    }
   };
   auto stash = [&](int slot) {
-    double* bs = buf + slot * (MAXQ * LDB);
+    double* bs = buf + slot * (kBsrQ * LDB);
 #pragma unroll
-    for (int qi = 0; qi < QI; ++qi)
-#pragma unroll
-      for (int ci = 0; ci < CI; ++ci) bs[(lane + 64 * qi) * LDB + wave + 4 * ci] = xv[qi][ci];
+    for (int ci = 0; ci < CI; ++ci) bs[lane * LDB + wave + 4 * ci] = xv[ci];
   };
 
   dbl4 acc[L > 0 ? L : 1][NB];
@@ -935,31 +935,39 @@ __device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const i
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-  fetch(jb);
+  // items (block j, rows qlo.. of it) in order; the next item's X is in
+  // flight while the current one computes from the other LDS buffer
+  int j = jb, qlo = 0, cur = 0;
+  fetch(j, qlo);
   stash(0);
   __syncthreads();
-  for (int j = jb; j < je; ++j) {
-    const int cur = (j - jb) & 1;
-    const bool more = j + 1 < je;
-    if (more) fetch(j + 1);  // in flight while block j computes
+  while (j < je) {
+    const int mb = height(j);
+    int nj = j, nq = qlo + kBsrQ;
+    if (nq >= mb) {
+      nj = j + 1;
+      nq = 0;
+    }
+    const bool more = nj < je;
+    if (more) fetch(nj, nq);
     if constexpr (L > 0) {
-      const int mb = height(j), mb4 = (mb + 3) & ~3;
+      const int qn = min(kBsrQ, mb - qlo), qn4 = (qn + 3) & ~3;
       const double* blk = blocks + boff(j);
-      const double* bs = buf + cur * (MAXQ * LDB);
-      for (int k0 = 0; k0 < mb4; k0 += 4 * KC) {
+      const double* bs = buf + cur * (kBsrQ * LDB);
+      for (int k0 = 0; k0 < qn4; k0 += 4 * KC) {
         double a[L][KC];
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-          const int q = k0 + 4 * kc + lk;
+          const int q = k0 + 4 * kc + lk, qg = qlo + q;
 #pragma unroll
           for (int t = 0; t < L; ++t) {
             const int row = (wave + 4 * t) * 16 + li;
-            a[t][kc] = (row < m && q < mb) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * m + row]) : 0.0;
+            a[t][kc] = (row < m && q < qn) ? (TR ? blk[int64_t(row) * mb + qg] : blk[int64_t(qg) * m + row]) : 0.0;
           }
         }
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-          if (k0 + 4 * kc >= mb4) break;
+          if (k0 + 4 * kc >= qn4) break;
           const int q = k0 + 4 * kc + lk;
 #pragma unroll
           for (int c = 0; c < NB; ++c) {
@@ -973,6 +981,9 @@ __device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const i
     }
     if (more) stash(cur ^ 1);
     __syncthreads();
+    cur ^= 1;
+    j = nj;
+    qlo = nq;
   }
 #pragma unroll
   for (int t = 0; t < L; ++t)
@@ -1001,9 +1012,8 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
                                                        int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
                                                        double alpha) {
   constexpr int LDB = NB * 16;
-  constexpr int MAXQ = 64 * RT;
   extern __shared__ double smem_raw[];
-  double* buf = smem_raw;  // two buffers of MAXQ x LDB
+  double* buf = smem_raw;  // two buffers of kBsrQ x LDB
   const int i = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
   const int c0 = blockIdx.y * LDB;
@@ -1014,7 +1024,7 @@ __global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict
   // Each block's column offset, height and storage offset are gathered into
   // LDS once per row (rows of up to kBsrMeta blocks), so the per-block chain
   // idx -> coloff -> X is not a sequence of dependent global loads.
-  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (MAXQ * LDB));
+  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (kBsrQ * LDB));
   int* s_mb = s_q0 + kBsrMeta;
   int64_t* s_bo = reinterpret_cast<int64_t*>(s_mb + kBsrMeta);
   const bool meta = je - jb <= kBsrMeta;
@@ -1860,8 +1870,8 @@ hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int
                          const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
   const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
-  if (rt * NB > 4) return hipErrorInvalidValue;
-  const size_t lds = 2 * size_t(64 * rt) * NB * 16 * sizeof(double) +
+  if (rt * NB > 8) return hipErrorInvalidValue;
+  const size_t lds = 2 * size_t(kBsrQ) * NB * 16 * sizeof(double) +
                      size_t(kBsrMeta) * (2 * sizeof(int) + sizeof(int64_t));
   hipError_t e = hipSuccess;
 #define H2_BSR_RT(RT)                                                                                    \
@@ -1886,11 +1896,11 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
   if (nrows <= 0 || nc <= 0) return hipSuccess;
   if (max_m < 1) max_m = 1;
-  // at most 64 columns per workgroup; RT * NB <= 4 keeps the two staged X
-  // tiles within 64 KB and the per-thread staging within 16 values
+  // at most 64 columns per workgroup (two staged 64-row X chunks, 64 KB);
+  // RT * NB <= 8 bounds the accumulators per wave
   int nb = (nc + 15) / 16;
   const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
-  if (nb > 4 / rt) nb = 4 / rt;
+  nb = std::min(nb, std::min(4, 8 / rt));
 #define H2_BSR_NB(NB)                                                                                              \
   (tpos ? launch_bsr_nb<NB, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, \
                                   max_m)                                                                             \
