@@ -437,10 +437,13 @@ struct SkBfSmem {
   uint32_t om[S][NC * kBfLdp];
 };
 
-template <int DIM, int KIND, int NC, int S>
+// PRE: Omega arrives pre-split (split_omega_kernel): word (t, c, p) at
+// wsplit[(t * ncr + c) * npairs + p] holds term t of points 2p, 2p+1 of column c.
+template <int DIM, int KIND, int NC, int S, bool PRE>
 __device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64_t tile0, int64_t n,
                                                  const double* __restrict__ X, int64_t ldx, float c2, int ncr,
                                                  const double* __restrict__ omega, int64_t ldo,
+                                                 const uint32_t* __restrict__ wsplit, int64_t npairs,
                                                  double* __restrict__ y, int64_t ldy) {
   static_assert(S == 2 || S == 3, "two or three bf16 terms");
   constexpr int NB = NC / 16;
@@ -478,7 +481,8 @@ __device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64
   // one column, which form one dword of each split Omega term.
   constexpr int PX = (DIM * kBfK + 255) / 256, PP = NC * (kBfK / 2) / 256;
   double rx[PX];
-  float ro0[PP], ro1[PP];
+  float ro0[PRE ? 1 : PP], ro1[PRE ? 1 : PP];
+  uint32_t rw[PRE ? S : 1][PRE ? PP : 1];
   auto fetch = [&](int64_t j0) {
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
@@ -488,9 +492,16 @@ __device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64
 #pragma unroll
     for (int u = 0; u < PP; ++u) {
       const int e = tid + 256 * u, c = e / (kBfK / 2), pp = e % (kBfK / 2);
-      const int64_t j = j0 + 2 * pp;
-      ro0[u] = (c < ncr && j < n) ? float(omega[c * ldo + j]) : 0.0f;
-      ro1[u] = (c < ncr && j + 1 < n) ? float(omega[c * ldo + j + 1]) : 0.0f;
+      if constexpr (PRE) {
+        const int64_t pw = j0 / 2 + pp;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          rw[t][u] = (c < ncr && pw < npairs) ? wsplit[(int64_t(t) * ncr + c) * npairs + pw] : 0u;
+      } else {
+        const int64_t j = j0 + 2 * pp;
+        ro0[u] = (c < ncr && j < n) ? float(omega[c * ldo + j]) : 0.0f;
+        ro1[u] = (c < ncr && j + 1 < n) ? float(omega[c * ldo + j + 1]) : 0.0f;
+      }
     }
   };
   fetch(0);
@@ -506,7 +517,12 @@ __device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64
     for (int u = 0; u < PP; ++u) {
       const int e = tid + 256 * u, c = e / (kBfK / 2), pp = e % (kBfK / 2);
       uint32_t w[S];
-      split_pair<S>(ro0[u], ro1[u], w);
+      if constexpr (PRE) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) w[t] = rw[t][u];
+      } else {
+        split_pair<S>(ro0[u], ro1[u], w);
+      }
 #pragma unroll
       for (int t = 0; t < S; ++t) om[t][c * LDP + pp] = w[t];
     }
@@ -586,10 +602,35 @@ __device__ __forceinline__ void sketch_bf16_body(SkBfSmem<DIM, NC, S>& sm, int64
 
 template <int DIM, int KIND, int NC, int S>
 __global__ __launch_bounds__(256) void sketch_bf16_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
-                                                          float c2, int ncr, const double* __restrict__ omega,
-                                                          int64_t ldo, double* __restrict__ y, int64_t ldy) {
+                                                          float c2, int ncr, const uint32_t* __restrict__ wsplit,
+                                                          int64_t npairs, double* __restrict__ y, int64_t ldy) {
   __shared__ SkBfSmem<DIM, NC, S> sm;
-  sketch_bf16_body<DIM, KIND, NC, S>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+  sketch_bf16_body<DIM, KIND, NC, S, true>(sm, int64_t(blockIdx.x) * kSkRows, n, X, ldx, c2, ncr, nullptr, 0,
+                                           wsplit, npairs, y, ldy);
+}
+
+// Omega columns split once for every workgroup of a sketch launch: word
+// (t, c, p) = term t of the pair (Omega[2p, c], Omega[2p+1, c]) (FP32 values,
+// the second zero past n), npairs = ceil(n / 2).
+template <int S>
+__global__ __launch_bounds__(256) void split_omega_kernel(int64_t n, int ncols, const double* __restrict__ omega,
+                                                          int64_t ldo, int64_t npairs, uint32_t* __restrict__ w) {
+  const int64_t total = int64_t(ncols) * npairs;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
+    const int c = static_cast<int>(e / npairs);
+    const int64_t pw = e % npairs, j = 2 * pw;
+    float a = float(omega[c * ldo + j]);
+    float b = j + 1 < n ? float(omega[c * ldo + j + 1]) : 0.0f;
+    // Omega is rounded to FP32 first and the FP32 value is split, as in the
+    // in-kernel split of the batched sketch: without this barrier the compiler
+    // fuses the two roundings of the first value into one double -> bf16
+    // rounding, which differs at FP32 values halfway between two bf16 values
+    asm volatile("" : "+v"(a), "+v"(b));
+    uint32_t v[S];
+    split_pair<S>(a, b, v);
+#pragma unroll
+    for (int t = 0; t < S; ++t) w[(int64_t(t) * ncols + c) * npairs + pw] = v[t];
+  }
 }
 
 template <int NC, int S>
@@ -603,9 +644,11 @@ __global__ __launch_bounds__(256) void sketch_bf16_batched(const SketchJob* __re
   const int64_t t0 = tiles[2 * blockIdx.x + 1];
   const float c2 = float(J.c2);
   if (J.kind == kExp)
-    sketch_bf16_body<3, kExp, NC, S>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+    sketch_bf16_body<3, kExp, NC, S, false>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, nullptr, 0,
+                                            y + J.base, ldy);
   else
-    sketch_bf16_body<3, kGauss, NC, S>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, y + J.base, ldy);
+    sketch_bf16_body<3, kGauss, NC, S, false>(sm, t0, J.n, X + J.base, ldx, c2, ncr, omega + J.base, ldo, nullptr, 0,
+                                              y + J.base, ldy);
 }
 
 // FP32 kernel entries, FP64 contraction: entries are evaluated in FP32 (FP64
@@ -736,31 +779,33 @@ __global__ __launch_bounds__(256) void sketch_e32_batched(const SketchJob* __res
 
 template <int P, int DIM, int KIND, int NC>
 void launch_sketch_one(dim3 grid, hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
-                       const double* omega, int64_t ldo, double* y, int64_t ldy) {
+                       const double* omega, int64_t ldo, const uint32_t* wsplit, int64_t npairs, double* y,
+                       int64_t ldy) {
   if constexpr (P == 0)
     sketch_f64_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, c2, ncr, omega, ldo, y, ldy);
   else if constexpr (P == 1)
     sketch_f32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
   else if constexpr (P == 2)
-    sketch_bf16_kernel<DIM, KIND, NC, 2><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+    sketch_bf16_kernel<DIM, KIND, NC, 2><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, wsplit, npairs, y, ldy);
   else if constexpr (P == 3)
     sketch_e32_kernel<DIM, KIND, NC><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
   else
-    sketch_bf16_kernel<DIM, KIND, NC, 3><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, omega, ldo, y, ldy);
+    sketch_bf16_kernel<DIM, KIND, NC, 3><<<grid, 256, 0, s>>>(n, X, ldx, float(c2), ncr, wsplit, npairs, y, ldy);
 }
 
 template <int P, int DIM, int KIND>
 hipError_t launch_sketch_nc(hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
-                            const double* omega, int64_t ldo, double* y, int64_t ldy) {
+                            const double* omega, int64_t ldo, const uint32_t* wsplit, int64_t npairs, double* y,
+                            int64_t ldy) {
   const dim3 grid(static_cast<unsigned>((n + kSkRows - 1) / kSkRows));
   if (ncr <= 16)
-    launch_sketch_one<P, DIM, KIND, 16>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 16>(grid, s, n, X, ldx, c2, ncr, omega, ldo, wsplit, npairs, y, ldy);
   else if (ncr <= 32)
-    launch_sketch_one<P, DIM, KIND, 32>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 32>(grid, s, n, X, ldx, c2, ncr, omega, ldo, wsplit, npairs, y, ldy);
   else if (ncr <= 48)
-    launch_sketch_one<P, DIM, KIND, 48>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 48>(grid, s, n, X, ldx, c2, ncr, omega, ldo, wsplit, npairs, y, ldy);
   else if (ncr <= 64)
-    launch_sketch_one<P, DIM, KIND, 64>(grid, s, n, X, ldx, c2, ncr, omega, ldo, y, ldy);
+    launch_sketch_one<P, DIM, KIND, 64>(grid, s, n, X, ldx, c2, ncr, omega, ldo, wsplit, npairs, y, ldy);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -768,15 +813,16 @@ hipError_t launch_sketch_nc(hipStream_t s, int64_t n, const double* X, int64_t l
 
 template <int P>
 hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const double* X, int64_t ldx, double c2,
-                           int nc, const double* om, int64_t ldo, double* yy, int64_t ldy) {
+                           int nc, const double* om, int64_t ldo, const uint32_t* w, int64_t npairs, double* yy,
+                           int64_t ldy) {
   if (kind == kExp) {
-    if (dim == 1) return launch_sketch_nc<P, 1, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
-    if (dim == 2) return launch_sketch_nc<P, 2, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
-    return launch_sketch_nc<P, 3, kExp>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+    if (dim == 1) return launch_sketch_nc<P, 1, kExp>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+    if (dim == 2) return launch_sketch_nc<P, 2, kExp>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+    return launch_sketch_nc<P, 3, kExp>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
   }
-  if (dim == 1) return launch_sketch_nc<P, 1, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
-  if (dim == 2) return launch_sketch_nc<P, 2, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
-  return launch_sketch_nc<P, 3, kGauss>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy);
+  if (dim == 1) return launch_sketch_nc<P, 1, kGauss>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+  if (dim == 2) return launch_sketch_nc<P, 2, kGauss>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+  return launch_sketch_nc<P, 3, kGauss>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
 }
 
 // ------------------------------------------------------ kernel block gen
@@ -1823,27 +1869,47 @@ hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* 
 hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
                   int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
+  if (precision < 0 || precision > 4) return hipErrorInvalidValue;
   const double c2 = -k.scale * kLog2e;
-  for (int c0 = 0; c0 < ncols; c0 += 64) {
+  // split-bf16 modes: Omega is split once per launch into stream-ordered scratch
+  const int S = precision == 2 ? 2 : (precision == 4 ? 3 : 0);
+  const int64_t npairs = (n + 1) / 2;
+  uint32_t* w = nullptr;
+  if (S > 0) {
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&w), size_t(S) * 64 * size_t(npairs) * sizeof(uint32_t), s);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = hipSuccess;
+  for (int c0 = 0; c0 < ncols && e == hipSuccess; c0 += 64) {
     const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
     const double* om = omega + int64_t(c0) * ldo;
     double* yy = y + int64_t(c0) * ldy;
-    hipError_t e;
+    if (S > 0) {
+      const int64_t total = int64_t(nc) * npairs;
+      const unsigned blocks = static_cast<unsigned>(std::min<int64_t>((total + 255) / 256, 65535));
+      if (S == 2)
+        split_omega_kernel<2><<<blocks, 256, 0, s>>>(n, nc, om, ldo, npairs, w);
+      else
+        split_omega_kernel<3><<<blocks, 256, 0, s>>>(n, nc, om, ldo, npairs, w);
+      e = hipGetLastError();
+      if (e != hipSuccess) break;
+    }
     if (precision == 0)
-      e = launch_sketch_p<0>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+      e = launch_sketch_p<0>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
     else if (precision == 1)
-      e = launch_sketch_p<1>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+      e = launch_sketch_p<1>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
     else if (precision == 2)
-      e = launch_sketch_p<2>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+      e = launch_sketch_p<2>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
     else if (precision == 3)
-      e = launch_sketch_p<3>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
-    else if (precision == 4)
-      e = launch_sketch_p<4>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, yy, ldy);
+      e = launch_sketch_p<3>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
     else
-      return hipErrorInvalidValue;
-    if (e != hipSuccess) return e;
+      e = launch_sketch_p<4>(s, n, dim, k.kind, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
   }
-  return hipSuccess;
+  if (w) {
+    const hipError_t f = hipFreeAsync(w, s);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
 }
 
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
