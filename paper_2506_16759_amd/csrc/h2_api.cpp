@@ -121,17 +121,22 @@ int PrefixConvTest::first_converged(hipStream_t s, std::initializer_list<const L
   return r[3] ? -1 : r[0];
 }
 
-// A stream of default priority for work that may overlap the build stream;
-// join() makes another stream wait for everything enqueued on it so far.
+// A stream of default priority for work that may overlap the build stream
+// (none if not wanted: then work() is the build stream itself); join() makes
+// another stream wait for everything enqueued on it so far.
 struct SideStream {
   hipStream_t s = nullptr;
-  SideStream() { H2_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)); }
+  explicit SideStream(bool wanted) {
+    if (wanted) H2_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  }
+  hipStream_t work(hipStream_t build) const { return s ? s : build; }
   ~SideStream() {
     if (s) (void)hipStreamDestroy(s);
   }
   SideStream(const SideStream&) = delete;
   SideStream& operator=(const SideStream&) = delete;
   void join(hipStream_t other) {
+    if (!s) return;
     hipEvent_t e = nullptr;
     H2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     hipError_t r = hipEventRecord(e, s);
@@ -313,11 +318,15 @@ class Builder {
     h.doff_h = prefix(dsz);
 
     // ---- tree-ordered points and the dense near-field blocks
-    // D_{tau,b} = K(I_tau, I_b) (Alg. 1 batchedGen) depend on the tree only:
-    // they are produced on a side stream while the first sketch still runs on
-    // the build stream, which then waits for them.  Their arrays are handed to
-    // the build stream, which orders their later release.
-    SideStream side;
+    // D_{tau,b} = K(I_tau, I_b) (Alg. 1 batchedGen) depend on the tree only.
+    // With the split-bf16 sketches they are produced on a side stream while
+    // the first sketch still runs on the build stream, which then waits for
+    // them; their arrays are handed to the build stream, which orders their
+    // later release.  The FP64 and FP32E sketches use the FP64 units that the
+    // FP64 block generation needs, and run faster alone (measured: overlapping
+    // them slowed the FP64 build by about 10 %).
+    SideStream side(o.precision == H2_BF16X3 || o.precision == H2_BF16X6);
+    const hipStream_t gs = side.work(s_);
     auto adopt_all = [&] {
       h.perm.adopt(s_);
       h.X.adopt(s_);
@@ -328,23 +337,23 @@ class Builder {
       h.Dblk.adopt(s_);
     };
     try {
-      ph = timer_.begin(kTree, side.s);
-      h.perm.upload(p.perm, side.s);
-      h.X.alloc(static_cast<size_t>(n) * dim, side.s);
-      H2_HIP(h2dev::permute_rows(side.s, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
-      timer_.end(ph, side.s);
-      ph = timer_.begin(kNearGen, side.s);
-      h.nptr.upload(p.near_ptr, side.s);
-      h.nidx.upload(p.near_idx, side.s);
-      h.leafoff.upload(h.leafoff_h, side.s);
-      h.doff.upload(h.doff_h, side.s);
-      h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), side.s);
-      H2_HIP(h2dev::gen_blocks(side.s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim,
+      ph = timer_.begin(kTree, gs);
+      h.perm.upload(p.perm, gs);
+      h.X.alloc(static_cast<size_t>(n) * dim, gs);
+      H2_HIP(h2dev::permute_rows(gs, n, h.perm.get(), false, points, n, h.X.get(), n, dim));
+      timer_.end(ph, gs);
+      ph = timer_.begin(kNearGen, gs);
+      h.nptr.upload(p.near_ptr, gs);
+      h.nidx.upload(p.near_idx, gs);
+      h.leafoff.upload(h.leafoff_h, gs);
+      h.doff.upload(h.doff_h, gs);
+      h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), gs);
+      H2_HIP(h2dev::gen_blocks(gs, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim,
                                h.X.get(), n, kf_, h.Dblk.get()));
-      timer_.end(ph, side.s);
+      timer_.end(ph, gs);
       side.join(s_);
     } catch (...) {
-      (void)hipStreamSynchronize(side.s);
+      (void)hipStreamSynchronize(gs);
       adopt_all();
       throw;
     }
