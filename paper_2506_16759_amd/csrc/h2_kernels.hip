@@ -1149,20 +1149,25 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
   }
   const int ldp = m | 1;
   double* P = kLds ? smem : gws + gws_off[i];
+  // element (r, c) of the panel: column-major with the odd stride ldp in LDS,
+  // row-major in the global workspace (threads of consecutive columns touch
+  // consecutive addresses)
+  const int cs = kLds ? ldp : 1, rs = kLds ? 1 : ncols;
+  auto at = [&](int r, int c) -> double& { return P[c * cs + r * rs]; };
   for (int e = tid; e < m * ncols; e += nt) {
     const int r = e % m, c = e / m;
-    P[c * ldp + r] = Y[int64_t(c) * ldy + r0 + r];
+    at(r, c) = Y[int64_t(c) * ldy + r0 + r];
   }
   __syncthreads();
   double mn = INFINITY;
   int found = -1;
   for (int j = 0; j < ncols; ++j) {
-    double* pj = P + j * ldp;
+    auto pj = [&](int r) -> double& { return at(r, j); };
     if (tid < kWave) {
       double sg = 0.0;
-      for (int r = j + 1 + tid; r < m; r += kWave) sg += pj[r] * pj[r];
+      for (int r = j + 1 + tid; r < m; r += kWave) sg += pj(r) * pj(r);
       sg = wave_sum(sg);
-      const double alpha = pj[j];
+      const double alpha = pj(j);
       double beta, tau, scal;
       if (sg == 0.0) {
         beta = alpha;
@@ -1174,7 +1179,7 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
         tau = (beta - alpha) / beta;
         scal = 1.0 / (alpha - beta);
       }
-      for (int r = j + 1 + tid; r < m; r += kWave) pj[r] *= scal;
+      for (int r = j + 1 + tid; r < m; r += kWave) pj(r) *= scal;
       if (tid == 0) {
         s_tau = tau;
         s_beta = beta;
@@ -1190,17 +1195,17 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
     if (dfirst > 0 && j + 1 + p >= dfirst) break;  // m + p <= d' reached first
     const double tau = s_tau;
     for (int c = j + 1 + tid; c < ncols; c += nt) {
-      double* pc = P + c * ldp;
-      double w0 = pc[j], w1 = 0.0;
+      auto pc = [&](int r) -> double& { return at(r, c); };
+      double w0 = pc(j), w1 = 0.0;
       int r = j + 1;
       for (; r + 1 < m; r += 2) {
-        w0 += pj[r] * pc[r];
-        w1 += pj[r + 1] * pc[r + 1];
+        w0 += pj(r) * pc(r);
+        w1 += pj(r + 1) * pc(r + 1);
       }
-      if (r < m) w0 += pj[r] * pc[r];
+      if (r < m) w0 += pj(r) * pc(r);
       const double w = (w0 + w1) * tau;
-      pc[j] -= w;
-      for (int rr = j + 1; rr < m; ++rr) pc[rr] -= w * pj[rr];
+      pc(j) -= w;
+      for (int rr = j + 1; rr < m; ++rr) pc(rr) -= w * pj(rr);
     }
     __syncthreads();
   }
@@ -1337,15 +1342,21 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
   double* vn2 = smem + m;
   int* piv = reinterpret_cast<int*>(smem + 2 * m);
   double* A = kLds ? smem + 3 * m : gws + gws_off[i];
+  // element (r, c) of the panel: column-major with the odd stride lda in LDS
+  // (a thread per column, no bank conflicts), row-major in the global
+  // workspace, so that the threads of consecutive columns touch consecutive
+  // addresses
+  const int cs = kLds ? lda : 1, rs = kLds ? 1 : m;
+  auto at = [&](int r, int c) -> double& { return A[c * cs + r * rs]; };
 
   for (int e = tid; e < m * d; e += nt) {
     const int c = e % m, r = e / m;
-    A[c * lda + r] = Y[int64_t(r) * ldy + r0 + c];
+    at(r, c) = Y[int64_t(r) * ldy + r0 + c];
   }
   __syncthreads();
   for (int c = tid; c < m; c += nt) {
     double s = 0.0;
-    for (int r = 0; r < d; ++r) s += A[c * lda + r] * A[c * lda + r];
+    for (int r = 0; r < d; ++r) s += at(r, c) * at(r, c);
     vn1[c] = sqrt(s);
     vn2[c] = vn1[c];
     piv[c] = c;
@@ -1376,9 +1387,9 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
     const int p = s_p;
     if (p != j) {
       for (int r = tid; r < d; r += nt) {
-        const double t = A[j * lda + r];
-        A[j * lda + r] = A[p * lda + r];
-        A[p * lda + r] = t;
+        const double t = at(r, j);
+        at(r, j) = at(r, p);
+        at(r, p) = t;
       }
       if (tid == 0) {
         double t = vn1[j];
@@ -1394,12 +1405,12 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
       __syncthreads();
     }
     // Householder reflector of column j, rows j..d-1
-    double* aj = A + j * lda;
+    auto aj = [&](int r) -> double& { return at(r, j); };
     if (wave == 0) {
       double sg = 0.0;
-      for (int r = j + 1 + lane; r < d; r += kWave) sg += aj[r] * aj[r];
+      for (int r = j + 1 + lane; r < d; r += kWave) sg += aj(r) * aj(r);
       sg = wave_sum(sg);
-      const double alpha = aj[j];
+      const double alpha = aj(j);
       double beta, tau, scal;
       if (sg == 0.0) {
         beta = alpha;
@@ -1418,7 +1429,7 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
       }
       // make sure every lane has read alpha before lane 0 overwrites it
       __builtin_amdgcn_wave_barrier();
-      if (lane == 0) aj[j] = beta;
+      if (lane == 0) aj(j) = beta;
     }
     __syncthreads();
     if (s_stop) {
@@ -1427,31 +1438,31 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
     }
     {
       const double scal = s_scal;
-      for (int r = j + 1 + tid; r < d; r += nt) aj[r] *= scal;
+      for (int r = j + 1 + tid; r < d; r += nt) aj(r) *= scal;
     }
     __syncthreads();
     const double tau = s_tau;
     for (int c = j + 1 + tid; c < m; c += nt) {
-      double* ac = A + c * lda;
-      double w0 = ac[j], w1 = 0.0;
+      auto ac = [&](int r) -> double& { return at(r, c); };
+      double w0 = ac(j), w1 = 0.0;
       int r = j + 1;
       for (; r + 1 < d; r += 2) {
-        w0 += aj[r] * ac[r];
-        w1 += aj[r + 1] * ac[r + 1];
+        w0 += aj(r) * ac(r);
+        w1 += aj(r + 1) * ac(r + 1);
       }
-      if (r < d) w0 += aj[r] * ac[r];
+      if (r < d) w0 += aj(r) * ac(r);
       const double w = (w0 + w1) * tau;
-      ac[j] -= w;
-      for (int rr = j + 1; rr < d; ++rr) ac[rr] -= w * aj[rr];
+      ac(j) -= w;
+      for (int rr = j + 1; rr < d; ++rr) ac(rr) -= w * aj(rr);
       // norm downdate with recompute safeguard
       if (vn1[c] != 0.0) {
-        double t = fabs(ac[j]) / vn1[c];
+        double t = fabs(ac(j)) / vn1[c];
         t = fmax(0.0, 1.0 - t * t);
         const double ratio = vn1[c] / vn2[c];
         const double t2 = t * ratio * ratio;
         if (t2 <= tol3z) {
           double s = 0.0;
-          for (int rr = j + 1; rr < d; ++rr) s += ac[rr] * ac[rr];
+          for (int rr = j + 1; rr < d; ++rr) s += ac(rr) * ac(rr);
           vn1[c] = sqrt(s);
           vn2[c] = vn1[c];
         } else {
@@ -1464,11 +1475,11 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
 
   // T = R11^{-1} R12, in place in rows 0..k-1 of the redundant columns
   for (int c = k + tid; c < m; c += nt) {
-    double* ac = A + c * lda;
+    auto ac = [&](int r) -> double& { return at(r, c); };
     for (int r = k - 1; r >= 0; --r) {
-      double s = ac[r];
-      for (int l = r + 1; l < k; ++l) s -= A[l * lda + r] * ac[l];
-      ac[r] = s / A[r * lda + r];
+      double s = ac(r);
+      for (int l = r + 1; l < k; ++l) s -= at(r, l) * ac(l);
+      ac(r) = s / at(r, r);
     }
   }
   __syncthreads();
@@ -1477,7 +1488,7 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
   double* U = Uout + uoff[i];
   for (int c = tid; c < m; c += nt) {
     const int q = piv[c];
-    for (int r = 0; r < k; ++r) U[q + int64_t(r) * m] = (c < k) ? (c == r ? 1.0 : 0.0) : A[c * lda + r];
+    for (int r = 0; r < k; ++r) U[q + int64_t(r) * m] = (c < k) ? (c == r ? 1.0 : 0.0) : at(r, c);
   }
 }
 
