@@ -287,6 +287,35 @@ def test_build_mixed_precision_meets_tol(ctx, precision, tol):
     assert eF <= 10 * tol
 
 
+@pytest.mark.parametrize("precision,tol", [(4, 1e-6), (1, 1e-6), (2, 1e-4)])
+def test_full_size_cube_mixed_precision_sampled(ctx, precision, tol):
+    """The timed workload at full size in the reduced-precision modes that the
+    benchmark times: every sketch in BF16X6 / FP32 at 1e-6 and bf16x3 at 1e-4,
+    checked on sampled rows of the matvec against the exact kernel rows, and
+    the sample count of the FP64 build at the same tolerance."""
+    w = CUBE_131K
+    pts = w.points()
+    _say(f"full size {w.name} precision={precision} tol={tol}")
+    H = h2.build(ctx, pts, w.kernel, w.length, tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0,
+                 d_inc=w.d_inc, seed=w.omega_seed, precision=precision)
+    info = H.info()
+    _say(f"built: {info['t_total']:.1f} ms samples={info['samples']} ranks={info['rank_min']}..{info['rank_max']}")
+    _check_tree_lists(H, pts, w.leaf_size, w.eta)
+    H64 = h2.build(ctx, pts, w.kernel, w.length, tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0,
+                   d_inc=w.d_inc, seed=w.omega_seed)
+    assert info["samples"] == H64.info()["samples"]
+    op = KernelOperator(pts, w.kernel, w.length)
+    rows = np.random.default_rng(23).choice(w.n, 48, replace=False)
+    x = np.random.default_rng(29).standard_normal((w.n, 3))
+    kx = op.entries(rows, np.arange(w.n)) @ x
+    e = np.linalg.norm(_np(H.matvec(_colmajor_from(x)))[rows] - kx) / np.linalg.norm(kx)
+    e64 = np.linalg.norm(_np(H64.matvec(_colmajor_from(x)))[rows] - kx) / np.linalg.norm(kx)
+    _say(f"sampled-row matvec error {e:.3e} (FP64 build {e64:.3e})")
+    assert e <= 10 * tol
+    H.close()
+    H64.close()
+
+
 def test_sketch_ahead_does_not_change_the_result(ctx):
     """Columns sketched ahead of need are used exactly as if drawn lazily: the
     construction is identical for any look-ahead (Omega is counter-based)."""
