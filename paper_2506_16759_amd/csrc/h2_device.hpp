@@ -168,14 +168,15 @@ hipError_t basis_rows(hipStream_t s, int nnodes, bool leaf, const int32_t* koff,
                       const int64_t* joff, const int32_t* kold_off, const int32_t* kold_child_off,
                       const int32_t* leafoff, const double* Uold, const int64_t* uoff_old, const int32_t* koff_child,
                       const double* Rc, int64_t ldrc, double* R, int64_t ldr);
-// B_new(s, b) = R_r_s B_old(s, b) R_c_b^T + U(pos_r of s) V(pos_c of b)^T for every far
-// pair j (row frow[j], column cluster fidx[j]).  Old ranks must be <= 128.
+// B_new(s, b) = R_r_s B_old(s, b) R_c_b^T + Ug_s Vg_b^T for every far pair j (row
+// frow[j], column cluster fidx[j]), where Ug (ld ldug) and Vg (ld ldvg) hold the rows
+// of U and V at the level's row and column skeletons, in skeleton order (rows koff_r
+// and koff_c).  Old ranks must be <= 128.
 hipError_t coupling_update(hipStream_t s, int npairs, const int32_t* frow, const int32_t* fidx,
                            const int32_t* koff_r, const int32_t* koff_c, const int32_t* kold_off, int max_kold,
                            const double* Bold, const int64_t* boff_old, const double* Rr, int64_t ldrr,
-                           const double* Rc, int64_t ldrc, const int32_t* pos_r, const int32_t* pos_c,
-                           const double* U, int64_t ldu, const double* V, int64_t ldv, int r, double* Bnew,
-                           const int64_t* boff_new);
+                           const double* Rc, int64_t ldrc, const double* Ug, int64_t ldug, const double* Vg,
+                           int64_t ldvg, int r, double* Bnew, const int64_t* boff_new);
 // out_j = D_j + U(rows s) V(rows b)^T for the near blocks (explicit dense blocks of an update).
 hipError_t dense_lowrank(hipStream_t s, int nleaves, const int32_t* ptr, const int32_t* idx,
                          const int32_t* leafoff, const int64_t* blkoff, const double* Din, const double* U,

@@ -1729,12 +1729,15 @@ __global__ __launch_bounds__(256) void basis_rows_kernel(int leaf, const int32_t
 
 // Coupling of the update at an admissible pair (s, b):
 //   B_new = R_r_s B_old(s, b) R_c_b^T + U(skel_r_s, :) V(skel_c_b, :)^T
-// (k_r_s x k_c_b, column-major at boff_new[j]).  One workgroup per pair, on the
-// FP64 matrix cores, 32 output columns at a time:
+// (k_r_s x k_c_b, column-major at boff_new[j]).  Ug and Vg hold the rows of U
+// and V at the level's row and column skeletons (gathered once per level, in
+// skeleton order).  One workgroup per pair, on the FP64 matrix cores, 32
+// output columns at a time:
 //   T      = B_old(s, b) R_c_b(cols)^T              (k_old_s x 32, in LDS)
-//   B_new  = [R_r_s | U_r] [T ; V_c(cols)^T]          (inner dim k_old_s + r)
-// Wave w owns output column tile (w & 1) and every other group of four 16-row
-// tiles (w >> 1), so each B operand it loads feeds four MFMAs.
+//   B_new  = [R_r_s | Ug_s] [T ; Vg_b(cols)^T]        (inner dim k_old_s + r)
+// Wave w owns the 16-row tiles w, w+4, ... of each product and both 16-column
+// tiles of the chunk, so every A operand it loads feeds two MFMAs and the
+// waves share the tiles evenly.
 // f64 16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16]; D[l/16 + 4q][l%16].
 constexpr int kCuCols = 32;
 constexpr int kCuMaxK = 128;
@@ -1743,9 +1746,9 @@ __global__ __launch_bounds__(256) void coupling_update_kernel(
     const int32_t* __restrict__ frow, const int32_t* __restrict__ fidx, const int32_t* __restrict__ koff_r,
     const int32_t* __restrict__ koff_c, const int32_t* __restrict__ kold_off, const double* __restrict__ Bold,
     const int64_t* __restrict__ boff_old, const double* __restrict__ Rr, int64_t ldrr,
-    const double* __restrict__ Rc, int64_t ldrc, const int32_t* __restrict__ pos_r,
-    const int32_t* __restrict__ pos_c, const double* __restrict__ U, int64_t ldu, const double* __restrict__ V,
-    int64_t ldv, int r, double* __restrict__ Bnew, const int64_t* __restrict__ boff_new) {
+    const double* __restrict__ Rc, int64_t ldrc, const double* __restrict__ Ug, int64_t ldug,
+    const double* __restrict__ Vg, int64_t ldvg, int r, double* __restrict__ Bnew,
+    const int64_t* __restrict__ boff_new) {
   __shared__ double T[kCuMaxK * kCuLdt];
   const int j = blockIdx.x;
   const int s = frow[j], b = fidx[j];
@@ -1758,66 +1761,58 @@ __global__ __launch_bounds__(256) void coupling_update_kernel(
   double* out = Bnew + boff_new[j];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int tn = wave & 1, half = wave >> 1;
   const int kin = kos + r;
   const int mt1 = (kos + 15) / 16, mt2 = (kr + 15) / 16;
   for (int c0 = 0; c0 < kc; c0 += kCuCols) {
     const int w = min(kCuCols, kc - c0);
-    const int ncol = tn * 16 + li;  // this lane's B column within the chunk
     // ---- T = B_old R_c^T for the chunk's columns
-    for (int tm0 = 4 * half; tm0 < mt1; tm0 += 8) {
-      dbl4 acc[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int t = wave; t < mt1; t += 4) {
+      const int m = t * 16 + li;
+      dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
       for (int k0 = 0; k0 < kob; k0 += 4) {
         const int k = k0 + lk;
-        const double bv = (ncol < w && k < kob) ? Rc[(kc0 + c0 + ncol) + int64_t(k) * ldrc] : 0.0;
+        const double a = (m < kos && k < kob) ? bo[m + int64_t(k) * kos] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int m = (tm0 + u) * 16 + li;
-          const double a = (m < kos && k < kob) ? bo[m + int64_t(k) * kos] : 0.0;
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+        for (int tn = 0; tn < 2; ++tn) {
+          const int col = tn * 16 + li;
+          const double bv = (col < w && k < kob) ? Rc[(kc0 + c0 + col) + int64_t(k) * ldrc] : 0.0;
+          acc[tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[tn], 0, 0, 0);
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int tn = 0; tn < 2; ++tn)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int row = (tm0 + u) * 16 + lk + 4 * q;
-          if (row < kos) T[row * kCuLdt + tn * 16 + li] = acc[u][q];
+          const int row = t * 16 + lk + 4 * q;
+          if (row < kos) T[row * kCuLdt + tn * 16 + li] = acc[tn][q];
         }
     }
     __syncthreads();
-    // ---- B_new(:, chunk) = [R_r | U_r] [T ; V_c^T]
-    const int64_t pc = ncol < w ? pos_c[kc0 + c0 + ncol] : 0;
-    for (int tm0 = 4 * half; tm0 < mt2; tm0 += 8) {
-      dbl4 acc[4];
-      int64_t pr[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
-        const int m = (tm0 + u) * 16 + li;
-        pr[u] = m < kr ? pos_r[kr0 + m] : 0;
-      }
+    // ---- B_new(:, chunk) = [R_r | Ug] [T ; Vg^T]
+    for (int t = wave; t < mt2; t += 4) {
+      const int m = t * 16 + li;
+      dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
       for (int k0 = 0; k0 < kin; k0 += 4) {
         const int k = k0 + lk;
-        double bv = 0.0;
-        if (ncol < w && k < kin) bv = k < kos ? T[k * kCuLdt + ncol] : V[int64_t(k - kos) * ldv + pc];
+        double a = 0.0;
+        if (m < kr && k < kin)
+          a = k < kos ? Rr[(kr0 + m) + int64_t(k) * ldrr] : Ug[(kr0 + m) + int64_t(k - kos) * ldug];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int m = (tm0 + u) * 16 + li;
-          double a = 0.0;
-          if (m < kr && k < kin) a = k < kos ? Rr[(kr0 + m) + int64_t(k) * ldrr] : U[int64_t(k - kos) * ldu + pr[u]];
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[u], 0, 0, 0);
+        for (int tn = 0; tn < 2; ++tn) {
+          const int col = tn * 16 + li;
+          double bv = 0.0;
+          if (col < w && k < kin)
+            bv = k < kos ? T[k * kCuLdt + col] : Vg[(kc0 + c0 + col) + int64_t(k - kos) * ldvg];
+          acc[tn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[tn], 0, 0, 0);
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int tn = 0; tn < 2; ++tn)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int row = (tm0 + u) * 16 + lk + 4 * q;
+          const int row = t * 16 + lk + 4 * q;
           const int col = tn * 16 + li;
-          if (row < kr && col < w) out[int64_t(c0 + col) * kr + row] = acc[u][q];
+          if (row < kr && col < w) out[int64_t(c0 + col) * kr + row] = acc[tn][q];
         }
     }
     __syncthreads();
@@ -2266,13 +2261,12 @@ hipError_t basis_rows(hipStream_t s, int nnodes, bool leaf, const int32_t* koff,
 hipError_t coupling_update(hipStream_t s, int npairs, const int32_t* frow, const int32_t* fidx,
                            const int32_t* koff_r, const int32_t* koff_c, const int32_t* kold_off, int max_kold,
                            const double* Bold, const int64_t* boff_old, const double* Rr, int64_t ldrr,
-                           const double* Rc, int64_t ldrc, const int32_t* pos_r, const int32_t* pos_c,
-                           const double* U, int64_t ldu, const double* V, int64_t ldv, int r, double* Bnew,
-                           const int64_t* boff_new) {
+                           const double* Rc, int64_t ldrc, const double* Ug, int64_t ldug, const double* Vg,
+                           int64_t ldvg, int r, double* Bnew, const int64_t* boff_new) {
   if (npairs <= 0) return hipSuccess;
   if (max_kold > kCuMaxK) return hipErrorInvalidValue;
   coupling_update_kernel<<<npairs, 256, 0, s>>>(frow, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
-                                                ldrc, pos_r, pos_c, U, ldu, V, ldv, r, Bnew, boff_new);
+                                                ldrc, Ug, ldug, Vg, ldvg, r, Bnew, boff_new);
   return hipGetLastError();
 }
 

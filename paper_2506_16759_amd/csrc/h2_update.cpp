@@ -433,12 +433,20 @@ class UpdateBuilder {
       for (int j = Lr.fptr_h[a]; j < Lr.fptr_h[a + 1]; ++j) frow[j] = a;
     DevArray<int32_t> frow_d;
     frow_d.upload(frow, s_);
+    // rows of U and V at the new skeletons, gathered once for every pair of the level
+    const int64_t Mr = std::max<int64_t>(Lr.koff_h.back(), 1), Mc = std::max<int64_t>(Lc.koff_h.back(), 1);
+    DevArray<double> Ug, Vg;
+    if (r_ > 0) {
+      Ug.alloc(size_t(Mr) * r_, s_);
+      Vg.alloc(size_t(Mc) * r_, s_);
+      H2_HIP(h2dev::permute_rows(s_, Lr.koff_h.back(), Lr.pos_out.get(), false, h.lrU.get(), h.plan.n, Ug.get(), Mr,
+                                 r_));
+      H2_HIP(h2dev::permute_rows(s_, Lc.koff_h.back(), Lc.pos_out.get(), false, h.lrV.get(), h.plan.n, Vg.get(), Mc,
+                                 r_));
+    }
     H2_HIP(h2dev::coupling_update(s_, static_cast<int>(frow.size()), frow_d.get(), Lr.fidx.get(), Lr.koff.get(),
-                                  Lc.koff.get(),
-                                  Ho.koff.get(), Ho.max_k, Ho.B.get(), Ho.boff.get(), Rr_[t].get(),
-                                  std::max<int64_t>(Lr.koff_h.back(), 1), Rc_[t].get(),
-                                  std::max<int64_t>(Lc.koff_h.back(), 1), Lr.pos_out.get(), Lc.pos_out.get(),
-                                  h.lrU.get(), h.plan.n, h.lrV.get(), h.plan.n, r_, Lr.B.get(), Lr.boff.get()));
+                                  Lc.koff.get(), Ho.koff.get(), Ho.max_k, Ho.B.get(), Ho.boff.get(), Rr_[t].get(), Mr,
+                                  Rc_[t].get(), Mc, Ug.get(), Mr, Vg.get(), Mc, r_, Lr.B.get(), Lr.boff.get()));
     timer_.end(ph);
     if (t == h.top) {
       Rr_[t].release();
