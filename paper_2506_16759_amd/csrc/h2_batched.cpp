@@ -13,16 +13,16 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <functional>
 #include <map>
 #include <string>
-#include <thread>
 #include <tuple>
 
 #include "h2_internal.hpp"
+#include "h2_pool.hpp"
 
 using namespace h2i;
 
@@ -73,6 +73,31 @@ struct Arena {
   }
 };
 
+// Small host arrays for many matrices, staged into one host buffer as they
+// are added and sent to the device in one copy: each array is a view into one
+// device block (256-byte aligned slices).
+struct Packed {
+  std::vector<char> host;
+  std::vector<std::function<void(char*)>> bind;
+  DevArray<char> block;
+  template <typename T>
+  void add(DevArray<T>& a, const std::vector<T>& h) {
+    const size_t off = host.size(), b = h.size() * sizeof(T);
+    host.resize(off + ((b + 255) & ~size_t(255)));
+    if (b) std::memcpy(host.data() + off, h.data(), b);
+    DevArray<T>* pa = &a;
+    const size_t n = h.size();
+    bind.push_back([pa, off, n](char* p) { pa->borrow(reinterpret_cast<T*>(p + off), n); });
+  }
+  // the host buffer must stay alive until the stream is synchronised
+  void commit(hipStream_t s) {
+    block.alloc(std::max<size_t>(host.size(), 256), s);
+    if (!host.empty()) H2_HIP(hipMemcpyAsync(block.get(), host.data(), host.size(), hipMemcpyHostToDevice, s));
+    for (auto& f : bind) f(block.get());
+    bind.clear();
+  }
+};
+
 struct Prob {
   int orig = 0;
   h2_problem in{};
@@ -108,6 +133,7 @@ struct BatchStore {
   DevArray<char> sjobs, tjobs;
   DevArray<int32_t> tiles;
   Arena keep, work;  // factors kept by the matrices; the build's working set
+  Packed meta;       // the matrices' index arrays (permutation, offsets, lists)
   int64_t bytes = 0;
 };
 
@@ -162,21 +188,20 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     }
     H2_HIP(hipStreamSynchronize(s));
     {
+      // one problem per pool participant, largest first; each plan runs
+      // serially inside its participant
       std::vector<std::string> errs(count);
-      std::atomic<int> next{0};
-      const int nt = std::max(1, std::min(16, count));
-      std::vector<std::thread> pool;
-      for (int w = 0; w < nt; ++w)
-        pool.emplace_back([&] {
-          for (int i; (i = next.fetch_add(1)) < count;) {
-            try {
-              P[i].plan = h2::make_plan(P[i].in.n, P[i].in.dim, pts[i].data(), P[i].in.leaf_size, P[i].in.eta);
-            } catch (const std::exception& e) {
-              errs[i] = e.what();
-            }
-          }
-        });
-      for (auto& t : pool) t.join();
+      std::vector<int> order(count);
+      for (int i = 0; i < count; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return problems[a].n > problems[b].n; });
+      h2::parallel_for(count, 1, [&](int r) {
+        const int i = order[r];
+        try {
+          P[i].plan = h2::make_plan(P[i].in.n, P[i].in.dim, pts[i].data(), P[i].in.leaf_size, P[i].in.eta);
+        } catch (const std::exception& e) {
+          errs[i] = e.what();
+        }
+      });
       for (int i = 0; i < count; ++i)
         if (!errs[i].empty()) throw Error(H2_ERR_ARG, "problem " + std::to_string(i) + ": " + errs[i]);
     }
@@ -531,11 +556,13 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       if (exh[q] && P[q].L > 0)
         throw Error(H2_ERR_SAMPLES, "problem " + std::to_string(P[q].orig) + " not converged within d_max = " +
                                         std::to_string(dcap) + " columns");
+    std::vector<std::vector<int32_t>> pos_h(Lmax);
     for (int l = 1; l <= Lmax; ++l) {
       LevelB& V = B.lv[l - 1];
       V.k_h = download(V.k.get(), V.G, s);
       V.koff_h = download(V.koff.get(), V.G + 1, s);
       if (l >= 2) V.rowoff_h = download(V.rowoff.get(), V.G + 1, s);
+      pos_h[l - 1] = download(V.pos.get(), size_t(V.koff_h.back()), s);
     }
     std::vector<std::unique_ptr<h2_matrix>> mats(np);
     double sketch_flops = 0;
@@ -567,17 +594,17 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       h->samples = p.L > 0 ? dprob[q] : 0;
       h->sketched = p.L > 0 ? dcap : 0;
       h->rounds = p.L > 0 ? (dprob[q] - p.in.d0) / p.in.d_inc : 0;
-      h->perm.upload(p.plan.perm, s);
+      B.meta.add(h->perm, p.plan.perm);
       const int nl = 1 << D;
       h->leafoff_h.resize(nl + 1);
       for (int a = 0; a <= nl; ++a) h->leafoff_h[a] = leafoff[p.leafbase + a] - static_cast<int32_t>(p.base);
-      h->leafoff.upload(h->leafoff_h, s);
-      h->nptr.upload(p.plan.near_ptr, s);
-      h->nidx.upload(p.plan.near_idx, s);
+      B.meta.add(h->leafoff, h->leafoff_h);
+      B.meta.add(h->nptr, p.plan.near_ptr);
+      B.meta.add(h->nidx, p.plan.near_idx);
       const int j0 = nptr[p.leafbase], j1 = nptr[p.leafbase + nl];
       h->doff_h.assign(doff.begin() + j0, doff.begin() + j1 + 1);
       for (auto& v : h->doff_h) v -= doff[j0];
-      h->doff.upload(h->doff_h, s);
+      B.meta.add(h->doff, h->doff_h);
       h->Dblk.borrow(B.Dblk.get() + doff[j0], size_t(doff[j1] - doff[j0]));
       h->lv.resize(D + 1);
       for (int t = 0; t <= D; ++t) {
@@ -608,25 +635,26 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
           L.max_m = std::max(L.max_m, L.rowoff_h[a + 1] - L.rowoff_h[a]);
           L.max_k = std::max(L.max_k, L.k_h[a]);
         }
-        L.rowoff.upload(L.rowoff_h, s);
-        L.koff.upload(L.koff_h, s);
-        L.joff.upload(L.joff_h, s);
-        L.uoff.upload(L.uoff_h, s);
+        B.meta.add(L.rowoff, L.rowoff_h);
+        B.meta.add(L.koff, L.koff_h);
+        B.meta.add(L.joff, L.joff_h);
+        B.meta.add(L.uoff, L.uoff_h);
         L.J.borrow(V.J.get() + jb, size_t(L.joff_h.back()));
         L.U.borrow(V.U.get() + ub, size_t(L.uoff_h.back()));
         // skeleton tree positions, local to the problem
-        std::vector<int32_t> pos = download(V.pos.get() + V.koff_h[g0], size_t(L.koff_h.back()), s);
+        std::vector<int32_t> pos(pos_h[l - 1].begin() + V.koff_h[g0],
+                                 pos_h[l - 1].begin() + V.koff_h[g0] + L.koff_h.back());
         for (auto& v : pos) v -= static_cast<int32_t>(p.base);
-        L.pos_out.upload(pos, s);
+        B.meta.add(L.pos_out, pos);
         L.fptr_h = p.plan.far_ptr[t];
         L.fidx_h = p.plan.far_idx[t];
         const int f0 = V.fptr[g0], f1 = V.fptr[g0 + nn];
         L.boff_h.assign(V.boff.begin() + f0, V.boff.begin() + f1 + 1);
         const int64_t bb = L.boff_h[0];
         for (auto& v : L.boff_h) v -= bb;
-        L.fptr.upload(L.fptr_h, s);
-        L.fidx.upload(L.fidx_h, s);
-        L.boff.upload(L.boff_h, s);
+        B.meta.add(L.fptr, L.fptr_h);
+        B.meta.add(L.fidx, L.fidx_h);
+        B.meta.add(L.boff, L.boff_h);
         L.B.borrow(V.B.get() + bb, size_t(L.boff_h.back()));
       }
       h->plan = std::move(p.plan);
@@ -638,8 +666,11 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       h->total_ms = dev_ms;
       mats[q] = std::move(h);
     }
+    bytes += static_cast<int64_t>(B.meta.host.size());
+    B.meta.commit(s);
     // only the factors stay: dense blocks, bases, skeleton indices, couplings
     H2_HIP(hipStreamSynchronize(s));
+    std::vector<char>().swap(B.meta.host);
     B.work.block.release();
     for (int q = 0; q < np; ++q) out[P[q].orig] = mats[q].release();
     if (info) {
