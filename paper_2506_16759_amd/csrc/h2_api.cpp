@@ -161,6 +161,8 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
   if (nc > 64) throw Error(H2_ERR_ARG, "matvec_tree: at most 64 columns");
   const std::vector<Level>& up = h.col_levels();  // column bases: x_hat = V^T x
   const std::vector<Level>& dn = h.lv;            // row bases: y += U y_hat
+  BsrScratch xr;  // sized for the leaf rows, the largest row space
+  xr.get(std::max<int64_t>(ldxt, n), nc, s);
   if (h.top <= D) {
     std::vector<DevArray<double>> xh(D + 1), yh(D + 1);
     for (int t = h.top; t <= D; ++t) {
@@ -179,9 +181,10 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
     for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b
       const Level& L = dn[t];
       const Level& C = up[t];
+      double* xrp = xr.get(C.koff_h.back(), nc, s);
       H2_HIP(h2dev::bsr_gemm2(s, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), C.koff.get(), nullptr,
                               L.boff.get(), L.B.get(), xh[t].get(), C.koff_h.back(), yh[t].get(), L.koff_h.back(), nc,
-                              1.0, std::max({L.max_k, C.max_k, 1})));
+                              1.0, std::max({L.max_k, C.max_k, 1}), xrp, xr.cap()));
     }
     for (int t = h.top; t <= D; ++t) {  // downsweep
       const Level& L = dn[t];
@@ -193,8 +196,9 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
   }
   int leaf_max = 0;
   for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
+  double* xrp = xr.get(ldxt, nc, s);
   H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,
-                         ldxt, yt, ldyt, nc, 1.0, leaf_max));
+                         ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr.cap()));
   if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b
     DevArray<double> W;
     W.alloc(size_t(nleaves) * h.lr_rank * nc, s);
@@ -267,6 +271,7 @@ class Builder {
   const double* points_ = nullptr;  // caller's points, original order (borrowed for the build)
   PanelWorkspace ws_;
   PrefixConvTest conv_;
+  BsrScratch xr_;
 
   void run_inner(int64_t n, int dim, const double* points) {
     h2_matrix& h = *h_;
@@ -420,15 +425,16 @@ class Builder {
     h2_matrix& h = *h_;
     const int D = h.plan.depth;
     Level& L = h.lv[t];
+    double* xr = xr_.get(L.M, nc, s_);
     if (t == D) {
       H2_HIP(h2dev::bsr_gemm(s_, L.nn, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             L.max_m));
+                             L.max_m, xr, xr_.cap()));
     } else {
       Level& C = h.lv[t + 1];
       H2_HIP(h2dev::bsr_gemm(s_, C.nn, C.fptr.get(), C.fidx.get(), C.koff.get(), C.boff.get(), C.B.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             std::max(C.max_k, 1)));
+                             std::max(C.max_k, 1), xr, xr_.cap()));
     }
   }
 

@@ -130,6 +130,7 @@ struct BatchStore {
   DevArray<int64_t> doff;
   DevArray<uint64_t> seeds;
   DevArray<double> c2s, nu, delta;
+  DevArray<double> xr;  // row-major staging of the block-sparse products (every level's row space fits)
   DevArray<char> sjobs, tjobs;
   DevArray<int32_t> tiles;
   Arena keep, work;  // factors kept by the matrices; the build's working set
@@ -347,6 +348,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     B.work.want(B.Om0, size_t(NT) * dcap);
     B.work.want(B.Y0, size_t(NT) * dcap);
     B.keep.want(B.Dblk, size_t(doff.back()));
+    B.work.want(B.xr, h2dev::bsr_scratch_doubles(NT, dcap));
     B.work.want(B.perm_g, perm_g);
     B.work.want(B.rowprob_o, rowprob_o);
     B.work.want(B.rowlocal_o, rowlocal_o);
@@ -467,7 +469,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
                                        B.Xt.get(), NT, B.leafprob.get(), B.kinds.get(), B.c2s.get(),
                                        B.Dblk.get()));
       H2_HIP(h2dev::bsr_gemm(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
-                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max));
+                             B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max, B.xr.get(),
+                             B.xr.size()));
       for (int l = 1; l <= Lmax; ++l) {
         LevelB& V = B.lv[l - 1];
         double* om = l == 1 ? Om1.get() : V.om.get();
@@ -477,7 +480,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
           LevelB& C = B.lv[l - 2];
           H2_HIP(h2dev::gather_i32(s, V.G, V.d_childfirst.get(), C.koff.get(), V.rowoff.get()));
           H2_HIP(h2dev::bsr_gemm(s, C.G, C.d_fptr.get(), C.d_fidx.get(), C.koff.get(), C.d_boff.get(), C.B.get(),
-                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1)));
+                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), B.xr.get(), B.xr.size()));
         }
         H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), B.ovprob.get(),
                                     V.d_nodeprob.get(), B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m,

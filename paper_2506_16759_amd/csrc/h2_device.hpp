@@ -43,18 +43,22 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out);
 
 // Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc
-// columns, on the FP64 matrix cores.  max_m bounds every block-row height (<= 256).
+// columns, on the FP64 matrix cores.  max_m bounds every block-row height.
+// X (ldx rows, column-major) is first copied row-major into `scratch`, which
+// must hold bsr_scratch_doubles(ldx, nc) doubles (else hipErrorInvalidValue).
+size_t bsr_scratch_doubles(int64_t ldx, int nc);
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m);
+                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles);
 
 // Two-sided form: block row i has rows [rowoff[i], rowoff[i+1]) of Y, block
 // column b rows [coloff[b], coloff[b+1]) of X; with tpos != nullptr the block of
 // entry j is the transpose of stored block tpos[j] (which is stored
-// (coloff height) x (rowoff height), column-major).  max_m bounds both heights.
+// (coloff height) x (rowoff height), column-major).  max_m bounds the row heights.
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m);
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
+                     double* scratch, size_t scratch_doubles);
 
 // Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
 // row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).

@@ -129,6 +129,18 @@ class DevArray {
   bool owned_ = true;
 };
 
+// Row-major staging buffer of the block-sparse products, grown on demand on
+// the stream that uses it.
+struct BsrScratch {
+  DevArray<double> buf;
+  double* get(int64_t ldx, int nc, hipStream_t s) {
+    const size_t need = h2dev::bsr_scratch_doubles(ldx, nc);
+    if (buf.size() < need) buf.alloc(need, s);
+    return buf.get();
+  }
+  size_t cap() const { return buf.size(); }
+};
+
 template <typename T>
 std::vector<T> download(const T* d, size_t n, hipStream_t s) {
   std::vector<T> h(n);

@@ -922,188 +922,148 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
 
 // ------------------------------------------------------- block-sparse GEMM
 
-// Block-sparse product on the FP64 matrix cores, one workgroup per block row i
-// and 16*NB columns:
+// Block-sparse product on the FP64 matrix cores:
 //   Y[rows_i, c0:c0+16NB] += alpha * sum_j Blk_j X[rows_b, c0:c0+16NB].
-// Wave w owns row tiles w, w+4, .. (RT of them, 16 rows each).  The X rows of
-// the next block chunk are fetched into registers while the current one runs
-// on the matrix cores from the other LDS buffer (double buffering, one barrier
-// per chunk of up to 64 rows); the blocks stream from HBM straight into the
-// MFMA A operand (lane l reads row l%16 of column l/16 of a 16x4 slice: four
-// 128-byte runs per load), 16/RT k-steps at a time.
-constexpr int kBsrMeta = 1024;  // blocks per row whose metadata is cached in LDS
+// X is read from a row-major copy Xr (row q at Xr + q*ldr, zero-padded to ldr
+// columns), so that one MFMA B operand (4 rows x 16 columns) is four 128-byte
+// runs; the blocks (column-major) stream into the A operand (16 rows x 4
+// columns, also four 128-byte runs).  One workgroup of four waves per block
+// row and 64-row slice of it (blockIdx.z); wave w takes the row's blocks
+// w, w+4, .., covering all of the slice's row tiles itself, so the main loop
+// has no LDS traffic and no barrier.  The four partial sums are added through
+// LDS at the end, one column tile at a time (wave c keeps column tile c).
+constexpr int kBsrKu = 4;  // k-steps (4 rows each) per batch of operand loads
 
-// The block row's products for a wave with L live row tiles (L <= RT): the
-// wave's row tiles w + 4t with t >= L lie past the block row's height, hold
-// zeros and are neither loaded nor multiplied.  Every wave stages its share of
-// X and takes part in every barrier whatever its L.  X is staged in chunks of
-// kBsrQ rows of a block (a block of height mb takes ceil(mb / kBsrQ) chunks),
-// so the LDS tile does not grow with the block height.
-constexpr int kBsrQ = 64;
-
-template <int NB, int RT, bool TR, int L>
-__device__ __forceinline__ void bsr_row(const int32_t* __restrict__ idx, const int32_t* __restrict__ coloff,
-                                        const int64_t* __restrict__ tpos, const int64_t* __restrict__ blkoff,
-                                        const double* __restrict__ blocks, const double* __restrict__ X, int64_t ldx,
-                                        double* __restrict__ Y, int64_t ldy, double alpha, double* buf,
-                                        const int* s_q0, const int* s_mb, const int64_t* s_bo, bool meta, int jb,
-                                        int je, int r0, int m, int c0, int ncl) {
-  constexpr int LDB = NB * 16;
-  constexpr int CI = LDB / 4;   // staged values per thread: row lane, columns wave + 4 ci
-  constexpr int KC = 16 / RT;   // k-steps per batch of A loads
+// Rows [rz, rz + m) of the block row, m <= 16 L.
+template <int NB, bool TR, int L>
+__device__ __forceinline__ void bsr_rows(const int32_t* __restrict__ idx, const int32_t* __restrict__ coloff,
+                                         const int64_t* __restrict__ tpos, const int64_t* __restrict__ blkoff,
+                                         const double* __restrict__ blocks, const double* __restrict__ Xr, int ldr,
+                                         double* __restrict__ Y, int64_t ldy, double alpha, int jb, int je, int r0,
+                                         int mfull, int rz, int m, int c0, int ncl, dbl4* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  auto col0 = [&](int j) { return meta ? s_q0[j - jb] : coloff[idx[j]]; };
-  auto height = [&](int j) { return meta ? s_mb[j - jb] : coloff[idx[j] + 1] - coloff[idx[j]]; };
-  auto boff = [&](int j) { return meta ? s_bo[j - jb] : blkoff[TR ? tpos[j] : j]; };
-
-  // Two-sided use: block columns index the row space `coloff`, and with TR
-  // the block of entry j is the transpose of the stored block tpos[j]
-  // (stored mb x m, column-major).
-  double xv[CI];
-  auto fetch = [&](int j, int qlo) {
-    const int q0 = col0(j) + qlo, qn = height(j) - qlo;
-#pragma unroll
-    for (int ci = 0; ci < CI; ++ci) {
-      const int c = wave + 4 * ci;
-      xv[ci] = (lane < qn && c < ncl) ? X[int64_t(c0 + c) * ldx + q0 + lane] : 0.0;
-    }
-  };
-  auto stash = [&](int slot) {
-    double* bs = buf + slot * (kBsrQ * LDB);
-#pragma unroll
-    for (int ci = 0; ci < CI; ++ci) bs[lane * LDB + wave + 4 * ci] = xv[ci];
-  };
-
-  dbl4 acc[L > 0 ? L : 1][NB];
+  dbl4 acc[L][NB];
 #pragma unroll
   for (int t = 0; t < L; ++t)
 #pragma unroll
     for (int c = 0; c < NB; ++c) acc[t][c] = dbl4{0.0, 0.0, 0.0, 0.0};
-
-  // items (block j, rows qlo.. of it) in order; the next item's X is in
-  // flight while the current one computes from the other LDS buffer
-  int j = jb, qlo = 0, cur = 0;
-  fetch(j, qlo);
-  stash(0);
-  __syncthreads();
-  while (j < je) {
-    const int mb = height(j);
-    int nj = j, nq = qlo + kBsrQ;
-    if (nq >= mb) {
-      nj = j + 1;
-      nq = 0;
-    }
-    const bool more = nj < je;
-    if (more) fetch(nj, nq);
-    if constexpr (L > 0) {
-      const int qn = min(kBsrQ, mb - qlo), qn4 = (qn + 3) & ~3;
-      const double* blk = blocks + boff(j);
-      const double* bs = buf + cur * (kBsrQ * LDB);
-      for (int k0 = 0; k0 < qn4; k0 += 4 * KC) {
-        double a[L][KC];
+  for (int j = jb + wave; j < je; j += 4) {
+    const int b = idx[j];
+    const int q0 = coloff[b], mb = coloff[b + 1] - q0;
+    // without TR the block is mfull x mb column-major; with TR it is the
+    // transpose of a stored mb x mfull column-major block
+    const double* blk = blocks + blkoff[TR ? tpos[j] : j];
+    const double* xb = Xr + int64_t(q0) * ldr + c0 + li;
+    for (int k0 = 0; k0 < mb; k0 += 4 * kBsrKu) {
+      double a[kBsrKu][L], x[kBsrKu][NB];
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-          const int q = k0 + 4 * kc + lk, qg = qlo + q;
+      for (int kc = 0; kc < kBsrKu; ++kc) {
+        const int q = k0 + 4 * kc + lk;
+        const bool ok = q < mb;
 #pragma unroll
-          for (int t = 0; t < L; ++t) {
-            const int row = (wave + 4 * t) * 16 + li;
-            a[t][kc] = (row < m && q < qn) ? (TR ? blk[int64_t(row) * mb + qg] : blk[int64_t(qg) * m + row]) : 0.0;
-          }
+        for (int t = 0; t < L; ++t) {
+          const int row = rz + t * 16 + li;
+          a[kc][t] = (ok && t * 16 + li < m) ? (TR ? blk[int64_t(row) * mb + q] : blk[int64_t(q) * mfull + row]) : 0.0;
         }
 #pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-          if (k0 + 4 * kc >= qn4) break;
-          const int q = k0 + 4 * kc + lk;
-#pragma unroll
-          for (int c = 0; c < NB; ++c) {
-            const double bv = bs[q * LDB + c * 16 + li];
-#pragma unroll
-            for (int t = 0; t < L; ++t)
-              acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][kc], bv, acc[t][c], 0, 0, 0);
-          }
-        }
+        for (int c = 0; c < NB; ++c) x[kc][c] = ok ? xb[int64_t(q) * ldr + c * 16] : 0.0;
       }
+#pragma unroll
+      for (int kc = 0; kc < kBsrKu; ++kc)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int t = 0; t < L; ++t)
+            acc[t][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kc][t], x[kc][c], acc[t][c], 0, 0, 0);
     }
-    if (more) stash(cur ^ 1);
-    __syncthreads();
-    cur ^= 1;
-    j = nj;
-    qlo = nq;
   }
+  dbl4 fin[L];
 #pragma unroll
-  for (int t = 0; t < L; ++t)
+  for (int c = 0; c < NB; ++c) {
 #pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const int col = c * 16 + li;
-      if (col >= ncl) continue;
+    for (int t = 0; t < L; ++t) red[(wave * L + t) * 64 + lane] = acc[t][c];
+    __syncthreads();
+    if (wave == c) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = (wave + 4 * t) * 16 + lk + 4 * q;
-        if (row < m) {
-          double* yp = Y + int64_t(c0 + col) * ldy + r0 + row;
-          *yp += alpha * acc[t][c][q];
-        }
+      for (int t = 0; t < L; ++t) {
+        dbl4 sum = red[t * 64 + lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) sum += red[(w * L + t) * 64 + lane];
+        fin[t] = sum;
       }
     }
+    __syncthreads();
+  }
+  if (wave < NB) {
+    const int col = wave * 16 + li;
+    if (col < ncl) {
+#pragma unroll
+      for (int t = 0; t < L; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = t * 16 + lk + 4 * q;  // MFMA C layout: lane (li, lk) holds rows lk + 4q of column li
+          if (row < m) {
+            double* yp = Y + int64_t(c0 + col) * ldy + r0 + row;
+            *yp += alpha * fin[t][q];
+          }
+        }
+    }
+  }
 }
 
-template <int NB, int RT, bool TR>
-__global__ __launch_bounds__(256) void bsr_gemm_kernel(const int32_t* __restrict__ ptr, const int32_t* __restrict__ idx,
-                                                       const int32_t* __restrict__ rowoff,
-                                                       const int32_t* __restrict__ coloff,
-                                                       const int64_t* __restrict__ tpos,
-                                                       const int64_t* __restrict__ blkoff,
-                                                       const double* __restrict__ blocks, const double* __restrict__ X,
-                                                       int64_t ldx, double* __restrict__ Y, int64_t ldy, int nc,
-                                                       double alpha) {
+// grid (nrows, ceil(nc / 16NB), ceil(max height / 64)); Xr has at least
+// gridDim.y * 16NB columns.  Two workgroups per CU by registers.
+template <int NB, bool TR>
+__global__ __launch_bounds__(256, 2) void bsr_gemm_kernel(const int32_t* __restrict__ ptr,
+                                                          const int32_t* __restrict__ idx,
+                                                          const int32_t* __restrict__ rowoff,
+                                                          const int32_t* __restrict__ coloff,
+                                                          const int64_t* __restrict__ tpos,
+                                                          const int64_t* __restrict__ blkoff,
+                                                          const double* __restrict__ blocks,
+                                                          const double* __restrict__ Xr, int ldr,
+                                                          double* __restrict__ Y, int64_t ldy, int nc, double alpha) {
   constexpr int LDB = NB * 16;
-  extern __shared__ double smem_raw[];
-  double* buf = smem_raw;  // two buffers of kBsrQ x LDB
-  const int i = blockIdx.x, tid = threadIdx.x, wave = tid >> 6;
-  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  __shared__ dbl4 red[4 * 4 * 64];
+  const int i = blockIdx.x;
+  const int mfull = rowoff[i + 1] - rowoff[i];
+  const int rz = blockIdx.z * 64;
+  const int jb = ptr[i], je = ptr[i + 1];
+  if (rz >= mfull || jb == je) return;  // uniform over the workgroup
+  const int m = min(64, mfull - rz);
+  const int r0 = rowoff[i] + rz;
   const int c0 = blockIdx.y * LDB;
   const int ncl = min(LDB, nc - c0);
-  const int jb = ptr[i], je = ptr[i + 1];
-  if (m == 0 || jb == je) return;  // uniform over the workgroup
+#define H2_BSR_ROWS(L) \
+  bsr_rows<NB, TR, L>(idx, coloff, tpos, blkoff, blocks, Xr, ldr, Y, ldy, alpha, jb, je, r0, mfull, rz, m, c0, ncl, red)
+  switch ((m + 15) >> 4) {
+    case 1: H2_BSR_ROWS(1); break;
+    case 2: H2_BSR_ROWS(2); break;
+    case 3: H2_BSR_ROWS(3); break;
+    default: H2_BSR_ROWS(4); break;
+  }
+#undef H2_BSR_ROWS
+}
 
-  // Each block's column offset, height and storage offset are gathered into
-  // LDS once per row (rows of up to kBsrMeta blocks), so the per-block chain
-  // idx -> coloff -> X is not a sequence of dependent global loads.
-  int* s_q0 = reinterpret_cast<int*>(buf + 2 * (kBsrQ * LDB));
-  int* s_mb = s_q0 + kBsrMeta;
-  int64_t* s_bo = reinterpret_cast<int64_t*>(s_mb + kBsrMeta);
-  const bool meta = je - jb <= kBsrMeta;
-  if (meta) {
-    for (int e = tid; e < je - jb; e += 256) {
-      const int b = idx[jb + e];
-      const int q0 = coloff[b];
-      s_q0[e] = q0;
-      s_mb[e] = coloff[b + 1] - q0;
-      s_bo[e] = blkoff[TR ? tpos[jb + e] : jb + e];
-    }
-    __syncthreads();
+// Xr[q * ldr + c] = X[c * ldx + q] for q < M, c < nc; zero for nc <= c < ldr.
+__global__ __launch_bounds__(256) void to_rows_kernel(int64_t M, int nc, int ldr, const double* __restrict__ X,
+                                                      int64_t ldx, double* __restrict__ Xr) {
+  __shared__ double tile[64][65];
+  const int64_t q0 = int64_t(blockIdx.x) * 64;
+  const int c0 = blockIdx.y * 64;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int cc = w; cc < 64; cc += 4) {
+    const int c = c0 + cc;
+    const int64_t q = q0 + lane;
+    tile[cc][lane] = (c < nc && q < M) ? X[int64_t(c) * ldx + q] : 0.0;
   }
-  // live row tiles of this wave: t with (wave + 4 t) * 16 < m (uniform over the wave)
-  const int live = min(RT, max(0, (m - 16 * wave + 63) / 64));
-#define H2_BSR_ROW(L)                                                                                          \
-  bsr_row<NB, RT, TR, L>(idx, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, alpha, buf, s_q0, s_mb, s_bo, meta, \
-                         jb, je, r0, m, c0, ncl)
-  if (live == 0) {
-    H2_BSR_ROW(0);
-  } else if (RT == 1 || live == 1) {
-    H2_BSR_ROW(1);
-  } else if constexpr (RT >= 2) {
-    if (live == 2 || RT == 2) {
-      H2_BSR_ROW(2);
-    } else if constexpr (RT >= 4) {
-      if (live == 3)
-        H2_BSR_ROW(3);
-      else
-        H2_BSR_ROW(4);
-    }
+  __syncthreads();
+  for (int qq = w; qq < 64; qq += 4) {
+    const int64_t q = q0 + qq;
+    const int c = c0 + lane;
+    if (q < M && c < ldr) Xr[q * ldr + c] = tile[lane][qq];
   }
-#undef H2_BSR_ROW
 }
 
 // ------------------------------------------------- adaptive convergence test
@@ -1937,60 +1897,52 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
 }
 
 template <int NB, bool TR>
-hipError_t launch_bsr_nb(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
-                         const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                         const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
-  const dim3 grid(nrows, (nc + NB * 16 - 1) / (NB * 16));
-  const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
-  if (rt * NB > 8) return hipErrorInvalidValue;
-  const size_t lds = 2 * size_t(kBsrQ) * NB * 16 * sizeof(double) +
-                     size_t(kBsrMeta) * (2 * sizeof(int) + sizeof(int64_t));
-  hipError_t e = hipSuccess;
-#define H2_BSR_RT(RT)                                                                                    \
-  if ((e = allow_lds(bsr_gemm_kernel<NB, RT, TR>, lds)) != hipSuccess) return e;                    \
-  bsr_gemm_kernel<NB, RT, TR><<<grid, 256, lds, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, \
-                                                          ldx, Y, ldy, nc, alpha)
-  if (max_m <= 64) {
-    H2_BSR_RT(1);
-  } else if (max_m <= 128) {
-    H2_BSR_RT(2);
-  } else if (max_m <= 256) {
-    H2_BSR_RT(4);
-  } else {
-    return hipErrorInvalidValue;
-  }
-#undef H2_BSR_RT
-  return hipGetLastError();
+void launch_bsr_nb(hipStream_t s, dim3 grid, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
+                   const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
+                   const double* Xr, int ldr, double* Y, int64_t ldy, int nc, double alpha) {
+  bsr_gemm_kernel<NB, TR><<<grid, 256, 0, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, Xr, ldr, Y, ldy, nc,
+                                               alpha);
+}
+
+size_t bsr_scratch_doubles(int64_t ldx, int nc) {
+  const int nb = std::min(4, (nc + 15) / 16);
+  const int ldr = ((nc + 16 * nb - 1) / (16 * nb)) * 16 * nb;
+  return size_t(ldx) * ldr;
 }
 
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m) {
-  if (nrows <= 0 || nc <= 0) return hipSuccess;
+                     const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
+                     double* scratch, size_t scratch_doubles) {
+  if (nrows <= 0 || nc <= 0 || ldx <= 0) return hipSuccess;
   if (max_m < 1) max_m = 1;
-  // at most 64 columns per workgroup (two staged 64-row X chunks, 64 KB);
-  // RT * NB <= 8 bounds the accumulators per wave
-  int nb = (nc + 15) / 16;
-  const int rt = max_m <= 64 ? 1 : (max_m <= 128 ? 2 : 4);
-  nb = std::min(nb, std::min(4, 8 / rt));
-#define H2_BSR_NB(NB)                                                                                              \
-  (tpos ? launch_bsr_nb<NB, true>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, \
-                                  max_m)                                                                             \
-        : launch_bsr_nb<NB, false>(s, nrows, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, X, ldx, Y, ldy, nc,       \
-                                   alpha, max_m))
+  const int nb = std::min(4, (nc + 15) / 16);
+  const int ngrp = (nc + 16 * nb - 1) / (16 * nb);
+  const int ldr = ngrp * 16 * nb;
+  const size_t need = size_t(ldx) * ldr;
+  double* xr = scratch;
+  if (!xr || scratch_doubles < need) return hipErrorInvalidValue;
+  const dim3 tgrid(unsigned((ldx + 63) / 64), unsigned((ldr + 63) / 64));
+  to_rows_kernel<<<tgrid, 256, 0, s>>>(ldx, nc, ldr, X, ldx, xr);
+  const dim3 grid(nrows, ngrp, (max_m + 63) / 64);
+#define H2_BSR_NB(NB)                                                                                               \
+  (tpos ? launch_bsr_nb<NB, true>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha) \
+        : launch_bsr_nb<NB, false>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha))
   switch (nb) {
-    case 1: return H2_BSR_NB(1);
-    case 2: return H2_BSR_NB(2);
-    case 3: return H2_BSR_NB(3);
-    default: return H2_BSR_NB(4);
+    case 1: H2_BSR_NB(1); break;
+    case 2: H2_BSR_NB(2); break;
+    case 3: H2_BSR_NB(3); break;
+    default: H2_BSR_NB(4); break;
   }
 #undef H2_BSR_NB
+  return hipGetLastError();
 }
 
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m) {
-  return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m);
+                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles) {
+  return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m,
+                   scratch, scratch_doubles);
 }
 
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
@@ -2194,18 +2146,6 @@ hipError_t prepare_kernels(size_t lds_limit) {
       reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, true>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, true>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 1, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 1, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 1, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 2, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 2, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 2, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<1, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<2, 4, false>),
-      reinterpret_cast<const void*>(bsr_gemm_kernel<3, 4, false>), reinterpret_cast<const void*>(bsr_gemm_kernel<4, 4, false>),
   };
   for (const void* f : ks) {
     const hipError_t e = set(f);

@@ -78,6 +78,7 @@ class UpdateBuilder {
   DevArray<double> lrW_, lrPart_, lrSum_;
   PanelWorkspace ws_;
   PrefixConvTest conv_;
+  BsrScratch xr_;
 
 
   void run_inner(const double* U, int64_t ldu, const double* V, int64_t ldv) {
@@ -221,9 +222,10 @@ class UpdateBuilder {
         const double* left = a == 0 ? h.lrU.get() : h.lrV.get();
         const double* right = a == 0 ? h.lrV.get() : h.lrU.get();
         // D_H is symmetric (D_H(b,s)^T = D_H(s,b) entry for entry), so both sides use it as stored
+        double* xr = xr_.get(n, nc, s_);
         H2_HIP(h2dev::bsr_gemm(s_, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(),
                                h.Dblk.get(), L.om.get() + int64_t(c0) * n, n, L.y.get() + int64_t(c0) * n, n, nc,
-                               -1.0, Lr.max_m));
+                               -1.0, Lr.max_m, xr, xr_.cap()));
         if (r_ > 0) {
           for (int q0 = 0; q0 < nc; q0 += 64) {
             const int w = std::min(64, nc - q0);
@@ -240,13 +242,14 @@ class UpdateBuilder {
     const Level& Cc = h.lvc[t + 1];
     const int mk = std::max({Cr.max_k, Cc.max_k, 1});
     // row side: Y -= B_{s,b} (V_b^T Omega_b); Omega of the row side lives in column rows
+    double* xr = xr_.get(std::max(Mr, Mc), nc, s_);
     H2_HIP(h2dev::bsr_gemm2(s_, Cr.nn, Cr.fptr.get(), Cr.fidx.get(), Cr.koff.get(), Cc.koff.get(), nullptr,
                             Cr.boff.get(), Cr.B.get(), Lr.om.get() + int64_t(c0) * Mc, Mc,
-                            Lr.y.get() + int64_t(c0) * Mr, Mr, nc, -1.0, mk));
+                            Lr.y.get() + int64_t(c0) * Mr, Mr, nc, -1.0, mk, xr, xr_.cap()));
     // column side: Z -= B_{b,s}^T (U_b^T Omega'_b)
     H2_HIP(h2dev::bsr_gemm2(s_, Cr.nn, Cr.fptr.get(), Cr.fidx.get(), Cc.koff.get(), Cr.koff.get(),
                             tpos_[t + 1].get(), Cr.boff.get(), Cr.B.get(), Lc.om.get() + int64_t(c0) * Mr, Mr,
-                            Lc.y.get() + int64_t(c0) * Mc, Mc, nc, -1.0, mk));
+                            Lc.y.get() + int64_t(c0) * Mc, Mc, nc, -1.0, mk, xr, xr_.cap()));
   }
 
   // Shrink with each side's own ID; random vectors carried up by the other side's ID.
