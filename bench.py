@@ -120,6 +120,7 @@ def bench_batched(h2, ctx, steps: int = 2):
                          "alloc_ms": info["t_alloc_ms"], "results_ms": info["t_results_ms"],
                          "capture_ms": info["t_capture_ms"], "graph_nodes": info["graph_nodes"],
                          "device_gb": info["device_bytes"] / 1e9,
+                         "first_pass_columns": info["first_pass"], "second_pass_problems": info["second_pass"],
                          "samples_range": [min(samples), max(samples)]}
     torch.cuda.synchronize()
     t0 = time.perf_counter()

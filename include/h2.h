@@ -260,12 +260,20 @@ typedef struct {
 } h2_problem;
 
 typedef struct {
-  int32_t precision; /* h2_precision, common to the batch */
-  int32_t d_max;     /* columns sketched up front for every problem, 1..96 */
-  int32_t use_graph; /* 1: capture the whole build in one hipGraph and launch it once */
+  int32_t precision;  /* h2_precision, common to the batch */
+  int32_t d_max;      /* most columns any problem may use, 1..96 */
+  int32_t use_graph;  /* 1: capture each launch sequence in one hipGraph and launch it once */
+  int32_t first_pass; /* columns sketched up front by the first launch sequence; 0: the
+                       * largest d0 plus 32 (the single build's default look-ahead); capped
+                       * at d_max.  Problems not converged within them are built again,
+                       * together, by a second sequence with d_max columns.  Results equal
+                       * those of one sequence with d_max columns: Omega is counter-based
+                       * and the prefix convergence test at a count does not depend on
+                       * later columns. */
 } h2_batch_opts;
 
 typedef struct {
+  /* times, nodes, bytes and flops are summed over both launch sequences */
   double t_total_ms;   /* wall time of the call */
   double t_plan_ms;    /* host cluster trees and lists of all problems (threaded) */
   double t_setup_ms;   /* host layout, device allocation and uploads */
@@ -274,10 +282,12 @@ typedef struct {
   int32_t levels;      /* levels of the longest problem */
   int32_t graph_nodes; /* nodes of the captured graph (0 without a graph) */
   int64_t device_bytes;
-  double sketch_flops; /* algorithmic 2 * n^2 * d_max summed over problems */
+  double sketch_flops; /* algorithmic 2 * n^2 * (columns sketched) summed over problems */
   double t_layout_ms;  /* part of t_setup_ms: host layout of the batch */
   double t_alloc_ms;   /* part of t_setup_ms: device allocation and uploads */
   double t_results_ms; /* per-problem result objects after the device work */
+  int32_t first_pass;  /* columns of the first launch sequence */
+  int32_t second_pass; /* problems built again with d_max columns */
 } h2_batch_info;
 
 /* Builds `count` independent H^2 matrices (Alg. 1 with adaptive sampling, Sec.

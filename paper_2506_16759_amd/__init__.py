@@ -236,14 +236,15 @@ def _problem_array(problems):
     return arr, keep
 
 
-def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP64, d_max: int = 96):
-    """Leaf size per problem from h2_autotune_leaf (problems as for build_batched)."""
+def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP64, d_max: int = 96,
+                  first_pass: int = 0):
+    """Leaf size per problem from h2_autotune_leaf (problems and options as for build_batched)."""
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
     arr, keep = _problem_array(problems)
     cand = (C.c_int32 * len(candidates))(*candidates)
     best = (C.c_int32 * len(problems))()
-    bo = _lib.BatchOpts(int(precision), int(d_max), 1)
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1, int(first_pass))
     _lib.check(_lib.load().h2_autotune_leaf(ctx._h, len(problems), arr, C.byref(bo), cand, len(candidates), best),
                "h2_autotune_leaf")
     del keep
@@ -251,17 +252,19 @@ def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP
 
 
 def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_graph: bool = True,
-                  return_info: bool = False):
+                  return_info: bool = False, first_pass: int = 0):
     """Many independent constructions in one launch sequence (h2_build_batched).
 
     problems: sequence of dicts with keys points ((dim, n) array or tensor),
     kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
-    norm_mode, oversample (defaults as h2_opts_default).  Returns a list of H2Matrix (and
+    norm_mode, oversample (defaults as h2_opts_default).  first_pass: columns
+    of the first launch sequence (0: largest d0 + 32; problems not converged
+    within them are built again with d_max).  Returns a list of H2Matrix (and
     the batch info dict when return_info)."""
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
     arr, keep = _problem_array(problems)
-    bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0)
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0, int(first_pass))
     handles = (C.c_void_p * len(problems))()
     info = _lib.BatchInfo()
     _lib.check(_lib.load().h2_build_batched(ctx._h, len(problems), arr, C.byref(bo), handles, C.byref(info)),

@@ -57,14 +57,16 @@ class Problem(C.Structure):
 
 
 class BatchOpts(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("d_max", C.c_int32), ("use_graph", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("d_max", C.c_int32), ("use_graph", C.c_int32),
+                ("first_pass", C.c_int32)]
 
 
 class BatchInfo(C.Structure):
     _fields_ = [("t_total_ms", C.c_double), ("t_plan_ms", C.c_double), ("t_setup_ms", C.c_double),
                 ("t_capture_ms", C.c_double), ("t_device_ms", C.c_double), ("levels", C.c_int32),
                 ("graph_nodes", C.c_int32), ("device_bytes", C.c_int64), ("sketch_flops", C.c_double),
-                ("t_layout_ms", C.c_double), ("t_alloc_ms", C.c_double), ("t_results_ms", C.c_double)]
+                ("t_layout_ms", C.c_double), ("t_alloc_ms", C.c_double), ("t_results_ms", C.c_double),
+                ("first_pass", C.c_int32), ("second_pass", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

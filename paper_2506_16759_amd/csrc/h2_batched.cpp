@@ -151,25 +151,14 @@ void check_problem(const h2_problem& p) {
   H2_REQUIRE(p.oversample >= 0 && p.oversample <= 64, "problem oversample must be in [0, 64]");
 }
 
-}  // namespace
-
-extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems,
-                                      const h2_batch_opts* bopts, h2_matrix** out, h2_batch_info* info) {
-  if (out && count > 0)
-    for (int i = 0; i < count; ++i) out[i] = nullptr;
-  return guarded([&] {
+// One launch sequence over `count` problems with dcap columns sketched up
+// front.  A problem not converged within dcap columns gets no matrix (out[i]
+// stays nullptr) and is listed in `exhausted`.  Arguments are validated by
+// the caller.
+void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec, int dcap, bool use_graph,
+                h2_matrix** out, std::vector<int>& exhausted, h2_batch_info* info) {
+  {
     const auto t_start = Clock::now();
-    H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
-    H2_REQUIRE(count >= 1, "count must be >= 1");
-    const int prec = bopts->precision;
-    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E || prec == H2_BF16X6,
-               "unknown precision");
-    const int dcap = bopts->d_max;
-    H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
-    for (int i = 0; i < count; ++i) {
-      check_problem(problems[i]);
-      H2_REQUIRE(problems[i].d0 <= dcap, "problem d0 exceeds d_max");
-    }
     H2_HIP(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
     auto store = std::make_shared<BatchStore>();
@@ -444,7 +433,6 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     // ---- the launch sequence
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const bool use_graph = bopts->use_graph != 0;
     hipStream_t cs = nullptr;  // capture stream
     if (use_graph) H2_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     auto enqueue = [&](hipStream_t s) {
@@ -556,9 +544,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     const std::vector<double> nu = download(B.nu.get(), np, s);
     const std::vector<double> delta = download(B.delta.get(), np, s);
     for (int q = 0; q < np; ++q)
-      if (exh[q] && P[q].L > 0)
-        throw Error(H2_ERR_SAMPLES, "problem " + std::to_string(P[q].orig) + " not converged within d_max = " +
-                                        std::to_string(dcap) + " columns");
+      if (exh[q] && P[q].L > 0) exhausted.push_back(P[q].orig);
     std::vector<std::vector<int32_t>> pos_h(Lmax);
     for (int l = 1; l <= Lmax; ++l) {
       LevelB& V = B.lv[l - 1];
@@ -571,6 +557,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     double sketch_flops = 0;
     for (int q = 0; q < np; ++q) {
       Prob& p = P[q];
+      if (exh[q] && p.L > 0) continue;
       auto h = std::make_unique<h2_matrix>();
       h->device = ctx->device;
       h->stream = s;
@@ -690,6 +677,92 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       r.graph_nodes = static_cast<int32_t>(graph_nodes);
       r.device_bytes = bytes;
       r.sketch_flops = sketch_flops;
+      *info = r;
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems,
+                                      const h2_batch_opts* bopts, h2_matrix** out, h2_batch_info* info) {
+  if (out && count > 0)
+    for (int i = 0; i < count; ++i) out[i] = nullptr;
+  return guarded([&] {
+    const auto t_start = Clock::now();
+    H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
+    H2_REQUIRE(count >= 1, "count must be >= 1");
+    const int prec = bopts->precision;
+    H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E || prec == H2_BF16X6,
+               "unknown precision");
+    const int dcap = bopts->d_max;
+    H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
+    H2_REQUIRE(bopts->first_pass >= 0, "first_pass must be >= 0");
+    int d0max = 1;
+    for (int i = 0; i < count; ++i) {
+      check_problem(problems[i]);
+      H2_REQUIRE(problems[i].d0 <= dcap, "problem d0 exceeds d_max");
+      d0max = std::max(d0max, problems[i].d0);
+    }
+    H2_HIP(hipSetDevice(ctx->device));
+    // first launch sequence: d0 plus the single build's default look-ahead
+    // (32 columns) unless given; problems not converged within it are built
+    // again, together, with d_max columns
+    int first = bopts->first_pass > 0 ? bopts->first_pass : d0max + 32;
+    first = std::max(d0max, std::min(first, dcap));
+    const bool graph = bopts->use_graph != 0;
+    std::vector<int> ex;
+    h2_batch_info i1{}, i2{};
+    int rerun = 0;
+    auto drop = [&](h2_matrix** m, int k) {
+      for (int i = 0; i < k; ++i)
+        if (m[i]) {
+          h2_free(m[i]);
+          m[i] = nullptr;
+        }
+    };
+    try {
+      build_pass(ctx, count, problems, prec, first, graph, out, ex, &i1);
+      if (!ex.empty() && first < dcap) {
+        std::vector<h2_problem> sub;
+        for (int i : ex) sub.push_back(problems[i]);
+        rerun = static_cast<int>(sub.size());
+        std::vector<h2_matrix*> o2(sub.size(), nullptr);
+        std::vector<int> ex2;
+        try {
+          build_pass(ctx, static_cast<int>(sub.size()), sub.data(), prec, dcap, graph, o2.data(), ex2, &i2);
+        } catch (...) {
+          drop(o2.data(), static_cast<int>(o2.size()));
+          throw;
+        }
+        std::vector<int> still;
+        for (int k : ex2) still.push_back(ex[k]);
+        for (size_t k = 0; k < sub.size(); ++k) out[ex[k]] = o2[k];
+        ex.swap(still);
+      }
+      if (!ex.empty())
+        throw Error(H2_ERR_SAMPLES, "problem " + std::to_string(*std::min_element(ex.begin(), ex.end())) +
+                                        " not converged within d_max = " + std::to_string(dcap) + " columns");
+    } catch (...) {
+      drop(out, count);
+      throw;
+    }
+    if (info) {
+      h2_batch_info r = i1;
+      r.t_total_ms = ms_since(t_start);
+      r.t_plan_ms += i2.t_plan_ms;
+      r.t_setup_ms += i2.t_setup_ms;
+      r.t_layout_ms += i2.t_layout_ms;
+      r.t_alloc_ms += i2.t_alloc_ms;
+      r.t_results_ms += i2.t_results_ms;
+      r.t_capture_ms += i2.t_capture_ms;
+      r.t_device_ms += i2.t_device_ms;
+      r.levels = std::max(i1.levels, i2.levels);
+      r.graph_nodes += i2.graph_nodes;
+      r.device_bytes += i2.device_bytes;
+      r.sketch_flops += i2.sketch_flops;
+      r.first_pass = first;
+      r.second_pass = rerun;
       *info = r;
     }
   });

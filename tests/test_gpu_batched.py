@@ -1,10 +1,11 @@
 """Batched construction (many independent problems in one launch sequence).
 
 The batched path runs the same kernels as single builds over concatenated
-problems, sketches all d_max columns up front and picks each problem's column
-count with a prefix QR per cluster.  It must therefore reproduce, problem by
-problem, what a single build with the same d_max and a look-ahead of
-d_max - d0 columns computes:
+problems, sketches the first launch sequence's columns up front (problems not
+converged within them are built again with d_max columns) and picks each
+problem's column count with a prefix QR per cluster.  It must therefore
+reproduce, problem by problem, what a single build with the same d_max and a
+look-ahead of d_max - d0 columns computes:
   * tree, lists and top depth bit-exact (same host plan),
   * the same sample count and (apart from thresholds that differ in the last
     bit, as the norm estimate is summed in another order) the same ranks,
@@ -145,6 +146,30 @@ def test_batched_graph_replays_are_identical(ctx):
         for key in ("ranks", "skel", "basis", "coupling"):
             for u, v in zip(fa[key], fb[key]):
                 np.testing.assert_array_equal(u, v)
+
+
+def test_batched_second_pass_equals_one_pass(ctx):
+    """Problems not converged within the first launch sequence's columns are
+    built again with d_max columns; every problem's factors equal, bit for bit,
+    those of one sequence with d_max columns (Omega is counter-based, the
+    prefix test at a count ignores later columns, problems are independent)."""
+    probs = _problems(MIXED_BATCH)
+    _say("batched: first pass of 32 columns + second pass vs one pass of 96")
+    m1, i1 = h2.build_batched(ctx, probs, d_max=96, first_pass=96, return_info=True)
+    m2, i2 = h2.build_batched(ctx, probs, d_max=96, first_pass=32, return_info=True)
+    _say(f"one pass: first {i1['first_pass']} rerun {i1['second_pass']}; "
+         f"two passes: first {i2['first_pass']} rerun {i2['second_pass']}")
+    assert i1["first_pass"] == 96 and i1["second_pass"] == 0
+    assert i2["first_pass"] == 32 and 0 < i2["second_pass"] < len(probs)
+    for a, b in zip(m1, m2):
+        assert a.info()["samples"] == b.info()["samples"]
+        fa, fb = _factors(a), _factors(b)
+        for key in ("ranks", "skel", "basis", "coupling"):
+            for u, v in zip(fa[key], fb[key]):
+                np.testing.assert_array_equal(u, v)
+        np.testing.assert_array_equal(fa["dense"], fb["dense"])
+    for H in m1 + m2:
+        H.close()
 
 
 def test_batched_sample_limit_is_reported(ctx):
