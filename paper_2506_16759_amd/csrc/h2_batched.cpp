@@ -75,9 +75,16 @@ struct Arena {
 
 // Small host arrays for many matrices, staged into one host buffer as they
 // are added and sent to the device in one copy: each array is a view into one
-// device block (256-byte aligned slices).
+// device block (256-byte aligned slices).  The staging buffer is kept per host
+// thread and reused, so repeated batches neither grow nor fault in fresh pages.
+std::vector<char>& packed_staging() {
+  thread_local std::vector<char> buf;
+  return buf;
+}
+
 struct Packed {
-  std::vector<char> host;
+  std::vector<char>& host = packed_staging();
+  Packed() { host.clear(); }
   std::vector<std::function<void(char*)>> bind;
   DevArray<char> block;
   template <typename T>
@@ -660,7 +667,7 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     B.meta.commit(s);
     // only the factors stay: dense blocks, bases, skeleton indices, couplings
     H2_HIP(hipStreamSynchronize(s));
-    std::vector<char>().swap(B.meta.host);
+    B.meta.host.clear();
     B.work.block.release();
     for (int q = 0; q < np; ++q) out[P[q].orig] = mats[q].release();
     if (info) {

@@ -828,9 +828,109 @@ hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const do
 // ------------------------------------------------------ kernel block gen
 
 // One workgroup per block row.  The row cluster's coordinates stay in LDS for
-// the whole row; each column cluster's coordinates are staged per block.
-// Consecutive threads write consecutive rows of the column-major block.
+// the whole row; the next column cluster's coordinates are fetched into
+// registers while the current block is evaluated and then stashed into the
+// other of two LDS buffers (one barrier per block).  Entry e = r + c*m of the
+// column-major block: when the threads can be laid out as fixed rows (m * (256/m)
+// of them, at least three quarters of the workgroup), thread t keeps row t % m
+// in registers and walks columns t/m, t/m + 256/m, ..; otherwise the threads
+// walk the entries in order.  Consecutive threads write consecutive entries;
+// the blocks are written once and read later, so the stores are non-temporal.
 constexpr int kGenMax = 256;
+constexpr int kGenPf = (3 * kGenMax + 255) / 256;  // staged coordinates per thread
+
+struct GenStage {
+  double v[kGenPf];
+  int mb;
+};
+
+template <int DIM>
+__device__ __forceinline__ void gen_fetch(GenStage& st, const int32_t* __restrict__ idx,
+                                          const int32_t* __restrict__ rowoff, const double* __restrict__ X,
+                                          int64_t ldx, int j, int tid) {
+  const int b = idx[j];
+  const int c0 = rowoff[b];
+  st.mb = rowoff[b + 1] - c0;
+#pragma unroll
+  for (int u = 0; u < kGenPf; ++u) {
+    const int e = tid + 256 * u;
+    st.v[u] = e < DIM * st.mb ? X[int64_t(e / st.mb) * ldx + c0 + e % st.mb] : 0.0;
+  }
+}
+
+template <int DIM>
+__device__ __forceinline__ void gen_stash(const GenStage& st, double (*xc)[kGenMax], int tid) {
+#pragma unroll
+  for (int u = 0; u < kGenPf; ++u) {
+    const int e = tid + 256 * u;
+    if (e < DIM * st.mb) xc[e / st.mb][e % st.mb] = st.v[u];
+  }
+}
+
+// The block row's blocks [jb, je); f(r2) gives the entry of squared distance r2.
+template <int DIM, typename F>
+__device__ __forceinline__ void gen_row(const int32_t* __restrict__ idx, const int32_t* __restrict__ rowoff,
+                                        const int64_t* __restrict__ blkoff, const double* __restrict__ X,
+                                        int64_t ldx, double* __restrict__ out, int jb, int je, int r0, int m,
+                                        double (*xr)[kGenMax], double (*xc)[DIM][kGenMax], F f) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < DIM * m; e += 256) xr[e / m][e % m] = X[int64_t(e / m) * ldx + r0 + e % m];
+  GenStage st;
+  gen_fetch<DIM>(st, idx, rowoff, X, ldx, jb, tid);
+  gen_stash<DIM>(st, xc[0], tid);
+  int mb = st.mb;
+  __syncthreads();
+  const int dc = 256 / m, act = m * dc;
+  const bool rows_fixed = act >= 192;
+  double rx[DIM];
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) rx[a] = xr[a][tid % m];
+  int cur = 0;
+  for (int j = jb; j < je; ++j) {
+    const bool more = j + 1 < je;
+    if (more) gen_fetch<DIM>(st, idx, rowoff, X, ldx, j + 1, tid);
+    double* o = out + blkoff[j];
+    const double(*xcc)[kGenMax] = xc[cur];
+    if (rows_fixed) {
+      if (tid < act) {
+#pragma unroll 4
+        for (int c = tid / m, e = tid; c < mb; c += dc, e += act) {
+          double r2 = 0.0;
+#pragma unroll
+          for (int a = 0; a < DIM; ++a) {
+            const double d = rx[a] - xcc[a][c];
+            r2 += d * d;
+          }
+          __builtin_nontemporal_store(f(r2), o + e);
+        }
+      }
+    } else {
+      const int dr = 256 % m;
+      int r = tid % m, c = tid / m;
+      for (int e = tid; e < m * mb; e += 256) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+          const double d = xr[a][r] - xcc[a][c];
+          r2 += d * d;
+        }
+        __builtin_nontemporal_store(f(r2), o + e);
+        r += dr;
+        c += dc;
+        if (r >= m) {
+          r -= m;
+          ++c;
+        }
+      }
+    }
+    if (more) {
+      gen_stash<DIM>(st, xc[cur ^ 1], tid);
+      mb = st.mb;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
 
 template <int DIM, int KIND>
 __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restrict__ ptr,
@@ -840,36 +940,13 @@ __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restri
                                                          const double* __restrict__ X, int64_t ldx, double c2,
                                                          double* __restrict__ out) {
   __shared__ double xr[DIM][kGenMax];
-  __shared__ double xc[DIM][kGenMax];
-  const int i = blockIdx.x, tid = threadIdx.x;
+  __shared__ double xc[2][DIM][kGenMax];
+  const int i = blockIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  if (ptr[i] == ptr[i + 1] || m == 0) return;
-  for (int e = tid; e < DIM * m; e += 256) xr[e / m][e % m] = X[(e / m) * ldx + r0 + e % m];
-  const int dr = 256 % m, dc = 256 / m;
-  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
-    const int b = idx[j];
-    const int c0 = rowoff[b], mb = rowoff[b + 1] - c0;
-    __syncthreads();
-    for (int e = tid; e < DIM * mb; e += 256) xc[e / mb][e % mb] = X[(e / mb) * ldx + c0 + e % mb];
-    __syncthreads();
-    double* o = out + blkoff[j];
-    int r = tid % m, c = tid / m;
-    for (int e = tid; e < m * mb; e += 256) {
-      double r2 = 0.0;
-#pragma unroll
-      for (int a = 0; a < DIM; ++a) {
-        const double d = xr[a][r] - xc[a][c];
-        r2 += d * d;
-      }
-      o[e] = kernel_of_r2<KIND>(r2, c2);
-      r += dr;
-      c += dc;
-      if (r >= m) {
-        r -= m;
-        ++c;
-      }
-    }
-  }
+  const int jb = ptr[i], je = ptr[i + 1];
+  if (jb == je || m == 0) return;  // uniform over the workgroup
+  gen_row<DIM>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+               [c2](double r2) { return kernel_of_r2<KIND>(r2, c2); });
 }
 
 // Batched form: block row i belongs to problem rowprob[i] with its own kernel
@@ -884,40 +961,19 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
                                                                  const double* __restrict__ c2s,
                                                                  double* __restrict__ out) {
   __shared__ double xr[3][kGenMax];
-  __shared__ double xc[3][kGenMax];
-  const int i = blockIdx.x, tid = threadIdx.x;
+  __shared__ double xc[2][3][kGenMax];
+  const int i = blockIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  if (ptr[i] == ptr[i + 1] || m == 0) return;
+  const int jb = ptr[i], je = ptr[i + 1];
+  if (jb == je || m == 0) return;  // uniform over the workgroup
   const int pr = rowprob[i];
-  const int kind = kinds[pr];
   const double c2 = c2s[pr];
-  for (int e = tid; e < 3 * m; e += 256) xr[e / m][e % m] = X[(e / m) * ldx + r0 + e % m];
-  const int dr = 256 % m, dc = 256 / m;
-  for (int j = ptr[i]; j < ptr[i + 1]; ++j) {
-    const int b = idx[j];
-    const int c0 = rowoff[b], mb = rowoff[b + 1] - c0;
-    __syncthreads();
-    for (int e = tid; e < 3 * mb; e += 256) xc[e / mb][e % mb] = X[(e / mb) * ldx + c0 + e % mb];
-    __syncthreads();
-    if (mb == 0) continue;
-    double* o = out + blkoff[j];
-    int r = tid % m, c = tid / m;
-    for (int e = tid; e < m * mb; e += 256) {
-      double r2 = 0.0;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double d = xr[a][r] - xc[a][c];
-        r2 += d * d;
-      }
-      o[e] = kind == kExp ? kernel_of_r2<kExp>(r2, c2) : kernel_of_r2<kGauss>(r2, c2);
-      r += dr;
-      c += dc;
-      if (r >= m) {
-        r -= m;
-        ++c;
-      }
-    }
-  }
+  if (kinds[pr] == kExp)
+    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+               [c2](double r2) { return kernel_of_r2<kExp>(r2, c2); });
+  else
+    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+               [c2](double r2) { return kernel_of_r2<kGauss>(r2, c2); });
 }
 
 // ------------------------------------------------------- block-sparse GEMM
