@@ -246,6 +246,12 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
       }
     }
     leafoff[nleaf_total] = static_cast<int32_t>(NT);
+    {
+      size_t nn = 0;
+      for (const auto& p : P) nn += p.plan.near_idx.size();
+      nidx.reserve(nn);
+      dsz.reserve(nn);
+    }
     int64_t dtot = 0;
     for (int q = 0; q < np; ++q) {
       auto& p = P[q];
@@ -318,6 +324,12 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
       // far lists at this level, global cluster indices; capacity offsets
       V.fptr.assign(V.G + 1, 0);
       std::vector<int64_t> bsz;
+      {
+        size_t nf = 0;
+        for (int q = 0; q < np && P[q].L >= l; ++q) nf += P[q].plan.far_idx[P[q].D - l + 1].size();
+        V.fidx.reserve(nf);
+        bsz.reserve(nf);
+      }
       for (int q = 0; q < np && P[q].L >= l; ++q) {
         const int t = P[q].D - l + 1;
         const auto& fp = P[q].plan.far_ptr[t];

@@ -1233,6 +1233,189 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
   }
 }
 
+// Blocked form of the same test for panels beyond LDS.  The panel lives
+// row-major in the global workspace; kQrNb columns at a time are copied to
+// LDS (rows jb.. only) and factored there with the same Householder steps,
+// their reflectors are accumulated as H_1..H_nb = I - V T V^T (T upper
+// triangular) and applied to the trailing columns as A -= V (T^T (V^T A)):
+// two passes over global memory per block instead of one per reflector.
+// Only the diagonal of R is used, so the factored block is not written back.
+constexpr int kQrNb = 16;
+
+__global__ __launch_bounds__(256, 2) void qr_first_conv_blocked_kernel(
+    const int32_t* __restrict__ rowoff, const double* __restrict__ Y, int64_t ldy, int dsk,
+    const int32_t* __restrict__ incprob, const int32_t* __restrict__ ovprob, const int32_t* __restrict__ nodeprob,
+    int32_t* __restrict__ dprob, const double* __restrict__ deltaprob, int32_t* __restrict__ exhausted,
+    double* __restrict__ gws, const int64_t* __restrict__ gws_off) {
+  extern __shared__ double smem[];
+  __shared__ double s_tau[kQrNb], s_z[kQrNb], s_T[kQrNb * kQrNb];
+  __shared__ double s_beta;
+  const int i = blockIdx.x;
+  const int pr = nodeprob[i];
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int dcur = dprob[pr];
+  const int inc = incprob[pr];
+  const int p = ovprob[pr];
+  const double delta = deltaprob[pr];
+  auto grid_at_least = [&](int x) {
+    if (x <= dcur) return dcur;
+    const int g = dcur + ((x - dcur + inc - 1) / inc) * inc;
+    return g <= dsk ? g : -1;
+  };
+  const int dfirst = grid_at_least(m + p);
+  const int ncols = min(m, dsk - p);
+  if (dfirst == dcur || ncols <= 0) {
+    if (tid == 0) {
+      if (dfirst < 0) atomicOr(&exhausted[pr], 1);
+      else atomicMax(&dprob[pr], dfirst);
+    }
+    return;
+  }
+  double* P = gws + gws_off[i];  // element (r, c) at P[r * ncols + c]
+  for (int e = tid; e < m * ncols; e += 256) {
+    const int r = e % m, c = e / m;
+    P[int64_t(r) * ncols + c] = Y[int64_t(c) * ldy + r0 + r];
+  }
+  __syncthreads();
+  constexpr int ld = kQrNb + 1;
+  double* V = smem;  // rows jb..m-1 of the block's columns, (m - jb) x ld
+  double mn = INFINITY;
+  int found = -1;
+  bool stop = false;
+  for (int jb = 0; jb < ncols && !stop; jb += kQrNb) {
+    const int nb = min(kQrNb, ncols - jb);
+    const int mr = m - jb;
+    // columns nb.. of V and the rows and columns nb.. of T are zero, so the
+    // trailing update needs no bounds on the block width
+    for (int e = tid; e < mr * kQrNb; e += 256) {
+      const int r = e / kQrNb, cl = e % kQrNb;
+      V[r * ld + cl] = cl < nb ? P[int64_t(jb + r) * ncols + jb + cl] : 0.0;
+    }
+    for (int e = tid; e < kQrNb * kQrNb; e += 256) s_T[e] = 0.0;
+    __syncthreads();
+    // factor the block's columns in LDS
+    for (int jl = 0; jl < nb; ++jl) {
+      const int j = jb + jl;
+      if (wave == 0) {
+        double sg = 0.0;
+        for (int r = jl + 1 + lane; r < mr; r += kWave) sg += V[r * ld + jl] * V[r * ld + jl];
+        sg = wave_sum(sg);
+        const double alpha = V[jl * ld + jl];
+        double beta, tau, scal;
+        if (sg == 0.0) {
+          beta = alpha;
+          tau = 0.0;
+          scal = 0.0;
+        } else {
+          const double nrm = sqrt(alpha * alpha + sg);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        for (int r = jl + 1 + lane; r < mr; r += kWave) V[r * ld + jl] *= scal;
+        if (lane == 0) {
+          s_tau[jl] = tau;
+          s_beta = beta;
+        }
+      }
+      __syncthreads();
+      mn = fmin(mn, fabs(s_beta));
+      if (mn < delta) {
+        found = grid_at_least(j + 1 + p);
+        stop = true;
+        break;
+      }
+      if (dfirst > 0 && j + 1 + p >= dfirst) {
+        stop = true;
+        break;
+      }
+      const double tau = s_tau[jl];
+      for (int cl = jl + 1 + wave; cl < nb; cl += 4) {
+        double w = 0.0;
+        for (int r = jl + 1 + lane; r < mr; r += kWave) w += V[r * ld + jl] * V[r * ld + cl];
+        w = (wave_sum(w) + V[jl * ld + cl]) * tau;
+        for (int r = jl + 1 + lane; r < mr; r += kWave) V[r * ld + cl] -= w * V[r * ld + jl];
+        if (lane == 0) V[jl * ld + cl] -= w;
+      }
+      __syncthreads();
+    }
+    if (stop || jb + nb >= ncols) break;  // uniform: s_beta and the counts are shared
+    // T: T_ll = tau_l, T[0:l, l] = -tau_l T[0:l, 0:l] (V[:, 0:l]^T v_l)
+    for (int l = 0; l < nb; ++l) {
+      for (int a = wave; a < l; a += 4) {
+        double z = 0.0;
+        for (int r = l + 1 + lane; r < mr; r += kWave) z += V[r * ld + a] * V[r * ld + l];
+        z = wave_sum(z) + V[l * ld + a];  // v_l is 1 at row l, zero above
+        if (lane == 0) s_z[a] = z;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double tl = s_tau[l];
+        for (int a = 0; a < l; ++a) {
+          double acc = 0.0;
+          for (int b = a; b < l; ++b) acc += s_T[a * kQrNb + b] * s_z[b];
+          s_T[a * kQrNb + l] = -tl * acc;
+        }
+        s_T[l * kQrNb + l] = tl;
+      }
+      __syncthreads();
+    }
+    // trailing columns: A -= V (T^T (V^T A)), one thread per column; rows
+    // below kQrNb hold only V's dense part, rows above it its unit triangle
+    const int rt = min(mr, kQrNb);
+    for (int c = jb + nb + tid; c < ncols; c += 256) {
+      double w[kQrNb];
+#pragma unroll
+      for (int l = 0; l < kQrNb; ++l) w[l] = 0.0;
+#pragma unroll 1
+      for (int r = 0; r < rt; ++r) {
+        const double a = P[int64_t(jb + r) * ncols + c];
+#pragma unroll
+        for (int l = 0; l < kQrNb; ++l) w[l] += (r > l ? V[r * ld + l] : (r == l ? 1.0 : 0.0)) * a;
+      }
+#pragma unroll 2
+      for (int r = kQrNb; r < mr; ++r) {
+        const double a = P[int64_t(jb + r) * ncols + c];
+#pragma unroll
+        for (int l = 0; l < kQrNb; ++l) w[l] += V[r * ld + l] * a;
+      }
+      // w <- T^T w in place (descending: column l of T only reads w[0..l]);
+      // the empty asm keeps T's LDS reads here instead of in registers for
+      // the whole loop
+      asm volatile("" ::: "memory");
+#pragma unroll
+      for (int l = kQrNb - 1; l >= 0; --l) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a <= l; ++a) acc += s_T[a * kQrNb + l] * w[a];
+        w[l] = acc;
+      }
+#pragma unroll 1
+      for (int r = 0; r < rt; ++r) {
+        double a = P[int64_t(jb + r) * ncols + c];
+#pragma unroll
+        for (int l = 0; l < kQrNb; ++l) a -= (r > l ? V[r * ld + l] : (r == l ? 1.0 : 0.0)) * w[l];
+        P[int64_t(jb + r) * ncols + c] = a;
+      }
+#pragma unroll 2
+      for (int r = kQrNb; r < mr; ++r) {
+        double a = P[int64_t(jb + r) * ncols + c];
+#pragma unroll
+        for (int l = 0; l < kQrNb; ++l) a -= V[r * ld + l] * w[l];
+        P[int64_t(jb + r) * ncols + c] = a;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int d = found;
+    if (d < 0 || (dfirst > 0 && dfirst < d)) d = dfirst;
+    if (d < 0) atomicOr(&exhausted[pr], 1);
+    else atomicMax(&dprob[pr], d);
+  }
+}
+
 // Exclusive scan of n int32 -> out[0..n] (out[n] = total), one workgroup.
 __global__ __launch_bounds__(1024) void scan_kernel(int n, const int32_t* __restrict__ in, int32_t* __restrict__ out) {
   __shared__ int32_t part[1024];
@@ -2164,8 +2347,16 @@ hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const
                                                               dprob, deltaprob, exhausted, gws, gws_off);
   } else {
     if (!gws || !gws_off) return hipErrorInvalidValue;
-    qr_first_conv_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob,
-                                                           dprob, deltaprob, exhausted, gws, gws_off);
+    const size_t blocked = size_t(max_m) * (kQrNb + 1) * sizeof(double);
+    if (blocked + 4096 <= lds_limit) {  // + the kernel's static LDS
+      hipError_t e = allow_lds(qr_first_conv_blocked_kernel, blocked);
+      if (e != hipSuccess) return e;
+      qr_first_conv_blocked_kernel<<<nnodes, 256, blocked, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob,
+                                                                dprob, deltaprob, exhausted, gws, gws_off);
+    } else {
+      qr_first_conv_kernel<false><<<nnodes, threads, 0, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob,
+                                                             dprob, deltaprob, exhausted, gws, gws_off);
+    }
   }
   return hipGetLastError();
 }
