@@ -187,6 +187,43 @@ def test_build_matches_dense_bound(ctx, n, dim, kind, length, leaf, tol, d0, din
     assert eF <= 10 * tol
 
 
+@pytest.mark.parametrize("n,leaf", [(1440, 96), (1100, 150), (3000, 64)])
+def test_dense_blocks_are_kernel_entries(ctx, n, leaf):
+    """Every near-field block equals the kernel on its clusters' points, for
+    leaf heights the block generator lays out as fixed rows per thread (64)
+    and as entries in order (90 and 137/138 rows)."""
+    pts = uniform_points(n, 3, 70 + leaf)
+    _say(f"dense blocks: n={n} leaf={leaf}")
+    H = h2.build(ctx, pts, "exp", 0.2, tol=1e-6, leaf_size=leaf, eta=0.7, d0=16, d_inc=16, seed=3)
+    D = int(H.export("DEPTH")[0])
+    nodes = H.export("NODES").reshape(-1, 2)
+    perm = H.export("PERM")
+    npp, ni = H.export("NEAR_PTR"), H.export("NEAR_IDX")
+    Dg = H.export("DENSE")
+    x = np.asarray(pts)[:, perm]   # tree order
+    heights = set()
+    off = 0
+    for s in range(1 << D):
+        bs, es = nodes[(1 << D) - 1 + s]
+        heights.add(int(es - bs))
+        for j in range(npp[s], npp[s + 1]):
+            b = int(ni[j])
+            bb, eb = nodes[(1 << D) - 1 + b]
+            d2 = ((x[:, bs:es, None] - x[:, None, bb:eb]) ** 2).sum(axis=0)
+            ref = np.exp(-np.sqrt(d2) / 0.2)
+            got = Dg[off:off + ref.size].reshape(eb - bb, es - bs).T
+            np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-300)
+            off += ref.size
+    assert off == Dg.size
+    # the near-field products of the build and of the matvec run on these
+    # block heights too (rows beyond 64 in 64-row slices)
+    K = KernelOperator(pts, "exp", 0.2).dense()
+    eF = np.linalg.norm(K - _dense_from_matvec(H, n)) / np.linalg.norm(K)
+    _say(f"leaf heights {sorted(heights)}, eF={eF:.3e}")
+    assert eF <= 10 * 1e-6
+    H.close()
+
+
 def test_edge_cases(ctx):
     import torch
     _say("edge: single leaf, nothing admissible, duplicates, n=1")
