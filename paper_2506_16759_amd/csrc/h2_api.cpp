@@ -121,18 +121,18 @@ int PrefixConvTest::first_converged(hipStream_t s, std::initializer_list<const L
   return r[3] ? -1 : r[0];
 }
 
-// A stream of default priority for work that may overlap the build stream
-// (none if not wanted: then work() is the build stream itself); join() makes
-// another stream wait for everything enqueued on it so far.
+// The context's second stream (default priority, created on first use and
+// kept until the context is destroyed) for work that may overlap the build
+// stream; none if not wanted, then work() is the build stream itself.  join() makes another stream wait for everything
+// enqueued on it so far.
 struct SideStream {
   hipStream_t s = nullptr;
-  explicit SideStream(bool wanted) {
-    if (wanted) H2_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  SideStream(h2_ctx* ctx, bool wanted) {
+    if (!wanted) return;
+    if (!ctx->side) H2_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    s = ctx->side;
   }
   hipStream_t work(hipStream_t build) const { return s ? s : build; }
-  ~SideStream() {
-    if (s) (void)hipStreamDestroy(s);
-  }
   SideStream(const SideStream&) = delete;
   SideStream& operator=(const SideStream&) = delete;
   void join(hipStream_t other) {
@@ -330,7 +330,7 @@ class Builder {
     // later release.  The FP64 and FP32E sketches use the FP64 units that the
     // FP64 block generation needs, and run faster alone (measured: overlapping
     // them slowed the FP64 build by about 10 %).
-    SideStream side(o.precision == H2_BF16X3 || o.precision == H2_BF16X6);
+    SideStream side(ctx_, o.precision == H2_BF16X3 || o.precision == H2_BF16X6);
     const hipStream_t gs = side.work(s_);
     auto adopt_all = [&] {
       h.perm.adopt(s_);
@@ -709,6 +709,10 @@ h2_status h2_ctx_destroy(h2_ctx* ctx) {
   return guarded([&] {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) {
+      (void)hipStreamSynchronize(ctx->side);
+      (void)hipStreamDestroy(ctx->side);
+    }
     delete ctx;
   });
 }

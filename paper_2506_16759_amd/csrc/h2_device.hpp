@@ -155,7 +155,7 @@ hipError_t thresholds(hipStream_t s, int nprob, const void* jobs, const double* 
 // A = H + U V^T with U, V (n x r, column-major, tree order).
 
 // W_b = V(leaf b rows, :)^T X(leaf b rows, :) for every leaf b: r x nc blocks,
-// column-major with ld r, block b at W + b*r*nc.
+// column-major with ld r, block b at W + b*r*nc; nc <= 64 (else hipErrorInvalidValue).
 hipError_t lr_leaf_project(hipStream_t s, int nleaves, const int32_t* leafoff, const double* V, int64_t ldv, int r,
                            const double* X, int64_t ldx, int nc, double* W);
 // out (len) = sum_b W_b in a fixed order; partial holds lr_sum_scratch doubles.

@@ -273,6 +273,7 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
 struct h2_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // created on first use, default priority, kept until h2_ctx_destroy
   size_t lds_limit = 65536;
 };
 

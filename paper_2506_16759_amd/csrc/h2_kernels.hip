@@ -1800,25 +1800,53 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(double* __restrict__ p, 
 // indices are tree positions.
 
 // W_b (r x nc, column-major, ld r, at b*r*nc) = V(leaf b rows, :)^T X(leaf b rows, :).
+// One workgroup per leaf: 32-row slices of V and X are staged in LDS and each
+// thread accumulates a 4 x 4 tile of W_b (64 x 64 per pass over q, nc <= 64).
+constexpr int kLrRows = 32;
+
 __global__ __launch_bounds__(256) void lr_leaf_project_kernel(const int32_t* __restrict__ leafoff,
                                                               const double* __restrict__ V, int64_t ldv, int r,
                                                               const double* __restrict__ X, int64_t ldx, int nc,
                                                               double* __restrict__ W) {
-  const int b = blockIdx.x;
+  __shared__ double sv[kLrRows][64 + 1], sx[kLrRows][64 + 1];
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int r0 = leafoff[b], m = leafoff[b + 1] - r0;
   double* Wb = W + int64_t(b) * r * nc;
-  for (int e = threadIdx.x; e < r * nc; e += blockDim.x) {
-    const int q = e % r, c = e / r;
-    const double* v = V + int64_t(q) * ldv + r0;
-    const double* x = X + int64_t(c) * ldx + r0;
-    double s0 = 0.0, s1 = 0.0;
-    int p = 0;
-    for (; p + 1 < m; p += 2) {
-      s0 += v[p] * x[p];
-      s1 += v[p + 1] * x[p + 1];
+  const int tq = (tid & 15) * 4, tc = (tid >> 4) * 4;
+  for (int q0 = 0; q0 < r; q0 += 64) {
+    const int qn = min(64, r - q0);
+    double acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+    for (int p0 = 0; p0 < m; p0 += kLrRows) {
+      const int pn = min(kLrRows, m - p0);
+      __syncthreads();
+      for (int e = tid; e < kLrRows * 64; e += 256) {
+        const int p = e % kLrRows, q = e / kLrRows;
+        sv[p][q] = (p < pn && q < qn) ? V[int64_t(q0 + q) * ldv + r0 + p0 + p] : 0.0;
+        sx[p][q] = (p < pn && q < nc) ? X[int64_t(q) * ldx + r0 + p0 + p] : 0.0;
+      }
+      __syncthreads();
+      for (int p = 0; p < pn; ++p) {
+        double v[4], x[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          v[a] = sv[p][tq + a];
+          x[a] = sx[p][tc + a];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] += v[a] * x[c];
+      }
     }
-    if (p < m) s0 += v[p] * x[p];
-    Wb[e] = s0 + s1;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (tq + a < qn && tc + c < nc) Wb[(q0 + tq + a) + int64_t(tc + c) * r] = acc[a][c];
   }
 }
 
@@ -2407,6 +2435,7 @@ hipError_t prepare_kernels(size_t lds_limit) {
 hipError_t lr_leaf_project(hipStream_t s, int nleaves, const int32_t* leafoff, const double* V, int64_t ldv, int r,
                            const double* X, int64_t ldx, int nc, double* W) {
   if (nleaves <= 0 || r <= 0 || nc <= 0) return hipSuccess;
+  if (nc > 64) return hipErrorInvalidValue;
   lr_leaf_project_kernel<<<nleaves, 256, 0, s>>>(leafoff, V, ldv, r, X, ldx, nc, W);
   return hipGetLastError();
 }
