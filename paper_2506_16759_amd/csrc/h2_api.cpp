@@ -84,6 +84,30 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
   return p;
 }
 
+SmallArena*& current_arena() {
+  thread_local SmallArena* a = nullptr;
+  return a;
+}
+
+void* SmallArena::take(size_t bytes, hipStream_t s) {
+  if (s != stream_ || bytes > kMaxBytes) return nullptr;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (used_ + bytes > cap_) {
+    const size_t c = std::max(kChunkBytes, bytes);
+    cur_ = static_cast<char*>(pool_alloc(c, stream_));
+    chunks_.push_back(cur_);
+    used_ = 0;
+    cap_ = c;
+  }
+  void* p = cur_ + used_;
+  used_ += bytes;
+  return p;
+}
+
+SmallArena::~SmallArena() {
+  for (void* c : chunks_) (void)hipFreeAsync(c, stream_);
+}
+
 void PanelWorkspace::ensure(int nodes, int max_m, int d, hipStream_t s) {
   const int64_t want = int64_t((max_m | 1) + 1) * int64_t((d | 1) + 1);
   if (want <= per && nodes <= nn) return;
@@ -786,8 +810,12 @@ h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, co
     h->stream = ctx->stream;
     h->kernel = *kernel;
     h->opts = *opts;
-    Builder b(ctx, h.get());
-    b.run(n, dim, points);
+    h->small = std::make_shared<SmallArena>(ctx->stream);
+    {
+      ArenaScope scope(h->small.get());
+      Builder b(ctx, h.get());
+      b.run(n, dim, points);
+    }
     *out = h.release();
   });
 }

@@ -70,7 +70,39 @@ constexpr size_t kLargeBytes = size_t(64) << 20;
 // cached free blocks are released (after the stream drains) and it retries once.
 void* pool_alloc(size_t bytes, hipStream_t s);
 
-// Stream-ordered device array; borrow() makes it a non-owning view.
+// Device chunks for the many small arrays of one single build (index arrays,
+// offsets, per-level scratch), released together with the matrix: one free
+// per chunk instead of one per array.  Only allocations on the arena's stream
+// and of at most kMaxBytes are served; others return nullptr.
+class SmallArena {
+ public:
+  static constexpr size_t kMaxBytes = size_t(4) << 20;
+  static constexpr size_t kChunkBytes = size_t(32) << 20;
+  explicit SmallArena(hipStream_t s) : stream_(s) {}
+  SmallArena(const SmallArena&) = delete;
+  SmallArena& operator=(const SmallArena&) = delete;
+  ~SmallArena();
+  void* take(size_t bytes, hipStream_t s);
+
+ private:
+  hipStream_t stream_;
+  std::vector<void*> chunks_;
+  char* cur_ = nullptr;
+  size_t used_ = 0, cap_ = 0;
+};
+// The arena that DevArray::alloc draws from on this host thread (nullptr: none).
+SmallArena*& current_arena();
+// Sets the current arena for a scope.
+struct ArenaScope {
+  SmallArena* prev;
+  explicit ArenaScope(SmallArena* a) : prev(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+};
+
+// Stream-ordered device array; borrow() makes it a non-owning view.  Small
+// arrays allocated while an arena is current are views into it.
 template <typename T>
 class DevArray {
  public:
@@ -98,6 +130,13 @@ class DevArray {
     n_ = n;
     owned_ = true;
     if (n == 0) return;
+    if (SmallArena* a = current_arena()) {
+      if (void* q = a->take(n * sizeof(T), s)) {
+        p_ = static_cast<T*>(q);
+        owned_ = false;
+        return;
+      }
+    }
     p_ = static_cast<T*>(pool_alloc(n * sizeof(T), s));
   }
   void upload(const std::vector<T>& h, hipStream_t s) {
@@ -304,6 +343,8 @@ struct h2_matrix {
   double sketch_flops = 0, sketch_entries = 0;
   std::shared_ptr<void> keep;    // storage shared with other matrices of a batched build
   std::shared_ptr<void> keep_d;  // owner of Dblk when it is shared with an update
+  std::shared_ptr<h2i::SmallArena> small;       // small arrays of a single build
+  std::shared_ptr<h2i::SmallArena> keep_small;  // the arena of the matrix an update shares Dblk with
   // Two-sided matrices (low-rank updates): column-side levels, empty when the
   // matrix is symmetric (column bases = row bases).
   std::vector<h2i::Level> lvc;

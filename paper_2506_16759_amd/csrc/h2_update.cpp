@@ -503,6 +503,7 @@ extern "C" h2_status h2_build_update(h2_ctx* ctx, h2_matrix* old, int32_t rank, 
     h->opts.eta = old->opts.eta;
     h->keep = old->keep;
     h->keep_d = old->keep_d;
+    h->keep_small = old->small ? old->small : old->keep_small;
     h->Dblk.borrow(old->Dblk.get(), old->Dblk.size());
     UpdateBuilder b(ctx, *old, h.get(), rank);
     b.run(U, ldu, V, ldv);
