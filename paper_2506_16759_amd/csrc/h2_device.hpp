@@ -88,7 +88,8 @@ hipError_t skeleton(hipStream_t s, int nnodes, const int32_t* rowoff, const int3
                     const int64_t* joff, const int32_t* pos_in, int32_t* pos_out, int dim, const double* X,
                     int64_t ldx, double* Xs, int64_t ldxs);
 
-// dst[p + c*ldd] = src[idx[p] + c*lds] (gather, scatter = false) or dst[idx[p] + c*ldd] = src[p + c*lds].
+// dst[p + c*ldd] = src[idx[p] + c*lds] (gather, scatter = false) or dst[idx[p] + c*ldd] = src[p + c*lds];
+// nc <= 65535 (else hipErrorInvalidValue).
 hipError_t permute_rows(hipStream_t s, int64_t n, const int32_t* idx, bool scatter, const double* src, int64_t lds,
                         double* dst, int64_t ldd, int nc);
 

@@ -1463,10 +1463,9 @@ __global__ __launch_bounds__(256) void threshold_kernel(const ThresholdJob* __re
   __shared__ double red[4];
   const ThresholdJob J = jobs[blockIdx.x];
   double acc = 0.0;
-  const int64_t total = J.n * J.d0;
-  for (int64_t e = threadIdx.x; e < total; e += 256) {
-    const double v = Y[(e / J.n) * ldy + J.base + e % J.n];
-    acc += v * v;
+  for (int c = 0; c < J.d0; ++c) {
+    const double* y = Y + int64_t(c) * ldy + J.base;
+    for (int64_t r = threadIdx.x; r < J.n; r += 256) acc += y[r] * y[r];
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -1764,9 +1763,9 @@ __global__ __launch_bounds__(256) void skeleton_kernel(const int32_t* __restrict
 __global__ __launch_bounds__(256) void permute_rows_kernel(int64_t n, const int32_t* __restrict__ idx, int scatter,
                                                            const double* __restrict__ src, int64_t lds,
                                                            double* __restrict__ dst, int64_t ldd, int nc) {
-  const int64_t total = n * nc;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t p = e % n, c = e / n;
+  // grid (row blocks, columns): no integer division per element
+  const int64_t c = blockIdx.y;
+  for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < n; p += int64_t(gridDim.x) * blockDim.x) {
     if (scatter)
       dst[c * ldd + idx[p]] = src[c * lds + p];
     else
@@ -2263,7 +2262,9 @@ hipError_t skeleton(hipStream_t s, int nnodes, const int32_t* rowoff, const int3
 hipError_t permute_rows(hipStream_t s, int64_t n, const int32_t* idx, bool scatter, const double* src, int64_t lds,
                         double* dst, int64_t ldd, int nc) {
   if (n <= 0 || nc <= 0) return hipSuccess;
-  permute_rows_kernel<<<grid_for(n * nc), 256, 0, s>>>(n, idx, scatter ? 1 : 0, src, lds, dst, ldd, nc);
+  if (nc > 65535) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(std::min<int64_t>((n + 255) / 256, 65536)), static_cast<unsigned>(nc));
+  permute_rows_kernel<<<grid, 256, 0, s>>>(n, idx, scatter ? 1 : 0, src, lds, dst, ldd, nc);
   return hipGetLastError();
 }
 
