@@ -64,7 +64,8 @@ hipMemPool_t large_pool() {
 }
 
 void* pool_alloc(size_t bytes, hipStream_t s) {
-  const bool large = bytes >= kLargeBytes;
+  const SmallArena* a = current_arena();
+  const bool large = bytes >= kLargeBytes && !(a && a->large_default && a->serves(s));
   auto once = [&](void** p) {
     return large ? hipMallocFromPoolAsync(p, bytes, large_pool(), s) : hipMallocAsync(p, bytes, s);
   };
@@ -811,6 +812,7 @@ h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, co
     h->kernel = *kernel;
     h->opts = *opts;
     h->small = std::make_shared<SmallArena>(ctx->stream);
+    h->small->large_default = !(opts->precision == H2_BF16X3 || opts->precision == H2_BF16X6);
     {
       ArenaScope scope(h->small.get());
       Builder b(ctx, h.get());
