@@ -293,11 +293,12 @@ typedef struct {
 /* Builds `count` independent H^2 matrices (Alg. 1 with adaptive sampling, Sec.
  * III) in one launch sequence: every stage of a level is one kernel over the
  * clusters of all problems, and with use_graph the whole sequence is captured
- * in one hipGraph.  All d_max columns are sketched up front; the adaptive loop
- * picks each problem's column count with one prefix QR per cluster, which
- * gives the same count, and the same factors, as adding d_inc columns at a
- * time.  A problem not converged within d_max makes the call fail with
- * H2_ERR_SAMPLES.  out: array of `count` handles (each freed with h2_free;
+ * in one hipGraph.  The first sequence sketches opts->first_pass columns up
+ * front (problems not converged within them are built again by a second
+ * sequence with d_max columns); the adaptive loop picks each problem's column
+ * count with one prefix QR per cluster, which gives the same count, and the
+ * same factors, as adding d_inc columns at a time.  A problem not converged
+ * within d_max makes the call fail with H2_ERR_SAMPLES.  out: array of `count` handles (each freed with h2_free;
  * they share device storage, released with the last one).  info may be NULL.
  * Synchronous. */
 h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
