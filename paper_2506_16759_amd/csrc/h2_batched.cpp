@@ -224,14 +224,14 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     H2_REQUIRE(NT < (int64_t{1} << 31), "total points must be < 2^31");
     // global tree order, original order maps
     std::vector<int32_t> perm_g(NT), rowprob_o(NT), rowlocal_o(NT);
-    for (int q = 0; q < np; ++q) {
+    h2::parallel_for(np, 1, [&](int q) {  // each problem fills its own rows
       const auto& p = P[q];
       for (int64_t r = 0; r < p.in.n; ++r) {
         perm_g[p.base + r] = static_cast<int32_t>(p.base + p.plan.perm[r]);
         rowprob_o[p.base + r] = q;
         rowlocal_o[p.base + r] = static_cast<int32_t>(r);
       }
-    }
+    });
     // leaves and near field
     std::vector<int32_t> leafoff(nleaf_total + 1), nptr(nleaf_total + 1, 0), nidx, leafprob(nleaf_total);
     std::vector<int64_t> dsz;
@@ -246,29 +246,34 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
       }
     }
     leafoff[nleaf_total] = static_cast<int32_t>(NT);
-    {
-      size_t nn = 0;
-      for (const auto& p : P) nn += p.plan.near_idx.size();
-      nidx.reserve(nn);
-      dsz.reserve(nn);
-    }
-    int64_t dtot = 0;
-    for (int q = 0; q < np; ++q) {
-      auto& p = P[q];
-      p.dbase = dtot;
+    // near lists of problem q occupy entries [noff[q], noff[q+1]); filled per
+    // problem in parallel, then the dense-block bases by a prefix over problems
+    std::vector<int64_t> noff(np + 1, 0), dq(np, 0);
+    for (int q = 0; q < np; ++q) noff[q + 1] = noff[q] + int64_t(P[q].plan.near_idx.size());
+    nidx.assign(size_t(noff[np]), 0);
+    dsz.assign(size_t(noff[np]), 0);
+    h2::parallel_for(np, 1, [&](int q) {
+      const auto& p = P[q];
       const int nl = 1 << p.D, lb = p.plan.level_begin(p.D);
+      int64_t tot = 0;
       for (int a = 0; a < nl; ++a) {
         const int g = p.leafbase + a;
         const int ma = p.plan.end[lb + a] - p.plan.begin[lb + a];
         for (int j = p.plan.near_ptr[a]; j < p.plan.near_ptr[a + 1]; ++j) {
           const int b = p.plan.near_idx[j];
-          nidx.push_back(p.leafbase + b);
+          nidx[noff[q] + j] = p.leafbase + b;
           const int64_t sz = int64_t(ma) * (p.plan.end[lb + b] - p.plan.begin[lb + b]);
-          dsz.push_back(sz);
-          dtot += sz;
+          dsz[noff[q] + j] = sz;
+          tot += sz;
         }
-        nptr[g + 1] = static_cast<int32_t>(nidx.size());
+        nptr[g + 1] = static_cast<int32_t>(noff[q] + p.plan.near_ptr[a + 1]);
       }
+      dq[q] = tot;
+    });
+    int64_t dtot = 0;
+    for (int q = 0; q < np; ++q) {
+      P[q].dbase = dtot;
+      dtot += dq[q];
     }
     const std::vector<int64_t> doff = prefix(dsz);
 
