@@ -12,7 +12,9 @@ One level does:
   1. subtract the part already represented at this level (Alg. 1):
        leaf : Y_loc = Y^1_tau - sum_{b in N_tau} D_{tau,b} Omega^1_b, D_{tau,b} = K(I_tau, I_b)
        inner: Y_loc = Y^l_tau - [sum_{b in F_nu1} B_{nu1,b} Omega^l_b ; sum_{b in F_nu2} B_{nu2,b} Omega^l_b]
-  2. adaptive test (Sec. III-B): a cluster is converged when the smallest |R_ii|
+  2. adaptive test (Sec. III-B; skipped with a fixed sample size, d_inc = 0,
+     which takes the d0 columns as they are, Sec. III-A): a cluster is
+     converged when the smallest |R_ii|
      of the unpivoted QR of the leading d - p columns of Y_loc is below the
      absolute threshold delta, or when m_tau + p <= d (p = oversampling margin,
      see ``converged``).  While some cluster is not converged, d_inc new columns are drawn,
@@ -210,7 +212,7 @@ class _Builder:
             om_in, y_in = self.level_inputs(t, om0, y0, child_om, child_y)
             yloc = self.subtract(t, y_in, om_in, child_om)
             rounds = 0
-            while not all(converged(yl, h.delta, self.oversample) for yl in yloc):
+            while self.d_inc > 0 and not all(converged(yl, h.delta, self.oversample) for yl in yloc):
                 om_b, yloc_b = self.update_samples(t)
                 om_in = [np.hstack([a, b]) for a, b in zip(om_in, om_b)]
                 yloc = [np.hstack([a, b]) for a, b in zip(yloc, yloc_b)]

@@ -5,11 +5,15 @@ evaluate any sub-block K(I_s, I_t).  Here both are written out plainly, in
 ORIGINAL point order:
   * ``KernelOperator`` -- K(x, y) = kappa(|x - y|) on a point cloud.  The sketch is
     the dense product computed block row by block row; entries are evaluated
-    directly.  Kernels:
-      exp   : exp(-r / l)            exponential covariance, eq. (cov)
-      gauss : exp(-r^2 / (2 l^2))    Gaussian covariance (reading: the usual
-                                     squared-exponential form)
-    The diagonal (x = y) is included: kappa(0) = 1.
+    directly.  Kernels (parameter p):
+      exp       : exp(-r / p)            exponential covariance, eq. (cov), p = l
+      gauss     : exp(-r^2 / (2 p^2))    Gaussian covariance (reading: the usual
+                                         squared-exponential form), p = l
+      helmholtz : cos(p r) / r           volume-IE operator of the Helmholtz
+                                         equation, eq. (ie), p = wavenumber k
+    The covariance kernels include the diagonal (x = y): kappa(0) = 1.  The IE
+    kernel is defined for x != y only; reading: its diagonal, and any pair of
+    coincident points (r = 0), is 0.
   * ``CallbackOperator`` -- user-supplied sketch and entry functions, used for
     the exactly-low-rank checks and for sketching an existing H^2 matrix plus a
     low-rank product.
@@ -28,11 +32,19 @@ def pair_distance(xa: np.ndarray, xb: np.ndarray) -> np.ndarray:
     return np.sqrt(r2)
 
 
-def kernel_from_distance(kind: str, length: float, r: np.ndarray) -> np.ndarray:
+def kernel_from_distance(kind: str, param: float, r: np.ndarray) -> np.ndarray:
+    """kappa(r) elementwise (Sec. V-A): param is the correlation length l, or the
+    wavenumber k of the Helmholtz kernel."""
     if kind == "exp":
-        return np.exp(-(r / length))
+        return np.exp(-(r / param))
     if kind == "gauss":
-        return np.exp(-(r * r) / (2.0 * length * length))
+        return np.exp(-(r * r) / (2.0 * param * param))
+    if kind == "helmholtz":
+        r = np.asarray(r, dtype=np.float64)
+        out = np.zeros_like(r)
+        pos = r > 0
+        out[pos] = np.cos(param * r[pos]) / r[pos]
+        return out
     raise ValueError(f"unknown kernel {kind!r}")
 
 
@@ -41,10 +53,10 @@ class KernelOperator:
 
     symmetric = True
 
-    def __init__(self, points: np.ndarray, kind: str, length: float, block_rows: int = 256):
+    def __init__(self, points: np.ndarray, kind: str, param: float, block_rows: int = 256):
         self.points = np.ascontiguousarray(points, dtype=np.float64)
         self.kind = kind
-        self.length = float(length)
+        self.length = float(param)      # correlation length, or the Helmholtz wavenumber
         self.block_rows = block_rows
         self.n = self.points.shape[1]
 

@@ -174,3 +174,27 @@ def test_convergence_test_keeps_an_oversampling_margin():
     B = rng.standard_normal((m, 6)) @ rng.standard_normal((6, 300))
     Y = B @ rng.standard_normal((300, 12))
     assert converged(Y, 1e-8, 5) and not converged(Y[:, :11], 1e-8, 5)
+
+
+def test_fixed_sample_size_recovers_exact_low_rank():
+    # Sec. III-A: with d >= r + p fixed columns and no adaptive test, an exactly
+    # rank-10 operator is reproduced to rounding and never needs more samples
+    pts = uniform_points(1500, 2, 31)
+    Phi = _monomials(pts, 3)
+    op = CallbackOperator(1500, sketch=lambda om: Phi @ (Phi.T @ om), entries=lambda i, j: Phi[i] @ Phi[j].T)
+    h = build_h2(op, pts, leaf_size=32, eta=0.7, tol=1e-13, d0=20, d_inc=0, seed=6)
+    assert h.samples == 20 and sum(h.rounds.values()) == 0
+    assert max(v.max() for v in h.ranks().values()) <= Phi.shape[1]
+    assert relative_fro_error(Phi @ Phi.T, h.dense()) < 1e-12
+
+
+def test_fixed_sample_size_takes_no_adaptive_round():
+    # the adaptive build of the same problem needs rounds; the fixed one stops at d0
+    pts = uniform_points(3000, 3, 6)
+    op = KernelOperator(pts, "exp", 0.2)
+    hf = build_h2(op, pts, leaf_size=48, eta=0.7, tol=1e-7, d0=8, d_inc=0, seed=3)
+    ha = build_h2(op, pts, leaf_size=48, eta=0.7, tol=1e-7, d0=8, d_inc=8, seed=3)
+    assert hf.samples == 8 and ha.samples > 8
+    # the first d0 columns are the same draw: the leaf-level row IDs agree up to
+    # the point where the adaptive build added columns
+    assert hf.delta == ha.delta
