@@ -1,8 +1,9 @@
 /*
  * h2.h -- C ABI of the MI355X (gfx950) H^2 construction library.
  *
- * Builds an H^2 matrix of a symmetric kernel matrix K(x_i, x_j) on a point
- * cloud with the bottom-up adaptive-sketching construction of
+ * Builds an H^2 matrix of a symmetric operator on a point cloud (a kernel
+ * matrix K(x_i, x_j), or any matrix given by a black-box product and an entry
+ * evaluator) with the bottom-up adaptive-sketching construction of
  * "Adaptive Sketching Based Construction of H2 Matrices on GPUs"
  * (Boukaram, Liu, Ghysels, Li; arXiv 2506.16759), Algorithm 1 with the
  * adaptive sampling of Sec. III-B.
@@ -20,8 +21,8 @@
  *     pointers are plain host memory.  The library never frees caller memory.
  *   - Calls that take an h2_ctx enqueue on the context's stream.  h2_build is
  *     synchronous (it returns after the build completed); h2_matvec,
- *     h2_sketch and h2_gaussian are stream-ordered (synchronise the stream
- *     before reading results on the host).
+ *     h2_entries, h2_sketch and h2_gaussian are stream-ordered (synchronise
+ *     the stream before reading results on the host).
  *   - One context per host thread; a context's calls must not overlap.
  */
 #ifndef H2_H
@@ -39,22 +40,59 @@ typedef enum {
   H2_ERR_ARG = -1,       /* invalid argument (NULL, size, ld, option out of range) */
   H2_ERR_HIP = -2,       /* a HIP runtime call failed */
   H2_ERR_OOM = -3,       /* device allocation failed */
-  H2_ERR_CALLBACK = -4,  /* reserved: a user callback returned non-zero */
+  H2_ERR_CALLBACK = -4,  /* a user callback (h2_sketch_fn, h2_entry_fn) returned non-zero */
   H2_ERR_SAMPLES = -5,   /* adaptive sampling reached d_max unconverged */
   H2_ERR_STATE = -6,     /* object in the wrong state (e.g. export of a missing part) */
   H2_ERR_UNSUPPORTED = -7 /* request outside what this build implements */
 } h2_status;
 
-/* Kernel functions kappa(r), r = |x - y| (Sec. V-A).  kappa(0) = 1. */
+/* Kernel functions kappa(r), r = |x - y| (Sec. V-A, the two test problems). */
 typedef enum {
-  H2_K_EXP = 1,   /* exponential covariance exp(-r / length), eq. (cov) */
-  H2_K_GAUSS = 2  /* Gaussian covariance exp(-r^2 / (2 length^2)) */
+  H2_K_EXP = 1,       /* exponential covariance exp(-r / length), eq. (cov); kappa(0) = 1 */
+  H2_K_GAUSS = 2,     /* Gaussian covariance exp(-r^2 / (2 length^2)); kappa(0) = 1 */
+  H2_K_HELMHOLTZ = 3  /* volume-IE operator of the Helmholtz equation cos(k r) / r, eq. (ie),
+                       * k = wavenumber.  The formula holds for x != y only; the diagonal
+                       * (and any pair of coincident points, r == 0) is taken as 0.
+                       * FP64 single builds only (other precisions and batched builds
+                       * return H2_ERR_UNSUPPORTED). */
 } h2_kernel_kind;
 
 typedef struct {
-  int32_t kind;   /* h2_kernel_kind */
-  double length;  /* correlation length l > 0 */
+  int32_t kind;       /* h2_kernel_kind */
+  double length;      /* correlation length l > 0 (H2_K_EXP, H2_K_GAUSS; ignored otherwise) */
+  double wavenumber;  /* k > 0 (H2_K_HELMHOLTZ; ignored otherwise) */
 } h2_kernel;
+
+/* ------------------------------------------------------- black-box inputs
+ * Alg. 1 takes the matrix through two user functions: the black box
+ * Y = K_blk(Omega) and a batched evaluator of sub-blocks (batchedGen, Sec.
+ * IV-A).  Both are called from the thread running h2_build, in stream order:
+ * they enqueue their device work on `stream` (a hipStream_t passed as void*,
+ * the context's stream) and return 0, or non-zero on failure, which aborts the
+ * build with H2_ERR_CALLBACK (nothing leaks).  They may call h2_matvec and
+ * h2_entries, on the building context or another one, and must not free or
+ * write memory the library passes them except their output.  The operator
+ * must be symmetric (the symmetric form of Alg. 1); an operator given by an
+ * H^2 matrix plus a low-rank product, which is not, is built by
+ * h2_build_update.
+ *
+ * Sketch callback: y(:, c) = A omega(:, c) for c < d.  omega: DEVICE n x d
+ * (ld ldo), y: DEVICE n x d (ld ldy, overwritten), both in ORIGINAL point
+ * order.  Called once per sketch pass (h2_info.sketch_calls). */
+typedef int (*h2_sketch_fn)(void* user, int64_t n, int32_t d, const double* omega, int64_t ldo, double* y,
+                            int64_t ldy, void* stream);
+
+/* Entry callback (batchedGen): for every block b < nblocks,
+ *   out[off[b] + r + c * rcnt[b]] = A(idx[rbeg[b] + r], idx[cbeg[b] + c]),
+ *   r < rcnt[b], c < ccnt[b]  (block b column-major, leading dimension rcnt[b]),
+ * with idx holding ORIGINAL point indices.  idx, rbeg, rcnt, cbeg, ccnt, off
+ * and out are DEVICE arrays; max_rows and max_cols bound rcnt[] and ccnt[]
+ * (host values, for launch shapes).  The library calls it for the dense leaf
+ * blocks D (nblocks = near pairs) and, per level, for the coupling blocks B at
+ * the skeletons (nblocks = far pairs of the level). */
+typedef int (*h2_entry_fn)(void* user, int32_t nblocks, const int32_t* idx, const int64_t* rbeg,
+                           const int32_t* rcnt, const int64_t* cbeg, const int32_t* ccnt, const int64_t* off,
+                           double* out, int32_t max_rows, int32_t max_cols, void* stream);
 
 /* Arithmetic of the dense on-the-fly sketch.  Kernel blocks D and B are
  * always evaluated and stored in FP64 and multiplied on the FP64 matrix cores
@@ -92,7 +130,9 @@ typedef struct {
   int32_t leaf_size;  /* KD-tree leaf size m0, 2..256 */
   double eta;         /* general admissibility parameter (Sec. II-A), > 0 */
   int32_t d0;         /* initial sample columns (Alg. 1 "sample block size"), 1..256 */
-  int32_t d_inc;      /* columns added per adaptive round (Sec. III-B), 1..128 */
+  int32_t d_inc;      /* columns added per adaptive round (Sec. III-B), 1..128; 0 = fixed
+                       * sample size (Sec. III-A): exactly d0 columns, no convergence test
+                       * and no adaptive rounds (single builds only) */
   int32_t d_max;      /* cap on total columns, <= 256; exceeding it -> H2_ERR_SAMPLES */
   uint64_t seed;      /* key of the counter-based Gaussian test matrix */
   int32_t precision;  /* h2_precision */
@@ -203,22 +243,53 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
 
 /* ------------------------------------------------------------------ build */
 
-/* Algorithm 1 + adaptive sampling (Sec. III) for the kernel matrix
- * K(i, j) = kappa(|x_i - x_j|).  points: DEVICE (dim x n) SoA, borrowed for
- * the call.  Synchronous.  *out owns every result until h2_free. */
+/* Algorithm 1 + adaptive sampling (Sec. III): the H^2 matrix of a symmetric
+ * n x n operator A on the cluster tree of `points` (DEVICE (dim x n) SoA,
+ * borrowed for the call; they define the tree and admissibility of Sec. II-A).
+ * Inputs of Alg. 1, in one of three forms:
+ *   kernel != NULL, sketch == NULL: A = K(i, j) = kappa(|x_i - x_j|); the
+ *       black box is the fused dense on-the-fly sketch (h2_sketch) and the
+ *       blocks are evaluated from kappa;
+ *   kernel != NULL, sketch != NULL: the black box is the callback (e.g. the
+ *       product with an existing H^2 matrix, as in Sec. V-A) and the blocks
+ *       are evaluated from kappa (entry == NULL);
+ *   kernel == NULL: both callbacks (sketch and entry) define A.
+ * opts->precision other than H2_FP64 applies to the built-in sketch only
+ * (H2_ERR_UNSUPPORTED with a sketch callback).  Synchronous.  *out owns
+ * every result until h2_free. */
 h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                   h2_sketch_fn sketch, void* sketch_user, h2_entry_fn entry, void* entry_user,
                    const h2_opts* opts, h2_matrix** out);
 
-/* y = K_H x for nrhs columns, x and y DEVICE n x nrhs in ORIGINAL order
- * (ld >= n); y overwritten.  Standard H^2 product: upsweep through the
- * nested basis, coupling, downsweep, near field.  Stream-ordered. */
-h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* h, int32_t nrhs, const double* x, int64_t ldx,
+/* y = A_H x (trans = 0) or y = A_H^T x (trans = 1) for nrhs columns, x and y
+ * DEVICE n x nrhs in ORIGINAL order (ld >= n), y overwritten.  Standard H^2
+ * product (the format of Sec. II-A, Table I): upsweep through the column
+ * bases, couplings, downsweep through the row bases, near field; the
+ * transpose swaps the bases and applies B^T and D^T.  For a symmetric build
+ * both are the same product.  Stream-ordered. */
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* h, int32_t trans, int32_t nrhs, const double* x, int64_t ldx,
                     double* y, int64_t ldy);
 
+/* Entries of a built H^2 matrix from the definition of the format (Sec.
+ * II-A, nested basis): entry (i, j) lies in exactly one block of the
+ * partition, a dense leaf block D_{s,b} (plus U_s V_b^T for an update) or an
+ * admissible pair (s, b) at some depth, where it equals
+ * row_i(U_s) B_{s,b} row_j(V_b)^T with the nested bases expanded through the
+ * transfer matrices.  Same block batch as h2_entry_fn (all arrays DEVICE,
+ * original indices), so a built matrix can serve as the entry callback of
+ * another build (Sec. IV-A batchedGen on an H^2 input).  The first call
+ * expands every point's nested-basis rows once (8 bytes x n x the largest
+ * rank of each processed depth, kept until h2_free).  Stream-ordered. */
+h2_status h2_entries(h2_ctx* ctx, const h2_matrix* h, int32_t nblocks, const int32_t* idx, const int64_t* rbeg,
+                     const int32_t* rcnt, const int64_t* cbeg, const int32_t* ccnt, const int64_t* off,
+                     double* out, int32_t max_rows, int32_t max_cols);
+
 /* Same parts as h2_plan_export plus the built factors (RANKS .. SKEL_POS).
- * Copies to HOST memory; synchronises the matrix's stream. */
-h2_status h2_export(const h2_matrix* h, int32_t part, int32_t depth, void* dst, size_t dst_bytes,
-                    size_t* needed);
+ * on_device = 0: dst is HOST memory; 1: dst is DEVICE memory on the
+ * matrix's device.  dst == NULL only reports the size in *needed (bytes).
+ * Synchronises the matrix's stream before returning. */
+h2_status h2_export(const h2_matrix* h, int32_t part, int32_t depth, int32_t on_device, void* dst,
+                    size_t dst_bytes, size_t* needed);
 
 typedef struct {
   int64_t n;
@@ -237,6 +308,9 @@ typedef struct {
   double t_host_plan;          /* host time of the tree + lists (overlaps the first sketch) */
   double sketch_flops;         /* algorithmic 2*n*n*columns summed over sketch passes */
   double sketch_entries;       /* kernel entries evaluated by the sketch passes */
+  int32_t sketch_calls;        /* sketch passes (calls of the black box) */
+  int32_t fixed_samples;       /* 1: built with the fixed sample size (d_inc = 0) */
+  int64_t bytes_peak;          /* device bytes held by the build at its largest (pool usage) */
 } h2_info;
 
 h2_status h2_query(const h2_matrix* h, h2_info* info);

@@ -16,13 +16,14 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import BF16X3, BF16X6, FP32, FP32E, FP64, K_EXP, K_GAUSS, NORM_FRO_SCALED, NORM_LITERAL, H2Error
+from ._lib import (BF16X3, BF16X6, FP32, FP32E, FP64, K_EXP, K_GAUSS, K_HELMHOLTZ, NORM_FRO_SCALED, NORM_LITERAL,
+                   H2Error)
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
-           "build_update", "autotune_leaf",
+           "build_update", "autotune_leaf", "device_view", "EntryBatch",
            "H2Matrix",
-           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "FP64", "FP32", "BF16X3", "FP32E", "BF16X6", "NORM_FRO_SCALED",
-           "NORM_LITERAL"]
+           "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "K_HELMHOLTZ", "FP64", "FP32", "BF16X3", "FP32E", "BF16X6",
+           "NORM_FRO_SCALED", "NORM_LITERAL"]
 
 
 def _torch():
@@ -30,9 +31,13 @@ def _torch():
     return torch
 
 
-def kernel_spec(kind, length: float) -> _lib.Kernel:
-    k = {"exp": K_EXP, "gauss": K_GAUSS}.get(kind, kind)
-    return _lib.Kernel(int(k), float(length))
+def kernel_spec(kind, length: float = 0.0, wavenumber: float | None = None) -> _lib.Kernel:
+    """h2_kernel for "exp" / "gauss" (correlation length) or "helmholtz" (wavenumber k,
+    taken from ``wavenumber``, else from the second argument)."""
+    k = {"exp": K_EXP, "gauss": K_GAUSS, "helmholtz": K_HELMHOLTZ}.get(kind, kind)
+    if int(k) == K_HELMHOLTZ:
+        return _lib.Kernel(int(k), 0.0, float(length if wavenumber is None else wavenumber))
+    return _lib.Kernel(int(k), float(length), 0.0)
 
 
 def opts_default(**over) -> _lib.Opts:
@@ -69,15 +74,75 @@ class _Handle:
             pass
 
 
-def _export(fn, handle, name: str, depth: int = 0) -> np.ndarray:
+def _export(fn, handle, name: str, depth: int = 0, device: bool = False):
+    """A part as a NumPy array, or (device=True, h2_export only) as a cuda tensor."""
     part = _lib.PART[name]
     need = C.c_size_t(0)
-    _lib.check(fn(handle, part, depth, None, 0, C.byref(need)), "export")
+    dev = (1,) if device else ((0,) if fn is _lib.load().h2_export else ())
+    _lib.check(fn(handle, part, depth, *dev, None, 0, C.byref(need)), "export")
     dt = np.dtype(_lib.PART_DTYPE[name])
-    out = np.empty(need.value // dt.itemsize, dtype=dt)
+    if device:
+        torch = _torch()
+        out = torch.empty(need.value // dt.itemsize, dtype=torch.float64 if dt.kind == "f" else torch.int32,
+                          device="cuda")
+        ptr = out.data_ptr()
+    else:
+        out = np.empty(need.value // dt.itemsize, dtype=dt)
+        ptr = out.ctypes.data
     if need.value:
-        _lib.check(fn(handle, part, depth, out.ctypes.data_as(C.c_void_p), need.value, C.byref(need)), "export")
+        _lib.check(fn(handle, part, depth, *dev, C.c_void_p(ptr), need.value, C.byref(need)), "export")
     return out
+
+
+class _CudaArray:
+    """__cuda_array_interface__ of memory the library hands to a callback."""
+
+    def __init__(self, ptr: int, shape, typestr: str, strides=None):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr, "data": (int(ptr), False),
+                                         "strides": strides, "version": 2}
+
+
+def device_view(ptr: int, shape, dtype="f8", ld: int | None = None):
+    """A torch cuda tensor aliasing device memory at ptr (no copy): 1-D of length
+    shape[0], or 2-D column-major (rows, cols) with leading dimension ld."""
+    torch = _torch()
+    typestr = {"f8": "<f8", "i4": "<i4", "i8": "<i8"}[dtype]
+    item = int(typestr[-1])
+    if len(shape) == 1 or shape[0] * shape[-1] == 0:
+        obj = _CudaArray(ptr, shape, typestr)
+    else:
+        rows, cols = shape
+        obj = _CudaArray(ptr, (rows, cols), typestr, (item, item * (ld if ld is not None else rows)))
+    return torch.as_tensor(obj, device="cuda")
+
+
+class EntryBatch:
+    """Arguments of an entry callback (h2_entry_fn) as device tensors.
+
+    Block b is A(idx[rbeg[b] : rbeg[b] + rcnt[b]], idx[cbeg[b] : cbeg[b] + ccnt[b]]),
+    written column-major at out[off[b]:].  Original point indices."""
+
+    def __init__(self, nblocks, idx, rbeg, rcnt, cbeg, ccnt, off, out, max_rows, max_cols):
+        self.nblocks, self.max_rows, self.max_cols = int(nblocks), int(max_rows), int(max_cols)
+        nb = self.nblocks
+        self.rbeg = device_view(rbeg, (nb,), "i8")
+        self.rcnt = device_view(rcnt, (nb,), "i4")
+        self.cbeg = device_view(cbeg, (nb,), "i8")
+        self.ccnt = device_view(ccnt, (nb,), "i4")
+        self.off = device_view(off, (nb,), "i8")
+        nidx = int(max((self.rbeg + self.rcnt).max().item(), (self.cbeg + self.ccnt).max().item()))
+        nout = int((self.off + self.rcnt.long() * self.ccnt.long()).max().item())
+        self.idx = device_view(idx, (nidx,), "i4")
+        self.out = device_view(out, (nout,), "f8")
+        self._ptrs = (idx, rbeg, rcnt, cbeg, ccnt, off, out)
+
+    def blocks(self):
+        """Host list of (row indices, column indices, out offset) per block."""
+        idx = self.idx.cpu().numpy()
+        rb, rc = self.rbeg.cpu().numpy(), self.rcnt.cpu().numpy()
+        cb, cc = self.cbeg.cpu().numpy(), self.ccnt.cpu().numpy()
+        off = self.off.cpu().numpy()
+        return [(idx[rb[b]:rb[b] + rc[b]], idx[cb[b]:cb[b] + cc[b]], int(off[b])) for b in range(self.nblocks)]
 
 
 class Plan(_Handle):
@@ -166,7 +231,7 @@ def sketch(ctx: Context, points, kernel, length: float, omega, precision: int = 
     ldo = _colmajor(omega, n)
     nc = omega.shape[1]
     y = empty_colmajor(n, nc)
-    k = kernel_spec(kernel, length)
+    k = kernel_spec(kernel, length)  # for "helmholtz", length is the wavenumber
     _lib.check(_lib.load().h2_sketch(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), C.byref(k), precision, nc,
                                      C.c_void_p(omega.data_ptr()), ldo, C.c_void_p(y.data_ptr()), max(n, 1)),
                "h2_sketch")
@@ -182,20 +247,41 @@ class H2Matrix(_Handle):
         self.ctx, self._h, self.n = ctx, handle, n
         self._lib_ref = _lib.load()
 
-    def matvec(self, x):
-        """K_H x for x an (n, c) column-major cuda tensor (or an (n,) vector)."""
+    def matvec(self, x, trans: bool = False):
+        """A_H x (or A_H^T x) for x an (n, c) column-major cuda tensor (or an (n,) vector)."""
         vec = x.dim() == 1
         if vec:
             x = x.reshape(1, -1).T
         ldx = _colmajor(x, self.n)
         c = x.shape[1]
         y = empty_colmajor(self.n, c)
-        _lib.check(_lib.load().h2_matvec(self.ctx._h, self._h, c, C.c_void_p(x.data_ptr()), ldx,
+        _lib.check(_lib.load().h2_matvec(self.ctx._h, self._h, 1 if trans else 0, c, C.c_void_p(x.data_ptr()), ldx,
                                          C.c_void_p(y.data_ptr()), self.n), "h2_matvec")
         return y[:, 0] if vec else y
 
-    def export(self, name: str, depth: int = 0) -> np.ndarray:
-        return _export(_lib.load().h2_export, self._h, name, depth)
+    def entries_raw(self, nblocks, idx, rbeg, rcnt, cbeg, ccnt, off, out, max_rows, max_cols):
+        """h2_entries on raw device pointers (the entry-callback argument list)."""
+        _lib.check(_lib.load().h2_entries(self.ctx._h, self._h, nblocks, *(C.c_void_p(p) for p in
+                                                                           (idx, rbeg, rcnt, cbeg, ccnt, off, out)),
+                                          max_rows, max_cols), "h2_entries")
+
+    def entries(self, rows, cols):
+        """A_H(rows, cols) for original indices (one block), as a (len(rows), len(cols)) cuda tensor."""
+        torch = _torch()
+        r = torch.as_tensor(np.asarray(rows), dtype=torch.int32)
+        c = torch.as_tensor(np.asarray(cols), dtype=torch.int32)
+        idx = torch.cat([r, c]).cuda()
+        z = lambda v, dt: torch.tensor([v], dtype=dt, device="cuda")
+        rb, rc, cb, cc, off = (z(0, torch.int64), z(r.numel(), torch.int32), z(r.numel(), torch.int64),
+                               z(c.numel(), torch.int32), z(0, torch.int64))
+        out = empty_colmajor(r.numel(), c.numel())
+        if r.numel() and c.numel():
+            self.entries_raw(1, idx.data_ptr(), rb.data_ptr(), rc.data_ptr(), cb.data_ptr(), cc.data_ptr(),
+                             off.data_ptr(), out.data_ptr(), r.numel(), c.numel())
+        return out
+
+    def export(self, name: str, depth: int = 0, device: bool = False):
+        return _export(_lib.load().h2_export, self._h, name, depth, device)
 
     def info(self) -> dict:
         inf = _lib.Info()
@@ -203,17 +289,71 @@ class H2Matrix(_Handle):
         return inf.as_dict()
 
 
+def _sketch_callback(fn):
+    """h2_sketch_fn from an H2Matrix (its product, zero copy) or from a callable
+    fn(omega, y) on (n, d) column-major cuda views that writes y = A omega."""
+    if isinstance(fn, H2Matrix):
+        H = fn
+
+        def raw(user, n, d, om, ldo, y, ldy, stream):
+            try:
+                _lib.check(_lib.load().h2_matvec(H.ctx._h, H._h, 0, d, C.c_void_p(om), ldo, C.c_void_p(y), ldy),
+                           "h2_matvec")
+                return 0
+            except Exception:   # any failure aborts the build with H2_ERR_CALLBACK
+                return 1
+    else:
+        def raw(user, n, d, om, ldo, y, ldy, stream):
+            try:
+                fn(device_view(om, (n, d), ld=ldo), device_view(y, (n, d), ld=ldy))
+                return 0
+            except Exception:
+                return 1
+    return _lib.SKETCH_FN(raw)
+
+
+def _entry_callback(fn):
+    """h2_entry_fn from an H2Matrix (h2_entries, zero copy) or from a callable
+    fn(batch: EntryBatch) that fills batch.out."""
+    if isinstance(fn, H2Matrix):
+        H = fn
+
+        def raw(user, nb, idx, rb, rc, cb, cc, off, out, mr, mc, stream):
+            try:
+                H.entries_raw(nb, idx, rb, rc, cb, cc, off, out, mr, mc)
+                return 0
+            except Exception:
+                return 1
+    else:
+        def raw(user, nb, idx, rb, rc, cb, cc, off, out, mr, mc, stream):
+            try:
+                fn(EntryBatch(nb, idx, rb, rc, cb, cc, off, out, mr, mc))
+                return 0
+            except Exception:
+                return 1
+    return _lib.ENTRY_FN(raw)
+
+
 def build(ctx: Context, points, kernel="exp", length: float = 0.2, opts: _lib.Opts | None = None,
-          **opt_over) -> H2Matrix:
-    """Algorithm 1 with adaptive sampling on the GPU (h2_build).  points: (dim, n)."""
+          sketch=None, entries=None, wavenumber: float | None = None, **opt_over) -> H2Matrix:
+    """Algorithm 1 with adaptive sampling on the GPU (h2_build).  points: (dim, n).
+
+    kernel: "exp", "gauss" (correlation length ``length``), "helmholtz"
+    (wavenumber ``wavenumber``, else ``length``) or None.  sketch: None (the
+    fused kernel sketch), an H2Matrix (its product is the black box) or a
+    callable fn(omega, y).  entries (only with kernel=None): an H2Matrix
+    (h2_entries) or a callable fn(EntryBatch)."""
     torch = _torch()
     pts = torch.as_tensor(points).to(device="cuda", dtype=torch.float64).contiguous()
     dim, n = pts.shape
     o = opts if opts is not None else opts_default(**opt_over)
-    k = kernel_spec(kernel, length)
+    kp = C.byref(kernel_spec(kernel, length, wavenumber)) if kernel is not None else None
+    sk = _sketch_callback(sketch) if sketch is not None else _lib.SKETCH_FN()
+    en = _entry_callback(entries) if entries is not None else _lib.ENTRY_FN()
     h = C.c_void_p()
-    _lib.check(_lib.load().h2_build(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), C.byref(k), C.byref(o),
-                                    C.byref(h)), "h2_build")
+    _lib.check(_lib.load().h2_build(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), kp, sk, None, en, None,
+                                    C.byref(o), C.byref(h)), "h2_build")
+    del sk, en   # the callbacks are not used after the build
     return H2Matrix(ctx, h, n)
 
 
@@ -229,7 +369,8 @@ def _problem_array(problems):
         nm = pr.get("norm_mode", d.norm_mode)
         if isinstance(nm, str):
             nm = {"fro_scaled": NORM_FRO_SCALED, "literal": NORM_LITERAL}[nm]
-        arr[i] = _lib.Problem(n, dim, pts.data_ptr(), kernel_spec(pr.get("kernel", "exp"), pr.get("length", 0.2)),
+        arr[i] = _lib.Problem(n, dim, pts.data_ptr(), kernel_spec(pr.get("kernel", "exp"), pr.get("length", 0.2),
+                                                                pr.get("wavenumber")),
                               pr.get("tol", d.tol), pr.get("leaf_size", d.leaf_size), pr.get("eta", d.eta),
                               pr.get("d0", d.d0), pr.get("d_inc", d.d_inc), pr.get("seed", d.seed), nm,
                               pr.get("oversample", d.oversample))

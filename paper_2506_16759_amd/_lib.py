@@ -11,7 +11,7 @@ H2_OK = 0
 STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_HIP", -3: "H2_ERR_OOM", -4: "H2_ERR_CALLBACK",
           -5: "H2_ERR_SAMPLES", -6: "H2_ERR_STATE", -7: "H2_ERR_UNSUPPORTED"}
 
-K_EXP, K_GAUSS = 1, 2
+K_EXP, K_GAUSS, K_HELMHOLTZ = 1, 2, 3
 FP64, FP32, BF16X3, FP32E, BF16X6 = 0, 1, 2, 3, 4
 NORM_FRO_SCALED, NORM_LITERAL = 0, 1
 
@@ -30,7 +30,7 @@ class Opts(C.Structure):
 
 
 class Kernel(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("length", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("length", C.c_double), ("wavenumber", C.c_double)]
 
 
 class Info(C.Structure):
@@ -44,7 +44,8 @@ class Info(C.Structure):
                 ("t_convtest", C.c_double), ("t_id", C.c_double), ("t_upsweep", C.c_double),
                 ("t_coupling", C.c_double), ("t_misc", C.c_double), ("t_host_plan", C.c_double),
                 ("sketch_flops", C.c_double),
-                ("sketch_entries", C.c_double)]
+                ("sketch_entries", C.c_double), ("sketch_calls", C.c_int32), ("fixed_samples", C.c_int32),
+                ("bytes_peak", C.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -73,6 +74,10 @@ class BatchInfo(C.Structure):
 
 
 _P = C.c_void_p
+# h2_sketch_fn(user, n, d, omega, ldo, y, ldy, stream)
+SKETCH_FN = C.CFUNCTYPE(C.c_int, _P, C.c_int64, C.c_int32, _P, C.c_int64, _P, C.c_int64, _P)
+# h2_entry_fn(user, nblocks, idx, rbeg, rcnt, cbeg, ccnt, off, out, max_rows, max_cols, stream)
+ENTRY_FN = C.CFUNCTYPE(C.c_int, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, _P)
 _SIGS = {
     "h2_opts_default": [C.POINTER(Opts)],
     "h2_status_string": [C.c_int],
@@ -85,9 +90,11 @@ _SIGS = {
     "h2_gaussian": [_P, C.c_uint64, C.c_int64, _P, C.c_int64, C.c_int32, _P, C.c_int64],
     "h2_sketch": [_P, C.c_int64, C.c_int32, _P, C.POINTER(Kernel), C.c_int32, C.c_int32, _P, C.c_int64, _P,
                   C.c_int64],
-    "h2_build": [_P, C.c_int64, C.c_int32, _P, C.POINTER(Kernel), C.POINTER(Opts), C.POINTER(_P)],
-    "h2_matvec": [_P, _P, C.c_int32, _P, C.c_int64, _P, C.c_int64],
-    "h2_export": [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)],
+    "h2_build": [_P, C.c_int64, C.c_int32, _P, C.POINTER(Kernel), SKETCH_FN, _P, ENTRY_FN, _P, C.POINTER(Opts),
+                 C.POINTER(_P)],
+    "h2_matvec": [_P, _P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64],
+    "h2_entries": [_P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
+    "h2_export": [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)],
     "h2_query": [_P, C.POINTER(Info)],
     "h2_free": [_P],
     "h2_build_batched": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(_P),

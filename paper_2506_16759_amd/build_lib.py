@@ -30,6 +30,7 @@ SOURCES = [
     ("h2_api.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
     ("h2_batched.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
     ("h2_update.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
+    ("h2_entries.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
     # host-only planning: no contraction, so box/admissibility arithmetic is
     # reproducible operation by operation
     ("h2_plan.cpp", ["-ffp-contract=off", "-fno-fast-math"]),

@@ -33,14 +33,57 @@ namespace h2i {
 h2dev::KernelFn kernel_fn(const h2_kernel& k) {
   h2dev::KernelFn f;
   f.kind = k.kind;
-  f.scale = k.kind == H2_K_EXP ? 1.0 / k.length : 1.0 / (2.0 * k.length * k.length);
+  if (k.kind == H2_K_EXP)
+    f.scale = 1.0 / k.length;
+  else if (k.kind == H2_K_GAUSS)
+    f.scale = 1.0 / (2.0 * k.length * k.length);
+  else
+    f.scale = k.wavenumber;
   return f;
 }
 
 void check_kernel(const h2_kernel* k) {
   H2_REQUIRE(k != nullptr, "kernel is NULL");
-  H2_REQUIRE(k->kind == H2_K_EXP || k->kind == H2_K_GAUSS, "unknown kernel kind");
-  H2_REQUIRE(k->length > 0.0 && std::isfinite(k->length), "kernel length must be finite and > 0");
+  H2_REQUIRE(k->kind == H2_K_EXP || k->kind == H2_K_GAUSS || k->kind == H2_K_HELMHOLTZ, "unknown kernel kind");
+  if (k->kind == H2_K_HELMHOLTZ)
+    H2_REQUIRE(k->wavenumber > 0.0 && std::isfinite(k->wavenumber), "wavenumber must be finite and > 0");
+  else
+    H2_REQUIRE(k->length > 0.0 && std::isfinite(k->length), "kernel length must be finite and > 0");
+}
+
+void call_sketch(h2_sketch_fn fn, void* user, int64_t n, int d, const double* om, int64_t ldo, double* y,
+                 int64_t ldy, hipStream_t s) {
+  ArenaScope none(nullptr);  // the callback's own library calls must not draw from the build's arena
+  const int rc = fn(user, n, d, om, ldo, y, ldy, s);
+  if (rc != 0) throw Error(H2_ERR_CALLBACK, "sketch callback returned " + std::to_string(rc));
+}
+
+void call_entries(h2_entry_fn fn, void* user, int nblocks, const int32_t* idx, const int64_t* rbeg,
+                  const int32_t* rcnt, const int64_t* cbeg, const int32_t* ccnt, const int64_t* off, double* out,
+                  int max_rows, int max_cols, hipStream_t s) {
+  if (nblocks <= 0) return;
+  ArenaScope none(nullptr);
+  const int rc = fn(user, nblocks, idx, rbeg, rcnt, cbeg, ccnt, off, out, max_rows, max_cols, s);
+  if (rc != 0) throw Error(H2_ERR_CALLBACK, "entry callback returned " + std::to_string(rc));
+}
+
+void pool_peak_reset(int device) {
+  uint64_t zero = 0;
+  hipMemPool_t def = nullptr;
+  if (hipDeviceGetDefaultMemPool(&def, device) == hipSuccess)
+    (void)hipMemPoolSetAttribute(def, hipMemPoolAttrUsedMemHigh, &zero);
+  (void)hipMemPoolSetAttribute(large_pool(), hipMemPoolAttrUsedMemHigh, &zero);
+}
+
+// Bytes in use (high = false) or the high-water mark since the last reset
+// (high = true) of the two stream-ordered pools the library allocates from.
+int64_t pool_bytes(int device, bool high) {
+  const hipMemPoolAttr attr = high ? hipMemPoolAttrUsedMemHigh : hipMemPoolAttrUsedMemCurrent;
+  uint64_t a = 0, b = 0;
+  hipMemPool_t def = nullptr;
+  if (hipDeviceGetDefaultMemPool(&def, device) == hipSuccess) (void)hipMemPoolGetAttribute(def, attr, &a);
+  (void)hipMemPoolGetAttribute(large_pool(), attr, &b);
+  return static_cast<int64_t>(a + b);
 }
 
 hipMemPool_t large_pool() {
@@ -178,14 +221,17 @@ int top_depth(const h2::Plan& p) {
 }
 
 void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt,
-                 int nc) {
+                 int nc, bool trans) {
   const int64_t n = h.plan.n;
   const int D = h.plan.depth;
   const int nleaves = 1 << D;
   if (nc <= 0) return;
   if (nc > 64) throw Error(H2_ERR_ARG, "matvec_tree: at most 64 columns");
-  const std::vector<Level>& up = h.col_levels();  // column bases: x_hat = V^T x
-  const std::vector<Level>& dn = h.lv;            // row bases: y += U y_hat
+  // A symmetric build is its own transpose.  For a two-sided one, A^T x runs
+  // up the row bases, applies B_{b,s}^T and goes down the column bases.
+  trans = trans && h.two_sided();
+  const std::vector<Level>& up = trans ? h.lv : h.col_levels();  // x_hat = (input-side basis)^T x
+  const std::vector<Level>& dn = trans ? h.col_levels() : h.lv;  // y += (output-side basis) y_hat
   BsrScratch xr;  // sized for the leaf rows, the largest row space
   xr.get(std::max<int64_t>(ldxt, n), nc, s);
   if (h.top <= D) {
@@ -203,13 +249,15 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
                               L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t].get(), M, nc));
       H2_HIP(h2dev::fill_zero(s, yh[t].get(), dn[t].koff_h.back() * nc));
     }
-    for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b
+    for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b (or B_{b,s}^T)
       const Level& L = dn[t];
       const Level& C = up[t];
+      const Level& R = h.lv[t];  // lists and blocks are stored with the row side
       double* xrp = xr.get(C.koff_h.back(), nc, s);
-      H2_HIP(h2dev::bsr_gemm2(s, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), C.koff.get(), nullptr,
-                              L.boff.get(), L.B.get(), xh[t].get(), C.koff_h.back(), yh[t].get(), L.koff_h.back(), nc,
-                              1.0, std::max({L.max_k, C.max_k, 1}), xrp, xr.cap()));
+      H2_HIP(h2dev::bsr_gemm2(s, L.nn, R.fptr.get(), R.fidx.get(), L.koff.get(), C.koff.get(),
+                              trans ? h.tpos[t].get() : nullptr, R.boff.get(), R.B.get(), xh[t].get(),
+                              C.koff_h.back(), yh[t].get(), L.koff_h.back(), nc, 1.0,
+                              std::max({L.max_k, C.max_k, 1}), xrp, xr.cap()));
     }
     for (int t = h.top; t <= D; ++t) {  // downsweep
       const Level& L = dn[t];
@@ -224,11 +272,13 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
   double* xrp = xr.get(ldxt, nc, s);
   H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,
                          ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr.cap()));
-  if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b
+  if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b (U, V swapped for A^T)
+    const double* left = trans ? h.lrV.get() : h.lrU.get();
+    const double* right = trans ? h.lrU.get() : h.lrV.get();
     DevArray<double> W;
     W.alloc(size_t(nleaves) * h.lr_rank * nc, s);
-    H2_HIP(h2dev::lr_leaf_project(s, nleaves, h.leafoff.get(), h.lrV.get(), n, h.lr_rank, xt, ldxt, nc, W.get()));
-    H2_HIP(h2dev::lr_apply(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), n, h.lrU.get(), n, h.lr_rank,
+    H2_HIP(h2dev::lr_leaf_project(s, nleaves, h.leafoff.get(), right, n, h.lr_rank, xt, ldxt, nc, W.get()));
+    H2_HIP(h2dev::lr_apply(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), n, left, n, h.lr_rank,
                            W.get(), nc, yt, ldyt, 1.0));
   }
 }
@@ -243,7 +293,7 @@ void check_opts(const h2_opts* o) {
   H2_REQUIRE(o->leaf_size >= 2 && o->leaf_size <= 256, "leaf_size must be in [2, 256]");
   H2_REQUIRE(o->eta > 0.0 && std::isfinite(o->eta), "eta must be finite and > 0");
   H2_REQUIRE(o->d0 >= 1 && o->d0 <= 256, "d0 must be in [1, 256]");
-  H2_REQUIRE(o->d_inc >= 1 && o->d_inc <= 128, "d_inc must be in [1, 128]");
+  H2_REQUIRE(o->d_inc >= 0 && o->d_inc <= 128, "d_inc must be in [0, 128]");
   H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 256, "d_max must be in [d0, 256]");
   H2_REQUIRE(o->precision == H2_FP64 || o->precision == H2_FP32 || o->precision == H2_BF16X3 ||
                  o->precision == H2_FP32E || o->precision == H2_BF16X6,
@@ -254,11 +304,24 @@ void check_opts(const h2_opts* o) {
 }
 
 
+// The matrix given to Alg. 1: a built-in kernel (dense on-the-fly sketch and
+// kernel entries) and/or the user's black box and entry evaluator.
+struct Operator {
+  const h2_kernel* kernel = nullptr;
+  h2_sketch_fn sketch = nullptr;
+  void* sketch_user = nullptr;
+  h2_entry_fn entry = nullptr;
+  void* entry_user = nullptr;
+};
+
 class Builder {
  public:
-  Builder(h2_ctx* ctx, h2_matrix* h) : ctx_(ctx), h_(h), s_(ctx->stream), timer_(ctx->stream) {}
+  Builder(h2_ctx* ctx, h2_matrix* h, const Operator& op)
+      : ctx_(ctx), h_(h), s_(ctx->stream), timer_(ctx->stream), op_(op) {}
 
   void run(int64_t n, int dim, const double* points) {
+    pool_peak_reset(ctx_->device);
+    const int64_t used0 = pool_bytes(ctx_->device, false);
     hipEvent_t t0, t1;
     H2_HIP(hipEventCreate(&t0));
     H2_HIP(hipEventCreate(&t1));
@@ -279,6 +342,7 @@ class Builder {
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     timer_.totals(h_->phase_ms, kNumPhase);
+    h_->bytes_peak = pool_bytes(ctx_->device, true) - used0;
     // drop the build-only sample buffers
     for (auto& L : h_->lv) {
       L.om.release();
@@ -291,6 +355,7 @@ class Builder {
   h2_matrix* h_;
   hipStream_t s_;
   PhaseTimer timer_;
+  Operator op_;
   h2dev::KernelFn kf_{};
   int dcap_ = 0, d_ = 0, dsk_ = 0, ahead_ = 0;
   const double* points_ = nullptr;  // caller's points, original order (borrowed for the build)
@@ -298,13 +363,18 @@ class Builder {
   PrefixConvTest conv_;
   BsrScratch xr_;
 
+  int64_t n_ = 0;
+  int dim_ = 0;
+
   void run_inner(int64_t n, int dim, const double* points) {
+    n_ = n;
+    dim_ = dim;
     h2_matrix& h = *h_;
     const h2_opts& o = h.opts;
-    kf_ = kernel_fn(h.kernel);
+    if (op_.kernel) kf_ = kernel_fn(*op_.kernel);
     points_ = points;
     dcap_ = o.d_max;
-    ahead_ = o.sketch_ahead;
+    ahead_ = o.d_inc > 0 ? o.sketch_ahead : 0;  // a fixed sample size draws d0 columns once
     std::vector<double> pts_h(static_cast<size_t>(n) * dim);
     H2_HIP(hipMemcpyAsync(pts_h.data(), points, pts_h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
     H2_HIP(hipStreamSynchronize(s_));
@@ -318,9 +388,7 @@ class Builder {
     om0.alloc(static_cast<size_t>(n) * first, s_);
     y0.alloc(static_cast<size_t>(n) * first, s_);
     H2_HIP(h2dev::gaussian(s_, o.seed, n, nullptr, 0, first, om0.get(), n));
-    H2_HIP(h2dev::sketch(s_, o.precision, n, dim, points, n, kf_, first, om0.get(), n, y0.get(), n));
-    h.sketch_flops += 2.0 * double(n) * double(n) * first;
-    h.sketch_entries += double(n) * double(n);
+    sketch_pass(om0.get(), y0.get(), first);
     const int nb = 512;
     part.alloc(nb, s_);
     // nu = ||Y_0||_F / sqrt(d0) from the first d0 columns: deterministic two-stage sum
@@ -378,8 +446,34 @@ class Builder {
       h.leafoff.upload(h.leafoff_h, gs);
       h.doff.upload(h.doff_h, gs);
       h.Dblk.alloc(static_cast<size_t>(h.doff_h.back()), gs);
-      H2_HIP(h2dev::gen_blocks(gs, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim,
-                               h.X.get(), n, kf_, h.Dblk.get()));
+      if (op_.entry) {
+        // D_{tau,b} = A(I_tau, I_b) from the entry callback: block j of the near
+        // list is rows leafoff[s].. and columns leafoff[b].. of perm
+        const size_t nnz = p.near_idx.size();
+        std::vector<int64_t> rb(nnz), cb(nnz);
+        std::vector<int32_t> rc(nnz), cc(nnz);
+        int mmax = 0;
+        for (int sl = 0; sl < nleaves; ++sl)
+          for (int j = p.near_ptr[sl]; j < p.near_ptr[sl + 1]; ++j) {
+            const int b = p.near_idx[j];
+            rb[j] = h.leafoff_h[sl];
+            rc[j] = h.leafoff_h[sl + 1] - h.leafoff_h[sl];
+            cb[j] = h.leafoff_h[b];
+            cc[j] = h.leafoff_h[b + 1] - h.leafoff_h[b];
+            mmax = std::max(mmax, rc[j]);
+          }
+        DevArray<int64_t> rb_d, cb_d;
+        DevArray<int32_t> rc_d, cc_d;
+        rb_d.upload(rb, gs);
+        cb_d.upload(cb, gs);
+        rc_d.upload(rc, gs);
+        cc_d.upload(cc, gs);
+        call_entries(op_.entry, op_.entry_user, static_cast<int>(nnz), h.perm.get(), rb_d.get(), rc_d.get(),
+                     cb_d.get(), cc_d.get(), h.doff.get(), h.Dblk.get(), mmax, mmax, gs);
+      } else {
+        H2_HIP(h2dev::gen_blocks(gs, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), dim,
+                                 h.X.get(), n, kf_, h.Dblk.get()));
+      }
       timer_.end(ph, gs);
       side.join(s_);
     } catch (...) {
@@ -398,6 +492,7 @@ class Builder {
     h.top = top_depth(p);
     if (h.top > D) {  // no admissible block: the dense blocks are the whole matrix
       h.sketch_flops = h.sketch_entries = 0;
+      h.sketch_calls = 0;
       return;
     }
 
@@ -420,7 +515,7 @@ class Builder {
     d_ = o.d0;
     timer_.end(ph);
 
-    conv_.init(s_, nleaves, h.opts.d_inc, h.opts.oversample, h.delta, ctx_->lds_limit);
+    if (o.d_inc > 0) conv_.init(s_, nleaves, o.d_inc, o.oversample, h.delta, ctx_->lds_limit);
 
     for (int t = D; t >= h.top; --t) level(t);
     h.samples = d_;
@@ -438,11 +533,23 @@ class Builder {
     om.alloc(static_cast<size_t>(n) * nc, s_);
     y.alloc(static_cast<size_t>(n) * nc, s_);
     H2_HIP(h2dev::gaussian(s_, h.opts.seed, n, nullptr, c0, nc, om.get(), n));
-    H2_HIP(h2dev::sketch(s_, h.opts.precision, n, h.plan.dim, points_, n, kf_, nc, om.get(), n, y.get(), n));
+    sketch_pass(om.get(), y.get(), nc);
     H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, om.get(), n, leaf.om.get() + int64_t(c0) * n, n, nc));
     H2_HIP(h2dev::permute_rows(s_, n, h.perm.get(), false, y.get(), n, leaf.y.get() + int64_t(c0) * n, n, nc));
-    h.sketch_flops += 2.0 * double(n) * double(n) * nc;
-    h.sketch_entries += double(n) * double(n);
+  }
+
+  // One pass of the black box Y = A Omega on nc columns in ORIGINAL order.
+  void sketch_pass(const double* om, double* y, int nc) {
+    h2_matrix& h = *h_;
+    const int64_t n = n_;
+    if (op_.sketch) {
+      call_sketch(op_.sketch, op_.sketch_user, n, nc, om, n, y, n, s_);
+    } else {
+      H2_HIP(h2dev::sketch(s_, h.opts.precision, n, dim_, points_, n, kf_, nc, om, n, y, n));
+      h.sketch_flops += 2.0 * double(n) * double(n) * nc;
+      h.sketch_entries += double(n) * double(n);
+    }
+    h.sketch_calls++;
   }
 
   // Y_loc = Y^l - (near or far contributions) on columns [c0, c0+nc) at depth t.
@@ -501,7 +608,7 @@ class Builder {
     // tested together on every sketched column (prefix test), then more
     // columns are sketched if none of them converges
     const int inc = h.opts.d_inc;
-    while (true) {
+    while (inc > 0) {  // a fixed sample size (inc = 0) takes the d0 columns as they are
       ph = timer_.begin(kConv);
       const int dconv = conv_.first_converged(s_, {&L}, d_, dsk_, ws_);
       timer_.end(ph);
@@ -580,10 +687,15 @@ class Builder {
     }
     // skeleton tree positions and coordinates
     L.pos_out.alloc(static_cast<size_t>(Mn), s_);
-    L.xs_out.alloc(static_cast<size_t>(Mn) * p.dim, s_);
     const int32_t* pos_in = (t == D) ? nullptr : h.lv[t + 1].pos_out.get();
-    H2_HIP(h2dev::skeleton(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), pos_in, L.pos_out.get(),
-                           p.dim, h.X.get(), p.n, L.xs_out.get(), Mn));
+    if (op_.entry) {  // entries come from the callback: no skeleton coordinates needed
+      H2_HIP(h2dev::skeleton(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), pos_in,
+                             L.pos_out.get(), 0, nullptr, 0, nullptr, 0));
+    } else {
+      L.xs_out.alloc(static_cast<size_t>(Mn) * p.dim, s_);
+      H2_HIP(h2dev::skeleton(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), pos_in,
+                             L.pos_out.get(), p.dim, h.X.get(), p.n, L.xs_out.get(), Mn));
+    }
     timer_.end(ph);
 
     // coupling matrices B_{tau,b} = K(I~_tau, I~_b), b in F_tau  (batchedGen)
@@ -598,20 +710,51 @@ class Builder {
     L.fidx.upload(L.fidx_h, s_);
     L.boff.upload(L.boff_h, s_);
     L.B.alloc(static_cast<size_t>(L.boff_h.back()), s_);
-    H2_HIP(h2dev::gen_blocks(s_, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), L.boff.get(), p.dim,
-                             L.xs_out.get(), Mn, kf_, L.B.get()));
+    if (op_.entry) {
+      // B_{tau,b} = A(I~_tau, I~_b): the skeletons' original indices, block j of
+      // the far list is rows koff[s].. and columns koff[b].. of them
+      DevArray<int32_t> sk;
+      sk.alloc(static_cast<size_t>(std::max<int64_t>(Mn, 1)), s_);
+      H2_HIP(h2dev::gather_idx(s_, Mn, L.pos_out.get(), h.perm.get(), sk.get()));
+      const size_t nnz = L.fidx_h.size();
+      std::vector<int64_t> rb(nnz), cb(nnz);
+      std::vector<int32_t> rc(nnz), cc(nnz);
+      for (int a = 0; a < L.nn; ++a)
+        for (int j = L.fptr_h[a]; j < L.fptr_h[a + 1]; ++j) {
+          const int b = L.fidx_h[j];
+          rb[j] = L.koff_h[a];
+          rc[j] = L.k_h[a];
+          cb[j] = L.koff_h[b];
+          cc[j] = L.k_h[b];
+        }
+      DevArray<int64_t> rb_d, cb_d;
+      DevArray<int32_t> rc_d, cc_d;
+      rb_d.upload(rb, s_);
+      cb_d.upload(cb, s_);
+      rc_d.upload(rc, s_);
+      cc_d.upload(cc, s_);
+      call_entries(op_.entry, op_.entry_user, static_cast<int>(nnz), sk.get(), rb_d.get(), rc_d.get(), cb_d.get(),
+                   cc_d.get(), L.boff.get(), L.B.get(), L.max_k, L.max_k, s_);
+    } else {
+      H2_HIP(h2dev::gen_blocks(s_, L.nn, L.fptr.get(), L.fidx.get(), L.koff.get(), L.boff.get(), p.dim,
+                               L.xs_out.get(), Mn, kf_, L.B.get()));
+    }
     timer_.end(ph);
   }
 };
 
-size_t copy_part(const void* src, size_t bytes, void* dst, size_t dst_bytes, size_t* needed, bool device,
-                 hipStream_t s) {
+// Copies `bytes` from src (device memory when src_dev) to dst (device memory
+// when dst_dev); dst == NULL only reports the size.
+size_t copy_part(const void* src, size_t bytes, void* dst, size_t dst_bytes, size_t* needed, bool src_dev,
+                 bool dst_dev, hipStream_t s) {
   if (needed) *needed = bytes;
   if (!dst) return bytes;
   if (dst_bytes < bytes) throw Error(H2_ERR_ARG, "destination too small");
   if (bytes == 0) return 0;
-  if (device) {
-    H2_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+  if (src_dev || dst_dev) {
+    const hipMemcpyKind kind = src_dev ? (dst_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost)
+                                       : hipMemcpyHostToDevice;
+    H2_HIP(hipMemcpyAsync(dst, src, bytes, kind, s));
     H2_HIP(hipStreamSynchronize(s));
   } else {
     std::memcpy(dst, src, bytes);
@@ -619,15 +762,16 @@ size_t copy_part(const void* src, size_t bytes, void* dst, size_t dst_bytes, siz
   return bytes;
 }
 
-void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst, size_t dst_bytes, size_t* needed) {
+void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst, size_t dst_bytes, size_t* needed,
+                      bool dst_dev = false, hipStream_t s = nullptr) {
   switch (part) {
     case H2_PART_DEPTH: {
       const int32_t d = p.depth;
-      copy_part(&d, sizeof d, dst, dst_bytes, needed, false, nullptr);
+      copy_part(&d, sizeof d, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     }
     case H2_PART_PERM:
-      copy_part(p.perm.data(), p.perm.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      copy_part(p.perm.data(), p.perm.size() * 4, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     case H2_PART_NODES: {
       std::vector<int32_t> v(2 * p.begin.size());
@@ -635,7 +779,7 @@ void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst,
         v[2 * i] = p.begin[i];
         v[2 * i + 1] = p.end[i];
       }
-      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     }
     case H2_PART_BOXES: {
@@ -645,20 +789,20 @@ void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst,
         for (int a = 0; a < p.dim; ++a) v.push_back(p.lo[size_t(i) * p.dim + a]);
         for (int a = 0; a < p.dim; ++a) v.push_back(p.hi[size_t(i) * p.dim + a]);
       }
-      copy_part(v.data(), v.size() * 8, dst, dst_bytes, needed, false, nullptr);
+      copy_part(v.data(), v.size() * 8, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     }
     case H2_PART_NEAR_PTR:
-      copy_part(p.near_ptr.data(), p.near_ptr.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      copy_part(p.near_ptr.data(), p.near_ptr.size() * 4, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     case H2_PART_NEAR_IDX:
-      copy_part(p.near_idx.data(), p.near_idx.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      copy_part(p.near_idx.data(), p.near_idx.size() * 4, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     case H2_PART_FAR_PTR:
     case H2_PART_FAR_IDX: {
       H2_REQUIRE(depth >= 0 && depth <= p.depth, "depth out of range");
       const auto& v = part == H2_PART_FAR_PTR ? p.far_ptr[depth] : p.far_idx[depth];
-      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, nullptr);
+      copy_part(v.data(), v.size() * 4, dst, dst_bytes, needed, false, dst_dev, s);
       return;
     }
     default:
@@ -790,12 +934,15 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
     H2_REQUIRE(ncols >= 0 && ncols <= 128, "ncols must be in [0, 128]");
     H2_REQUIRE(ldo >= std::max<int64_t>(n, 1) && ldy >= std::max<int64_t>(n, 1), "ld < n");
     H2_REQUIRE((points && omega && y) || n * int64_t(ncols) == 0, "NULL pointer");
+    if (kernel->kind == H2_K_HELMHOLTZ && precision != H2_FP64)
+      throw Error(H2_ERR_UNSUPPORTED, "the Helmholtz kernel is evaluated in FP64 only");
     H2_HIP(hipSetDevice(ctx->device));
     H2_HIP(h2dev::sketch(ctx->stream, precision, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
   });
 }
 
 h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, const h2_kernel* kernel,
+                   h2_sketch_fn sketch, void* sketch_user, h2_entry_fn entry, void* entry_user,
                    const h2_opts* opts, h2_matrix** out) {
   if (out) *out = nullptr;
   return guarded([&] {
@@ -803,29 +950,43 @@ h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, co
     H2_REQUIRE(points != nullptr, "points is NULL");
     H2_REQUIRE(n >= 1 && n <= (int64_t{1} << 30), "n must be in [1, 2^30]");
     H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
-    check_kernel(kernel);
+    if (kernel) {
+      check_kernel(kernel);
+      H2_REQUIRE(entry == nullptr, "entry callback given together with a kernel");
+    } else {
+      H2_REQUIRE(sketch != nullptr && entry != nullptr, "without a kernel both callbacks are required");
+    }
     check_opts(opts);
+    if ((sketch || (kernel && kernel->kind == H2_K_HELMHOLTZ)) && opts->precision != H2_FP64)
+      throw Error(H2_ERR_UNSUPPORTED, "reduced precision applies to the built-in covariance sketches only");
     H2_HIP(hipSetDevice(ctx->device));
     auto h = std::make_unique<h2_matrix>();
     h->device = ctx->device;
     h->stream = ctx->stream;
-    h->kernel = *kernel;
+    if (kernel) h->kernel = *kernel;
     h->opts = *opts;
     h->small = std::make_shared<SmallArena>(ctx->stream);
     h->small->large_default = !(opts->precision == H2_BF16X3 || opts->precision == H2_BF16X6);
+    Operator op;
+    op.kernel = kernel;
+    op.sketch = sketch;
+    op.sketch_user = sketch_user;
+    op.entry = entry;
+    op.entry_user = entry_user;
     {
       ArenaScope scope(h->small.get());
-      Builder b(ctx, h.get());
+      Builder b(ctx, h.get(), op);
       b.run(n, dim, points);
     }
     *out = h.release();
   });
 }
 
-h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t nrhs, const double* x, int64_t ldx, double* y,
-                    int64_t ldy) {
+h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t trans, int32_t nrhs, const double* x, int64_t ldx,
+                    double* y, int64_t ldy) {
   return guarded([&] {
     H2_REQUIRE(ctx != nullptr && hm != nullptr, "NULL argument");
+    H2_REQUIRE(trans == 0 || trans == 1, "trans must be 0 or 1");
     const h2_matrix& h = *hm;
     const int64_t n = h.plan.n;
     H2_REQUIRE(nrhs >= 0, "nrhs < 0");
@@ -833,6 +994,7 @@ h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t nrhs, const double
     H2_REQUIRE(x && y, "NULL vector");
     H2_REQUIRE(ldx >= n && ldy >= n, "ld < n");
     H2_HIP(hipSetDevice(ctx->device));
+    ArenaScope none(nullptr);  // temporaries of a matvec called inside a build are not the build's
     hipStream_t s = ctx->stream;
     const int chunk = 64;
     DevArray<double> xt, yt;
@@ -842,31 +1004,35 @@ h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t nrhs, const double
       const int nc = std::min(chunk, nrhs - c0);
       H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), false, x + int64_t(c0) * ldx, ldx, xt.get(), n, nc));
       H2_HIP(h2dev::fill_zero(s, yt.get(), n * nc));
-      matvec_tree(h, s, xt.get(), n, yt.get(), n, nc);
+      matvec_tree(h, s, xt.get(), n, yt.get(), n, nc, trans != 0);
       H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), true, yt.get(), n, y + int64_t(c0) * ldy, ldy, nc));
     }
     // temporaries are released stream-ordered; inputs stay valid until the stream passes this point
   });
 }
 
-h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst, size_t dst_bytes, size_t* needed) {
+h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, int32_t on_device, void* dst,
+                    size_t dst_bytes, size_t* needed) {
   return guarded([&] {
     H2_REQUIRE(hm != nullptr, "matrix is NULL");
+    H2_REQUIRE(on_device == 0 || on_device == 1, "on_device must be 0 or 1");
     const h2_matrix& h = *hm;
     const h2::Plan& p = h.plan;
     hipStream_t s = h.stream;
+    const bool dd = on_device != 0;
+    if (dd) H2_HIP(hipSetDevice(h.device));
     if (part <= H2_PART_FAR_IDX) {
-      export_plan_part(p, part, depth, dst, dst_bytes, needed);
+      export_plan_part(p, part, depth, dst, dst_bytes, needed, dd, s);
       return;
     }
     if (part == H2_PART_TOP) {
       const int32_t v = h.top;
-      copy_part(&v, 4, dst, dst_bytes, needed, false, s);
+      copy_part(&v, 4, dst, dst_bytes, needed, false, dd, s);
       return;
     }
     if (part == H2_PART_DENSE) {
       if (h.lr_rank == 0 || !dst) {
-        copy_part(h.Dblk.get(), h.Dblk.bytes(), dst, dst_bytes, needed, true, s);
+        copy_part(h.Dblk.get(), h.Dblk.bytes(), dst, dst_bytes, needed, true, dd, s);
         return;
       }
       // an update keeps D_old and the factors of U V^T: write the blocks out
@@ -874,7 +1040,7 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
       tmp.alloc(h.Dblk.size(), s);
       H2_HIP(h2dev::dense_lowrank(s, 1 << p.depth, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(),
                                   h.Dblk.get(), h.lrU.get(), p.n, h.lrV.get(), p.n, h.lr_rank, tmp.get()));
-      copy_part(tmp.get(), tmp.bytes(), dst, dst_bytes, needed, true, s);
+      copy_part(tmp.get(), tmp.bytes(), dst, dst_bytes, needed, true, dd, s);
       return;
     }
     H2_REQUIRE(depth >= 0 && depth <= p.depth, "depth out of range");
@@ -890,13 +1056,13 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
       case H2_PART_RANKS: {
         std::vector<int32_t> k(size_t(1) << depth, 0);
         if (have) k = L.k_h;
-        copy_part(k.data(), k.size() * 4, dst, dst_bytes, needed, false, s);
+        copy_part(k.data(), k.size() * 4, dst, dst_bytes, needed, false, dd, s);
         return;
       }
       case H2_PART_SKEL:
       case H2_PART_SKEL_POS: {
         if (!have) {
-          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, dd, s);
           return;
         }
         std::vector<int32_t> pos(L.pos_out.size());
@@ -906,12 +1072,12 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
         }
         if (part == H2_PART_SKEL)
           for (auto& v : pos) v = p.perm[v];
-        copy_part(pos.data(), pos.size() * 4, dst, dst_bytes, needed, false, s);
+        copy_part(pos.data(), pos.size() * 4, dst, dst_bytes, needed, false, dd, s);
         return;
       }
       case H2_PART_BASIS: {
         if (!have) {
-          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, dd, s);
           return;
         }
         // packed m x k per node (U is stored with capacity m x min(m, d))
@@ -926,12 +1092,12 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
           const int64_t k = L.k_h[i];
           packed.insert(packed.end(), all.begin() + L.uoff_h[i], all.begin() + L.uoff_h[i] + m * k);
         }
-        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, s);
+        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, dd, s);
         return;
       }
       case H2_PART_COUPLING: {
         if (!have) {
-          copy_part(nullptr, 0, dst, dst_bytes, needed, false, s);
+          copy_part(nullptr, 0, dst, dst_bytes, needed, false, dd, s);
           return;
         }
         // packed k_s x k_b per far pair in CSR order (storage may hold gaps)
@@ -946,7 +1112,7 @@ h2_status h2_export(const h2_matrix* hm, int32_t part, int32_t depth, void* dst,
             const int64_t sz = int64_t(L.k_h[a]) * Lc.k_h[L.fidx_h[j]];
             packed.insert(packed.end(), all.begin() + L.boff_h[j], all.begin() + L.boff_h[j] + sz);
           }
-        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, s);
+        copy_part(packed.data(), packed.size() * 8, dst, dst_bytes, needed, false, dd, s);
         return;
       }
       default:
@@ -1008,6 +1174,9 @@ h2_status h2_query(const h2_matrix* hm, h2_info* info) {
     r.t_misc = std::max(0.0, h.total_ms - acc);
     r.sketch_flops = h.sketch_flops;
     r.sketch_entries = h.sketch_entries;
+    r.sketch_calls = h.sketch_calls;
+    r.fixed_samples = h.opts.d_inc == 0 ? 1 : 0;
+    r.bytes_peak = h.bytes_peak;
     *info = r;
   });
 }

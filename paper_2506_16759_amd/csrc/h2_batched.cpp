@@ -150,6 +150,8 @@ void check_problem(const h2_problem& p) {
   H2_REQUIRE(p.n >= 1 && p.n <= (int64_t{1} << 30), "problem n must be in [1, 2^30]");
   H2_REQUIRE(p.dim >= 1 && p.dim <= 3, "problem dim must be 1..3");
   check_kernel(&p.kernel);
+  if (p.kernel.kind == H2_K_HELMHOLTZ)
+    throw Error(H2_ERR_UNSUPPORTED, "batched builds take the covariance kernels only");
   H2_REQUIRE(p.tol > 0.0 && std::isfinite(p.tol), "problem tol must be finite and > 0");
   H2_REQUIRE(p.leaf_size >= 2 && p.leaf_size <= 256, "problem leaf_size must be in [2, 256]");
   H2_REQUIRE(p.eta > 0.0 && std::isfinite(p.eta), "problem eta must be finite and > 0");

@@ -17,11 +17,12 @@
 
 namespace h2dev {
 
-enum KernelKind : int { kExp = 1, kGauss = 2 };
+enum KernelKind : int { kExp = 1, kGauss = 2, kHelm = 3 };
 
 struct KernelFn {
   int kind;      // KernelKind
-  double scale;  // exp: 1/l (kappa = exp(-r*scale)); gauss: 1/(2 l^2) (kappa = exp(-r^2*scale))
+  double scale;  // exp: 1/l (kappa = exp(-r*scale)); gauss: 1/(2 l^2) (kappa = exp(-r^2*scale));
+                 // helm: the wavenumber k (kappa = cos(k r)/r, 0 at r = 0)
 };
 
 // Omega(rows[p], col0 + c) -> out[p + c*ldo]; counter-based Philox4x64-10 + Box-Muller.
@@ -140,6 +141,9 @@ hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const
                          const int32_t* incprob, const int32_t* ovprob, const int32_t* nodeprob, int32_t* dprob,
                          const double* deltaprob, int32_t* exhausted, int max_m, size_t lds_limit, double* gws,
                          const int64_t* gws_off);
+
+// dst[i] = src[map[i]] for i < n (index gather, e.g. original indices of skeleton positions).
+hipError_t gather_idx(hipStream_t s, int64_t n, const int32_t* map, const int32_t* src, int32_t* dst);
 
 // Exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total.
 hipError_t scan_i32(hipStream_t s, int n, const int32_t* in, int32_t* out);

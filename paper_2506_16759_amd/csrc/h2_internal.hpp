@@ -311,10 +311,12 @@ class PrefixConvTest {
 
 struct h2_matrix;
 namespace h2i {
-// yt += A xt for nc <= 64 columns, both in TREE order (ld >= n): the standard
-// H^2 product (upsweep through the column bases, couplings, downsweep through
-// the row bases) plus the near field.  Stream-ordered on s.
-void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt, int nc);
+// yt += A xt (or A^T xt when trans) for nc <= 64 columns, both in TREE order
+// (ld >= n): the standard H^2 product (upsweep through the column bases,
+// couplings, downsweep through the row bases) plus the near field.
+// Stream-ordered on s.
+void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt, int nc,
+                 bool trans = false);
 }  // namespace h2i
 
 struct h2_ctx {
@@ -349,6 +351,8 @@ struct h2_matrix {
   double phase_ms[h2i::kNumPhase] = {};
   double total_ms = 0;
   double sketch_flops = 0, sketch_entries = 0;
+  int sketch_calls = 0;
+  int64_t bytes_peak = 0;
   std::shared_ptr<void> keep;    // storage shared with other matrices of a batched build
   std::shared_ptr<void> keep_d;  // owner of Dblk when it is shared with an update
   std::shared_ptr<h2i::SmallArena> small;       // small arrays of a single build
@@ -359,6 +363,11 @@ struct h2_matrix {
   // Near blocks of an update are Dblk + U_s V_b^T: factors n x lr_rank, tree order.
   int lr_rank = 0;
   h2i::DevArray<double> lrU, lrV;
+  // Two-sided matrices, per depth: CSR position of the mirrored far pair
+  // (b, s) for every stored pair (s, b), for products with B^T.
+  std::vector<h2i::DevArray<int64_t>> tpos;
+  // Nested-basis rows of every point, expanded on the first h2_entries call.
+  mutable std::shared_ptr<void> entry_cache;
   bool two_sided() const { return !lvc.empty(); }
   const std::vector<h2i::Level>& col_levels() const { return lvc.empty() ? lv : lvc; }
 };

@@ -30,15 +30,25 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// kappa as a function of the squared distance; c2 = -scale * log2(e) so that
-// exp(-scale * x) = 2^(c2 * x).
+// kappa as a function of the squared distance.  Covariance kernels: c2 =
+// -scale * log2(e) so that exp(-scale * x) = 2^(c2 * x).  Helmholtz IE
+// kernel: c2 is the wavenumber k and kappa = cos(k r) / r for r > 0, 0 at
+// r == 0 (the diagonal, where the formula is undefined).
 template <int KIND>
 __device__ __forceinline__ double kernel_of_r2(double r2, double c2) {
   if constexpr (KIND == kExp) {
     return exp2_nonpos(c2 * sqrt_nonneg(r2));
-  } else {
+  } else if constexpr (KIND == kGauss) {
     return exp2_nonpos(c2 * r2);
+  } else {
+    const double r = sqrt(r2);
+    return r2 > 0.0 ? cos(c2 * r) / r : 0.0;
   }
+}
+
+// Argument of kernel_of_r2 for a kernel function.
+__host__ __device__ inline double kernel_c2(KernelFn k) {
+  return k.kind == kHelm ? k.scale : -k.scale * kLog2e;
 }
 
 // ---------------------------------------------------------- Philox4x64-10
@@ -815,6 +825,14 @@ template <int P>
 hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const double* X, int64_t ldx, double c2,
                            int nc, const double* om, int64_t ldo, const uint32_t* w, int64_t npairs, double* yy,
                            int64_t ldy) {
+  if (kind == kHelm) {  // FP64 only
+    if constexpr (P == 0) {
+      if (dim == 1) return launch_sketch_nc<P, 1, kHelm>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+      if (dim == 2) return launch_sketch_nc<P, 2, kHelm>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+      return launch_sketch_nc<P, 3, kHelm>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
+    }
+    return hipErrorInvalidValue;
+  }
   if (kind == kExp) {
     if (dim == 1) return launch_sketch_nc<P, 1, kExp>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
     if (dim == 2) return launch_sketch_nc<P, 2, kExp>(s, n, X, ldx, c2, nc, om, ldo, w, npairs, yy, ldy);
@@ -2102,7 +2120,8 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
                   int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   if (precision < 0 || precision > 4) return hipErrorInvalidValue;
-  const double c2 = -k.scale * kLog2e;
+  if (k.kind == kHelm && precision != 0) return hipErrorInvalidValue;
+  const double c2 = kernel_c2(k);
   // split-bf16 modes: Omega is split once per launch into stream-ordered scratch
   const int S = precision == 2 ? 2 : (precision == 4 ? 3 : 0);
   const int64_t npairs = (n + 1) / 2;
@@ -2147,12 +2166,16 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out) {
   if (nrows <= 0) return hipSuccess;
-  const double c2 = -k.scale * kLog2e;
+  const double c2 = kernel_c2(k);
 #define H2_GEN(D, K) gen_blocks_kernel<D, K><<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, c2, out)
   if (k.kind == kExp) {
     if (dim == 1) H2_GEN(1, kExp);
     else if (dim == 2) H2_GEN(2, kExp);
     else H2_GEN(3, kExp);
+  } else if (k.kind == kHelm) {
+    if (dim == 1) H2_GEN(1, kHelm);
+    else if (dim == 2) H2_GEN(2, kHelm);
+    else H2_GEN(3, kHelm);
   } else {
     if (dim == 1) H2_GEN(1, kGauss);
     else if (dim == 2) H2_GEN(2, kGauss);

@@ -72,7 +72,6 @@ class UpdateBuilder {
   int r_;
   int dcap_ = 0, d_ = 0, dsk_ = 0, ahead_ = 0;
   DevArray<int32_t> perm_dev_;
-  std::vector<DevArray<int64_t>> tpos_;  // per depth: CSR position of the mirrored far pair
   std::vector<DevArray<double>> Rr_, Rc_;  // per depth: rows of H's basis at the new skeletons
   std::vector<int> maxko_;
   DevArray<double> lrW_, lrPart_, lrSum_;
@@ -122,7 +121,7 @@ class UpdateBuilder {
     if (h.top > D) return;  // no admissible block: the dense blocks are the whole matrix
 
     // transposed positions of the far lists (column-side subtraction uses B_{b,s}^T)
-    tpos_.resize(D + 1);
+    h.tpos.resize(D + 1);
     for (int t = h.top; t <= D; ++t) {
       const auto& fp = p.far_ptr[t];
       const auto& fi = p.far_idx[t];
@@ -136,7 +135,7 @@ class UpdateBuilder {
           if (it == hi || *it != a) throw Error(H2_ERR_STATE, "far lists are not symmetric");
           tp[j] = it - fi.data();
         }
-      tpos_[t].upload(tp, s_);
+      h.tpos[t].upload(tp, s_);
     }
 
     // ---- first sketch of both sides (tree order), threshold from the row sketch
@@ -248,7 +247,7 @@ class UpdateBuilder {
                             Lr.y.get() + int64_t(c0) * Mr, Mr, nc, -1.0, mk, xr, xr_.cap()));
     // column side: Z -= B_{b,s}^T (U_b^T Omega'_b)
     H2_HIP(h2dev::bsr_gemm2(s_, Cr.nn, Cr.fptr.get(), Cr.fidx.get(), Cc.koff.get(), Cr.koff.get(),
-                            tpos_[t + 1].get(), Cr.boff.get(), Cr.B.get(), Lc.om.get() + int64_t(c0) * Mr, Mr,
+                            h.tpos[t + 1].get(), Cr.boff.get(), Cr.B.get(), Lc.om.get() + int64_t(c0) * Mr, Mr,
                             Lc.y.get() + int64_t(c0) * Mc, Mc, nc, -1.0, mk, xr, xr_.cap()));
   }
 
