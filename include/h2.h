@@ -270,6 +270,26 @@ h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, co
 h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* h, int32_t trans, int32_t nrhs, const double* x, int64_t ldx,
                     double* y, int64_t ldy);
 
+/* h2_matvec without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, layout and result as h2_matvec.  Its
+ * temporaries (tree-ordered copies of x and y, x_hat and y_hat per depth, the
+ * row-major staging copy of the block-sparse products, the leaf projection of
+ * a low-rank term) live in a static device array of H2_NOALLOC_SCRATCH_BYTES
+ * that every device the library runs on holds until the process ends; its
+ * address is looked up when a context is created.  Columns are processed in
+ * chunks of the widest width (<= 64) whose temporaries fit; a matrix whose
+ * temporaries do not fit for one column (about 8 * (3 n + sum of ranks) bytes)
+ * is rejected with H2_ERR_ARG and a message giving the bytes it needs.  The
+ * array keeps the last call's contents, and every call on a device uses that
+ * device's one array: calls that overlap on one device (other streams or
+ * threads, other contexts) race and give wrong results.  Results equal
+ * h2_matvec's up to the summation order of the chunked products.
+ * Stream-ordered. */
+#define H2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+h2_status h2_matvec_noalloc(h2_ctx* ctx, const h2_matrix* h, int32_t trans, int32_t nrhs, const double* x,
+                            int64_t ldx, double* y, int64_t ldy);
+
 /* Entries of a built H^2 matrix from the definition of the format (Sec.
  * II-A, nested basis): entry (i, j) lies in exactly one block of the
  * partition, a dense leaf block D_{s,b} (plus U_s V_b^T for an update) or an

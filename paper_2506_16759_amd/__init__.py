@@ -259,6 +259,19 @@ class H2Matrix(_Handle):
                                          C.c_void_p(y.data_ptr()), self.n), "h2_matvec")
         return y[:, 0] if vec else y
 
+    def matvec_noalloc(self, x, y, trans: bool = False):
+        """y = A_H x (or A_H^T x) through h2_matvec_noalloc, which allocates no
+        device memory: x and y are (n, c) column-major cuda tensors the caller
+        allocated (y is overwritten)."""
+        ldx = _colmajor(x, self.n)
+        ldy = _colmajor(y, self.n)
+        if x.shape[1] != y.shape[1]:
+            raise ValueError("x and y must have the same number of columns")
+        _lib.check(_lib.load().h2_matvec_noalloc(self.ctx._h, self._h, 1 if trans else 0, x.shape[1],
+                                                 C.c_void_p(x.data_ptr()), ldx, C.c_void_p(y.data_ptr()), ldy),
+                   "h2_matvec_noalloc")
+        return y
+
     def entries_raw(self, nblocks, idx, rbeg, rcnt, cbeg, ccnt, off, out, max_rows, max_cols):
         """h2_entries on raw device pointers (the entry-callback argument list)."""
         _lib.check(_lib.load().h2_entries(self.ctx._h, self._h, nblocks, *(C.c_void_p(p) for p in

@@ -93,6 +93,7 @@ _SIGS = {
     "h2_build": [_P, C.c_int64, C.c_int32, _P, C.POINTER(Kernel), SKETCH_FN, _P, ENTRY_FN, _P, C.POINTER(Opts),
                  C.POINTER(_P)],
     "h2_matvec": [_P, _P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64],
+    "h2_matvec_noalloc": [_P, _P, C.c_int32, C.c_int32, _P, C.c_int64, _P, C.c_int64],
     "h2_entries": [_P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32],
     "h2_export": [_P, C.c_int32, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)],
     "h2_query": [_P, C.POINTER(Info)],

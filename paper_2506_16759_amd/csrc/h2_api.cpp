@@ -220,66 +220,99 @@ int top_depth(const h2::Plan& p) {
   return p.depth + 1;
 }
 
+// Every temporary of matvec_tree, in the order it takes them: the row-major
+// staging copy of the block-sparse products, x_hat and y_hat per processed
+// depth, and the leaf projection of a low-rank term.
+template <typename Take>
+static void matvec_temporaries(const h2_matrix& h, int64_t ldxt, int nc, bool trans, Take take, double** xr,
+                               size_t* xr_cap, double** xh, double** yh, double** W) {
+  const int D = h.plan.depth;
+  trans = trans && h.two_sided();
+  const std::vector<Level>& up = trans ? h.lv : h.col_levels();
+  const std::vector<Level>& dn = trans ? h.col_levels() : h.lv;
+  *xr_cap = h2dev::bsr_scratch_doubles(std::max<int64_t>(ldxt, h.plan.n), nc);
+  *xr = take(*xr_cap);
+  if (h.top <= D)
+    for (int t = h.top; t <= D; ++t) {
+      xh[t] = take(size_t(up[t].koff_h.back()) * nc);
+      yh[t] = take(size_t(dn[t].koff_h.back()) * nc);
+    }
+  *W = h.lr_rank > 0 ? take(size_t(1 << D) * h.lr_rank * nc) : nullptr;
+}
+
+size_t matvec_tree_scratch(const h2_matrix& h, int nc, bool trans) {
+  Workspace count(nullptr, 0);
+  double* xh[32] = {};
+  double* yh[32] = {};
+  double *xr = nullptr, *W = nullptr;
+  size_t cap = 0;
+  matvec_temporaries(h, h.plan.n, nc, trans, [&](size_t d) { return count.take(d); }, &xr, &cap, xh, yh, &W);
+  return count.used() / sizeof(double);
+}
+
 void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt,
-                 int nc, bool trans) {
+                 int nc, bool trans, Workspace* ws) {
   const int64_t n = h.plan.n;
   const int D = h.plan.depth;
   const int nleaves = 1 << D;
   if (nc <= 0) return;
   if (nc > 64) throw Error(H2_ERR_ARG, "matvec_tree: at most 64 columns");
+  if (D > 30) throw Error(H2_ERR_ARG, "matvec_tree: tree too deep");
   // A symmetric build is its own transpose.  For a two-sided one, A^T x runs
   // up the row bases, applies B_{b,s}^T and goes down the column bases.
   trans = trans && h.two_sided();
   const std::vector<Level>& up = trans ? h.lv : h.col_levels();  // x_hat = (input-side basis)^T x
   const std::vector<Level>& dn = trans ? h.col_levels() : h.lv;  // y += (output-side basis) y_hat
-  BsrScratch xr;  // sized for the leaf rows, the largest row space
-  xr.get(std::max<int64_t>(ldxt, n), nc, s);
+  // temporaries: from the caller's workspace, else stream-ordered allocations
+  DevArray<double> owned[2 * 32 + 2];
+  int n_owned = 0;
+  auto take = [&](size_t count) -> double* {
+    if (ws) return ws->take(count);
+    owned[n_owned].alloc(count, s);
+    return owned[n_owned++].get();
+  };
+  double* xh[32] = {};
+  double* yh[32] = {};
+  double *xrp = nullptr, *W = nullptr;
+  size_t xr_cap = 0;
+  matvec_temporaries(h, ldxt, nc, trans, take, &xrp, &xr_cap, xh, yh, &W);
   if (h.top <= D) {
-    std::vector<DevArray<double>> xh(D + 1), yh(D + 1);
-    for (int t = h.top; t <= D; ++t) {
-      xh[t].alloc(size_t(up[t].koff_h.back()) * nc, s);
-      yh[t].alloc(size_t(dn[t].koff_h.back()) * nc, s);
-    }
     for (int t = D; t >= h.top; --t) {  // upsweep
       const Level& L = up[t];
       const int64_t M = L.koff_h.back();
-      const double* src = t == D ? xt : xh[t + 1].get();
+      const double* src = t == D ? xt : xh[t + 1];
       const int64_t lds = t == D ? ldxt : up[t + 1].koff_h.back();
       H2_HIP(h2dev::shrink_up(s, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(),
-                              L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t].get(), M, nc));
-      H2_HIP(h2dev::fill_zero(s, yh[t].get(), dn[t].koff_h.back() * nc));
+                              L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t], M, nc));
+      H2_HIP(h2dev::fill_zero(s, yh[t], dn[t].koff_h.back() * nc));
     }
     for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b (or B_{b,s}^T)
       const Level& L = dn[t];
       const Level& C = up[t];
       const Level& R = h.lv[t];  // lists and blocks are stored with the row side
-      double* xrp = xr.get(C.koff_h.back(), nc, s);
       H2_HIP(h2dev::bsr_gemm2(s, L.nn, R.fptr.get(), R.fidx.get(), L.koff.get(), C.koff.get(),
-                              trans ? h.tpos[t].get() : nullptr, R.boff.get(), R.B.get(), xh[t].get(),
-                              C.koff_h.back(), yh[t].get(), L.koff_h.back(), nc, 1.0,
-                              std::max({L.max_k, C.max_k, 1}), xrp, xr.cap()));
+                              trans ? h.tpos[t].get() : nullptr, R.boff.get(), R.B.get(), xh[t],
+                              C.koff_h.back(), yh[t], L.koff_h.back(), nc, 1.0,
+                              std::max({L.max_k, C.max_k, 1}), xrp, xr_cap));
     }
     for (int t = h.top; t <= D; ++t) {  // downsweep
       const Level& L = dn[t];
-      double* dst = t == D ? yt : yh[t + 1].get();
+      double* dst = t == D ? yt : yh[t + 1];
       const int64_t ldd = t == D ? ldyt : dn[t + 1].koff_h.back();
-      H2_HIP(h2dev::expand(s, L.nn, L.rowoff.get(), L.koff.get(), L.U.get(), L.uoff.get(), yh[t].get(),
+      H2_HIP(h2dev::expand(s, L.nn, L.rowoff.get(), L.koff.get(), L.U.get(), L.uoff.get(), yh[t],
                            L.koff_h.back(), dst, ldd, nc));
     }
   }
   int leaf_max = 0;
   for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
-  double* xrp = xr.get(ldxt, nc, s);
   H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,
-                         ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr.cap()));
+                         ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr_cap));
   if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b (U, V swapped for A^T)
     const double* left = trans ? h.lrV.get() : h.lrU.get();
     const double* right = trans ? h.lrU.get() : h.lrV.get();
-    DevArray<double> W;
-    W.alloc(size_t(nleaves) * h.lr_rank * nc, s);
-    H2_HIP(h2dev::lr_leaf_project(s, nleaves, h.leafoff.get(), right, n, h.lr_rank, xt, ldxt, nc, W.get()));
+    H2_HIP(h2dev::lr_leaf_project(s, nleaves, h.leafoff.get(), right, n, h.lr_rank, xt, ldxt, nc, W));
     H2_HIP(h2dev::lr_apply(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), n, left, n, h.lr_rank,
-                           W.get(), nc, yt, ldyt, 1.0));
+                           W, nc, yt, ldyt, 1.0));
   }
 }
 
@@ -812,6 +845,33 @@ void export_plan_part(const h2::Plan& p, int32_t part, int32_t depth, void* dst,
 
 }  // namespace
 
+// ------------------------------------------- no-allocation product scratch
+// h2_matvec_noalloc keeps its temporaries in this array instead of allocating.
+// Each device holds its own copy (placed when the code object is loaded) until
+// the process ends.  In host code the array's name is a host-side stand-in:
+// kernels get the device address that hipGetSymbolAddress returned for the
+// current device, looked up once per device when a context is created.
+namespace {
+constexpr size_t kNoAllocScratchBytes = H2_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `device`'s scratch array; `device` must be current.
+void* scratch_address(int device) {
+  H2_REQUIRE(device >= 0 && device < kMaxDevices, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    H2_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    H2_REQUIRE(ptr != nullptr, "no device address for the scratch array");
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 // =================================================================== C ABI
 
 extern "C" {
@@ -859,6 +919,7 @@ h2_status h2_ctx_create(int device, void* stream, h2_ctx** out) {
     H2_HIP(hipSetDevice(device));
     auto c = std::make_unique<h2_ctx>();
     c->device = device;
+    c->scratch = scratch_address(device);
     c->stream = static_cast<hipStream_t>(stream);
     int lds = 0;
     H2_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
@@ -1008,6 +1069,47 @@ h2_status h2_matvec(h2_ctx* ctx, const h2_matrix* hm, int32_t trans, int32_t nrh
       H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), true, yt.get(), n, y + int64_t(c0) * ldy, ldy, nc));
     }
     // temporaries are released stream-ordered; inputs stay valid until the stream passes this point
+  });
+}
+
+h2_status h2_matvec_noalloc(h2_ctx* ctx, const h2_matrix* hm, int32_t trans, int32_t nrhs, const double* x,
+                            int64_t ldx, double* y, int64_t ldy) {
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr && hm != nullptr, "NULL argument");
+    H2_REQUIRE(trans == 0 || trans == 1, "trans must be 0 or 1");
+    const h2_matrix& h = *hm;
+    const int64_t n = h.plan.n;
+    H2_REQUIRE(nrhs >= 0, "nrhs < 0");
+    if (nrhs == 0) return;
+    H2_REQUIRE(x && y, "NULL vector");
+    H2_REQUIRE(ldx >= n && ldy >= n, "ld < n");
+    H2_REQUIRE(ctx->scratch != nullptr, "context has no scratch array");
+    H2_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    // the widest column chunk (<= 64) whose temporaries fit: tree-ordered x
+    // and y, then matvec_tree's own
+    auto need = [&](int nc) {
+      return 2 * ((size_t(n) * nc * sizeof(double) + 255) & ~size_t(255)) +
+             matvec_tree_scratch(h, nc, trans != 0) * sizeof(double);
+    };
+    int chunk = std::min(64, nrhs);
+    while (chunk > 1 && need(chunk) > kNoAllocScratchBytes) --chunk;
+    if (need(chunk) > kNoAllocScratchBytes)
+      throw Error(H2_ERR_ARG, "h2_matvec_noalloc: one column needs " + std::to_string(need(1)) +
+                                  " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
+                                  " bytes it has (use h2_matvec)");
+    char* base = static_cast<char*>(ctx->scratch);
+    Workspace io(base, kNoAllocScratchBytes);
+    double* xt = io.take(size_t(n) * chunk);
+    double* yt = io.take(size_t(n) * chunk);
+    for (int c0 = 0; c0 < nrhs; c0 += chunk) {
+      const int nc = std::min(chunk, nrhs - c0);
+      Workspace tree(base + io.used(), kNoAllocScratchBytes - io.used());
+      H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), false, x + int64_t(c0) * ldx, ldx, xt, n, nc));
+      H2_HIP(h2dev::fill_zero(s, yt, n * nc));
+      matvec_tree(h, s, xt, n, yt, n, nc, trans != 0, &tree);
+      H2_HIP(h2dev::permute_rows(s, n, h.perm.get(), true, yt, n, y + int64_t(c0) * ldy, ldy, nc));
+    }
   });
 }
 

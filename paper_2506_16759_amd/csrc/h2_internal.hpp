@@ -311,12 +311,35 @@ class PrefixConvTest {
 
 struct h2_matrix;
 namespace h2i {
+// Bump allocator over device memory the caller owns: take() hands out
+// consecutive 256-byte aligned slices and never allocates.  With base ==
+// nullptr it only counts (used() is then the size a later run needs).
+class Workspace {
+ public:
+  Workspace(void* base, size_t cap_bytes) : base_(static_cast<char*>(base)), cap_(cap_bytes) {}
+  double* take(size_t doubles) {
+    const size_t bytes = (doubles * sizeof(double) + 255) & ~size_t(255);
+    if (base_ && used_ + bytes > cap_) throw Error(H2_ERR_ARG, "workspace exhausted");
+    double* p = base_ ? reinterpret_cast<double*>(base_ + used_) : nullptr;
+    used_ += bytes;
+    return p;
+  }
+  size_t used() const { return used_; }
+
+ private:
+  char* base_;
+  size_t cap_, used_ = 0;
+};
+
 // yt += A xt (or A^T xt when trans) for nc <= 64 columns, both in TREE order
 // (ld >= n): the standard H^2 product (upsweep through the column bases,
 // couplings, downsweep through the row bases) plus the near field.
-// Stream-ordered on s.
+// Stream-ordered on s.  Temporaries come from ws when given (no allocation),
+// else from the stream-ordered pools.
 void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt, int nc,
-                 bool trans = false);
+                 bool trans = false, Workspace* ws = nullptr);
+// Doubles of workspace matvec_tree takes for nc columns with ldxt = n.
+size_t matvec_tree_scratch(const h2_matrix& h, int nc, bool trans);
 }  // namespace h2i
 
 struct h2_ctx {
@@ -324,6 +347,7 @@ struct h2_ctx {
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // created on first use, default priority, kept until h2_ctx_destroy
   size_t lds_limit = 65536;
+  void* scratch = nullptr;  // device address of this device's no-allocation scratch array
 };
 
 struct h2_plan {
