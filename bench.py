@@ -49,33 +49,88 @@ def measured_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(w, samples_used: int, rows: int = 2048):
-    """The oracle's dense sketch on a sample of rows, scaled to the full pass count."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(w, sketch_passes: int, rows: int = 2048):
+    """The oracle (plain NumPy FP64, never tuned) timed on this host.
+
+    value: the oracle's time for the benchmarked 131072-point build, estimated
+    from two bounded measurements on the same workload recipe, one thread:
+      * its dense sketch of `rows` of the N rows x d0 columns, scaled to all
+        rows and to the build's sketch passes (each pass evaluates all N^2
+        kernel entries, which dominates the time);
+      * everything else, from a full oracle build of the same recipe at
+        n = 16384 minus that build's own sketch time, scaled by N / 16384 (the
+        construction outside the sketch is O(n) in the paper's analysis).
+    measured: full oracle builds of the 4096-point square with 1 and with all
+    threads, and the 16384-point cube build above."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
+    from oracle.build import build_h2
     from oracle.kernels import KernelOperator
     from oracle.philox import gaussian
+    from paper_2506_16759_amd.workloads import SMALL_2D, uniform_points
+
+    nthreads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+    class TimedOperator(KernelOperator):
+        """The oracle's kernel operator with its sketch time accumulated."""
+        sketch_s = 0.0
+
+        def sketch(self, omega):
+            t0 = time.perf_counter()
+            out = super().sketch(omega)
+            self.sketch_s += time.perf_counter() - t0
+            return out
+
+    def full_build(pts, kind, length, wl, threads):
+        op = TimedOperator(pts, kind, length)
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            h = build_h2(op, pts, wl.leaf_size, wl.eta, wl.tol, wl.d0, wl.d_inc, 256, wl.omega_seed)
+            dt = time.perf_counter() - t0
+        return dt, op.sketch_s, h.samples
 
     pts = w.points()
     op = KernelOperator(pts, w.kernel, w.length)
-    sel = np.arange(rows)
     omega = gaussian(w.omega_seed, np.arange(w.n), 0, w.d0)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        op.sketch_rows(sel, omega)
-        dt = time.perf_counter() - t0
-    per_pass_full = dt * (w.n / rows)
-    # the build draws d0 columns, then d_inc per adaptive round; every pass costs the same
-    passes = 1 + max(0, samples_used - w.d0) // w.d_inc
+        op.sketch_rows(np.arange(rows), omega)
+        t_rows = time.perf_counter() - t0
+    sketch_est = t_rows * (w.n / rows) * sketch_passes
+    n_mid = 16384
+    p_mid = uniform_points(n_mid, w.dim, w.point_seed)
+    t_mid1, s_mid1, samples_mid = full_build(p_mid, w.kernel, w.length, w, 1)
+    rest_est = (t_mid1 - s_mid1) * (w.n / n_mid)
+    s2 = SMALL_2D
+    t_c0_1, _, _ = full_build(s2.points(), s2.kernel, s2.length, s2, 1)
+    t_c0_n, _, _ = full_build(s2.points(), s2.kernel, s2.length, s2, nthreads)
     return {
-        "value": per_pass_full * passes,
+        "value": sketch_est + rest_est,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle dense sketch of {rows} of {w.n} rows x {w.d0} columns ({dt:.2f} s), scaled to all rows "
-                   f"and the build's {passes} sketch passes; the oracle's O(N) steps are not included, so this is "
-                   f"a lower bound on its build time"),
+        "sample": (f"one thread: the oracle's dense sketch of {rows} of {w.n} rows x {w.d0} columns ({t_rows:.2f} s) "
+                   f"scaled to all rows and the build's {sketch_passes} sketch passes ({sketch_est:.0f} s), plus "
+                   f"the rest of a full oracle build of the same recipe at n={n_mid} ({t_mid1 - s_mid1:.1f} s of "
+                   f"{t_mid1:.1f} s, {samples_mid} samples) scaled by {w.n // n_mid} ({rest_est:.0f} s)"),
+        "cpu": _cpu_model(),
+        "host_threads": nthreads,
+        "measured_full_builds_s": {
+            f"{s2.name}_threads1": t_c0_1, f"{s2.name}_threads{nthreads}": t_c0_n,
+            f"exp3d_n{n_mid}_threads1": t_mid1,
+        },
     }
 
 
@@ -175,6 +230,150 @@ def bench_update(h2, ctx, n: int = 1 << 17):
     return out
 
 
+def bench_scaling_series(h2, ctx, sizes=(1 << 15, 1 << 16, 1 << 17, 1 << 18)):
+    """Doubling-N series of the FP64 build on the timed workload's recipe
+    (uniform cube, exp(-r/0.2), leaf 64, eta 0.7, tol 1e-6): phase times,
+    stored bytes and the device high-water mark per N (Sec. V-B: everything
+    but the O(N^2) dense sketch grows linearly with N)."""
+    import torch
+
+    from paper_2506_16759_amd.workloads import CUBE_131K, uniform_points
+    w = CUBE_131K
+    out = []
+    for n in sizes:
+        pts = torch.from_numpy(uniform_points(n, w.dim, w.point_seed)).cuda()
+        info = None
+        for _ in range(2):   # the second build's numbers (pool pages mapped by the first)
+            H = h2.build(ctx, pts, w.kernel, w.length, tol=w.tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0,
+                         d_inc=w.d_inc, seed=w.omega_seed)
+            info = H.info()
+            H.close()
+        rec = {"n": n, "samples": info["samples"], "sketch_passes": info["sketch_calls"],
+               "rank_range": [info["rank_min"], info["rank_max"]], "near_blocks": info["near_blocks"],
+               "far_blocks": info["far_blocks"], "bytes_dense": info["bytes_dense"],
+               "bytes_coupling": info["bytes_coupling"], "bytes_basis": info["bytes_basis"],
+               "bytes_peak": info["bytes_peak"],
+               "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
+        rec["non_sketch_ms"] = round(info["t_total"] - info["t_sample"], 3)
+        out.append(rec)
+        print(f"[bench] series n={n}: {info['t_total']:.1f} ms (sketch {info['t_sample']:.1f}), "
+              f"peak {info['bytes_peak'] / 1e9:.2f} GB", file=sys.stderr, flush=True)
+    return out
+
+
+def _power_norm_ratio(apply_diff, apply_ref, n, iters=12, seed=7):
+    """||A_diff||_2 / ||A_ref||_2 by power iteration on both symmetric operators
+    (Sec. V-A measures the error this way against the sampler)."""
+    import torch
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    norms = []
+    for apply in (apply_diff, apply_ref):
+        x = torch.randn(n, dtype=torch.float64, device="cuda", generator=g)
+        nrm = 0.0
+        for _ in range(iters):
+            x = x / torch.linalg.norm(x)
+            x = apply(x)
+            nrm = float(torch.linalg.norm(x))
+        norms.append(nrm)
+    return norms[0] / norms[1]
+
+
+def bench_table2(h2, ctx, n=1 << 18):
+    """Table II's setting at one GPU: the black box is the product with an
+    existing H^2 matrix (Sec. V-A), entries come from the kernel, N = 2^18
+    uniform points in the cube, tol 1e-6; fixed sample size d = leaf size
+    (Sec. III-A, no convergence test) against adaptive sampling with blocks of
+    32 columns (Sec. III-B), leaf 256 and 128; covariance exp(-r/0.2) and the
+    Helmholtz volume-IE kernel cos(3r)/r.  The black-box matrix is this
+    library's own H^2 matrix of the kernel built from the dense sketch at tol
+    1e-8, leaf 64.  Error: relative 2-norm distance to the black box by power
+    iteration."""
+    import torch
+
+    from paper_2506_16759_amd.workloads import uniform_points
+    pts = torch.from_numpy(uniform_points(n, 3, 1)).cuda()
+    rows = []
+    for prob, kind, par in (("covariance exp(-r/0.2)", "exp", 0.2), ("helmholtz cos(3r)/r", "helmholtz", 3.0)):
+        kw = dict(wavenumber=par) if kind == "helmholtz" else dict(length=par)
+        t0 = time.perf_counter()
+        Hbb = h2.build(ctx, pts, kind, tol=1e-8, leaf_size=64, **kw)
+        bb_info = Hbb.info()
+        print(f"[bench] table2 {prob}: black box built in {(time.perf_counter() - t0) * 1e3:.0f} ms, "
+              f"{bb_info['samples']} samples", file=sys.stderr, flush=True)
+        for leaf in (256, 128):
+            for mode in ("fixed", "adaptive"):
+                d0, dinc = (leaf, 0) if mode == "fixed" else (32, 32)
+                times, info, H = [], None, None
+                for rep in range(2):
+                    if H is not None:
+                        H.close()
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    H = h2.build(ctx, pts, kind, sketch=Hbb, tol=1e-6, leaf_size=leaf, d0=d0, d_inc=dinc,
+                                 d_max=256, seed=1001, **kw)
+                    torch.cuda.synchronize()
+                    times.append((time.perf_counter() - t0) * 1e3)
+                    info = H.info()
+                err = _power_norm_ratio(lambda x: H.matvec(x) - Hbb.matvec(x), Hbb.matvec, n)
+                stored = info["bytes_dense"] + info["bytes_coupling"] + info["bytes_basis"]
+                rec = {"problem": prob, "mode": mode, "leaf": leaf, "sample_block": d0 if mode == "fixed" else 32,
+                       "total_samples": info["samples"], "build_ms": times[-1], "device_ms": info["t_total"],
+                       "rank_range": [info["rank_min"], info["rank_max"]], "stored_gb": stored / 1e9,
+                       "peak_gb": info["bytes_peak"] / 1e9, "rel_error_2norm": err,
+                       "sketch_calls": info["sketch_calls"],
+                       "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
+                rows.append(rec)
+                print(f"[bench] table2 {prob} leaf {leaf} {mode}: {times[-1]:.1f} ms, samples {info['samples']}, "
+                      f"ranks {info['rank_min']}..{info['rank_max']}, {stored / 1e9:.2f} GB, error {err:.3e}",
+                      file=sys.stderr, flush=True)
+                H.close()
+        Hbb.close()
+    return rows
+
+
+def first_pass_columns(h2, w) -> int:
+    """Columns of a build's first sketch pass: d0 plus the default look-ahead."""
+    o = h2.opts_default()
+    return min(w.d0 + o.sketch_ahead, o.d_max)
+
+
+def load_goldens() -> dict:
+    """The oracle's stored results for the benchmarked cube (written by
+    tests/golden/make_cube_golden.py, which runs only the oracle), by tol."""
+    out = {}
+    gdir = os.path.join(ROOT, "tests", "golden")
+    for name in sorted(os.listdir(gdir)):
+        if name.startswith("cube_exp3d_n131072_tol") and name.endswith(".json"):
+            g = json.load(open(os.path.join(gdir, name)))
+            out[float(g["tol"])] = g
+    return out
+
+
+def sampled_errors(H, golden: dict, tol: float) -> dict:
+    """Relative error of the built matrix's product on the stored sampled rows:
+    against the exact kernel rows, and against the FP64 oracle's H^2 matrix
+    built at the same tolerance (when the oracle's result is stored)."""
+    import numpy as np
+    import torch
+
+    from paper_2506_16759_amd.workloads import gaussian_vectors
+    if not golden:
+        return {}
+    g0 = next(iter(golden.values()))
+    rows = np.array(g0["rows"])
+    x = gaussian_vectors(g0["n"], 4, g0["x_seed"])
+    xt = torch.from_numpy(np.ascontiguousarray(x.T)).cuda().T
+    y = H.matvec(xt).cpu().numpy()[rows]
+    y_exact = np.array(g0["y_exact"])
+    out = {"rows": len(rows), "vs_exact": float(np.linalg.norm(y - y_exact) / np.linalg.norm(y_exact))}
+    g = golden.get(float(tol))
+    if g is not None:
+        y_or = np.array(g["y_h2"])
+        out["vs_fp64_oracle"] = float(np.linalg.norm(y - y_or) / np.linalg.norm(y_or))
+        out["oracle_samples"] = g["samples"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +386,10 @@ def main():
                     help="skip the 64-problem batched build and the low-rank update measurements")
     ap.add_argument("--only-extras", action="store_true",
                     help="only the 64-problem batched build and the low-rank update (printed as one JSON line)")
+    ap.add_argument("--scaling-series", action="store_true",
+                    help="only the doubling-N series of the FP64 build (2^15..2^18 points), one JSON line")
+    ap.add_argument("--table2", action="store_true",
+                    help="only the fixed-vs-adaptive runs of Table II's setting (2^18 points, H^2 black box)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
@@ -207,7 +410,8 @@ def main():
     if args.profile_kernels:
         ctx = h2.Context(0)
         pts = torch.from_numpy(w.points()).cuda()
-        omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, w.d0)
+        nc = first_pass_columns(h2, w)
+        omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, nc)
         for prec in (h2.FP64, h2.FP32, h2.BF16X3, h2.FP32E, h2.BF16X6):
             for _ in range(2):
                 h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=prec)
@@ -218,6 +422,12 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_kernels": "done", "copy_bytes": a.numel() * 8}), flush=True)
         return
+    if args.scaling_series:
+        print(json.dumps({"scaling_series": bench_scaling_series(h2, h2.Context(0))}), flush=True)
+        return
+    if args.table2:
+        print(json.dumps({"table2": bench_table2(h2, h2.Context(0))}), flush=True)
+        return
     if args.only_extras:
         ctx = h2.Context(0)
         upd = bench_update(h2, ctx)
@@ -227,6 +437,8 @@ def main():
     ctx = h2.Context(0)
     pts = torch.from_numpy(w.points()).cuda()
     opts = h2.opts_default(tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed)
+
+    golden = load_goldens()
 
     def timed_builds(o, label, steps, warmup):
         infos = []
@@ -244,6 +456,8 @@ def main():
             torch.cuda.synchronize()
             times.append(time.perf_counter() - ts)
             infos.append(H.info())
+            if i == steps - 1:   # accuracy of the last build (outside its timed interval)
+                infos[-1]["errors"] = sampled_errors(H, golden, o.tol)
             H.close()
             print(f"[bench] {label} step {i} {times[-1] * 1e3:.1f} ms", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -257,14 +471,16 @@ def main():
     # ~2^-17 relative error), with FP64 at 1e-4 for comparison
     mixed = {}
     for name, prec, mtol in (("bf16x6", h2.BF16X6, tol), ("fp32", h2.FP32, tol), ("fp32e", h2.FP32E, tol),
-                             ("fp64_tol1e-4", h2.FP64, 1e-4), ("bf16x3_tol1e-4", h2.BF16X3, 1e-4)):
+                             ("fp64_tol1e-4", h2.FP64, 1e-4), ("bf16x3_tol1e-4", h2.BF16X3, 1e-4),
+                             ("fp64_tol1e-8", h2.FP64, 1e-8), ("fp32e_tol1e-8", h2.FP32E, 1e-8)):
         o = h2.opts_default(tol=mtol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed,
                             precision=prec)
         try:
             mms, mtimes, minfo = timed_builds(o, name, max(1, args.steps // 2 + 1), 1)
             mixed[name] = {"tol": mtol, "ms_per_build": mms, "samples": minfo["samples"],
                            "adaptive_rounds": minfo["rounds"], "rank_range": [minfo["rank_min"], minfo["rank_max"]],
-                           "sketch_phase_ms": minfo["t_sample"]}
+                           "sketch_phase_ms": minfo["t_sample"], "sketch_passes": minfo["sketch_calls"],
+                           "errors": minfo["errors"]}
             if mtol == tol:
                 mixed[name]["speedup_vs_fp64"] = ms_per_step / mms
         except h2.H2Error as exc:
@@ -273,8 +489,9 @@ def main():
         mixed["bf16x3_tol1e-4"]["speedup_vs_fp64"] = (mixed["fp64_tol1e-4"]["ms_per_build"]
                                                       / mixed["bf16x3_tol1e-4"]["ms_per_build"])
 
-    # dominant kernel: the fused sketch, timed live on the library's stream
-    nc = w.d0
+    # dominant kernel of the timed build: its one fused sketch pass (d0 plus
+    # the look-ahead columns), timed live on the library's stream
+    nc = first_pass_columns(h2, w)
     omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, nc)
     h2.sketch(ctx, pts, w.kernel, w.length, omega)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -321,18 +538,22 @@ def main():
         "mixed_vs_fp64_speedup": mixed.get("bf16x6", {}).get("speedup_vs_fp64"),
         "mixed": mixed,
         "samples": info["samples"],
+        "sketch_passes": info["sketch_calls"],
+        "errors": info["errors"],
         "adaptive_rounds": info["rounds"],
         "rank_range": [info["rank_min"], info["rank_max"]],
         "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")},
         "bytes": {"dense": info["bytes_dense"], "coupling": info["bytes_coupling"], "basis": info["bytes_basis"]},
         "roofline": {
-            "kernel": "sketch_f64_kernel<3,exp,32>",
+            "kernel": f"sketch_f64_kernel<3,exp,{nc}>",
             "bound": "alu",
             "achieved": achieved,
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": measured_traffic("sketch_f64_kernel<3,exp,32>"),
+            "traffic": measured_traffic(f"sketch_f64_kernel<3,exp,{nc}>"),
+            "algorithmic_flop_per_launch": sketch_flops_per_entry(w.dim, nc) * entries,
+            "launch_ms": sk_ms,
         },
     }
     if not args.no_extras:
@@ -342,7 +563,8 @@ def main():
         out["batched"] = bench_batched(h2, ctx)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(w, info["samples"])
+        passes = 1 + max(0, info["samples"] - w.d0) // w.d_inc   # the oracle draws d_inc columns per round
+        out["cpu_baseline"] = cpu_baseline(w, passes)
     print(json.dumps(out), flush=True)
 
 

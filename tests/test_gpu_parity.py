@@ -17,6 +17,8 @@ point tolerances:
     samples differ by summation-order rounding, which the triangular solve for
     T amplifies by cond(R11) <~ ||Y|| / delta); products within 1e-10.
 """
+import json
+import os
 import sys
 
 import numpy as np
@@ -25,7 +27,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 import paper_2506_16759_amd as h2
-from paper_2506_16759_amd.workloads import CUBE_131K, SMALL_2D, uniform_points
+from paper_2506_16759_amd.workloads import CUBE_131K, SMALL_2D, gaussian_vectors, uniform_points
 from oracle.build import build_h2
 from oracle.kernels import KernelOperator
 from oracle.philox import gaussian as oracle_gaussian
@@ -304,6 +306,50 @@ def test_full_size_cube_sampled_parity(ctx):
     emv = np.linalg.norm(yh[rows] - kx) / np.linalg.norm(kx)
     _say(f"sampled-row matvec error {emv:.3e}")
     assert emv <= 10 * w.tol
+
+
+CUBE_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cube_exp3d_n131072_tol{:.0e}.json")
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_full_size_cube_matches_oracle_golden(ctx, tol):
+    """The benchmarked 131072-point cube at tol 1e-6 and 1e-8 against the
+    oracle's construction of it (stored by tests/golden/make_cube_golden.py,
+    which runs only the oracle): the same sample count, threshold, top depth
+    and ranks of all 4094 clusters, the same skeleton index sets at every
+    depth (SHA-256 of the SKEL export), and sampled products within 1e-10 of
+    the oracle's H^2 matrix and within 10 tol of the exact kernel."""
+    import hashlib
+    path = CUBE_GOLDEN.format(tol)
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not written yet (tests/golden/make_cube_golden.py)")
+    g = json.load(open(path))
+    w = CUBE_131K
+    _say(f"full size {w.name} tol={tol} against the stored oracle construction")
+    pts = w.points()
+    H = h2.build(ctx, pts, w.kernel, w.length, tol=tol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc,
+                 d_max=g["d_max"], seed=w.omega_seed)
+    info = H.info()
+    _say(f"built: {info['t_total']:.1f} ms samples={info['samples']} (oracle {g['samples']}) "
+         f"ranks={info['rank_min']}..{info['rank_max']}")
+    assert info["samples"] == g["samples"]
+    assert abs(info["delta"] - g["delta"]) <= 1e-12 * g["delta"]
+    assert int(H.export("TOP")[0]) == g["top"]
+    for t, ko in g["ranks"].items():
+        np.testing.assert_array_equal(H.export("RANKS", int(t)), np.array(ko), err_msg=f"ranks at depth {t}")
+    for t, sha in g["skel_sha256"].items():
+        got = hashlib.sha256(H.export("SKEL", int(t)).astype("<i4").tobytes()).hexdigest()
+        assert got == sha, f"skeletons at depth {t}"
+    rows = np.array(g["rows"])
+    x = gaussian_vectors(w.n, 4, g["x_seed"])
+    y = _np(H.matvec(_colmajor_from(x)))[rows]
+    y_or, y_ex = np.array(g["y_h2"]), np.array(g["y_exact"])
+    e_or = np.linalg.norm(y - y_or) / np.linalg.norm(y_or)
+    e_ex = np.linalg.norm(y - y_ex) / np.linalg.norm(y_ex)
+    _say(f"sampled rows: vs oracle H^2 {e_or:.3e}, vs exact kernel {e_ex:.3e}")
+    assert e_or <= 1e-10
+    assert e_ex <= 10 * tol
+    H.close()
 
 
 # ------------------------------------------------------------------ mixed precision
