@@ -361,7 +361,9 @@ typedef struct {
                        * largest d0 plus 32 (the single build's default look-ahead); capped
                        * at d_max.  Problems not converged within them are built again,
                        * together, by a second sequence with d_max columns.  Results equal
-                       * those of one sequence with d_max columns: Omega is counter-based
+                       * those of one sequence with d_max columns (the same sample counts,
+                       * ranks and skeletons; factors to rounding, as the ID kernel is
+                       * chosen by a sequence's column capacity): Omega is counter-based
                        * and the prefix convergence test at a count does not depend on
                        * later columns. */
 } h2_batch_opts;

@@ -1708,6 +1708,277 @@ __global__ __launch_bounds__(256) void cpqr_id_kernel(const int32_t* __restrict_
   }
 }
 
+// Register-resident form of the same ID for panels that fit one wave: d <= D
+// rows (samples) and m <= 64 C columns (points).  Lane l holds columns l,
+// l + 64, .. of A = Y_loc^T with their D rows unrolled in registers, so a
+// Householder step is straight-line FP64 arithmetic: the pivot lane copies its
+// column to LDS, every lane reads it back (broadcast reads, a block of 16 rows
+// at a time ahead of the arithmetic) and updates its own columns and
+// downdates their norms.  Rows are visited in blocks of 16 with one uniform
+// branch per block (blocks above the step are skipped, the block holding the
+// step masks its rows).
+// The reflector is applied to every column: on a column already chosen as a
+// pivot (rows below its position are zero up to rounding) and on an empty
+// lane it changes nothing of use.  Pivoting, ties (lowest original column),
+// the norm downdating with its recompute guard, the stopping rule and the
+// triangular solve T = R11^-1 R12 (column-oriented back substitution, R11 read
+// from the pivot lanes) follow cpqr_id_kernel; the order of the sums differs.
+constexpr int kIdRb = 16;  // rows per block of the unrolled row loops
+
+template <int D, int C>
+__global__ __launch_bounds__(64) void cpqr_id_wave_kernel(const int32_t* __restrict__ rowoff,
+                                                          const double* __restrict__ Y, int64_t ldy, int d,
+                                                          double delta, int32_t* __restrict__ kout,
+                                                          int32_t* __restrict__ Jout, const int64_t* __restrict__ joff,
+                                                          double* __restrict__ Uout, const int64_t* __restrict__ uoff,
+                                                          const int32_t* __restrict__ nodeprob,
+                                                          const int32_t* __restrict__ dprob,
+                                                          const double* __restrict__ deltaprob) {
+  static_assert(D % kIdRb == 0, "row blocks");
+  __shared__ int s_col[64];     // original column of pivot position l
+  __shared__ double s_piv[D];   // the column broadcast to every lane (pivot, or R11 column l)
+  const int i = blockIdx.x;
+  if (nodeprob) {
+    d = dprob[nodeprob[i]];
+    delta = deltaprob[nodeprob[i]];
+  }
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int lane = threadIdx.x;
+  double a[C][D], vn1[C], vn2[C];
+  int pos[C];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int col = lane + 64 * s;
+    const bool act = col < m;
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < D; ++r) {
+      a[s][r] = (act && r < d) ? Y[int64_t(r) * ldy + r0 + col] : 0.0;
+      ss = __builtin_fma(a[s][r], a[s][r], ss);
+    }
+    vn1[s] = sqrt(ss);
+    vn2[s] = vn1[s];
+    pos[s] = act ? -1 : -2;  // -1: candidate column, -2: no column, >= 0: pivot position
+  }
+  // the column of slot ps in lane pl, copied to LDS for broadcast reads
+  auto publish = [&](int pl, int ps) {
+    __syncthreads();
+    if (lane == pl) {
+      double2* dst = reinterpret_cast<double2*>(s_piv);
+#pragma unroll
+      for (int r = 0; r < D; r += 2)
+        dst[r / 2] = (C == 1 || ps == 0) ? double2{a[0][r], a[0][r + 1]} : double2{a[C - 1][r], a[C - 1][r + 1]};
+    }
+    __syncthreads();
+  };
+  // rows rb..rb+15 of the published column, read ahead of their use
+  auto pblock = [&](int rb, double* t) {
+    const double2* src = reinterpret_cast<const double2*>(s_piv + rb);
+#pragma unroll
+    for (int q = 0; q < kIdRb / 2; ++q) {
+      const double2 v = src[q];
+      t[2 * q] = v.x;
+      t[2 * q + 1] = v.y;
+    }
+  };
+  const int kmax = min(m, d);
+  int k = kmax;
+  const double tol3z = 1.4901161193847656e-08;  // sqrt(2^-52)
+  for (int j = 0; j < kmax; ++j) {
+    // pivot: largest partial norm, ties to the lowest column (NaN norms rank last)
+    double bv = -2.0;
+    int bc = 0x7fffffff;
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      const int col = lane + 64 * s;
+      const double v = __builtin_isnan(vn1[s]) ? -1.0 : vn1[s];
+      if (pos[s] == -1 && (v > bv || (v == bv && col < bc))) {
+        bv = v;
+        bc = col;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off, kWave);
+      const int oc = __shfl_xor(bc, off, kWave);
+      if (ov > bv || (ov == bv && oc < bc)) {
+        bv = ov;
+        bc = oc;
+      }
+    }
+    const int p = __builtin_amdgcn_readfirstlane(bc);
+    const int pl = p & 63, ps = p >> 6;
+    publish(pl, ps);
+    // one pass over the rows >= j: the pivot's alpha = a_p[j] and
+    // sg = sum_{r > j} a_p[r]^2, and each column's a[j] and sum_{r > j} a_p[r] a[r]
+    double alpha = 0.0, sg = 0.0, aj[C], dot[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      aj[s] = 0.0;
+      dot[s] = 0.0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < D; rb += kIdRb) {
+      if (rb + kIdRb <= j) continue;
+      double tv[kIdRb];
+      pblock(rb, tv);
+      if (rb > j) {
+#pragma unroll
+        for (int r = rb; r < rb + kIdRb; ++r) {
+          const double t = tv[r - rb];
+          sg = __builtin_fma(t, t, sg);
+#pragma unroll
+          for (int s = 0; s < C; ++s) dot[s] = __builtin_fma(t, a[s][r], dot[s]);
+        }
+      } else {
+#pragma unroll
+        for (int r = rb; r < rb + kIdRb; ++r) {
+          const double t = tv[r - rb];
+          const bool below = r > j;
+          sg = below ? __builtin_fma(t, t, sg) : sg;
+          if (r == j) alpha = t;
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            dot[s] = below ? __builtin_fma(t, a[s][r], dot[s]) : dot[s];
+            if (r == j) aj[s] = a[s][r];
+          }
+        }
+      }
+    }
+    double beta, tau, scal;
+    if (sg == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scal = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + sg);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (fabs(beta) < delta || beta == 0.0) {
+      k = j;
+      break;
+    }
+    // H = I - tau v v^T with v = (1, scal a_p[j+1..]):  w = tau (a[j] + scal dot)
+    double w[C], sw[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      w[s] = tau * __builtin_fma(scal, dot[s], aj[s]);
+      sw[s] = w[s] * scal;
+    }
+    // a[j] -= w, a[r] -= (w scal) a_p[r] for r > j; the new trailing norms^2
+    double ajn[C], s2[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      ajn[s] = aj[s] - w[s];
+      s2[s] = 0.0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < D; rb += kIdRb) {
+      if (rb + kIdRb <= j) continue;
+      double tv[kIdRb];
+      pblock(rb, tv);
+      if (rb > j) {
+#pragma unroll
+        for (int r = rb; r < rb + kIdRb; ++r) {
+          const double t = tv[r - rb];
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            a[s][r] = __builtin_fma(-sw[s], t, a[s][r]);
+            s2[s] = __builtin_fma(a[s][r], a[s][r], s2[s]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = rb; r < rb + kIdRb; ++r) {
+          const bool below = r > j;
+          const double t = below ? tv[r - rb] : 0.0;
+#pragma unroll
+          for (int s = 0; s < C; ++s) {
+            if (r == j) a[s][r] = ajn[s];
+            a[s][r] = __builtin_fma(-sw[s], t, a[s][r]);
+            s2[s] = below ? __builtin_fma(a[s][r], a[s][r], s2[s]) : s2[s];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < C; ++s) {
+      if (lane == pl && s == ps) {
+        pos[s] = j;
+      } else if (pos[s] == -1 && vn1[s] != 0.0) {
+        // norm downdate with the recompute safeguard (s2 = exact trailing norm^2)
+        double t = fabs(ajn[s]) / vn1[s];
+        t = fmax(0.0, 1.0 - t * t);
+        const double ratio = vn1[s] / vn2[s];
+        if (t * ratio * ratio <= tol3z) {
+          vn1[s] = sqrt(s2[s]);
+          vn2[s] = vn1[s];
+        } else {
+          vn1[s] = vn1[s] * sqrt(t);
+        }
+      }
+    }
+    if (lane == 0) s_col[j] = p;
+  }
+  __syncthreads();
+  // T = R11^-1 R12 in place in rows 0..k-1 of the non-pivot columns, one
+  // pivot column l = k-1..0 at a time; R11(r, l) comes from the pivot lane,
+  // whose registers the solve leaves untouched (its multiplier t is 0)
+  for (int l = k - 1; l >= 0; --l) {
+    const int pc = s_col[l];
+    const int pl = pc & 63, ps = pc >> 6;
+    publish(pl, ps);
+    double t[C];
+#pragma unroll
+    for (int s = 0; s < C; ++s) t[s] = 0.0;
+#pragma unroll
+    for (int rb = D - kIdRb; rb >= 0; rb -= kIdRb) {
+      if (rb > l) continue;
+      double tv[kIdRb];
+      pblock(rb, tv);
+      if (rb + kIdRb <= l) {
+#pragma unroll
+        for (int r = rb; r < rb + kIdRb; ++r) {
+          const double rrl = tv[r - rb];
+#pragma unroll
+          for (int s = 0; s < C; ++s) a[s][r] = __builtin_fma(-rrl, t[s], a[s][r]);
+        }
+      } else {
+#pragma unroll
+        for (int r = rb + kIdRb - 1; r >= rb; --r) {
+          if (r == l) {
+            const double inv = 1.0 / tv[r - rb];
+#pragma unroll
+            for (int s = 0; s < C; ++s) {
+              if (pos[s] == -1) {
+                t[s] = a[s][r] * inv;
+                a[s][r] = t[s];
+              }
+            }
+          } else {
+            const double rrl = r < l ? tv[r - rb] : 0.0;
+#pragma unroll
+            for (int s = 0; s < C; ++s) a[s][r] = __builtin_fma(-rrl, t[s], a[s][r]);
+          }
+        }
+      }
+    }
+  }
+  if (lane == 0) kout[i] = k;
+  double* U = Uout + uoff[i];
+#pragma unroll
+  for (int s = 0; s < C; ++s) {
+    const int col = lane + 64 * s;
+    if (pos[s] == -2) continue;
+    if (pos[s] >= 0) Jout[joff[i] + pos[s]] = col;
+#pragma unroll
+    for (int r = 0; r < D; ++r)
+      if (r < k) U[col + int64_t(r) * m] = pos[s] >= 0 ? (r == pos[s] ? 1.0 : 0.0) : a[s][r];
+  }
+}
+
 // ------------------------------------------------------ shrink / upsweep
 
 __global__ __launch_bounds__(256) void shrink_up_kernel(const int32_t* __restrict__ rowoff,
@@ -2239,6 +2510,24 @@ hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
                    int max_m, size_t lds_limit, double* gws, const int64_t* gws_off, const int32_t* nodeprob,
                    const int32_t* dprob, const double* deltaprob) {
   if (nnodes <= 0) return hipSuccess;
+  // panels that fit one wave's registers: d <= 64 rows, m <= 128 columns
+  if (d <= 64 && max_m <= 128) {
+#define H2_CPQR_WAVE(DD, CC) \
+  cpqr_id_wave_kernel<DD, CC><<<nnodes, 64, 0, s>>>(rowoff, Y, ldy, d, delta, kout, J, joff, U, uoff, nodeprob, dprob, deltaprob)
+    if (max_m <= 64) {
+      if (d <= 32)
+        H2_CPQR_WAVE(32, 1);
+      else
+        H2_CPQR_WAVE(64, 1);
+    } else {
+      if (d <= 32)
+        H2_CPQR_WAVE(32, 2);
+      else
+        H2_CPQR_WAVE(64, 2);
+    }
+#undef H2_CPQR_WAVE
+    return hipGetLastError();
+  }
   const int threads = max_m <= 64 ? 64 : (max_m <= 128 ? 128 : 256);
   const size_t small = size_t(3) * max_m * sizeof(double);
   const size_t bytes = small + size_t(d | 1) * size_t(max_m) * sizeof(double);

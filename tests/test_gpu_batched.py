@@ -210,9 +210,12 @@ def test_batched_graph_replays_are_identical(ctx):
 
 def test_batched_second_pass_equals_one_pass(ctx):
     """Problems not converged within the first launch sequence's columns are
-    built again with d_max columns; every problem's factors equal, bit for bit,
-    those of one sequence with d_max columns (Omega is counter-based, the
-    prefix test at a count ignores later columns, problems are independent)."""
+    built again with d_max columns; every problem's construction equals that of
+    one sequence with d_max columns (Omega is counter-based, the prefix test at
+    a count ignores later columns, problems are independent): the same sample
+    counts, ranks and skeletons, and factors to rounding (the ID kernel is
+    chosen by the sequence's column capacity, so the two sequences may sum in
+    different orders)."""
     probs = _problems(MIXED_BATCH)
     _say("batched: first pass of 32 columns + second pass vs one pass of 96")
     m1, i1 = h2.build_batched(ctx, probs, d_max=96, first_pass=96, return_info=True)
@@ -224,9 +227,12 @@ def test_batched_second_pass_equals_one_pass(ctx):
     for a, b in zip(m1, m2):
         assert a.info()["samples"] == b.info()["samples"]
         fa, fb = _factors(a), _factors(b)
-        for key in ("ranks", "skel", "basis", "coupling"):
+        for key in ("ranks", "skel"):
             for u, v in zip(fa[key], fb[key]):
                 np.testing.assert_array_equal(u, v)
+        for key in ("basis", "coupling"):
+            for u, v in zip(fa[key], fb[key]):
+                np.testing.assert_allclose(u, v, rtol=0, atol=1e-9 * max(np.abs(v).max(initial=0.0), 1e-300))
         np.testing.assert_array_equal(fa["dense"], fb["dense"])
     for H in m1 + m2:
         H.close()
