@@ -278,56 +278,68 @@ def _power_norm_ratio(apply_diff, apply_ref, n, iters=12, seed=7):
     return norms[0] / norms[1]
 
 
-def bench_table2(h2, ctx, n=1 << 18):
-    """Table II's setting at one GPU: the black box is the product with an
-    existing H^2 matrix (Sec. V-A), entries come from the kernel, N = 2^18
-    uniform points in the cube, tol 1e-6; fixed sample size d = leaf size
-    (Sec. III-A, no convergence test) against adaptive sampling with blocks of
-    32 columns (Sec. III-B), leaf 256 and 128; covariance exp(-r/0.2) and the
-    Helmholtz volume-IE kernel cos(3r)/r.  The black-box matrix is this
-    library's own H^2 matrix of the kernel built from the dense sketch at tol
-    1e-8, leaf 64.  Error: relative 2-norm distance to the black box by power
-    iteration."""
+TABLE2_PROBLEMS = {"covariance": ("covariance exp(-r/0.2)", "exp", 0.2),
+                   "helmholtz": ("helmholtz cos(3r)/r", "helmholtz", 3.0)}
+
+
+def bench_table2_one(h2, ctx, problem: str, leaf: int, mode: str, n=1 << 18):
+    """One configuration of Table II's setting: the black box is the product
+    with an existing H^2 matrix (Sec. V-A), entries come from the kernel,
+    N = 2^18 uniform points in the cube, tol 1e-6; fixed sample size d = leaf
+    size (Sec. III-A, no convergence test) or adaptive sampling with blocks of
+    32 columns (Sec. III-B).  The black-box matrix is this library's own H^2
+    matrix of the kernel built from the dense sketch at tol 1e-8, leaf 64.
+    Error: relative 2-norm distance to the black box by power iteration."""
     import torch
 
     from paper_2506_16759_amd.workloads import uniform_points
+    prob, kind, par = TABLE2_PROBLEMS[problem]
+    kw = dict(wavenumber=par) if kind == "helmholtz" else dict(length=par)
     pts = torch.from_numpy(uniform_points(n, 3, 1)).cuda()
-    rows = []
-    for prob, kind, par in (("covariance exp(-r/0.2)", "exp", 0.2), ("helmholtz cos(3r)/r", "helmholtz", 3.0)):
-        kw = dict(wavenumber=par) if kind == "helmholtz" else dict(length=par)
+    t0 = time.perf_counter()
+    Hbb = h2.build(ctx, pts, kind, tol=1e-8, leaf_size=64, **kw)
+    bb_ms = (time.perf_counter() - t0) * 1e3
+    d0, dinc = (leaf, 0) if mode == "fixed" else (32, 32)
+    times, info, H = [], None, None
+    for _ in range(2):   # the second build is reported (the first maps the memory)
+        if H is not None:
+            H.close()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        Hbb = h2.build(ctx, pts, kind, tol=1e-8, leaf_size=64, **kw)
-        bb_info = Hbb.info()
-        print(f"[bench] table2 {prob}: black box built in {(time.perf_counter() - t0) * 1e3:.0f} ms, "
-              f"{bb_info['samples']} samples", file=sys.stderr, flush=True)
+        H = h2.build(ctx, pts, kind, sketch=Hbb, tol=1e-6, leaf_size=leaf, d0=d0, d_inc=dinc, d_max=256, seed=1001,
+                     **kw)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        info = H.info()
+    err = _power_norm_ratio(lambda x: H.matvec(x) - Hbb.matvec(x), Hbb.matvec, n)
+    stored = info["bytes_dense"] + info["bytes_coupling"] + info["bytes_basis"]
+    return {"problem": prob, "mode": mode, "leaf": leaf, "sample_block": d0 if mode == "fixed" else 32,
+            "total_samples": info["samples"], "build_ms": times[-1], "device_ms": info["t_total"],
+            "rank_range": [info["rank_min"], info["rank_max"]], "stored_gb": stored / 1e9,
+            "peak_gb": info["bytes_peak"] / 1e9, "rel_error_2norm": err, "sketch_calls": info["sketch_calls"],
+            "black_box": {"samples": Hbb.info()["samples"], "build_ms": bb_ms},
+            "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
+
+
+def bench_table2():
+    """Every configuration of Table II's setting, each in a fresh process: a
+    ~100 GB matrix next to the ~80 GB black box leaves the memory pools in a
+    state that depends on the previous builds, so every configuration starts
+    from a clean device (the first of its two builds maps the memory)."""
+    import subprocess
+    rows = []
+    for problem in TABLE2_PROBLEMS:
         for leaf in (256, 128):
             for mode in ("fixed", "adaptive"):
-                d0, dinc = (leaf, 0) if mode == "fixed" else (32, 32)
-                times, info, H = [], None, None
-                for rep in range(2):
-                    if H is not None:
-                        H.close()
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    H = h2.build(ctx, pts, kind, sketch=Hbb, tol=1e-6, leaf_size=leaf, d0=d0, d_inc=dinc,
-                                 d_max=256, seed=1001, **kw)
-                    torch.cuda.synchronize()
-                    times.append((time.perf_counter() - t0) * 1e3)
-                    info = H.info()
-                err = _power_norm_ratio(lambda x: H.matvec(x) - Hbb.matvec(x), Hbb.matvec, n)
-                stored = info["bytes_dense"] + info["bytes_coupling"] + info["bytes_basis"]
-                rec = {"problem": prob, "mode": mode, "leaf": leaf, "sample_block": d0 if mode == "fixed" else 32,
-                       "total_samples": info["samples"], "build_ms": times[-1], "device_ms": info["t_total"],
-                       "rank_range": [info["rank_min"], info["rank_max"]], "stored_gb": stored / 1e9,
-                       "peak_gb": info["bytes_peak"] / 1e9, "rel_error_2norm": err,
-                       "sketch_calls": info["sketch_calls"],
-                       "phases_ms": {k[2:]: round(info[k], 3) for k in info if k.startswith("t_")}}
+                cmd = [sys.executable, os.path.abspath(__file__), "--table2-one", f"{problem},{leaf},{mode}"]
+                res = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+                if res.returncode != 0:
+                    raise RuntimeError(f"{' '.join(cmd)} failed ({res.returncode}):\n{res.stderr[-2000:]}")
+                rec = json.loads(res.stdout.strip().splitlines()[-1])
                 rows.append(rec)
-                print(f"[bench] table2 {prob} leaf {leaf} {mode}: {times[-1]:.1f} ms, samples {info['samples']}, "
-                      f"ranks {info['rank_min']}..{info['rank_max']}, {stored / 1e9:.2f} GB, error {err:.3e}",
-                      file=sys.stderr, flush=True)
-                H.close()
-        Hbb.close()
+                print(f"[bench] table2 {rec['problem']} leaf {leaf} {mode}: {rec['build_ms']:.1f} ms, samples "
+                      f"{rec['total_samples']}, ranks {rec['rank_range'][0]}..{rec['rank_range'][1]}, "
+                      f"{rec['stored_gb']:.2f} GB, error {rec['rel_error_2norm']:.3e}", file=sys.stderr, flush=True)
     return rows
 
 
@@ -390,6 +402,7 @@ def main():
                     help="only the doubling-N series of the FP64 build (2^15..2^18 points), one JSON line")
     ap.add_argument("--table2", action="store_true",
                     help="only the fixed-vs-adaptive runs of Table II's setting (2^18 points, H^2 black box)")
+    ap.add_argument("--table2-one", default=None, help=argparse.SUPPRESS)   # problem,leaf,mode (child process)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
@@ -426,7 +439,11 @@ def main():
         print(json.dumps({"scaling_series": bench_scaling_series(h2, h2.Context(0))}), flush=True)
         return
     if args.table2:
-        print(json.dumps({"table2": bench_table2(h2, h2.Context(0))}), flush=True)
+        print(json.dumps({"table2": bench_table2()}), flush=True)
+        return
+    if args.table2_one:
+        problem, leaf, mode = args.table2_one.split(",")
+        print(json.dumps(bench_table2_one(h2, h2.Context(0), problem, int(leaf), mode)), flush=True)
         return
     if args.only_extras:
         ctx = h2.Context(0)
