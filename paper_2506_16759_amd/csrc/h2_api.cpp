@@ -67,7 +67,29 @@ void call_entries(h2_entry_fn fn, void* user, int nblocks, const int32_t* idx, c
   if (rc != 0) throw Error(H2_ERR_CALLBACK, "entry callback returned " + std::to_string(rc));
 }
 
+namespace {
+struct HugeBlock {
+  void* p;
+  size_t bytes;
+  hipStream_t s;
+  int dev;
+};
+std::mutex g_huge_mu;
+std::vector<HugeBlock> g_huge_free;         // released, kept for reuse
+std::map<void*, HugeBlock> g_huge_live;     // handed out (bytes = the block's own size)
+std::map<int, int64_t> g_huge_taken;        // bytes handed out from the cache since the last peak reset
+}  // namespace
+
+int64_t huge_taken(int device) {
+  std::lock_guard<std::mutex> lock(g_huge_mu);
+  return g_huge_taken[device];
+}
+
 void pool_peak_reset(int device) {
+  {
+    std::lock_guard<std::mutex> lock(g_huge_mu);
+    g_huge_taken[device] = 0;
+  }
   uint64_t zero = 0;
   hipMemPool_t def = nullptr;
   if (hipDeviceGetDefaultMemPool(&def, device) == hipSuccess)
@@ -106,7 +128,64 @@ hipMemPool_t large_pool() {
   return pool;
 }
 
+void* huge_take(size_t bytes, hipStream_t s) {
+  int dev = 0;
+  H2_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_huge_mu);
+  // the smallest cached block that holds the request with at most 1/8 to spare
+  size_t best = g_huge_free.size();
+  for (size_t b = 0; b < g_huge_free.size(); ++b) {
+    const HugeBlock& h = g_huge_free[b];
+    if (h.dev == dev && h.s == s && h.bytes >= bytes && h.bytes - bytes <= bytes / 8 &&
+        (best == g_huge_free.size() || h.bytes < g_huge_free[best].bytes))
+      best = b;
+  }
+  if (best == g_huge_free.size()) return nullptr;
+  const HugeBlock h = g_huge_free[best];
+  g_huge_free.erase(g_huge_free.begin() + static_cast<std::ptrdiff_t>(best));
+  g_huge_live[h.p] = h;
+  g_huge_taken[dev] += static_cast<int64_t>(h.bytes);
+  return h.p;
+}
+
+bool huge_put(void* p, hipStream_t s) {
+  std::lock_guard<std::mutex> lock(g_huge_mu);
+  auto it = g_huge_live.find(p);
+  if (it == g_huge_live.end()) return false;
+  HugeBlock h = it->second;
+  g_huge_live.erase(it);
+  h.s = s;  // the block's last use is ordered on s
+  g_huge_free.push_back(h);
+  return true;
+}
+
+void huge_trim(hipStream_t s) {
+  std::vector<HugeBlock> drop;
+  {
+    std::lock_guard<std::mutex> lock(g_huge_mu);
+    for (size_t b = 0; b < g_huge_free.size();) {
+      if (!s || g_huge_free[b].s == s) {
+        drop.push_back(g_huge_free[b]);
+        g_huge_free.erase(g_huge_free.begin() + static_cast<std::ptrdiff_t>(b));
+      } else {
+        ++b;
+      }
+    }
+  }
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  for (const HugeBlock& h : drop) {
+    (void)hipSetDevice(h.dev);
+    if (!s) (void)hipStreamSynchronize(h.s);
+    (void)hipFreeAsync(h.p, h.s);
+  }
+  (void)hipSetDevice(cur);
+}
+
 void* pool_alloc(size_t bytes, hipStream_t s) {
+  if (bytes >= kHugeBytes) {
+    if (void* p = huge_take(bytes, s)) return p;
+  }
   const SmallArena* a = current_arena();
   const bool large = bytes >= kLargeBytes && !(a && a->large_default && a->serves(s));
   auto once = [&](void** p) {
@@ -116,6 +195,7 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
   hipError_t e = once(&p);
   if (e == hipErrorOutOfMemory) {
     (void)hipGetLastError();
+    huge_trim(nullptr);
     H2_HIP(hipStreamSynchronize(s));
     int dev = 0;
     H2_HIP(hipGetDevice(&dev));
@@ -125,6 +205,12 @@ void* pool_alloc(size_t bytes, hipStream_t s) {
     e = once(&p);
   }
   H2_HIP(e);
+  if (bytes >= kHugeBytes) {
+    std::lock_guard<std::mutex> lock(g_huge_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    g_huge_live[p] = HugeBlock{p, bytes, s, dev};
+  }
   return p;
 }
 
@@ -375,7 +461,8 @@ class Builder {
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     timer_.totals(h_->phase_ms, kNumPhase);
-    h_->bytes_peak = pool_bytes(ctx_->device, true) - used0;
+    // pool growth plus the cached huge blocks the build took (already counted in used0)
+    h_->bytes_peak = pool_bytes(ctx_->device, true) - used0 + huge_taken(ctx_->device);
     // drop the build-only sample buffers
     for (auto& L : h_->lv) {
       L.om.release();
@@ -941,8 +1028,10 @@ h2_status h2_ctx_destroy(h2_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) {
       (void)hipStreamSynchronize(ctx->side);
+      huge_trim(ctx->side);
       (void)hipStreamDestroy(ctx->side);
     }
+    huge_trim(ctx->stream);  // the stream is borrowed: keep no block ordered on it
     delete ctx;
   });
 }

@@ -71,6 +71,20 @@ h2_status guarded(F&& f) {
 // pool's releases measured slower instead (about 6.6 ms per matrix).
 hipMemPool_t large_pool();
 constexpr size_t kLargeBytes = size_t(64) << 20;
+// Device blocks of 1 GiB and more (dense near-field blocks, the largest
+// coupling levels) are kept by the library when released and handed to the
+// next request of about their size on the same device and stream: the
+// stream-ordered pool does not reliably return a freed block of tens of GB to
+// a later request of the same size (a build's smaller arrays may be carved out
+// of it first), and mapping that much memory anew stalls the host about a
+// second per 30 GB.  huge_take returns nullptr when no cached block fits;
+// huge_put keeps a released block (false: not one of its blocks, the caller
+// frees it); huge_trim frees the cached blocks of a stream (nullptr: of every
+// stream, after synchronising them).
+constexpr size_t kHugeBytes = size_t(1) << 30;
+void* huge_take(size_t bytes, hipStream_t s);
+bool huge_put(void* p, hipStream_t s);
+void huge_trim(hipStream_t s);
 // Stream-ordered allocation from the matching pool; on exhaustion the pools'
 // cached free blocks are released (after the stream drains) and it retries once.
 void* pool_alloc(size_t bytes, hipStream_t s);
@@ -158,7 +172,7 @@ class DevArray {
     owned_ = false;
   }
   void release() {
-    if (p_ && owned_) (void)hipFreeAsync(p_, s_);
+    if (p_ && owned_ && !huge_put(p_, s_)) (void)hipFreeAsync(p_, s_);
     p_ = nullptr;
     n_ = 0;
   }
