@@ -278,6 +278,58 @@ def _power_norm_ratio(apply_diff, apply_ref, n, iters=12, seed=7):
     return norms[0] / norms[1]
 
 
+def bench_update_one(h2, ctx, n: int):
+    """The rank-64 update workload at n points (child process): H's build, the
+    update, their stored bytes and device high-water marks, and the error
+    against the sampler on two vectors; an out-of-memory error is reported."""
+    import torch
+
+    from paper_2506_16759_amd.workloads import cube_update
+    w = cube_update(n)
+    b = w.base
+    pts = torch.from_numpy(b.points()).cuda()
+    rec = {"n": n, "rank": w.rank}
+    try:
+        H = h2.build(ctx, pts, b.kernel, b.length, tol=b.tol, leaf_size=b.leaf_size, eta=b.eta, d0=b.d0,
+                     d_inc=b.d_inc, seed=b.omega_seed)
+        hi = H.info()
+        rec["old"] = {"ms": hi["t_total"], "samples": hi["samples"], "dense_gb": hi["bytes_dense"] / 1e9,
+                      "coupling_gb": hi["bytes_coupling"] / 1e9, "peak_gb": hi["bytes_peak"] / 1e9}
+        U, V = w.factors()
+        Ut, Vt = torch.from_numpy(U).cuda(), torch.from_numpy(V).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Hu = h2.build_update(ctx, H, Ut, Vt, tol=w.tol, d0=w.d0, d_inc=w.d_inc, d_max=w.d_max, seed=w.omega_seed,
+                             oversample=w.oversample)
+        torch.cuda.synchronize()
+        ui = Hu.info()
+        x = torch.randn(2, n, dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(5)).T
+        ref = H.matvec(x) + Ut @ (Vt.T @ x)
+        rec["update"] = {"ms": (time.perf_counter() - t0) * 1e3, "device_ms": ui["t_total"], "samples": ui["samples"],
+                         "rank_range": [ui["rank_min"], ui["rank_max"]], "coupling_gb": ui["bytes_coupling"] / 1e9,
+                         "basis_gb": ui["bytes_basis"] / 1e9, "peak_gb": ui["bytes_peak"] / 1e9,
+                         "error_vs_sampler": float(torch.linalg.norm(Hu.matvec(x) - ref) / torch.linalg.norm(ref))}
+    except h2.H2Error as exc:
+        rec["error"] = str(exc)
+    rec["device_total_gb"] = torch.cuda.get_device_properties(0).total_memory / 1e9
+    return rec
+
+
+def bench_update_series(sizes=(1 << 16, 1 << 17, 1 << 18, 1 << 19)):
+    """The update workload at doubling sizes, each in a fresh process."""
+    import subprocess
+    out = []
+    for n in sizes:
+        cmd = [sys.executable, os.path.abspath(__file__), "--update-one", str(n)]
+        res = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+        if res.returncode != 0:
+            out.append({"n": n, "error": f"exit {res.returncode}: {res.stderr[-500:]}"})
+        else:
+            out.append(json.loads(res.stdout.strip().splitlines()[-1]))
+        print(f"[bench] update series n={n}: {json.dumps(out[-1])[:300]}", file=sys.stderr, flush=True)
+    return out
+
+
 TABLE2_PROBLEMS = {"covariance": ("covariance exp(-r/0.2)", "exp", 0.2),
                    "helmholtz": ("helmholtz cos(3r)/r", "helmholtz", 3.0)}
 
@@ -409,6 +461,9 @@ def main():
     ap.add_argument("--table2", action="store_true",
                     help="only the fixed-vs-adaptive runs of Table II's setting (2^18 points, H^2 black box)")
     ap.add_argument("--table2-one", default=None, help=argparse.SUPPRESS)   # problem,leaf,mode (child process)
+    ap.add_argument("--update-series", action="store_true",
+                    help="only the rank-64 update workload at 2^16..2^19 points (time, memory), one JSON line")
+    ap.add_argument("--update-one", type=int, default=0, help=argparse.SUPPRESS)   # n (child process)
     ap.add_argument("--profile-build", action="store_true",
                     help="only two FP64 builds of the benchmarked cube and a 1 GiB copy of known size, for counter "
                          "collection on every kernel of a build")
@@ -449,6 +504,12 @@ def main():
         return
     if args.table2:
         print(json.dumps({"table2": bench_table2()}), flush=True)
+        return
+    if args.update_series:
+        print(json.dumps({"update_series": bench_update_series()}), flush=True)
+        return
+    if args.update_one:
+        print(json.dumps(bench_update_one(h2, h2.Context(0), args.update_one)), flush=True)
         return
     if args.table2_one:
         problem, leaf, mode = args.table2_one.split(",")
