@@ -135,8 +135,9 @@ def cpu_baseline(w, sketch_passes: int, rows: int = 2048):
 
 
 def bench_batched(h2, ctx, steps: int = 2):
-    """The 64-problem covariance batch: batched FP64 and FP32 builds (one
-    hipGraph each) against 64 sequential single FP64 builds."""
+    """The 64-problem covariance batch: leaf sizes and tile shapes from the
+    autotuners, then batched FP64 and BF16X6 builds (one hipGraph each) against
+    64 sequential single FP64 builds."""
     import torch
 
     from paper_2506_16759_amd.workloads import batch_problems
@@ -154,11 +155,21 @@ def bench_batched(h2, ctx, steps: int = 2):
         p["leaf_size"] = leaf
     for name, prec in (("fp64", h2.FP64), ("bf16x6", h2.BF16X6)):
         times, info = [], None
+        t0 = time.perf_counter()
+        try:
+            tuned = h2.autotune_tiles(ctx, probs, precision=prec, d_max=96)
+        except h2.H2Error as exc:
+            res[name] = {"error": str(exc)}
+            continue
+        tune_ms = (time.perf_counter() - t0) * 1e3
+        print(f"[bench] batched {name} tiles {tuned['sketch_cols']}/{tuned['bsr_cols']} "
+              f"({', '.join(f'{v:.1f}' for v in tuned['times_ms'])} ms)", file=sys.stderr, flush=True)
         for i in range(steps + 1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             try:
-                mats, info = h2.build_batched(ctx, probs, precision=prec, d_max=96, return_info=True)
+                mats, info = h2.build_batched(ctx, probs, precision=prec, d_max=96, return_info=True,
+                                              sketch_cols=tuned["sketch_cols"], bsr_cols=tuned["bsr_cols"])
             except h2.H2Error as exc:
                 res[name] = {"error": str(exc)}
                 break
@@ -176,7 +187,12 @@ def bench_batched(h2, ctx, steps: int = 2):
                          "capture_ms": info["t_capture_ms"], "graph_nodes": info["graph_nodes"],
                          "device_gb": info["device_bytes"] / 1e9,
                          "first_pass_columns": info["first_pass"], "second_pass_problems": info["second_pass"],
-                         "samples_range": [min(samples), max(samples)]}
+                         "samples_range": [min(samples), max(samples)],
+                         "tiles": {"sketch_cols": info["sketch_cols"], "bsr_cols": info["bsr_cols"],
+                                   "tune_ms": tune_ms,
+                                   "candidate_device_ms": dict(zip(
+                                       ["sketch64", "sketch48", "sketch32", "bsr64", "bsr48", "bsr32", "bsr16"],
+                                       tuned["times_ms"]))}}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for p in probs:

@@ -182,6 +182,17 @@ h2_status h2_ctx_destroy(h2_ctx* ctx);
  * traversal from (root, root).  points: HOST, (dim x n) SoA. */
 h2_status h2_plan_create(int64_t n, int32_t dim, const double* points_host, int32_t leaf_size,
                          double eta, h2_plan** out);
+
+/* The same plan built by device kernels (Sec. II-A's tree and dual-tree
+ * traversal on the GPU): equal to h2_plan_create's bit for bit (permutation,
+ * nodes, boxes, near and far lists).  Each node finds its split by radix
+ * selection on (coordinate, original index) and partitions its points; the
+ * last split sorts each node in LDS; each depth of the traversal tests every
+ * cluster's candidate partners in one launch.  points: DEVICE, (dim x n)
+ * SoA, original order, read on ctx's stream.  Errors as h2_plan_create
+ * (non-finite coordinates: H2_ERR_ARG).  Synchronous. */
+h2_status h2_plan_create_device(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, int32_t leaf_size,
+                                double eta, h2_plan** out);
 h2_status h2_plan_free(h2_plan* plan);
 
 /* Parts exported by h2_plan_export and h2_export.  `depth` selects the tree
@@ -366,6 +377,12 @@ typedef struct {
                        * chosen by a sequence's column capacity): Omega is counter-based
                        * and the prefix convergence test at a count does not depend on
                        * later columns. */
+  /* Tile shapes (0: the default, 64; else 16, 32, 48 or 64; h2_autotune_tiles
+   * picks them).  Results are the same bit for bit for every choice. */
+  int32_t sketch_cols; /* columns of Omega per dense-sketch launch: every launch
+                        * evaluates each kernel entry once for that many columns */
+  int32_t bsr_cols;    /* column-tile width of one workgroup of the block-sparse
+                        * products (near-field and far-field subtraction) */
 } h2_batch_opts;
 
 typedef struct {
@@ -384,6 +401,8 @@ typedef struct {
   double t_results_ms; /* per-problem result objects after the device work */
   int32_t first_pass;  /* columns of the first launch sequence */
   int32_t second_pass; /* problems built again with d_max columns */
+  int32_t sketch_cols; /* tile shapes used (defaults resolved) */
+  int32_t bsr_cols;
 } h2_batch_info;
 
 /* Builds `count` independent H^2 matrices (Alg. 1 with adaptive sampling, Sec.
@@ -410,6 +429,20 @@ h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_problem* problem
  * converges the call fails with H2_ERR_SAMPLES.  Synchronous. */
 h2_status h2_autotune_leaf(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
                            const int32_t* candidates, int32_t ncand, int32_t* best);
+
+/* Tile-shape autotuner for h2_build_batched (Sec. IV runs each stage of a
+ * level as one batched launch; the shapes of those launches are tuned here):
+ * builds the given batch with candidate shapes and writes the fastest to
+ * tuned (a copy of opts with sketch_cols and bsr_cols set).  The search is
+ * coordinate-wise: sketch_cols over {64, 48, 32} with bsr_cols 64, then
+ * bsr_cols over {64, 48, 32, 16} with the chosen sketch_cols; each candidate
+ * is built twice and the smaller device time counts (one warm-up build with
+ * the defaults comes first).  times_ms (HOST double[7], may be NULL) receives
+ * those times in that order (sketch 64, 48, 32; bsr 64, 48, 32, 16).  Results
+ * do not depend on the shapes, so a tuned batch gives the same matrices.
+ * Synchronous; fails as h2_build_batched. */
+h2_status h2_autotune_tiles(h2_ctx* ctx, int32_t count, const h2_problem* problems, const h2_batch_opts* opts,
+                            h2_batch_opts* tuned, double* times_ms);
 
 /* ------------------------------------------------------------ low-rank update */
 

@@ -20,7 +20,7 @@ from ._lib import (BF16X3, BF16X6, FP32, FP32E, FP64, K_EXP, K_GAUSS, K_HELMHOLT
                    H2Error)
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
-           "build_update", "autotune_leaf", "device_view", "EntryBatch",
+           "build_update", "autotune_leaf", "autotune_tiles", "device_view", "EntryBatch",
            "H2Matrix",
            "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "K_HELMHOLTZ", "FP64", "FP32", "BF16X3", "FP32E", "BF16X6",
            "NORM_FRO_SCALED", "NORM_LITERAL"]
@@ -146,18 +146,27 @@ class EntryBatch:
 
 
 class Plan(_Handle):
-    """Host-only cluster tree + interaction lists (h2_plan_*)."""
+    """Cluster tree + interaction lists (h2_plan_*): built on the host, or by
+    device kernels when a Context is given (h2_plan_create_device; points may
+    then be a device tensor)."""
 
     _free = "h2_plan_free"
 
-    def __init__(self, points: np.ndarray, leaf_size: int, eta: float):
+    def __init__(self, points, leaf_size: int, eta: float, ctx: "Context | None" = None):
         self._h = None
-        pts = np.ascontiguousarray(points, dtype=np.float64)
-        dim, n = pts.shape
         h = C.c_void_p()
         lib = self._lib_ref = _lib.load()
-        _lib.check(lib.h2_plan_create(n, dim, pts.ctypes.data_as(C.c_void_p), leaf_size, float(eta), C.byref(h)),
-                   "h2_plan_create")
+        if ctx is None:
+            pts = np.ascontiguousarray(points, dtype=np.float64)
+            dim, n = pts.shape
+            _lib.check(lib.h2_plan_create(n, dim, pts.ctypes.data_as(C.c_void_p), leaf_size, float(eta),
+                                          C.byref(h)), "h2_plan_create")
+        else:
+            torch = _torch()
+            pts = torch.as_tensor(points).to(device=f"cuda:{ctx.device}", dtype=torch.float64).contiguous()
+            dim, n = pts.shape
+            _lib.check(lib.h2_plan_create_device(ctx._h, n, dim, C.c_void_p(pts.data_ptr()), leaf_size,
+                                                 float(eta), C.byref(h)), "h2_plan_create_device")
         self._h = h
         self.n, self.dim = n, dim
 
@@ -165,8 +174,9 @@ class Plan(_Handle):
         return _export(_lib.load().h2_plan_export, self._h, name, depth)
 
 
-def plan_create(points: np.ndarray, leaf_size: int = 64, eta: float = 0.7) -> Plan:
-    return Plan(points, leaf_size, eta)
+def plan_create(points, leaf_size: int = 64, eta: float = 0.7, ctx: "Context | None" = None) -> Plan:
+    """h2_plan_create (host), or h2_plan_create_device when ctx is given."""
+    return Plan(points, leaf_size, eta, ctx)
 
 
 class Context(_Handle):
@@ -405,20 +415,39 @@ def autotune_leaf(ctx: Context, problems, candidates=(32, 64, 128), precision=FP
     return [int(b) for b in best]
 
 
+def autotune_tiles(ctx: Context, problems, precision=FP64, d_max: int = 96, first_pass: int = 0):
+    """Tile shapes for this batch from h2_autotune_tiles (problems and options
+    as for build_batched).  Returns dict(sketch_cols, bsr_cols, times_ms), the
+    device times of the candidates (sketch_cols 64, 48, 32 with bsr_cols 64,
+    then bsr_cols 64, 48, 32, 16 with the chosen sketch_cols)."""
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
+    arr, keep = _problem_array(problems)
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1, int(first_pass))
+    tuned = _lib.BatchOpts()
+    times = (C.c_double * 7)()
+    _lib.check(_lib.load().h2_autotune_tiles(ctx._h, len(problems), arr, C.byref(bo), C.byref(tuned), times),
+               "h2_autotune_tiles")
+    del keep
+    return {"sketch_cols": int(tuned.sketch_cols), "bsr_cols": int(tuned.bsr_cols), "times_ms": list(times)}
+
+
 def build_batched(ctx: Context, problems, precision=FP64, d_max: int = 96, use_graph: bool = True,
-                  return_info: bool = False, first_pass: int = 0):
+                  return_info: bool = False, first_pass: int = 0, sketch_cols: int = 0, bsr_cols: int = 0):
     """Many independent constructions in one launch sequence (h2_build_batched).
 
     problems: sequence of dicts with keys points ((dim, n) array or tensor),
     kernel, length, and optionally tol, leaf_size, eta, d0, d_inc, seed,
     norm_mode, oversample (defaults as h2_opts_default).  first_pass: columns
     of the first launch sequence (0: largest d0 + 32; problems not converged
-    within them are built again with d_max).  Returns a list of H2Matrix (and
+    within them are built again with d_max).  sketch_cols, bsr_cols: tile
+    shapes (0: default; see autotune_tiles).  Returns a list of H2Matrix (and
     the batch info dict when return_info)."""
     if isinstance(precision, str):
         precision = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp32e": FP32E, "bf16x6": BF16X6}[precision]
     arr, keep = _problem_array(problems)
-    bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0, int(first_pass))
+    bo = _lib.BatchOpts(int(precision), int(d_max), 1 if use_graph else 0, int(first_pass), int(sketch_cols),
+                        int(bsr_cols))
     handles = (C.c_void_p * len(problems))()
     info = _lib.BatchInfo()
     _lib.check(_lib.load().h2_build_batched(ctx._h, len(problems), arr, C.byref(bo), handles, C.byref(info)),

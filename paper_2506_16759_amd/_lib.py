@@ -59,7 +59,7 @@ class Problem(C.Structure):
 
 class BatchOpts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("d_max", C.c_int32), ("use_graph", C.c_int32),
-                ("first_pass", C.c_int32)]
+                ("first_pass", C.c_int32), ("sketch_cols", C.c_int32), ("bsr_cols", C.c_int32)]
 
 
 class BatchInfo(C.Structure):
@@ -67,7 +67,8 @@ class BatchInfo(C.Structure):
                 ("t_capture_ms", C.c_double), ("t_device_ms", C.c_double), ("levels", C.c_int32),
                 ("graph_nodes", C.c_int32), ("device_bytes", C.c_int64), ("sketch_flops", C.c_double),
                 ("t_layout_ms", C.c_double), ("t_alloc_ms", C.c_double), ("t_results_ms", C.c_double),
-                ("first_pass", C.c_int32), ("second_pass", C.c_int32)]
+                ("first_pass", C.c_int32), ("second_pass", C.c_int32), ("sketch_cols", C.c_int32),
+                ("bsr_cols", C.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -85,6 +86,7 @@ _SIGS = {
     "h2_ctx_create": [C.c_int, _P, C.POINTER(_P)],
     "h2_ctx_destroy": [_P],
     "h2_plan_create": [C.c_int64, C.c_int32, _P, C.c_int32, C.c_double, C.POINTER(_P)],
+    "h2_plan_create_device": [_P, C.c_int64, C.c_int32, _P, C.c_int32, C.c_double, C.POINTER(_P)],
     "h2_plan_free": [_P],
     "h2_plan_export": [_P, C.c_int32, C.c_int32, _P, C.c_size_t, C.POINTER(C.c_size_t)],
     "h2_gaussian": [_P, C.c_uint64, C.c_int64, _P, C.c_int64, C.c_int32, _P, C.c_int64],
@@ -103,6 +105,8 @@ _SIGS = {
     "h2_build_update": [_P, _P, C.c_int32, _P, C.c_int64, _P, C.c_int64, C.POINTER(Opts), C.POINTER(_P)],
     "h2_autotune_leaf": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(C.c_int32), C.c_int32,
                          C.POINTER(C.c_int32)],
+    "h2_autotune_tiles": [_P, C.c_int32, C.POINTER(Problem), C.POINTER(BatchOpts), C.POINTER(BatchOpts),
+                          C.POINTER(C.c_double)],
 }
 EXPORTED = tuple(_SIGS)
 

@@ -31,6 +31,9 @@ SOURCES = [
     ("h2_batched.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
     ("h2_update.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
     ("h2_entries.cpp", [f"--offload-arch={ARCH}", "-x", "hip"] + DEVICE_FLAGS),
+    # device planning: no contraction either (the admissibility test must
+    # round like the host planner's)
+    ("h2_plan_device.hip", [f"--offload-arch={ARCH}", "-ffp-contract=off"] + DEVICE_FLAGS),
     # host-only planning: no contraction, so box/admissibility arithmetic is
     # reproducible operation by operation
     ("h2_plan.cpp", ["-ffp-contract=off", "-fno-fast-math"]),

@@ -1047,6 +1047,18 @@ h2_status h2_plan_create(int64_t n, int32_t dim, const double* points_host, int3
   });
 }
 
+h2_status h2_plan_create_device(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, int32_t leaf_size,
+                                double eta, h2_plan** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    H2_REQUIRE(ctx != nullptr && out != nullptr, "NULL argument");
+    H2_HIP(hipSetDevice(ctx->device));
+    auto p = std::make_unique<h2_plan>();
+    p->plan = h2::make_plan_device(ctx->stream, n, dim, points, leaf_size, eta);
+    *out = p.release();
+  });
+}
+
 h2_status h2_plan_free(h2_plan* plan) {
   return guarded([&] { delete plan; });
 }

@@ -164,8 +164,15 @@ void check_problem(const h2_problem& p) {
 // front.  A problem not converged within dcap columns gets no matrix (out[i]
 // stays nullptr) and is listed in `exhausted`.  Arguments are validated by
 // the caller.
+// Tile shapes of one launch sequence (columns per sketch launch, column-tile
+// width of the block-sparse products).
+struct Tiles {
+  int sketch_cols = 64;
+  int bsr_cols = 64;
+};
+
 void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec, int dcap, bool use_graph,
-                h2_matrix** out, std::vector<int>& exhausted, h2_batch_info* info) {
+                const Tiles& tiles_shape, h2_matrix** out, std::vector<int>& exhausted, h2_batch_info* info) {
   {
     const auto t_start = Clock::now();
     H2_HIP(hipSetDevice(ctx->device));
@@ -363,7 +370,7 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     B.work.want(B.Om0, size_t(NT) * dcap);
     B.work.want(B.Y0, size_t(NT) * dcap);
     B.keep.want(B.Dblk, size_t(doff.back()));
-    B.work.want(B.xr, h2dev::bsr_scratch_doubles(NT, dcap));
+    B.work.want(B.xr, h2dev::bsr_scratch_doubles(NT, dcap, tiles_shape.bsr_cols));
     B.work.want(B.perm_g, perm_g);
     B.work.want(B.rowprob_o, rowprob_o);
     B.work.want(B.rowlocal_o, rowlocal_o);
@@ -473,7 +480,8 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
       H2_HIP(h2dev::gaussian_batched(s, NT, B.rowlocal_o.get(), B.rowprob_o.get(), B.seeds.get(), 0, dcap,
                                      B.Om0.get(), NT));
       H2_HIP(h2dev::sketch_batched(s, prec, static_cast<int>(tiles.size() / 2), B.sjobs.get(), B.tiles.get(),
-                                   B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT));
+                                   B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT,
+                                   tiles_shape.sketch_cols));
       H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Om0.get(), NT, Om1.get(), NT, dcap));
       H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Y0.get(), NT, Y1.get(), NT, dcap));
       H2_HIP(h2dev::thresholds(s, np, B.tjobs.get(), Y1.get(), NT, B.nu.get(), B.delta.get(), B.dprob.get()));
@@ -484,7 +492,7 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
                                        B.Dblk.get()));
       H2_HIP(h2dev::bsr_gemm(s, nleaf_total, B.nptr.get(), B.nidx.get(), B.leafoff.get(), B.doff.get(),
                              B.Dblk.get(), Om1.get(), NT, Y1.get(), NT, dcap, -1.0, leaf_max, B.xr.get(),
-                             B.xr.size()));
+                             B.xr.size(), tiles_shape.bsr_cols));
       for (int l = 1; l <= Lmax; ++l) {
         LevelB& V = B.lv[l - 1];
         double* om = l == 1 ? Om1.get() : V.om.get();
@@ -494,7 +502,8 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
           LevelB& C = B.lv[l - 2];
           H2_HIP(h2dev::gather_i32(s, V.G, V.d_childfirst.get(), C.koff.get(), V.rowoff.get()));
           H2_HIP(h2dev::bsr_gemm(s, C.G, C.d_fptr.get(), C.d_fidx.get(), C.koff.get(), C.d_boff.get(), C.B.get(),
-                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), B.xr.get(), B.xr.size()));
+                                 om, ld, y, ld, dcap, -1.0, std::max(C.max_k, 1), B.xr.get(), B.xr.size(),
+                                 tiles_shape.bsr_cols));
         }
         H2_HIP(h2dev::qr_first_conv(s, V.G, V.rowoff.get(), y, ld, dcap, B.incprob.get(), B.ovprob.get(),
                                     V.d_nodeprob.get(), B.dprob.get(), B.delta.get(), B.exhausted.get(), V.max_m,
@@ -724,6 +733,12 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     const int dcap = bopts->d_max;
     H2_REQUIRE(dcap >= 1 && dcap <= 96, "d_max must be in [1, 96]");
     H2_REQUIRE(bopts->first_pass >= 0, "first_pass must be >= 0");
+    auto tile_ok = [](int c) { return c == 0 || c == 16 || c == 32 || c == 48 || c == 64; };
+    H2_REQUIRE(tile_ok(bopts->sketch_cols), "sketch_cols must be 0, 16, 32, 48 or 64");
+    H2_REQUIRE(tile_ok(bopts->bsr_cols), "bsr_cols must be 0, 16, 32, 48 or 64");
+    Tiles shape;
+    if (bopts->sketch_cols) shape.sketch_cols = bopts->sketch_cols;
+    if (bopts->bsr_cols) shape.bsr_cols = bopts->bsr_cols;
     int d0max = 1;
     for (int i = 0; i < count; ++i) {
       check_problem(problems[i]);
@@ -748,7 +763,7 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
         }
     };
     try {
-      build_pass(ctx, count, problems, prec, first, graph, out, ex, &i1);
+      build_pass(ctx, count, problems, prec, first, graph, shape, out, ex, &i1);
       if (!ex.empty() && first < dcap) {
         std::vector<h2_problem> sub;
         for (int i : ex) sub.push_back(problems[i]);
@@ -756,7 +771,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
         std::vector<h2_matrix*> o2(sub.size(), nullptr);
         std::vector<int> ex2;
         try {
-          build_pass(ctx, static_cast<int>(sub.size()), sub.data(), prec, dcap, graph, o2.data(), ex2, &i2);
+          build_pass(ctx, static_cast<int>(sub.size()), sub.data(), prec, dcap, graph, shape, o2.data(), ex2,
+                     &i2);
         } catch (...) {
           drop(o2.data(), static_cast<int>(o2.size()));
           throw;
@@ -789,6 +805,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
       r.sketch_flops += i2.sketch_flops;
       r.first_pass = first;
       r.second_pass = rerun;
+      r.sketch_cols = shape.sketch_cols;
+      r.bsr_cols = shape.bsr_cols;
       *info = r;
     }
   });
@@ -844,5 +862,63 @@ extern "C" h2_status h2_autotune_leaf(h2_ctx* ctx, int32_t count, const h2_probl
       if (choice < 0) throw Error(H2_ERR_SAMPLES, "autotune: no candidate leaf size converged within d_max");
       for (int i : members) best[i] = choice;
     }
+  });
+}
+
+// Tile-shape autotuner: coordinate search over the columns per sketch launch,
+// then the column-tile width of the block-sparse products, on the batch
+// itself (graph launches; the smaller device time of two builds counts).
+extern "C" h2_status h2_autotune_tiles(h2_ctx* ctx, int32_t count, const h2_problem* problems,
+                                       const h2_batch_opts* opts, h2_batch_opts* tuned, double* times_ms) {
+  return guarded([&] {
+    H2_REQUIRE(ctx && problems && opts && tuned, "NULL argument");
+    H2_REQUIRE(count >= 1, "count must be >= 1");
+    for (int i = 0; i < count; ++i) check_problem(problems[i]);
+    std::vector<h2_matrix*> mats(count, nullptr);
+    auto timed = [&](int sketch_cols, int bsr_cols, int reps) {
+      h2_batch_opts o = *opts;
+      o.use_graph = 1;
+      o.sketch_cols = sketch_cols;
+      o.bsr_cols = bsr_cols;
+      double best = -1;
+      for (int r = 0; r < reps; ++r) {
+        h2_batch_info info{};
+        const h2_status st = h2_build_batched(ctx, count, problems, &o, mats.data(), &info);
+        if (st != H2_OK) throw Error(st, std::string("autotune build: ") + h2_last_error());
+        for (auto& m : mats) {
+          h2_free(m);
+          m = nullptr;
+        }
+        if (best < 0 || info.t_device_ms < best) best = info.t_device_ms;
+      }
+      return best;
+    };
+    (void)timed(64, 64, 1);  // warm-up: allocations and code objects
+    static const int kSketch[3] = {64, 48, 32};
+    static const int kBsr[4] = {64, 48, 32, 16};
+    double t[7];
+    int sk = 64;
+    double tbest = 0;
+    for (int c = 0; c < 3; ++c) {
+      t[c] = timed(kSketch[c], 64, 2);
+      if (c == 0 || t[c] < tbest) {
+        tbest = t[c];
+        sk = kSketch[c];
+      }
+    }
+    int bc = 64;
+    for (int c = 0; c < 4; ++c) {
+      // (sk, 64) was timed by the first search when sk is 64
+      t[3 + c] = (c == 0 && sk == 64) ? t[0] : timed(sk, kBsr[c], 2);
+      if (c == 0 || t[3 + c] < tbest) {
+        tbest = t[3 + c];
+        bc = kBsr[c];
+      }
+    }
+    *tuned = *opts;
+    tuned->sketch_cols = sk;
+    tuned->bsr_cols = bc;
+    if (times_ms)
+      for (int c = 0; c < 7; ++c) times_ms[c] = t[c];
   });
 }

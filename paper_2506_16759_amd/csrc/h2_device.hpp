@@ -46,11 +46,15 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
 // Block-sparse product Y[rows_i, :] += alpha * sum_j Blk_j X[rows_b, :] over nc
 // columns, on the FP64 matrix cores.  max_m bounds every block-row height.
 // X (ldx rows, column-major) is first copied row-major into `scratch`, which
-// must hold bsr_scratch_doubles(ldx, nc) doubles (else hipErrorInvalidValue).
-size_t bsr_scratch_doubles(int64_t ldx, int nc);
+// must hold bsr_scratch_doubles(ldx, nc, tile_cols) doubles (else
+// hipErrorInvalidValue).  tile_cols (16, 32, 48 or 64) is the column-tile width
+// of one workgroup: the columns are covered by ceil(nc / tile_cols) tiles, each
+// reading the blocks once; the sums are the same bit for bit for every width.
+size_t bsr_scratch_doubles(int64_t ldx, int nc, int tile_cols = 64);
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles);
+                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles,
+                    int tile_cols = 64);
 
 // Two-sided form: block row i has rows [rowoff[i], rowoff[i+1]) of Y, block
 // column b rows [coloff[b], coloff[b+1]) of X; with tpos != nullptr the block of
@@ -59,7 +63,7 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     double* scratch, size_t scratch_doubles);
+                     double* scratch, size_t scratch_doubles, int tile_cols = 64);
 
 // Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
 // row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).
@@ -118,9 +122,12 @@ hipError_t gaussian_batched(hipStream_t s, int64_t nrows, const int32_t* rows, c
 
 // y = K_p omega for every problem: workgroup b computes row tile tiles[2b+1]
 // (a multiple of 128) of problem tiles[2b].  jobs: device array of packed jobs.
+// The columns go through launches of at most chunk_cols (16, 32, 48 or 64)
+// columns each; every launch evaluates all kernel entries once, and each
+// column's sum is the same bit for bit for every chunk width.
 hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* jobs, const int32_t* tiles,
                           const double* X, int64_t ldx, int ncols, const double* omega, int64_t ldo, double* y,
-                          int64_t ldy);
+                          int64_t ldy, int chunk_cols = 64);
 size_t sketch_job_bytes();
 void pack_sketch_job(void* dst, int64_t n, int64_t base, int kind, double scale);
 

@@ -409,3 +409,10 @@ struct h2_matrix {
   bool two_sided() const { return !lvc.empty(); }
   const std::vector<h2i::Level>& col_levels() const { return lvc.empty() ? lv : lvc; }
 };
+
+namespace h2 {
+// The plan of make_plan built by device kernels on stream s from DEVICE points
+// ((dim x n) SoA, original order); the same plan bit for bit.  Synchronises s.
+// Throws std::invalid_argument like make_plan, Error on a HIP failure.
+Plan make_plan_device(hipStream_t s, int64_t n, int dim, const double* points, int leaf_size, double eta);
+}  // namespace h2

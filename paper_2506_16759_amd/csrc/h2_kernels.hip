@@ -2464,8 +2464,14 @@ void launch_bsr_nb(hipStream_t s, dim3 grid, const int32_t* ptr, const int32_t* 
                                                alpha);
 }
 
-size_t bsr_scratch_doubles(int64_t ldx, int nc) {
-  const int nb = std::min(4, (nc + 15) / 16);
+// 16-column groups per workgroup for nc columns and a tile width of tile_cols.
+static int bsr_groups(int nc, int tile_cols) {
+  const int cap = tile_cols >= 16 && tile_cols <= 64 ? tile_cols / 16 : 4;
+  return std::min(cap, (nc + 15) / 16);
+}
+
+size_t bsr_scratch_doubles(int64_t ldx, int nc, int tile_cols) {
+  const int nb = std::max(1, bsr_groups(nc, tile_cols));
   const int ldr = ((nc + 16 * nb - 1) / (16 * nb)) * 16 * nb;
   return size_t(ldx) * ldr;
 }
@@ -2473,10 +2479,11 @@ size_t bsr_scratch_doubles(int64_t ldx, int nc) {
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     double* scratch, size_t scratch_doubles) {
+                     double* scratch, size_t scratch_doubles, int tile_cols) {
   if (nrows <= 0 || nc <= 0 || ldx <= 0) return hipSuccess;
+  if (tile_cols != 16 && tile_cols != 32 && tile_cols != 48 && tile_cols != 64) return hipErrorInvalidValue;
   if (max_m < 1) max_m = 1;
-  const int nb = std::min(4, (nc + 15) / 16);
+  const int nb = bsr_groups(nc, tile_cols);
   const int ngrp = (nc + 16 * nb - 1) / (16 * nb);
   const int ldr = ngrp * 16 * nb;
   const size_t need = size_t(ldx) * ldr;
@@ -2500,9 +2507,10 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
 
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
-                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles) {
+                    int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles,
+                    int tile_cols) {
   return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m,
-                   scratch, scratch_doubles);
+                   scratch, scratch_doubles, tile_cols);
 }
 
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
@@ -2601,11 +2609,12 @@ hipError_t gaussian_batched(hipStream_t s, int64_t nrows, const int32_t* rows, c
 
 hipError_t sketch_batched(hipStream_t s, int precision, int ntiles, const void* jobs, const int32_t* tiles,
                           const double* X, int64_t ldx, int ncols, const double* omega, int64_t ldo, double* y,
-                          int64_t ldy) {
+                          int64_t ldy, int chunk_cols) {
   if (ntiles <= 0 || ncols <= 0) return hipSuccess;
+  if (chunk_cols != 16 && chunk_cols != 32 && chunk_cols != 48 && chunk_cols != 64) return hipErrorInvalidValue;
   const SketchJob* J = static_cast<const SketchJob*>(jobs);
-  for (int c0 = 0; c0 < ncols; c0 += 64) {
-    const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
+  for (int c0 = 0; c0 < ncols; c0 += chunk_cols) {
+    const int nc = ncols - c0 < chunk_cols ? ncols - c0 : chunk_cols;
     const double* om = omega + int64_t(c0) * ldo;
     double* yy = y + int64_t(c0) * ldy;
 #define H2_SKB(K, NCT) K<NCT><<<ntiles, 256, 0, s>>>(J, tiles, X, ldx, nc, om, ldo, yy, ldy)

@@ -127,6 +127,12 @@ Plan make_plan(int64_t n, int dim, const double* points, int leaf_size, double e
           if (v < lo[a]) lo[a] = v;
           if (v > hi[a]) hi[a] = v;
         }
+      // a signed zero becomes +0 (-0 and +0 compare equal; which one is the
+      // first extreme depends on the point order inside the node)
+      for (int a = 0; a < dim; ++a) {
+        lo[a] = lo[a] + 0.0;
+        hi[a] = hi[a] + 0.0;
+      }
       if (t == D) return;
       int axis = 0;
       double widest = hi[0] - lo[0];

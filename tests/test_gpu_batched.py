@@ -311,3 +311,54 @@ def test_autotuned_leaf_sizes(ctx):
         kx = op.entries(rows, np.arange(w.n)) @ x
         assert np.linalg.norm(y[rows] - kx) / np.linalg.norm(kx) <= 10 * w.tol
         H.close()
+
+
+def _same_factors(a, b):
+    for key in ("ranks", "skel", "basis", "coupling"):
+        for x, y in zip(a[key], b[key]):
+            assert np.array_equal(x, y), key
+    assert np.array_equal(a["dense"], b["dense"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x6"])
+def test_tile_shapes_give_identical_matrices(ctx, precision):
+    """Every tile shape of the batched launches (columns per sketch launch,
+    column-tile width of the block-sparse products) gives the same matrices
+    bit for bit: each column's sums run in the same order whatever the tile."""
+    # the split-bf16 sketch stops at FP32-level accuracy: problems at tol >= 1e-6
+    probs = _problems([q for q in MIXED_BATCH if precision == "fp64" or q[5] >= 1e-6])
+    _say(f"tile shapes {precision}")
+    ref_mats, ref_info = h2.build_batched(ctx, probs, precision=precision, d_max=96, return_info=True)
+    assert (ref_info["sketch_cols"], ref_info["bsr_cols"]) == (64, 64)
+    ref = [_factors(H) for H in ref_mats]
+    for H in ref_mats:
+        H.close()
+    for sk, bc in ((16, 64), (32, 16), (48, 48), (64, 32), (32, 48)):
+        _say(f"tile shapes {precision} sketch_cols={sk} bsr_cols={bc}")
+        mats, info = h2.build_batched(ctx, probs, precision=precision, d_max=96, return_info=True,
+                                      sketch_cols=sk, bsr_cols=bc)
+        assert (info["sketch_cols"], info["bsr_cols"]) == (sk, bc)
+        for H, r in zip(mats, ref):
+            _same_factors(_factors(H), r)
+            H.close()
+
+
+def test_autotuned_tile_shapes(ctx):
+    """The tile autotuner times every candidate, returns the fastest it saw,
+    and the batch built with the tuned shapes is the default batch bit for bit."""
+    probs = _problems(MIXED_BATCH[:4])
+    _say("autotune tile shapes")
+    tuned = h2.autotune_tiles(ctx, probs, d_max=96)
+    _say(f"tuned {tuned}")
+    t = tuned["times_ms"]
+    assert all(v > 0 for v in t)
+    sk, bc = tuned["sketch_cols"], tuned["bsr_cols"]
+    assert sk in (64, 48, 32) and bc in (64, 48, 32, 16)
+    assert t[(64, 48, 32).index(sk)] == min(t[:3])
+    assert t[3 + (64, 48, 32, 16).index(bc)] == min(t[3:])
+    ref = h2.build_batched(ctx, probs, d_max=96)
+    mats = h2.build_batched(ctx, probs, d_max=96, sketch_cols=sk, bsr_cols=bc)
+    for H, R in zip(mats, ref):
+        _same_factors(_factors(H), _factors(R))
+        H.close()
+        R.close()

@@ -140,3 +140,26 @@ def test_autotune_rejects_bad_arguments_before_any_device_work():
     cand = (C.c_int32 * 1)(64)
     best = (C.c_int32 * 1)()
     assert lib.h2_autotune_leaf(None, 1, prob, C.byref(bo), cand, 1, best) == -1
+
+
+def test_tile_autotune_rejects_bad_arguments_before_any_device_work():
+    import ctypes as C
+
+    from paper_2506_16759_amd import _lib
+    lib = _lib.load()
+    prob = (_lib.Problem * 1)()
+    bo = _lib.BatchOpts(0, 64, 1)
+    tuned = _lib.BatchOpts()
+    assert lib.h2_autotune_tiles(None, 1, prob, C.byref(bo), C.byref(tuned), None) == -1
+    assert "NULL" in lib.h2_last_error().decode()
+
+
+def test_device_plan_rejects_null_context():
+    import ctypes as C
+
+    from paper_2506_16759_amd import _lib
+    lib = _lib.load()
+    out = C.c_void_p()
+    assert lib.h2_plan_create_device(None, 100, 3, None, 64, 0.7, C.byref(out)) == -1
+    assert "NULL" in lib.h2_last_error().decode()
+    assert out.value is None
