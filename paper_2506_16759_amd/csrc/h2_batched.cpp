@@ -141,6 +141,7 @@ struct BatchStore {
   DevArray<char> sjobs, tjobs;
   DevArray<int32_t> tiles;
   Arena keep, work;  // factors kept by the matrices; the build's working set
+  Arena pre;         // the original-order sketch's arrays (allocated before planning)
   Packed meta;       // the matrices' index arrays (permutation, offsets, lists)
   int64_t bytes = 0;
 };
@@ -160,16 +161,22 @@ void check_problem(const h2_problem& p) {
   H2_REQUIRE(p.oversample >= 0 && p.oversample <= 64, "problem oversample must be in [0, 64]");
 }
 
-// One launch sequence over `count` problems with dcap columns sketched up
-// front.  A problem not converged within dcap columns gets no matrix (out[i]
-// stays nullptr) and is listed in `exhausted`.  Arguments are validated by
-// the caller.
 // Tile shapes of one launch sequence (columns per sketch launch, column-tile
 // width of the block-sparse products).
 struct Tiles {
   int sketch_cols = 64;
   int bsr_cols = 64;
 };
+
+// One launch sequence over `count` problems with dcap columns sketched up
+// front.  A problem not converged within dcap columns gets no matrix (out[i]
+// stays nullptr) and is listed in `exhausted`.  Arguments are validated by
+// the caller.
+//
+// The dense sketch works in the problems' original point order and input
+// order, so it needs no plan: it is enqueued first, and the host plans and
+// lays out the batch while the device sketches.  Everything after it (tree
+// order, near field, the levels) is one launch sequence, captured in a graph.
 
 void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec, int dcap, bool use_graph,
                 const Tiles& tiles_shape, h2_matrix** out, std::vector<int>& exhausted, h2_batch_info* info) {
@@ -181,7 +188,8 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     BatchStore& B = *store;
     int64_t& bytes = B.bytes;
 
-    // ---- host plans (threaded over problems)
+    // ---- points to the host for planning (before any device work of this
+    // build is enqueued, so that this wait covers the copies only)
     auto t0 = Clock::now();
     std::vector<Prob> P(count);
     std::vector<std::vector<double>> pts(count);
@@ -193,6 +201,79 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
                             hipMemcpyDeviceToHost, s));
     }
     H2_HIP(hipStreamSynchronize(s));
+
+    // ---- the dense sketch in original order (problems in input order: rows
+    // [base0[i], base0[i] + n_i) belong to problem i)
+    std::vector<int64_t> base0(count + 1, 0);
+    for (int i = 0; i < count; ++i) base0[i + 1] = base0[i] + problems[i].n;
+    const int64_t NT = base0[count];
+    H2_REQUIRE(NT < (int64_t{1} << 31), "total points must be < 2^31");
+    // device events around the whole device work of this call
+    struct Events {
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      ~Events() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+      }
+    } ev;
+    H2_HIP(hipEventCreate(&ev.e0));
+    H2_HIP(hipEventCreate(&ev.e1));
+    // host sources of the uploads live until the end of the call
+    std::vector<int32_t> tiles, rowprob_o(NT), rowlocal_o(NT);
+    std::vector<uint64_t> seeds(count);
+    std::vector<char> sj(h2dev::sketch_job_bytes() * count);
+    // on an error after this point, let the enqueued work finish before the
+    // host sources and the arrays it uses go away
+    struct SyncOnUnwind {
+      hipStream_t s;
+      int n = std::uncaught_exceptions();
+      ~SyncOnUnwind() {
+        if (std::uncaught_exceptions() > n) (void)hipStreamSynchronize(s);
+      }
+    } unwind{s};
+    {
+      for (int i = 0; i < count; ++i)
+        for (int64_t r = 0; r < problems[i].n; ++r) {
+          rowprob_o[base0[i] + r] = i;
+          rowlocal_o[base0[i] + r] = static_cast<int32_t>(r);
+        }
+      std::vector<std::pair<int64_t, int>> order(count);
+      for (int i = 0; i < count; ++i) {
+        seeds[i] = problems[i].seed;
+        const h2dev::KernelFn kf = kernel_fn(problems[i].kernel);
+        h2dev::pack_sketch_job(sj.data() + i * h2dev::sketch_job_bytes(), problems[i].n, base0[i], kf.kind,
+                               kf.scale);
+        order[i] = {problems[i].n, i};
+      }
+      // sketch tiles, largest problems first
+      std::stable_sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
+      for (auto& o : order)
+        for (int64_t r0 = 0; r0 < o.first; r0 += 128) {
+          tiles.push_back(o.second);
+          tiles.push_back(static_cast<int32_t>(r0));
+        }
+      B.pre.want(B.Xo, size_t(3) * NT);
+      B.pre.want(B.Om0, size_t(NT) * dcap);
+      B.pre.want(B.Y0, size_t(NT) * dcap);
+      B.pre.want(B.rowprob_o, rowprob_o);
+      B.pre.want(B.rowlocal_o, rowlocal_o);
+      B.pre.want(B.seeds, seeds);
+      B.pre.want(B.sjobs, sj);
+      B.pre.want(B.tiles, tiles);
+      B.pre.commit(s);
+      H2_HIP(hipEventRecord(ev.e0, s));
+      H2_HIP(h2dev::fill_zero(s, B.Xo.get(), 3 * NT));
+      for (int i = 0; i < count; ++i)
+        for (int a = 0; a < problems[i].dim; ++a)
+          H2_HIP(hipMemcpyAsync(B.Xo.get() + a * NT + base0[i], problems[i].points + a * problems[i].n,
+                                problems[i].n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      H2_HIP(h2dev::gaussian_batched(s, NT, B.rowlocal_o.get(), B.rowprob_o.get(), B.seeds.get(), 0, dcap,
+                                     B.Om0.get(), NT));
+      H2_HIP(h2dev::sketch_batched(s, prec, static_cast<int>(tiles.size() / 2), B.sjobs.get(), B.tiles.get(),
+                                   B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT, tiles_shape.sketch_cols));
+    }
+
+    // ---- host plans (threaded over problems)
     {
       // one problem per pool participant, largest first; each plan runs
       // serially inside its participant
@@ -222,24 +303,20 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     t0 = Clock::now();
     std::stable_sort(P.begin(), P.end(), [](const Prob& a, const Prob& b) { return a.L > b.L; });
     const int np = count;
-    int64_t NT = 0;
+    int64_t nt = 0;
     int nleaf_total = 0;
     for (auto& p : P) {
-      p.base = NT;
-      NT += p.in.n;
+      p.base = nt;
+      nt += p.in.n;
       p.leafbase = nleaf_total;
       nleaf_total += 1 << p.D;
     }
-    H2_REQUIRE(NT < (int64_t{1} << 31), "total points must be < 2^31");
-    // global tree order, original order maps
-    std::vector<int32_t> perm_g(NT), rowprob_o(NT), rowlocal_o(NT);
+    // global tree order: row p.base + r of the tree-ordered arrays is row
+    // base0[orig] + perm[r] of the original-order ones
+    std::vector<int32_t> perm_g(NT);
     h2::parallel_for(np, 1, [&](int q) {  // each problem fills its own rows
       const auto& p = P[q];
-      for (int64_t r = 0; r < p.in.n; ++r) {
-        perm_g[p.base + r] = static_cast<int32_t>(p.base + p.plan.perm[r]);
-        rowprob_o[p.base + r] = q;
-        rowlocal_o[p.base + r] = static_cast<int32_t>(r);
-      }
+      for (int64_t r = 0; r < p.in.n; ++r) perm_g[p.base + r] = static_cast<int32_t>(base0[p.orig] + p.plan.perm[r]);
     });
     // leaves and near field
     std::vector<int32_t> leafoff(nleaf_total + 1), nptr(nleaf_total + 1, 0), nidx, leafprob(nleaf_total);
@@ -362,57 +439,35 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     }
 
     // ---- device allocation and static uploads
-    H2_HIP(hipStreamSynchronize(s));
     const double t_layout = ms_since(t0);
     const auto t_alloc0 = Clock::now();
-    B.work.want(B.Xo, size_t(3) * NT);
     B.work.want(B.Xt, size_t(3) * NT);
-    B.work.want(B.Om0, size_t(NT) * dcap);
-    B.work.want(B.Y0, size_t(NT) * dcap);
     B.keep.want(B.Dblk, size_t(doff.back()));
     B.work.want(B.xr, h2dev::bsr_scratch_doubles(NT, dcap, tiles_shape.bsr_cols));
     B.work.want(B.perm_g, perm_g);
-    B.work.want(B.rowprob_o, rowprob_o);
-    B.work.want(B.rowlocal_o, rowlocal_o);
     B.work.want(B.leafoff, leafoff);
     B.work.want(B.nptr, nptr);
     B.work.want(B.nidx, nidx);
     B.work.want(B.doff, doff);
     B.work.want(B.leafprob, leafprob);
-    std::vector<uint64_t> seeds(np);
     std::vector<int32_t> kinds(np), incs(np), ovs(np);
     std::vector<double> c2s(np);
-    std::vector<char> sj(h2dev::sketch_job_bytes() * np), tj(h2dev::threshold_job_bytes() * np);
-    std::vector<int32_t> tiles;
-    std::vector<std::pair<int64_t, int>> order(np);
+    std::vector<char> tj(h2dev::threshold_job_bytes() * np);
     for (int q = 0; q < np; ++q) {
       const auto& p = P[q];
-      seeds[q] = p.in.seed;
       kinds[q] = p.in.kernel.kind;
       incs[q] = p.in.d_inc;
       ovs[q] = p.in.oversample;
       const h2dev::KernelFn kf = kernel_fn(p.in.kernel);
       c2s[q] = -kf.scale * 1.4426950408889634;
-      h2dev::pack_sketch_job(sj.data() + q * h2dev::sketch_job_bytes(), p.in.n, p.base, kf.kind, kf.scale);
       h2dev::pack_threshold_job(tj.data() + q * h2dev::threshold_job_bytes(), p.base, p.in.n, p.in.d0, 1 << p.D,
                                 p.in.norm_mode == H2_NORM_FRO_SCALED ? 0 : 1, p.in.tol);
-      order[q] = {p.in.n, q};
     }
-    // sketch tiles, largest problems first
-    std::stable_sort(order.begin(), order.end(), [](auto& a, auto& b) { return a.first > b.first; });
-    for (auto& o : order)
-      for (int64_t r0 = 0; r0 < o.first; r0 += 128) {
-        tiles.push_back(o.second);
-        tiles.push_back(static_cast<int32_t>(r0));
-      }
-    B.work.want(B.seeds, seeds);
     B.work.want(B.kinds, kinds);
     B.work.want(B.incprob, incs);
     B.work.want(B.ovprob, ovs);
     B.work.want(B.c2s, c2s);
-    B.work.want(B.sjobs, sj);
     B.work.want(B.tjobs, tj);
-    B.work.want(B.tiles, tiles);
     B.work.want(B.nu, np);
     B.work.want(B.delta, np);
     B.work.want(B.dprob, np);
@@ -458,8 +513,7 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     B.work.want(Y1, size_t(NT) * dcap);
     B.keep.commit(s);
     B.work.commit(s);
-    bytes = static_cast<int64_t>(B.keep.total + B.work.total);
-    H2_HIP(hipStreamSynchronize(s));
+    bytes = static_cast<int64_t>(B.pre.total + B.keep.total + B.work.total);
     const double t_setup = ms_since(t0);
     const double t_alloc = ms_since(t_alloc0);
 
@@ -469,19 +523,8 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     hipStream_t cs = nullptr;  // capture stream
     if (use_graph) H2_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     auto enqueue = [&](hipStream_t s) {
-      // points: caller's arrays -> 3 x NT original order; then tree order
-      H2_HIP(h2dev::fill_zero(s, B.Xo.get(), 3 * NT));
-      for (const auto& p : P)
-        for (int a = 0; a < p.in.dim; ++a)
-          H2_HIP(hipMemcpyAsync(B.Xo.get() + a * NT + p.base, p.in.points + a * p.in.n, p.in.n * sizeof(double),
-                                hipMemcpyDeviceToDevice, s));
+      // points, Omega and the sketch (enqueued before planning) to tree order
       H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Xo.get(), NT, B.Xt.get(), NT, 3));
-      // sketch in original order (same evaluation as single builds), then tree order
-      H2_HIP(h2dev::gaussian_batched(s, NT, B.rowlocal_o.get(), B.rowprob_o.get(), B.seeds.get(), 0, dcap,
-                                     B.Om0.get(), NT));
-      H2_HIP(h2dev::sketch_batched(s, prec, static_cast<int>(tiles.size() / 2), B.sjobs.get(), B.tiles.get(),
-                                   B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT,
-                                   tiles_shape.sketch_cols));
       H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Om0.get(), NT, Om1.get(), NT, dcap));
       H2_HIP(h2dev::permute_rows(s, NT, B.perm_g.get(), false, B.Y0.get(), NT, Y1.get(), NT, dcap));
       H2_HIP(h2dev::thresholds(s, np, B.tjobs.get(), Y1.get(), NT, B.nu.get(), B.delta.get(), B.dprob.get()));
@@ -527,9 +570,6 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     };
     double t_capture = 0;
     size_t graph_nodes = 0;
-    hipEvent_t e0, e1;
-    H2_HIP(hipEventCreate(&e0));
-    H2_HIP(hipEventCreate(&e1));
     try {
       if (use_graph) {
         t0 = Clock::now();
@@ -546,31 +586,25 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
         H2_HIP(hipGraphGetNodes(graph, nullptr, &graph_nodes));
         H2_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         t_capture = ms_since(t0);
-        H2_HIP(hipEventRecord(e0, s));
         H2_HIP(hipGraphLaunch(exec, s));
-        H2_HIP(hipEventRecord(e1, s));
       } else {
-        H2_HIP(hipEventRecord(e0, s));
         enqueue(s);
-        H2_HIP(hipEventRecord(e1, s));
       }
+      H2_HIP(hipEventRecord(ev.e1, s));
       H2_HIP(hipStreamSynchronize(s));
     } catch (...) {
       (void)hipStreamSynchronize(s);
       if (exec) (void)hipGraphExecDestroy(exec);
       if (graph) (void)hipGraphDestroy(graph);
       if (cs) (void)hipStreamDestroy(cs);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
       throw;
     }
+    // from the sketch's start (before planning) to the end of the sequence
     float dev_ms = 0;
-    H2_HIP(hipEventElapsedTime(&dev_ms, e0, e1));
+    H2_HIP(hipEventElapsedTime(&dev_ms, ev.e0, ev.e1));
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cs) (void)hipStreamDestroy(cs);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
 
     // ---- results back to per-problem matrices (views into the batch storage)
     const auto t_res0 = Clock::now();
