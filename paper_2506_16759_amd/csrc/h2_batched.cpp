@@ -37,6 +37,8 @@ double ms_since(Clock::time_point t0) {
 // the factors the matrices keep (dense blocks, IDs, couplings) and the
 // build's working set, released after the build.  Equal-sized blocks on
 // repeated builds come straight back from the stream-ordered pool.
+struct PinnedStage;
+
 struct Arena {
   struct Item {
     size_t off, bytes;
@@ -71,7 +73,57 @@ struct Arena {
         H2_HIP(hipMemcpyAsync(block.get() + it.off, it.src, it.bytes, hipMemcpyHostToDevice, s));
     }
   }
+  // The same through a pinned staging buffer: the arrays with host sources
+  // are laid out first and sent in one asynchronous copy, so the call does not
+  // wait for earlier work on the stream (a copy from pageable memory does).
+  // The staging buffer must not be reused before the stream is synchronised.
+  void commit_staged(hipStream_t s, PinnedStage& stage);
 };
+
+// A pinned host buffer, grown on demand (one per host thread and use).
+struct PinnedStage {
+  char* p = nullptr;
+  size_t cap = 0;
+  PinnedStage() = default;
+  PinnedStage(const PinnedStage&) = delete;
+  PinnedStage& operator=(const PinnedStage&) = delete;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+  char* get(size_t bytes) {
+    if (bytes > cap) {
+      const size_t want = std::max(bytes, cap * 2);
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      H2_HIP(hipHostMalloc(reinterpret_cast<void**>(&p), want, hipHostMallocDefault));
+      cap = want;
+    }
+    return p;
+  }
+};
+
+void Arena::commit_staged(hipStream_t s, PinnedStage& stage) {
+  size_t up = 0;
+  for (auto& it : items)
+    if (it.src) {
+      it.off = up;
+      up += (it.bytes + 255) & ~size_t(255);
+    }
+  size_t off = up;
+  for (auto& it : items)
+    if (!it.src) {
+      it.off = off;
+      off += (it.bytes + 255) & ~size_t(255);
+    }
+  block.alloc(std::max<size_t>(total, 256), s);
+  char* h = up ? stage.get(up) : nullptr;
+  for (auto& it : items) {
+    it.bind(block.get() + it.off);
+    if (it.src && it.bytes) std::memcpy(h + it.off, it.src, it.bytes);
+  }
+  if (up) H2_HIP(hipMemcpyAsync(block.get(), h, up, hipMemcpyHostToDevice, s));
+}
 
 // Small host arrays for many matrices, staged into one host buffer as they
 // are added and sent to the device in one copy: each array is a view into one
@@ -188,19 +240,12 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     BatchStore& B = *store;
     int64_t& bytes = B.bytes;
 
-    // ---- points to the host for planning (before any device work of this
-    // build is enqueued, so that this wait covers the copies only)
     auto t0 = Clock::now();
     std::vector<Prob> P(count);
-    std::vector<std::vector<double>> pts(count);
     for (int i = 0; i < count; ++i) {
       P[i].orig = i;
       P[i].in = problems[i];
-      pts[i].resize(static_cast<size_t>(problems[i].n) * problems[i].dim);
-      H2_HIP(hipMemcpyAsync(pts[i].data(), problems[i].points, pts[i].size() * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
     }
-    H2_HIP(hipStreamSynchronize(s));
 
     // ---- the dense sketch in original order (problems in input order: rows
     // [base0[i], base0[i] + n_i) belong to problem i)
@@ -210,14 +255,17 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     H2_REQUIRE(NT < (int64_t{1} << 31), "total points must be < 2^31");
     // device events around the whole device work of this call
     struct Events {
-      hipEvent_t e0 = nullptr, e1 = nullptr;
+      hipEvent_t e0 = nullptr, e1 = nullptr, ready = nullptr;
       ~Events() {
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
+        if (ready) (void)hipEventDestroy(ready);
       }
     } ev;
     H2_HIP(hipEventCreate(&ev.e0));
     H2_HIP(hipEventCreate(&ev.e1));
+    H2_HIP(hipEventCreateWithFlags(&ev.ready, hipEventDisableTiming));
+    H2_HIP(hipEventRecord(ev.ready, s));  // the caller's earlier work on the stream (the points)
     // host sources of the uploads live until the end of the call
     std::vector<int32_t> tiles, rowprob_o(NT), rowlocal_o(NT);
     std::vector<uint64_t> seeds(count);
@@ -271,6 +319,20 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
                                      B.Om0.get(), NT));
       H2_HIP(h2dev::sketch_batched(s, prec, static_cast<int>(tiles.size() / 2), B.sjobs.get(), B.tiles.get(),
                                    B.Xo.get(), NT, dcap, B.Om0.get(), NT, B.Y0.get(), NT, tiles_shape.sketch_cols));
+    }
+
+    // ---- points to the host for planning, on the side stream (after the
+    // caller's earlier work, beside the sketch)
+    std::vector<std::vector<double>> pts(count);
+    {
+      if (!ctx->side) H2_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+      H2_HIP(hipStreamWaitEvent(ctx->side, ev.ready, 0));
+      for (int i = 0; i < count; ++i) {
+        pts[i].resize(static_cast<size_t>(problems[i].n) * problems[i].dim);
+        H2_HIP(hipMemcpyAsync(pts[i].data(), problems[i].points, pts[i].size() * sizeof(double),
+                              hipMemcpyDeviceToHost, ctx->side));
+      }
+      H2_HIP(hipStreamSynchronize(ctx->side));
     }
 
     // ---- host plans (threaded over problems)
@@ -512,7 +574,9 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
     B.work.want(Om1, size_t(NT) * dcap);
     B.work.want(Y1, size_t(NT) * dcap);
     B.keep.commit(s);
-    B.work.commit(s);
+    // uploads after the sketch was enqueued: pinned, so the host goes on
+    thread_local PinnedStage stage;
+    B.work.commit_staged(s, stage);
     bytes = static_cast<int64_t>(B.pre.total + B.keep.total + B.work.total);
     const double t_setup = ms_since(t0);
     const double t_alloc = ms_since(t_alloc0);
