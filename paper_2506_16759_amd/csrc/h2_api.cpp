@@ -337,7 +337,7 @@ size_t matvec_tree_scratch(const h2_matrix& h, int nc, bool trans) {
 }
 
 void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt,
-                 int nc, bool trans, Workspace* ws) {
+                 int nc, bool trans, Workspace* ws, bool near) {
   const int64_t n = h.plan.n;
   const int D = h.plan.depth;
   const int nleaves = 1 << D;
@@ -389,6 +389,7 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
                            L.koff_h.back(), dst, ldd, nc));
     }
   }
+  if (!near) return;
   int leaf_max = 0;
   for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
   H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,

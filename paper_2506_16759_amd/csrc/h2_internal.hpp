@@ -347,11 +347,12 @@ class Workspace {
 
 // yt += A xt (or A^T xt when trans) for nc <= 64 columns, both in TREE order
 // (ld >= n): the standard H^2 product (upsweep through the column bases,
-// couplings, downsweep through the row bases) plus the near field.
-// Stream-ordered on s.  Temporaries come from ws when given (no allocation),
-// else from the stream-ordered pools.
+// couplings, downsweep through the row bases) plus the near field (left out
+// when near is false: the far-field part alone).  Stream-ordered on s.
+// Temporaries come from ws when given (no allocation), else from the
+// stream-ordered pools.
 void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ldxt, double* yt, int64_t ldyt, int nc,
-                 bool trans = false, Workspace* ws = nullptr);
+                 bool trans = false, Workspace* ws = nullptr, bool near = true);
 // Doubles of workspace matvec_tree takes for nc columns with ldxt = n.
 size_t matvec_tree_scratch(const h2_matrix& h, int nc, bool trans);
 }  // namespace h2i

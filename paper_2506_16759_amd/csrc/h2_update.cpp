@@ -12,6 +12,15 @@
 // sample count d serves both sides (a level is converged when every cluster
 // of both sides is); Omega' uses seed + 1; delta comes from the row sketch.
 //
+// The leaf samples Alg. 1 works on are Y_loc = Y - sum_{b near s} A(s, b)
+// Omega_b.  With H's own product as the sampler, the part D_H(s, b) Omega_b
+// of Y is exactly what the subtraction removes, so neither is formed: the
+// sampler runs H's product without its near field and the subtraction
+// removes only the low-rank part U_s V_b^T Omega_b of the near blocks (the
+// same Y_loc up to rounding, without reading the dense blocks twice per
+// pass).  The norm estimate needs the full first d0 columns of Y: their near
+// field is added once, to a copy.
+//
 // Entries of A at the new skeletons:
 //   D_new(s, b) = D_H(s, b) + U_s V_b^T      kept as D_H plus the factors
 //   B_new(s, b) = R_r_s B_H(s, b) R_c_b^T + U(I~r_s) V(I~c_b)^T
@@ -151,7 +160,24 @@ class UpdateBuilder {
     const int nb = 512;
     DevArray<double> part;
     part.alloc(nb, s_);
-    H2_HIP(h2dev::sumsq_partial(s_, n, o.d0, h.lv[D].y.get(), n, part.get(), nb));
+    {
+      // Y(:, 0:d0) = (far field + low rank, as drawn) + D_H Omega(:, 0:d0)
+      Level& Lr = h.lv[D];
+      DevArray<double> full;
+      full.alloc(size_t(n) * o.d0, s_);
+      H2_HIP(hipMemcpyAsync(full.get(), Lr.y.get(), size_t(n) * o.d0 * sizeof(double), hipMemcpyDeviceToDevice,
+                            s_));
+      int leaf_max = 0;
+      for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
+      for (int q0 = 0; q0 < o.d0; q0 += 64) {
+        const int w = std::min(64, o.d0 - q0);
+        double* xr = xr_.get(n, w, s_);
+        H2_HIP(h2dev::bsr_gemm(s_, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(),
+                               old_.Dblk.get(), Lr.om.get() + int64_t(q0) * n, n, full.get() + int64_t(q0) * n, n,
+                               w, 1.0, leaf_max, xr, xr_.cap()));
+      }
+      H2_HIP(h2dev::sumsq_partial(s_, n, o.d0, full.get(), n, part.get(), nb));
+    }
     std::vector<double> part_h = download(part.get(), nb, s_);
     double ss = 0;
     for (double v : part_h) ss += v;
@@ -196,7 +222,7 @@ class UpdateBuilder {
         const double* x = L.om.get() + int64_t(c0 + q0) * n;
         double* y = L.y.get() + int64_t(c0 + q0) * n;
         H2_HIP(h2dev::fill_zero(s_, y, n * w));
-        matvec_tree(old_, s_, x, n, y, n, w);
+        matvec_tree(old_, s_, x, n, y, n, w, false, nullptr, false);  // far field of H (its near field cancels)
         if (r_ > 0) {
           H2_HIP(h2dev::lr_leaf_project(s_, nleaves, h.leafoff.get(), right, n, r_, x, n, w, lrW_.get()));
           H2_HIP(h2dev::lr_sum(s_, nleaves, r_ * w, lrW_.get(), lrPart_.get(), lrSum_.get()));
@@ -220,11 +246,8 @@ class UpdateBuilder {
         Level& L = a == 0 ? Lr : Lc;
         const double* left = a == 0 ? h.lrU.get() : h.lrV.get();
         const double* right = a == 0 ? h.lrV.get() : h.lrU.get();
-        // D_H is symmetric (D_H(b,s)^T = D_H(s,b) entry for entry), so both sides use it as stored
-        double* xr = xr_.get(n, nc, s_);
-        H2_HIP(h2dev::bsr_gemm(s_, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(),
-                               h.Dblk.get(), L.om.get() + int64_t(c0) * n, n, L.y.get() + int64_t(c0) * n, n, nc,
-                               -1.0, Lr.max_m, xr, xr_.cap()));
+        // the drawn samples hold no D_H part (see the top of this file): only
+        // the low-rank part of the near blocks is subtracted
         if (r_ > 0) {
           for (int q0 = 0; q0 < nc; q0 += 64) {
             const int w = std::min(64, nc - q0);
