@@ -369,7 +369,7 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
       const double* src = t == D ? xt : xh[t + 1];
       const int64_t lds = t == D ? ldxt : up[t + 1].koff_h.back();
       H2_HIP(h2dev::shrink_up(s, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(),
-                              L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t], M, nc));
+                              L.uoff.get(), nullptr, 0, src, lds, nullptr, 0, xh[t], M, nc, L.max_k));
       H2_HIP(h2dev::fill_zero(s, yh[t], dn[t].koff_h.back() * nc));
     }
     for (int t = h.top; t <= D; ++t) {  // couplings y_hat_s = sum_b B_{s,b} x_hat_b (or B_{b,s}^T)
@@ -698,7 +698,8 @@ class Builder {
     Level& P = h.lv[t - 1];
     H2_HIP(h2dev::shrink_up(s_, L.nn, L.rowoff.get(), L.koff.get(), L.J.get(), L.joff.get(), L.U.get(), L.uoff.get(),
                             L.y.get() + int64_t(c0) * L.M, L.M, L.om.get() + int64_t(c0) * L.M, L.M,
-                            P.y.get() + int64_t(c0) * P.M, P.M, P.om.get() + int64_t(c0) * P.M, P.M, nc));
+                            P.y.get() + int64_t(c0) * P.M, P.M, P.om.get() + int64_t(c0) * P.M, P.M, nc,
+                            L.max_k));
   }
 
 

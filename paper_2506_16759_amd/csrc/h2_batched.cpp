@@ -622,7 +622,8 @@ void build_pass(h2_ctx* ctx, int32_t count, const h2_problem* problems, int prec
         if (l < Lmax) {
           LevelB& N = B.lv[l];
           H2_HIP(h2dev::shrink_up(s, V.G, V.rowoff.get(), V.koff.get(), V.J.get(), V.d_joff.get(), V.U.get(),
-                                  V.d_uoff.get(), y, ld, om, ld, N.y.get(), N.rcap, N.om.get(), N.rcap, dcap));
+                                  V.d_uoff.get(), y, ld, om, ld, N.y.get(), N.rcap, N.om.get(), N.rcap, dcap,
+                                  V.max_k));
         }
         const int32_t* pos_in = l == 1 ? nullptr : B.lv[l - 2].pos.get();
         H2_HIP(h2dev::skeleton(s, V.G, V.rowoff.get(), V.koff.get(), V.J.get(), V.d_joff.get(), pos_in,

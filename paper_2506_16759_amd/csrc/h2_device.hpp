@@ -78,10 +78,11 @@ hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
 // Shrink and upsweep (Alg. 1 batchedShrink + batchedGemm) on nc columns:
 //   Yout[koff[i] + r, :] = Yloc[rowoff[i] + J[r], :]           (skipped when Yloc == nullptr)
 //   Wout[koff[i] + r, :] = sum_q U[q, r] Win[rowoff[i] + q, :]    (skipped when Win == nullptr)
+// kmax bounds every node's k (at most 256, else hipErrorInvalidValue).
 hipError_t shrink_up(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
                      const int64_t* joff, const double* U, const int64_t* uoff, const double* Yloc, int64_t ldyl,
                      const double* Win, int64_t ldwi, double* Yout, int64_t ldyo, double* Wout, int64_t ldwo,
-                     int nc);
+                     int nc, int kmax = 256);
 
 // Downsweep of the matvec: Yt[rowoff[i] + q, :] += sum_r U[q, r] Yh[koff[i] + r, :].
 hipError_t expand(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const double* U,

@@ -1981,6 +1981,94 @@ __global__ __launch_bounds__(64) void cpqr_id_wave_kernel(const int32_t* __restr
 
 // ------------------------------------------------------ shrink / upsweep
 
+// W(k0 + r, c) = sum_q U_i(q, r) Win(r0 + q, c) on the FP64 matrix cores: the
+// node's U (m x k, column-major) and a 64-column slice of Win are staged
+// through LDS 16 rows (q) at a time, so that both are read along their
+// contiguous dimension; each wave accumulates up to TPW 16 x 16 output tiles
+// (tile t of the slice's ceil(k/16) x ceil(w/16) goes to wave t mod 4).
+// Yout(k0 + r, c) = Yloc(r0 + J[r], c) as in shrink_up_kernel.
+constexpr int kShrMaxK = 256;
+constexpr int kShrLdu = kShrMaxK + 2;
+constexpr int kShrLdw = 64 + 2;
+template <int TPW>
+__global__ __launch_bounds__(256) void shrink_up_mfma_kernel(
+    const int32_t* __restrict__ rowoff, const int32_t* __restrict__ koff, const int32_t* __restrict__ J,
+    const int64_t* __restrict__ joff, const double* __restrict__ U, const int64_t* __restrict__ uoff,
+    const double* __restrict__ Yloc, int64_t ldyl, const double* __restrict__ Win, int64_t ldwi,
+    double* __restrict__ Yout, int64_t ldyo, double* __restrict__ Wout, int64_t ldwo, int nc) {
+  __shared__ double Us[16 * kShrLdu];
+  __shared__ double Ws[16 * kShrLdw];
+  const int i = blockIdx.x;
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int k0 = koff[i], k = koff[i + 1] - k0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  if (Yloc) {
+    const int* Ji = J + joff[i];
+    for (int e = tid; e < k * nc; e += blockDim.x) {
+      const int r = e % k, c = e / k;
+      Yout[int64_t(c) * ldyo + k0 + r] = Yloc[int64_t(c) * ldyl + r0 + Ji[r]];
+    }
+  }
+  if (!Win || k == 0 || k > kShrMaxK) return;  // uniform; k <= d <= 256 by construction
+  const double* Ui = U + uoff[i];
+  const int RT = (k + 15) >> 4;
+  // tiles beyond 4 x TPW are taken by further passes over the panel
+  for (int c0 = 0, t0 = 0; c0 < nc;) {
+    const int w = min(64, nc - c0);
+    const int CT = (w + 15) >> 4, ntiles = RT * CT;
+    dbl4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int q0 = 0; q0 < m; q0 += 16) {
+      __syncthreads();
+      for (int e = tid; e < 16 * k; e += 256) {
+        const int qq = e & 15, r = e >> 4;
+        Us[qq * kShrLdu + r] = q0 + qq < m ? Ui[q0 + qq + int64_t(r) * m] : 0.0;
+      }
+      for (int e = tid; e < 16 * w; e += 256) {
+        const int qq = e & 15, c = e >> 4;
+        Ws[qq * kShrLdw + c] = q0 + qq < m ? Win[int64_t(c0 + c) * ldwi + r0 + q0 + qq] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int q = kk * 4 + lk;
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+          const int t = t0 + wave + 4 * u;
+          if (t < ntiles) {
+            const int rt = t / CT, ct = t - rt * CT;
+            // rows r >= k and columns c >= w of the staged panels hold stale
+            // values; they reach only output rows and columns that are not written
+            const double a = Us[q * kShrLdu + rt * 16 + li];
+            const double b = Ws[q * kShrLdw + ct * 16 + li];
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int t = t0 + wave + 4 * u;
+      if (t < ntiles) {
+        const int rt = t / CT, ct = t - rt * CT;
+        const int c = ct * 16 + li;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = rt * 16 + lk + 4 * q;
+          if (r < k && c < w) Wout[int64_t(c0 + c) * ldwo + k0 + r] = acc[u][q];
+        }
+      }
+    }
+    t0 += 4 * TPW;
+    if (t0 >= ntiles) {
+      t0 = 0;
+      c0 += 64;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void shrink_up_kernel(const int32_t* __restrict__ rowoff,
                                                         const int32_t* __restrict__ koff,
                                                         const int32_t* __restrict__ J,
@@ -2557,10 +2645,23 @@ hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const doubl
 hipError_t shrink_up(hipStream_t s, int nnodes, const int32_t* rowoff, const int32_t* koff, const int32_t* J,
                      const int64_t* joff, const double* U, const int64_t* uoff, const double* Yloc, int64_t ldyl,
                      const double* Win, int64_t ldwi, double* Yout, int64_t ldyo, double* Wout, int64_t ldwo,
-                     int nc) {
+                     int nc, int kmax) {
   if (nnodes <= 0 || nc <= 0) return hipSuccess;
-  shrink_up_kernel<<<nnodes, 256, 0, s>>>(rowoff, koff, J, joff, U, uoff, Yloc, ldyl, Win, ldwi, Yout, ldyo, Wout,
-                                          ldwo, nc);
+  if (kmax < 0 || kmax > kShrMaxK) return hipErrorInvalidValue;
+  if (!Win) {  // gather only
+    shrink_up_kernel<<<nnodes, 256, 0, s>>>(rowoff, koff, J, joff, U, uoff, Yloc, ldyl, Win, ldwi, Yout, ldyo, Wout,
+                                            ldwo, nc);
+    return hipGetLastError();
+  }
+  const int tiles = ((kmax + 15) / 16) * ((std::min(nc, 64) + 15) / 16);
+#define H2_SHR(T)                                                                                                    shrink_up_mfma_kernel<T><<<nnodes, 256, 0, s>>>(rowoff, koff, J, joff, U, uoff, Yloc, ldyl, Win, ldwi, Yout, ldyo,                                                   Wout, ldwo, nc)
+  if (tiles <= 16)
+    H2_SHR(4);
+  else if (tiles <= 32)
+    H2_SHR(8);
+  else
+    H2_SHR(16);
+#undef H2_SHR
   return hipGetLastError();
 }
 

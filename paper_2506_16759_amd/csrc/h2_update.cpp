@@ -288,14 +288,14 @@ class UpdateBuilder {
                             Pr.y.get() + int64_t(c0) * PMr, PMr, nullptr, 0, nc));
     H2_HIP(h2dev::shrink_up(s_, Lc.nn, Lc.rowoff.get(), Lc.koff.get(), Lc.J.get(), Lc.joff.get(), Lc.U.get(),
                             Lc.uoff.get(), nullptr, 0, Lr.om.get() + int64_t(c0) * Mc, Mc, nullptr, 0,
-                            Pr.om.get() + int64_t(c0) * PMc, PMc, nc));
+                            Pr.om.get() + int64_t(c0) * PMc, PMc, nc, Lc.max_k));
     // column side: Z_next = Z_loc(J_c); Omega'_next = U^T Omega' (row-side ID, row rows)
     H2_HIP(h2dev::shrink_up(s_, Lc.nn, Lc.rowoff.get(), Lc.koff.get(), Lc.J.get(), Lc.joff.get(), Lc.U.get(),
                             Lc.uoff.get(), Lc.y.get() + int64_t(c0) * Mc, Mc, nullptr, 0,
                             Pc.y.get() + int64_t(c0) * PMc, PMc, nullptr, 0, nc));
     H2_HIP(h2dev::shrink_up(s_, Lr.nn, Lr.rowoff.get(), Lr.koff.get(), Lr.J.get(), Lr.joff.get(), Lr.U.get(),
                             Lr.uoff.get(), nullptr, 0, Lc.om.get() + int64_t(c0) * Mr, Mr, nullptr, 0,
-                            Pc.om.get() + int64_t(c0) * PMr, PMr, nc));
+                            Pc.om.get() + int64_t(c0) * PMr, PMr, nc, Lr.max_k));
   }
 
   void in_rows(Level& L, const Level* C, int t, int D) {
