@@ -2422,6 +2422,120 @@ __global__ __launch_bounds__(256) void coupling_update_kernel(
   }
 }
 
+// The same coupling update in 64-column chunks with only T in LDS (kos x
+// kCu2Ld doubles of dynamic LDS, so that several pairs share a CU): T =
+// B_old R_c^T for the chunk, then [R_r | Ug] [T ; Vg^T].  Each wave keeps up
+// to two 16-row tiles and the chunk's 16-column tiles in registers, and the
+// contraction runs in batches of four 4-deep steps whose loads are all issued
+// before their matrix-core products, so that a pair waits for memory once
+// per batch rather than once per step.  Only the chunk's column tiles are
+// computed.
+constexpr int kCu2Ld = 64 + 2;
+constexpr int kCu2Kb = 4;  // 4-deep steps per batch
+__global__ __launch_bounds__(256) void coupling_update2_kernel(
+    const int32_t* __restrict__ frow, const int32_t* __restrict__ fidx, const int32_t* __restrict__ koff_r,
+    const int32_t* __restrict__ koff_c, const int32_t* __restrict__ kold_off, const double* __restrict__ Bold,
+    const int64_t* __restrict__ boff_old, const double* __restrict__ Rr, int64_t ldrr,
+    const double* __restrict__ Rc, int64_t ldrc, const double* __restrict__ Ug, int64_t ldug,
+    const double* __restrict__ Vg, int64_t ldvg, int r, double* __restrict__ Bnew,
+    const int64_t* __restrict__ boff_new) {
+  extern __shared__ double T[];
+  const int j = blockIdx.x;
+  const int s = frow[j], b = fidx[j];
+  const int kr0 = koff_r[s], kr = koff_r[s + 1] - kr0;
+  const int kc0 = koff_c[b], kc = koff_c[b + 1] - kc0;
+  const int kos = kold_off[s + 1] - kold_off[s];
+  const int kob = kold_off[b + 1] - kold_off[b];
+  if (kr == 0 || kc == 0) return;  // uniform
+  const double* bo = Bold + boff_old[j];
+  double* out = Bnew + boff_new[j];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int kin = kos + r;
+  const int mt1 = (kos + 15) >> 4, RT = (kr + 15) >> 4;
+  for (int c0 = 0; c0 < kc; c0 += 64) {
+    const int w = min(64, kc - c0), CT = (w + 15) >> 4;
+    __syncthreads();  // the previous chunk's products have read T
+    // ---- T = B_old R_c^T (tile (rt, ct) to wave (rt * CT + ct) mod 4)
+    for (int t = wave; t < mt1 * CT; t += 4) {
+      const int rt = t / CT, ct = t - rt * CT;
+      const int m = rt * 16 + li, col = ct * 16 + li;
+      dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < kob; k0 += 4 * kCu2Kb) {
+        double a[kCu2Kb], bv[kCu2Kb];
+#pragma unroll
+        for (int kb = 0; kb < kCu2Kb; ++kb) {
+          const int k = k0 + 4 * kb + lk;
+          a[kb] = (m < kos && k < kob) ? bo[m + int64_t(k) * kos] : 0.0;
+          bv[kb] = (col < w && k < kob) ? Rc[(kc0 + c0 + col) + int64_t(k) * ldrc] : 0.0;
+        }
+#pragma unroll
+        for (int kb = 0; kb < kCu2Kb; ++kb) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb], bv[kb], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = rt * 16 + lk + 4 * q;
+        if (row < kos) T[row * kCu2Ld + col] = acc[q];
+      }
+    }
+    __syncthreads();
+    // ---- B_new(:, chunk) = [R_r | Ug] [T ; Vg^T], 8 row tiles per pass
+    for (int rt0 = 0; rt0 < RT; rt0 += 8) {
+      dbl4 acc[2][4];
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[u][ct] = dbl4{0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < kin; k0 += 4 * kCu2Kb) {
+        double a[kCu2Kb][2], bv[kCu2Kb][4];
+#pragma unroll
+        for (int kb = 0; kb < kCu2Kb; ++kb) {
+          const int k = k0 + 4 * kb + lk;
+          const bool kok = k < kin;
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const int col = ct * 16 + li;
+            double v = 0.0;
+            if (ct < CT && kok)
+              v = k < kos ? T[k * kCu2Ld + col] : (col < w ? Vg[(kc0 + c0 + col) + int64_t(k - kos) * ldvg] : 0.0);
+            bv[kb][ct] = v;
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int m = (rt0 + wave + 4 * u) * 16 + li;
+            double v = 0.0;
+            if (m < kr && kok) v = k < kos ? Rr[(kr0 + m) + int64_t(k) * ldrr] : Ug[(kr0 + m) + int64_t(k - kos) * ldug];
+            a[kb][u] = v;
+          }
+        }
+#pragma unroll
+        for (int kb = 0; kb < kCu2Kb; ++kb)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+            if (rt0 + wave + 4 * u < RT)
+#pragma unroll
+              for (int ct = 0; ct < 4; ++ct)
+                if (ct < CT) acc[u][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kb][u], bv[kb][ct], acc[u][ct], 0, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int rt = rt0 + wave + 4 * u;
+        if (rt < RT)
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            const int col = ct * 16 + li;
+            if (ct < CT)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int row = rt * 16 + lk + 4 * q;
+                if (row < kr && col < w) out[int64_t(c0 + col) * kr + row] = acc[u][ct][q];
+              }
+          }
+      }
+    }
+  }
+}
+
 // Dense blocks of the update, written out: out_j = D_j + U(rows s, :) V(rows b, :)^T.
 __global__ __launch_bounds__(256) void dense_lowrank_kernel(const int32_t* __restrict__ ptr,
                                                             const int32_t* __restrict__ idx,
@@ -2844,6 +2958,7 @@ hipError_t prepare_kernels(size_t lds_limit) {
       reinterpret_cast<const void*>(qr_first_conv_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<true>),
       reinterpret_cast<const void*>(cpqr_id_kernel<false>),
+      reinterpret_cast<const void*>(coupling_update2_kernel),
   };
   for (const void* f : ks) {
     const hipError_t e = set(f);
@@ -2904,8 +3019,14 @@ hipError_t coupling_update(hipStream_t s, int npairs, const int32_t* frow, const
                            int64_t ldvg, int r, double* Bnew, const int64_t* boff_new) {
   if (npairs <= 0) return hipSuccess;
   if (max_kold > kCuMaxK) return hipErrorInvalidValue;
-  coupling_update_kernel<<<npairs, 256, 0, s>>>(frow, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
-                                                ldrc, Ug, ldug, Vg, ldvg, r, Bnew, boff_new);
+  const size_t lds = size_t(std::max(max_kold, 1)) * kCu2Ld * sizeof(double);
+  if (lds <= 65536 || lds <= g_lds_prepared) {
+    coupling_update2_kernel<<<npairs, 256, lds, s>>>(frow, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr,
+                                                     Rc, ldrc, Ug, ldug, Vg, ldvg, r, Bnew, boff_new);
+  } else {
+    coupling_update_kernel<<<npairs, 256, 0, s>>>(frow, fidx, koff_r, koff_c, kold_off, Bold, boff_old, Rr, ldrr, Rc,
+                                                  ldrc, Ug, ldug, Vg, ldvg, r, Bnew, boff_new);
+  }
   return hipGetLastError();
 }
 
