@@ -31,22 +31,73 @@ def sketch_flops_per_entry(dim: int, ncols: int) -> float:
     return (3 * dim - 1 + 3) + 2 * ncols
 
 
+def sketch_source_digest() -> str:
+    """SHA-256 of the sources the sketch kernels are compiled from: h2_kernels.hip
+    up to the block generator (helpers, Philox, the FP64 and reduced-precision
+    sketch kernels), its sketch launcher, and h2_devmath.hpp."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2506_16759_amd", "csrc")
+    text = open(os.path.join(csrc, "h2_kernels.hip")).read()
+    head = text[:text.index("// ------------------------------------------------------ kernel block gen")]
+    i = text.index("hipError_t sketch(hipStream_t s, int precision")
+    j = text.index("\nhipError_t ", i + 1)
+    math = open(os.path.join(csrc, "h2_devmath.hpp")).read()
+    return hashlib.sha256((head + text[i:j] + math).encode()).hexdigest()
+
+
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter runs
-    (profiles/sketch_traffic.json), or None when the kernel sources changed
+    (profiles/sketch_traffic.json), or None when the sketch sources changed
     since the counters were taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "sketch_traffic.json")))
-        csrc = os.path.join(ROOT, "paper_2506_16759_amd", "csrc")
-        src = hashlib.sha256(open(os.path.join(csrc, "h2_kernels.hip"), "rb").read()
-                             + open(os.path.join(csrc, "h2_devmath.hpp"), "rb").read()).hexdigest()
-        if rec.get("source_sha256") != src or kernel not in rec["kernels"]:
+        if rec.get("source_sha256") != sketch_source_digest() or kernel not in rec["kernels"]:
             return None
         k = rec["kernels"][kernel]
         return k["fetch_bytes"] + k["write_bytes"]
     except (OSError, ValueError, KeyError):
         return None
+
+
+def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
+    """HBM bytes per sketch launch from two rocprofv3 --pmc runs of
+    --profile-kernels (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+    scaled by what the same counter reads for the run's 1 GiB copy; the first
+    launch of each 64-column FP64/reduced-precision sketch counts."""
+    import csv
+    import glob
+    import re
+
+    def load(d, counter):
+        rows = list(csv.DictReader(open(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])))
+        out = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            k = int(r["Dispatch_Id"])
+            name, val = out.get(k, (r["Kernel_Name"], 0.0))
+            out[k] = (name, val + float(r["Counter_Value"]))
+        return out
+
+    def short(name):
+        m = re.search(r"::(\w+)(<[^>]*>)?\(", name)
+        return (m.group(1) + (m.group(2) or "").replace(" ", "")) if m else name[:40]
+
+    f, w = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    fs = gib_kib / next(v for n, v in f.values() if "copyBuffer" in n)
+    ws = gib_kib / next(v for n, v in w.values() if "copyBuffer" in n)
+    names = {"sketch_f64_kernel<3,1,64>": "sketch_f64_kernel<3,exp,64>",
+             "sketch_f32_kernel<3,1,64>": "sketch_f32_kernel<3,exp,64>",
+             "sketch_bf16_kernel<3,1,64,2>": "sketch_bf16_kernel<3,exp,64,2>",
+             "sketch_e32_kernel<3,1,64>": "sketch_e32_kernel<3,exp,64>",
+             "sketch_bf16_kernel<3,1,64,3>": "sketch_bf16_kernel<3,exp,64,3>"}
+    kernels = {}
+    for k in sorted(f):
+        n = names.get(short(f[k][0]))
+        if n and n not in kernels and k in w:
+            kernels[n] = {"fetch_bytes": f[k][1] * fs * 1024, "write_bytes": w[k][1] * ws * 1024}
+    return {"source_sha256": sketch_source_digest(), "fetch_scale": fs, "write_scale": ws, "kernels": kernels}
 
 
 def _cpu_model() -> str:
@@ -483,10 +534,17 @@ def main():
     ap.add_argument("--profile-build", action="store_true",
                     help="only two FP64 builds of the benchmarked cube and a 1 GiB copy of known size, for counter "
                          "collection on every kernel of a build")
+    ap.add_argument("--traffic-from", default=None,
+                    help="FETCH_DIR,WRITE_DIR: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of "
+                         "--profile-kernels; write the sketch launches' HBM bytes (scaled by the 1 GiB copy) as JSON "
+                         "to stdout")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(json.dumps(traffic_summary(*args.traffic_from.split(",")), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
