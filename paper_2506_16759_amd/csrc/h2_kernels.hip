@@ -1251,6 +1251,118 @@ __global__ void qr_first_conv_kernel(const int32_t* __restrict__ rowoff, const d
   }
 }
 
+// Register-resident form of the same test for panels of m <= 4R rows and at
+// most 64 tested columns: thread t of 256 holds rows [qR, qR + R) (q = t & 3)
+// of column c = t >> 2 in registers.  Each step's Householder vector goes
+// through LDS with zeros above the diagonal, so every thread runs the same
+// unrolled loops over its R rows; the four threads of a column (one quad of
+// a wave) combine their partial sums by shuffles.  Same reflectors as
+// qr_first_conv_kernel (sums of squares in another order).
+template <int R>
+__global__ __launch_bounds__(256) void qr_conv_reg_kernel(const int32_t* __restrict__ rowoff,
+                                                          const double* __restrict__ Y, int64_t ldy, int dsk,
+                                                          const int32_t* __restrict__ incprob,
+                                                          const int32_t* __restrict__ ovprob,
+                                                          const int32_t* __restrict__ nodeprob,
+                                                          int32_t* __restrict__ dprob,
+                                                          const double* __restrict__ deltaprob,
+                                                          int32_t* __restrict__ exhausted) {
+  __shared__ double vbuf[4 * R];
+  __shared__ double s_tau, s_beta;
+  const int i = blockIdx.x;
+  const int pr = nodeprob[i];
+  const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
+  const int tid = threadIdx.x;
+  const int dcur = dprob[pr];
+  const int inc = incprob[pr];
+  const int p = ovprob[pr];
+  const double delta = deltaprob[pr];
+  auto grid_at_least = [&](int x) {
+    if (x <= dcur) return dcur;
+    const int g = dcur + ((x - dcur + inc - 1) / inc) * inc;
+    return g <= dsk ? g : -1;
+  };
+  const int dfirst = grid_at_least(m + p);
+  const int ncols = min(m, dsk - p);
+  if (dfirst == dcur || ncols <= 0 || m > 4 * R || ncols > 64) {  // uniform; the launcher keeps the bounds
+    if (tid == 0 && m <= 4 * R && ncols <= 64) {
+      if (dfirst < 0) atomicOr(&exhausted[pr], 1);
+      else atomicMax(&dprob[pr], dfirst);
+    }
+    return;
+  }
+  const int c = tid >> 2, q = tid & 3, rb = q * R;
+  double a[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) a[r] = (c < ncols && rb + r < m) ? Y[int64_t(c) * ldy + r0 + rb + r] : 0.0;
+  double mn = INFINITY;
+  int found = -1;
+  for (int j = 0; j < ncols; ++j) {
+    if (c == j) {
+      double sg = 0.0, al = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = rb + r;
+        if (row > j) sg += a[r] * a[r];
+        if (row == j) al = a[r];
+      }
+      sg += __shfl_xor(sg, 1);
+      sg += __shfl_xor(sg, 2);
+      al += __shfl_xor(al, 1);
+      al += __shfl_xor(al, 2);
+      double beta, tau, scal;
+      if (sg == 0.0) {
+        beta = al;
+        tau = 0.0;
+        scal = 0.0;
+      } else {
+        const double nrm = sqrt(al * al + sg);
+        beta = al >= 0.0 ? -nrm : nrm;
+        tau = (beta - al) / beta;
+        scal = 1.0 / (al - beta);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int row = rb + r;
+        vbuf[row] = row > j ? a[r] * scal : (row == j ? 1.0 : 0.0);
+      }
+      if (q == 0) {
+        s_tau = tau;
+        s_beta = beta;
+      }
+    }
+    __syncthreads();
+    mn = fmin(mn, fabs(s_beta));
+    if (mn < delta) {
+      found = grid_at_least(j + 1 + p);
+      break;
+    }
+    if (dfirst > 0 && j + 1 + p >= dfirst) break;  // m + p <= d' reached first
+    const double tau = s_tau;
+    if (c > j && c < ncols) {
+      double v[R];
+      double w = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        v[r] = vbuf[rb + r];
+        w += v[r] * a[r];
+      }
+      w += __shfl_xor(w, 1);
+      w += __shfl_xor(w, 2);
+      w *= tau;
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[r] -= w * v[r];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int d = found;
+    if (d < 0 || (dfirst > 0 && dfirst < d)) d = dfirst;
+    if (d < 0) atomicOr(&exhausted[pr], 1);
+    else atomicMax(&dprob[pr], d);
+  }
+}
+
 // Blocked form of the same test for panels beyond LDS.  The panel lives
 // row-major in the global workspace; kQrNb columns at a time are copied to
 // LDS (rows jb.. only) and factored there with the same Householder steps,
@@ -2903,6 +3015,15 @@ hipError_t qr_first_conv(hipStream_t s, int nnodes, const int32_t* rowoff, const
                          const double* deltaprob, int32_t* exhausted, int max_m, size_t lds_limit, double* gws,
                          const int64_t* gws_off) {
   if (nnodes <= 0) return hipSuccess;
+  if (max_m <= 128 && std::min(max_m, dsk) <= 64) {  // every panel fits the register form
+    if (max_m <= 64)
+      qr_conv_reg_kernel<16><<<nnodes, 256, 0, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob, dprob, deltaprob,
+                                                     exhausted);
+    else
+      qr_conv_reg_kernel<32><<<nnodes, 256, 0, s>>>(rowoff, Y, ldy, dsk, incprob, ovprob, nodeprob, dprob, deltaprob,
+                                                     exhausted);
+    return hipGetLastError();
+  }
   const int threads = dsk <= 64 ? 64 : (dsk <= 128 ? 128 : 256);
   const size_t bytes = size_t(max_m | 1) * size_t(dsk) * sizeof(double);
   if (bytes <= lds_limit) {
