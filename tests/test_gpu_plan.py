@@ -128,3 +128,36 @@ def test_device_plan_rejects_bad_input(ctx):
     with pytest.raises(h2.H2Error) as e:
         h2.plan_create(uniform_points(100, 3, 1), 1, 0.7, ctx=ctx)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("case", ["uniform 3d", "grid ties", "ragged 2d"])
+def test_device_plan_equals_oracle(ctx, case):
+    """The device plan against the oracle's own tree and traversal (the host
+    planner is pinned to the oracle on the CPU; this closes the chain
+    directly)."""
+    from oracle.tree import build_lists, build_tree
+    if case == "uniform 3d":
+        pts, leaf, eta = uniform_points(5000, 3, 3), 64, 0.7
+    elif case == "grid ties":
+        g = np.stack(np.meshgrid(np.arange(16.0), np.arange(16.0)), 0).reshape(2, -1)
+        pts, leaf, eta = np.ascontiguousarray(g), 4, 0.7
+    else:
+        pts, leaf, eta = uniform_points(3001, 2, 8), 37, 1.5
+    _say(f"device plan vs oracle: {case}")
+    pd = h2.plan_create(pts, leaf, eta, ctx=ctx)
+    tr = build_tree(pts, leaf)
+    L = build_lists(tr, eta)
+    D = int(pd.export("DEPTH")[0])
+    assert D == tr.depth
+    np.testing.assert_array_equal(pd.export("PERM"), tr.perm)
+    nodes = pd.export("NODES").reshape(-1, 2)
+    np.testing.assert_array_equal(nodes[:, 0], tr.begin)
+    np.testing.assert_array_equal(nodes[:, 1], tr.end)
+    boxes = pd.export("BOXES").reshape(-1, 2, pts.shape[0])
+    np.testing.assert_array_equal(boxes[:, 0], tr.lo)
+    np.testing.assert_array_equal(boxes[:, 1], tr.hi)
+    np.testing.assert_array_equal(pd.export("NEAR_PTR"), L.near_ptr)
+    np.testing.assert_array_equal(pd.export("NEAR_IDX"), L.near_idx)
+    for t in range(D + 1):
+        np.testing.assert_array_equal(pd.export("FAR_PTR", t), L.far_ptr[t])
+        np.testing.assert_array_equal(pd.export("FAR_IDX", t), L.far_idx[t])

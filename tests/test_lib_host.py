@@ -163,3 +163,22 @@ def test_device_plan_rejects_null_context():
     assert lib.h2_plan_create_device(None, 100, 3, None, 64, 0.7, C.byref(out)) == -1
     assert "NULL" in lib.h2_last_error().decode()
     assert out.value is None
+
+
+def test_traffic_summary_scales_by_the_copy(tmp_path):
+    """bench.py --traffic-from: KiB counters scaled so that the 1 GiB copy reads
+    and writes exactly 1 GiB; the first launch of each sketch variant counts."""
+    import bench
+    hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+    sk = "void h2dev::(anonymous namespace)::sketch_f64_kernel<3, 1, 64>(long, double const*)"
+    for counter, copy_kib, sk_kib in (("FETCH_SIZE", 2 ** 19, 1000.0), ("WRITE_SIZE", 2 ** 20, 64.0)):
+        d = tmp_path / counter
+        d.mkdir()
+        (d / "run_counter_collection.csv").write_text(
+            hdr + f'1,"{sk}",{counter},{sk_kib / 2}\n1,"{sk}",{counter},{sk_kib / 2}\n'
+            f'2,"{sk}",{counter},{9 * sk_kib}\n3,"__amd_rocclr_copyBuffer",{counter},{copy_kib}\n')
+    rec = bench.traffic_summary(str(tmp_path / "FETCH_SIZE"), str(tmp_path / "WRITE_SIZE"))
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    k = rec["kernels"]["sketch_f64_kernel<3,exp,64>"]
+    assert k["fetch_bytes"] == 1000.0 * 2.0 * 1024 and k["write_bytes"] == 64.0 * 1024
+    assert rec["source_sha256"] == bench.sketch_source_digest()
