@@ -846,42 +846,65 @@ hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const do
 // ------------------------------------------------------ kernel block gen
 
 // One workgroup per block row.  The row cluster's coordinates stay in LDS for
-// the whole row; the next column cluster's coordinates are fetched into
-// registers while the current block is evaluated and then stashed into the
-// other of two LDS buffers (one barrier per block).  Entry e = r + c*m of the
-// column-major block: when the threads can be laid out as fixed rows (m * (256/m)
-// of them, at least three quarters of the workgroup), thread t keeps row t % m
-// in registers and walks columns t/m, t/m + 256/m, ..; otherwise the threads
-// walk the entries in order.  Consecutive threads write consecutive entries;
-// the blocks are written once and read later, so the stores are non-temporal.
+// the whole row.  The row's blocks are taken in stages of consecutive blocks
+// with at most kGenMax columns together (several small coupling blocks per
+// stage, one barrier per stage): thread t fetches the coordinates and output
+// offset of stage column t into registers while the current stage is
+// evaluated and stashes them into the other of two LDS buffers.  Entry
+// (r, column cc of the stage) goes to out[off[cc] + r] (column-major blocks):
+// when the threads can be laid out as fixed rows (m * (256/m) of them, at
+// least three quarters of the workgroup), thread t keeps row t % m in
+// registers and walks stage columns t/m, t/m + 256/m, ..; otherwise the
+// threads walk the entries in order.  Consecutive threads write consecutive
+// entries; the blocks are written once and read later, so the stores are
+// non-temporal.
 constexpr int kGenMax = 256;
-constexpr int kGenPf = (3 * kGenMax + 255) / 256;  // staged coordinates per thread
 
 struct GenStage {
-  double v[kGenPf];
-  int mb;
+  double v[3];  // this thread's stage column: coordinates
+  int64_t off;  // and output offset of its first row
+  int jend;     // the stage covers blocks [j, jend)
+  int total;    // columns in the stage
 };
 
+// The stage that starts at block j: blocks while their columns fit kGenMax;
+// thread tid fetches stage column tid.
 template <int DIM>
 __device__ __forceinline__ void gen_fetch(GenStage& st, const int32_t* __restrict__ idx,
-                                          const int32_t* __restrict__ rowoff, const double* __restrict__ X,
-                                          int64_t ldx, int j, int tid) {
-  const int b = idx[j];
-  const int c0 = rowoff[b];
-  st.mb = rowoff[b + 1] - c0;
+                                          const int32_t* __restrict__ rowoff, const int64_t* __restrict__ blkoff,
+                                          const double* __restrict__ X, int64_t ldx, int m, int j, int je, int tid) {
+  int total = 0, jj = j;
+  int myb = -1, mycol = 0;
+  while (jj < je) {
+    const int b = idx[jj];
+    const int mb = rowoff[b + 1] - rowoff[b];
+    if (total + mb > kGenMax && jj > j) break;
+    if (tid >= total && tid < total + mb) {
+      myb = jj;
+      mycol = tid - total;
+    }
+    total += mb;
+    ++jj;
+  }
+  st.jend = jj;
+  st.total = total;
+  st.off = 0;
 #pragma unroll
-  for (int u = 0; u < kGenPf; ++u) {
-    const int e = tid + 256 * u;
-    st.v[u] = e < DIM * st.mb ? X[int64_t(e / st.mb) * ldx + c0 + e % st.mb] : 0.0;
+  for (int a = 0; a < 3; ++a) st.v[a] = 0.0;
+  if (myb >= 0) {
+    const int c0 = rowoff[idx[myb]] + mycol;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) st.v[a] = X[int64_t(a) * ldx + c0];
+    st.off = blkoff[myb] + int64_t(mycol) * m;
   }
 }
 
 template <int DIM>
-__device__ __forceinline__ void gen_stash(const GenStage& st, double (*xc)[kGenMax], int tid) {
+__device__ __forceinline__ void gen_stash(const GenStage& st, double (*xc)[kGenMax], int64_t* off, int tid) {
+  if (tid < st.total) {
 #pragma unroll
-  for (int u = 0; u < kGenPf; ++u) {
-    const int e = tid + 256 * u;
-    if (e < DIM * st.mb) xc[e / st.mb][e % st.mb] = st.v[u];
+    for (int a = 0; a < DIM; ++a) xc[a][tid] = st.v[a];
+    off[tid] = st.off;
   }
 }
 
@@ -890,13 +913,14 @@ template <int DIM, typename F>
 __device__ __forceinline__ void gen_row(const int32_t* __restrict__ idx, const int32_t* __restrict__ rowoff,
                                         const int64_t* __restrict__ blkoff, const double* __restrict__ X,
                                         int64_t ldx, double* __restrict__ out, int jb, int je, int r0, int m,
-                                        double (*xr)[kGenMax], double (*xc)[DIM][kGenMax], F f) {
+                                        double (*xr)[kGenMax], double (*xc)[DIM][kGenMax], int64_t (*off)[kGenMax],
+                                        F f) {
   const int tid = threadIdx.x;
   for (int e = tid; e < DIM * m; e += 256) xr[e / m][e % m] = X[int64_t(e / m) * ldx + r0 + e % m];
   GenStage st;
-  gen_fetch<DIM>(st, idx, rowoff, X, ldx, jb, tid);
-  gen_stash<DIM>(st, xc[0], tid);
-  int mb = st.mb;
+  gen_fetch<DIM>(st, idx, rowoff, blkoff, X, ldx, m, jb, je, tid);
+  gen_stash<DIM>(st, xc[0], off[0], tid);
+  int total = st.total, jn = st.jend;
   __syncthreads();
   const int dc = 256 / m, act = m * dc;
   const bool rows_fixed = act >= 192;
@@ -904,35 +928,36 @@ __device__ __forceinline__ void gen_row(const int32_t* __restrict__ idx, const i
 #pragma unroll
   for (int a = 0; a < DIM; ++a) rx[a] = xr[a][tid % m];
   int cur = 0;
-  for (int j = jb; j < je; ++j) {
-    const bool more = j + 1 < je;
-    if (more) gen_fetch<DIM>(st, idx, rowoff, X, ldx, j + 1, tid);
-    double* o = out + blkoff[j];
+  for (int j = jb; j < je;) {
+    const bool more = jn < je;
+    if (more) gen_fetch<DIM>(st, idx, rowoff, blkoff, X, ldx, m, jn, je, tid);
     const double(*xcc)[kGenMax] = xc[cur];
+    const int64_t* oc = off[cur];
     if (rows_fixed) {
       if (tid < act) {
+        const int r = tid % m;
 #pragma unroll 4
-        for (int c = tid / m, e = tid; c < mb; c += dc, e += act) {
+        for (int c = tid / m; c < total; c += dc) {
           double r2 = 0.0;
 #pragma unroll
           for (int a = 0; a < DIM; ++a) {
             const double d = rx[a] - xcc[a][c];
             r2 += d * d;
           }
-          __builtin_nontemporal_store(f(r2), o + e);
+          __builtin_nontemporal_store(f(r2), out + oc[c] + r);
         }
       }
     } else {
       const int dr = 256 % m;
       int r = tid % m, c = tid / m;
-      for (int e = tid; e < m * mb; e += 256) {
+      for (int e = tid; e < m * total; e += 256) {
         double r2 = 0.0;
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
           const double d = xr[a][r] - xcc[a][c];
           r2 += d * d;
         }
-        __builtin_nontemporal_store(f(r2), o + e);
+        __builtin_nontemporal_store(f(r2), out + oc[c] + r);
         r += dr;
         c += dc;
         if (r >= m) {
@@ -941,9 +966,11 @@ __device__ __forceinline__ void gen_row(const int32_t* __restrict__ idx, const i
         }
       }
     }
+    j = jn;
     if (more) {
-      gen_stash<DIM>(st, xc[cur ^ 1], tid);
-      mb = st.mb;
+      gen_stash<DIM>(st, xc[cur ^ 1], off[cur ^ 1], tid);
+      total = st.total;
+      jn = st.jend;
     }
     __syncthreads();
     cur ^= 1;
@@ -959,11 +986,12 @@ __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restri
                                                          double* __restrict__ out) {
   __shared__ double xr[DIM][kGenMax];
   __shared__ double xc[2][DIM][kGenMax];
+  __shared__ int64_t off[2][kGenMax];
   const int i = blockIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
   const int jb = ptr[i], je = ptr[i + 1];
   if (jb == je || m == 0) return;  // uniform over the workgroup
-  gen_row<DIM>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+  gen_row<DIM>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc, off,
                [c2](double r2) { return kernel_of_r2<KIND>(r2, c2); });
 }
 
@@ -980,6 +1008,7 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
                                                                  double* __restrict__ out) {
   __shared__ double xr[3][kGenMax];
   __shared__ double xc[2][3][kGenMax];
+  __shared__ int64_t off[2][kGenMax];
   const int i = blockIdx.x;
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
   const int jb = ptr[i], je = ptr[i + 1];
@@ -987,10 +1016,10 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
   const int pr = rowprob[i];
   const double c2 = c2s[pr];
   if (kinds[pr] == kExp)
-    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc, off,
                [c2](double r2) { return kernel_of_r2<kExp>(r2, c2); });
   else
-    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc,
+    gen_row<3>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc, off,
                [c2](double r2) { return kernel_of_r2<kGauss>(r2, c2); });
 }
 
