@@ -85,8 +85,9 @@ def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
 
     f, w = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
     gib_kib = float(1 << 20)
-    fs = gib_kib / next(v for n, v in f.values() if "copyBuffer" in n)
-    ws = gib_kib / next(v for n, v in w.values() if "copyBuffer" in n)
+    # the 1 GiB copy is the largest copy of the run
+    fs = gib_kib / max(v for n, v in f.values() if "copyBuffer" in n)
+    ws = gib_kib / max(v for n, v in w.values() if "copyBuffer" in n)
     names = {"sketch_f64_kernel<3,1,64>": "sketch_f64_kernel<3,exp,64>",
              "sketch_f32_kernel<3,1,64>": "sketch_f32_kernel<3,exp,64>",
              "sketch_bf16_kernel<3,1,64,2>": "sketch_bf16_kernel<3,exp,64,2>",
@@ -98,6 +99,65 @@ def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
         if n and n not in kernels and k in w:
             kernels[n] = {"fetch_bytes": f[k][1] * fs * 1024, "write_bytes": w[k][1] * ws * 1024}
     return {"source_sha256": sketch_source_digest(), "fetch_scale": fs, "write_scale": ws, "kernels": kernels}
+
+
+def _load_pmc(d: str):
+    """Per dispatch of one rocprofv3 --pmc run: kernel name, counters (summed
+    over dimensions) and the kernel-trace duration in ms."""
+    import csv
+    import glob
+    out = {}
+    for r in csv.DictReader(open(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])):
+        k = int(r["Dispatch_Id"])
+        e = out.setdefault(k, {"name": r["Kernel_Name"], "c": {}, "ms": 0.0})
+        e["c"][r["Counter_Name"]] = e["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    for r in csv.DictReader(open(glob.glob(os.path.join(d, "*kernel_trace.csv"))[0])):
+        k = int(r["Dispatch_Id"])
+        if k in out:
+            out[k]["ms"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+    return out
+
+
+def build_counter_table(fetch_dir: str, write_dir: str, sq_dir: str) -> str:
+    """Markdown rows: every kernel of the second FP64 build of --profile-build
+    (from its FP64 sketch launch to the 1 GiB copy's fill), HBM bytes scaled by
+    the copy as in traffic_summary, SQ instruction counts, counter-run times."""
+    import re
+    f, w, q = _load_pmc(fetch_dir), _load_pmc(write_dir), _load_pmc(sq_dir)
+    gib_kib = float(1 << 20)
+    # the 1 GiB copy is the largest copy of the run
+    fs = gib_kib / max(v["c"].get("FETCH_SIZE", 0.0) for v in f.values() if "copyBuffer" in v["name"])
+    ws = gib_kib / max(v["c"].get("WRITE_SIZE", 0.0) for v in w.values() if "copyBuffer" in v["name"])
+
+    def short(name):
+        m = re.search(r"::(\w+)(<[^>]*>)?\(", name)
+        return (m.group(1) + (m.group(2) or "").replace(" ", "")) if m else name[:40]
+
+    keys = sorted(f)
+    sk = [k for k in keys if "sketch_f64" in f[k]["name"]]
+    start = sk[1]
+    end = next((k for k in keys if k > start and "FillFunctor" in f[k]["name"]), keys[-1] + 1)
+    agg = {}
+    for k in keys:
+        if k < start or k >= end:
+            continue
+        a = agg.setdefault(short(f[k]["name"]), {"calls": 0, "ms": 0.0, "fetch": 0.0, "write": 0.0, "valu": 0.0,
+                                                 "mfma": 0.0, "lds": 0.0})
+        a["calls"] += 1
+        a["fetch"] += f[k]["c"].get("FETCH_SIZE", 0.0) * fs * 1024
+        a["write"] += w.get(k, {"c": {}})["c"].get("WRITE_SIZE", 0.0) * ws * 1024
+        sq = q.get(k, {"c": {}, "ms": 0.0})
+        a["valu"] += sq["c"].get("SQ_INSTS_VALU", 0.0)
+        a["mfma"] += sq["c"].get("SQ_INSTS_MFMA", 0.0)
+        a["lds"] += sq["c"].get("SQ_INSTS_LDS", 0.0)
+        a["ms"] += sq["ms"]
+    rows = [f"calibration: FETCH_SIZE x {fs:.3f}, WRITE_SIZE x {ws:.3f}", "",
+            "| kernel | calls | ms | HBM fetch GB | HBM write GB | VALU instr | MFMA instr | LDS instr |",
+            "|---|---|---|---|---|---|---|---|"]
+    for n, a in sorted(agg.items(), key=lambda kv: -kv[1]["ms"]):
+        rows.append(f"| `{n}` | {a['calls']} | {a['ms']:.3f} | {a['fetch'] / 1e9:.3f} | {a['write'] / 1e9:.3f} | "
+                    f"{a['valu']:.3e} | {a['mfma']:.3e} | {a['lds']:.3e} |")
+    return "\n".join(rows)
 
 
 def _cpu_model() -> str:
@@ -538,12 +598,18 @@ def main():
                     help="FETCH_DIR,WRITE_DIR: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of "
                          "--profile-kernels; write the sketch launches' HBM bytes (scaled by the 1 GiB copy) as JSON "
                          "to stdout")
+    ap.add_argument("--build-counters", default=None,
+                    help="FETCH_DIR,WRITE_DIR,SQ_DIR: rocprofv3 --pmc output directories of --profile-build; print "
+                         "the per-kernel counter table of its second build (markdown rows)")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
                          "known size, for counter collection")
     args = ap.parse_args()
     if args.traffic_from:
         print(json.dumps(traffic_summary(*args.traffic_from.split(",")), indent=1))
+        return
+    if args.build_counters:
+        print(build_counter_table(*args.build_counters.split(",")))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
