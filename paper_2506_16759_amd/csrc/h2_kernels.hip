@@ -100,13 +100,17 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, int64_t nr
 // holds D[l/16 + 4q][l%16] in accumulator element q (rows interleaved by 4).
 constexpr int kSkRows = 128;
 constexpr int kSkK = 64;
+// Points per LDS stage of the FP64 sketch: 32 keeps its registers within
+// three waves per SIMD (the contraction runs over the same points in the
+// same order whatever the stage size).
+constexpr int kSkF64 = 32;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int DIM, int NC>
 struct SkF64Smem {
-  double xs[DIM][kSkK];
-  double om[kSkK][NC + 2];
+  double xs[DIM][kSkF64];
+  double om[kSkF64][NC + 2];
 };
 
 // Rows [tile0, tile0 + 128) of y = K omega for one point set of n points.
@@ -142,37 +146,37 @@ __device__ __forceinline__ void sketch_f64_body(SkF64Smem<DIM, NC>& sm, int64_t 
 
   // The next stage's points and Omega rows are fetched into registers while
   // the current stage computes, then written to LDS between two barriers.
-  constexpr int PX = (DIM * kSkK + 255) / 256, PO = NC * kSkK / 256;
+  constexpr int PX = (DIM * kSkF64 + 255) / 256, PO = NC * kSkF64 / 256;
   double rx[PX], ro[PO];
   auto fetch = [&](int64_t j0) {
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
-      const int e = tid + 256 * u, a = e / kSkK, jj = e % kSkK;
-      rx[u] = (e < DIM * kSkK && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
+      const int e = tid + 256 * u, a = e / kSkF64, jj = e % kSkF64;
+      rx[u] = (e < DIM * kSkF64 && j0 + jj < n) ? X[a * ldx + j0 + jj] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < PO; ++u) {
-      const int e = tid + 256 * u, c = e / kSkK, jj = e % kSkK;
+      const int e = tid + 256 * u, c = e / kSkF64, jj = e % kSkF64;
       ro[u] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
     }
   };
   fetch(0);
-  for (int64_t j0 = 0; j0 < n; j0 += kSkK) {
+  for (int64_t j0 = 0; j0 < n; j0 += kSkF64) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PX; ++u) {
       const int e = tid + 256 * u;
-      if (e < DIM * kSkK) xs[e / kSkK][e % kSkK] = rx[u];
+      if (e < DIM * kSkF64) xs[e / kSkF64][e % kSkF64] = rx[u];
     }
 #pragma unroll
     for (int u = 0; u < PO; ++u) {
       const int e = tid + 256 * u;
-      om[e % kSkK][e / kSkK] = ro[u];
+      om[e % kSkF64][e / kSkF64] = ro[u];
     }
     __syncthreads();
-    if (j0 + kSkK < n) fetch(j0 + kSkK);
+    if (j0 + kSkF64 < n) fetch(j0 + kSkF64);
 #pragma unroll 4
-    for (int kk = 0; kk < kSkK / 4; ++kk) {
+    for (int kk = 0; kk < kSkF64 / 4; ++kk) {
       const int jj = kk * 4 + lk;
       double ra = 0.0, rb = 0.0;
 #pragma unroll
@@ -216,7 +220,8 @@ struct SketchJob {
 };
 
 template <int DIM, int KIND, int NC>
-__global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(256, KIND == kHelm ? 2 : 3) void sketch_f64_kernel(int64_t n, const double* __restrict__ X,
+                                                                                int64_t ldx,
                                                          double c2, int ncr, const double* __restrict__ omega,
                                                          int64_t ldo, double* __restrict__ y, int64_t ldy) {
   __shared__ SkF64Smem<DIM, NC> sm;
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(int64_t n, const double
 // Batched: workgroup b handles row tile tiles[2b+1] of job tiles[2b] (3-D
 // coordinates; lower-dimensional point sets carry zero coordinates).
 template <int NC>
-__global__ __launch_bounds__(256) void sketch_f64_batched(const SketchJob* __restrict__ jobs,
+__global__ __launch_bounds__(256, 3) void sketch_f64_batched(const SketchJob* __restrict__ jobs,
                                                           const int32_t* __restrict__ tiles,
                                                           const double* __restrict__ X, int64_t ldx, int ncr,
                                                           const double* __restrict__ omega, int64_t ldo,
