@@ -707,10 +707,12 @@ def main():
 
     # mixed precision on the same points at the same tolerance: three-term
     # split bf16 products (bf16x6), FP32 matrix cores (fp32), FP32 entries
-    # contracted in FP64 (fp32e); bf16x3 at tol 1e-4 (its products carry
-    # ~2^-17 relative error), with FP64 at 1e-4 for comparison
+    # contracted in FP64 (fp32e), FP64 with symmetric-tile reuse in the sketch
+    # (fp64_sym); bf16x3 at tol 1e-4 (its products carry ~2^-17 relative
+    # error), with FP64 at 1e-4 for comparison
     mixed = {}
     for name, prec, mtol in (("bf16x6", h2.BF16X6, tol), ("fp32", h2.FP32, tol), ("fp32e", h2.FP32E, tol),
+                             ("fp64_sym", h2.FP64_SYM, tol),
                              ("fp64_tol1e-4", h2.FP64, 1e-4), ("bf16x3_tol1e-4", h2.BF16X3, 1e-4),
                              ("fp64_tol1e-8", h2.FP64, 1e-8), ("fp32e_tol1e-8", h2.FP32E, 1e-8)):
         o = h2.opts_default(tol=mtol, leaf_size=w.leaf_size, eta=w.eta, d0=w.d0, d_inc=w.d_inc, seed=w.omega_seed,
@@ -749,6 +751,15 @@ def main():
     ev1.record(ctx.stream)
     ev1.synchronize()
     sk6_ms = ev0.elapsed_time(ev1) / args.sketch_launches
+    # and with symmetric-tile reuse (each entry of the upper block triangle
+    # evaluated once; its timing includes the scratch reduction)
+    h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=h2.FP64_SYM)
+    ev0.record(ctx.stream)
+    for _ in range(args.sketch_launches):
+        h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=h2.FP64_SYM)
+    ev1.record(ctx.stream)
+    ev1.synchronize()
+    sksym_ms = ev0.elapsed_time(ev1) / args.sketch_launches
     entries = float(w.n) * w.n
     achieved = sketch_flops_per_entry(w.dim, nc) * entries / (sk_ms * 1e-3) / 1e12
     sketch_tflops = 2.0 * entries * nc / (sk_ms * 1e-3) / 1e12
@@ -775,6 +786,7 @@ def main():
         "sketch_kernel_ms": sk_ms,
         "sketch_bf16x6_kernel_ms": sk6_ms,
         "sketch_bf16x6_tflops": 2.0 * entries * nc / (sk6_ms * 1e-3) / 1e12,
+        "sketch_fp64_sym_kernel_ms": sksym_ms,
         "mixed_vs_fp64_speedup": mixed.get("bf16x6", {}).get("speedup_vs_fp64"),
         "mixed": mixed,
         "samples": info["samples"],

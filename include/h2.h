@@ -116,7 +116,17 @@ typedef int (*h2_entry_fn)(void* user, int32_t nblocks, const int32_t* idx, cons
  *              most 2 run on the bf16 matrix cores with FP32 accumulation,
  *              folded into FP64 every 64 points: FP32-accurate products at a
  *              fraction of the FP32 matrix-core cycles. */
-typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2, H2_FP32E = 3, H2_BF16X6 = 4 } h2_precision;
+typedef enum { H2_FP64 = 0, H2_FP32 = 1, H2_BF16X3 = 2, H2_FP32E = 3, H2_BF16X6 = 4, H2_FP64_SYM = 5 } h2_precision;
+/*   H2_FP64_SYM: FP64 entries and matrix cores as H2_FP64, with the symmetry
+ *              of K used in the sketch: the entries of each pair of 128-point
+ *              tiles (a, b), a < b, are evaluated once and contracted with
+ *              both Omega(I_b) (for Y(I_a)) and Omega(I_a) (for Y(I_b)).  The
+ *              transposed products pass through device scratch that each
+ *              sketch call allocates and frees in stream order:
+ *              512 * sum_a max(0, n - 128 (a + 1)) bytes, about 2 n^2 (34 GB at
+ *              n = 131072), so n <= 163840.  Results equal H2_FP64's to
+ *              rounding (another summation order).  h2_sketch and single
+ *              builds with a built-in kernel only. */
 
 /* How the absolute ID/stopping threshold delta is derived from tol
  * (Sec. III-B: "an approximate norm of the matrix ... via sketching"):

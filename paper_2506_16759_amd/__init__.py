@@ -16,14 +16,14 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (BF16X3, BF16X6, FP32, FP32E, FP64, K_EXP, K_GAUSS, K_HELMHOLTZ, NORM_FRO_SCALED, NORM_LITERAL,
+from ._lib import (BF16X3, BF16X6, FP32, FP32E, FP64, FP64_SYM, K_EXP, K_GAUSS, K_HELMHOLTZ, NORM_FRO_SCALED, NORM_LITERAL,
                    H2Error)
 
 __all__ = ["opts_default", "Context", "Plan", "plan_create", "gaussian", "sketch", "build", "build_batched",
            "build_update", "autotune_leaf", "autotune_tiles", "device_view", "EntryBatch",
            "H2Matrix",
            "kernel_spec", "H2Error", "K_EXP", "K_GAUSS", "K_HELMHOLTZ", "FP64", "FP32", "BF16X3", "FP32E", "BF16X6",
-           "NORM_FRO_SCALED", "NORM_LITERAL"]
+           "FP64_SYM", "NORM_FRO_SCALED", "NORM_LITERAL"]
 
 
 def _torch():

@@ -12,7 +12,7 @@ STATUS = {0: "H2_OK", -1: "H2_ERR_ARG", -2: "H2_ERR_HIP", -3: "H2_ERR_OOM", -4: 
           -5: "H2_ERR_SAMPLES", -6: "H2_ERR_STATE", -7: "H2_ERR_UNSUPPORTED"}
 
 K_EXP, K_GAUSS, K_HELMHOLTZ = 1, 2, 3
-FP64, FP32, BF16X3, FP32E, BF16X6 = 0, 1, 2, 3, 4
+FP64, FP32, BF16X3, FP32E, BF16X6, FP64_SYM = 0, 1, 2, 3, 4, 5
 NORM_FRO_SCALED, NORM_LITERAL = 0, 1
 
 PART = dict(DEPTH=0, PERM=1, NODES=2, BOXES=3, NEAR_PTR=4, NEAR_IDX=5, FAR_PTR=6, FAR_IDX=7, RANKS=8,

@@ -407,6 +407,11 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
 
 namespace {
 
+// The symmetric-tile sketch's scratch grows as 2 n^2 bytes.
+void check_sym_size(int64_t n) {
+  if (n > 163840) throw Error(H2_ERR_UNSUPPORTED, "H2_FP64_SYM needs about 2 n^2 bytes of scratch: n <= 163840");
+}
+
 void check_opts(const h2_opts* o) {
   H2_REQUIRE(o != nullptr, "opts is NULL");
   H2_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be finite and > 0");
@@ -416,7 +421,7 @@ void check_opts(const h2_opts* o) {
   H2_REQUIRE(o->d_inc >= 0 && o->d_inc <= 128, "d_inc must be in [0, 128]");
   H2_REQUIRE(o->d_max >= o->d0 && o->d_max <= 256, "d_max must be in [d0, 256]");
   H2_REQUIRE(o->precision == H2_FP64 || o->precision == H2_FP32 || o->precision == H2_BF16X3 ||
-                 o->precision == H2_FP32E || o->precision == H2_BF16X6,
+                 o->precision == H2_FP32E || o->precision == H2_BF16X6 || o->precision == H2_FP64_SYM,
              "unknown precision");
   H2_REQUIRE(o->norm_mode == H2_NORM_FRO_SCALED || o->norm_mode == H2_NORM_LITERAL, "unknown norm_mode");
   H2_REQUIRE(o->sketch_ahead >= 0 && o->sketch_ahead <= 256, "sketch_ahead must be in [0, 256]");
@@ -1091,15 +1096,16 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
     H2_REQUIRE(ctx != nullptr, "ctx is NULL");
     check_kernel(kernel);
     H2_REQUIRE(precision == H2_FP64 || precision == H2_FP32 || precision == H2_BF16X3 || precision == H2_FP32E ||
-                 precision == H2_BF16X6,
+                 precision == H2_BF16X6 || precision == H2_FP64_SYM,
                "unknown precision");
     H2_REQUIRE(n >= 0 && n < (int64_t{1} << 31), "n out of range");
     H2_REQUIRE(dim >= 1 && dim <= 3, "dim must be 1..3");
     H2_REQUIRE(ncols >= 0 && ncols <= 128, "ncols must be in [0, 128]");
     H2_REQUIRE(ldo >= std::max<int64_t>(n, 1) && ldy >= std::max<int64_t>(n, 1), "ld < n");
     H2_REQUIRE((points && omega && y) || n * int64_t(ncols) == 0, "NULL pointer");
-    if (kernel->kind == H2_K_HELMHOLTZ && precision != H2_FP64)
+    if (kernel->kind == H2_K_HELMHOLTZ && precision != H2_FP64 && precision != H2_FP64_SYM)
       throw Error(H2_ERR_UNSUPPORTED, "the Helmholtz kernel is evaluated in FP64 only");
+    if (precision == H2_FP64_SYM) check_sym_size(n);
     H2_HIP(hipSetDevice(ctx->device));
     H2_HIP(h2dev::sketch(ctx->stream, precision, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
   });
@@ -1121,8 +1127,11 @@ h2_status h2_build(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, co
       H2_REQUIRE(sketch != nullptr && entry != nullptr, "without a kernel both callbacks are required");
     }
     check_opts(opts);
-    if ((sketch || (kernel && kernel->kind == H2_K_HELMHOLTZ)) && opts->precision != H2_FP64)
-      throw Error(H2_ERR_UNSUPPORTED, "reduced precision applies to the built-in covariance sketches only");
+    if (sketch && opts->precision != H2_FP64)
+      throw Error(H2_ERR_UNSUPPORTED, "the precision modes apply to the built-in sketches only");
+    if (kernel && kernel->kind == H2_K_HELMHOLTZ && opts->precision != H2_FP64 && opts->precision != H2_FP64_SYM)
+      throw Error(H2_ERR_UNSUPPORTED, "the Helmholtz kernel is evaluated in FP64 only");
+    if (opts->precision == H2_FP64_SYM) check_sym_size(n);
     H2_HIP(hipSetDevice(ctx->device));
     auto h = std::make_unique<h2_matrix>();
     h->device = ctx->device;

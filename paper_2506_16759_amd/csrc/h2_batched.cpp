@@ -827,6 +827,8 @@ extern "C" h2_status h2_build_batched(h2_ctx* ctx, int32_t count, const h2_probl
     H2_REQUIRE(ctx && problems && bopts && out, "NULL argument");
     H2_REQUIRE(count >= 1, "count must be >= 1");
     const int prec = bopts->precision;
+    if (prec == H2_FP64_SYM)
+      throw Error(H2_ERR_UNSUPPORTED, "batched builds use the dense sketch (H2_FP64_SYM is for single builds)");
     H2_REQUIRE(prec == H2_FP64 || prec == H2_FP32 || prec == H2_BF16X3 || prec == H2_FP32E || prec == H2_BF16X6,
                "unknown precision");
     const int dcap = bopts->d_max;

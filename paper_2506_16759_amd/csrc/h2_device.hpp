@@ -31,12 +31,16 @@ hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* 
                     double* out, int64_t ldo);
 
 // Dense on-the-fly sketch y = K(X,X) omega, X = (dim x n) SoA with leading
-// dimension ldx.  precision 0: FP64 entries and FP64 MFMA; 1: FP32 entries
-// and FP32 MFMA; 2: FP32 entries split into bf16 pairs, three bf16 MFMA
-// products.  Mixed modes fold FP32 partial sums into FP64 every 256 points;
-// y is always FP64.
+// dimension ldx; precision is an h2_precision value (0 FP64, 1 FP32, 2
+// BF16X3, 3 FP32E, 4 BF16X6, 5 FP64 with symmetric-tile reuse).  Mixed modes
+// fold FP32 partial sums into FP64 every 64 points; y is always FP64.  The
+// split-bf16 modes and mode 5 take stream-ordered scratch (hipMallocAsync).
 hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
                   int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy);
+
+// Device scratch of one symmetric-tile sketch call (precision 5):
+// 512 * sum over tiles a of max(0, n - 128 (a + 1)) bytes, about 2 n^2.
+size_t sketch_sym_scratch_bytes(int64_t n);
 
 // Kernel blocks of a CSR block pattern: for block row i and entry j in [ptr[i], ptr[i+1]) with
 // b = idx[j], writes kappa(X[rowoff[i] + r], X[rowoff[b] + c]) to out[blkoff[j] + r + c*m_i].

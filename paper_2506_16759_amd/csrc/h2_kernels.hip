@@ -245,6 +245,270 @@ __global__ __launch_bounds__(256, 3) void sketch_f64_batched(const SketchJob* __
     sketch_f64_body<3, kGauss, NC>(sm, t0, J.n, X + J.base, ldx, J.c2, ncr, omega + J.base, ldo, y + J.base, ldy);
 }
 
+// --------------------------------------------- symmetric-tile FP64 sketch
+//
+// K is symmetric, so the entries of a pair of 128-row tiles (a, b), a < b,
+// serve both Y(I_a) += K(I_a, I_b) Omega(I_b) and Y(I_b) += K(I_a, I_b)^T
+// Omega(I_a): every entry of the upper block triangle is evaluated once.
+// Workgroup a keeps rows I_a stationary and streams the points from the start
+// of I_a to n, 32 per stage:
+//  * the row side accumulates in registers as in sketch_f64_body (the
+//    diagonal tile in full, then every later point);
+//  * in stages past the diagonal tile the entries also go to LDS, and the
+//    four waves form P = K(I_a, stage)^T Omega(I_a) (32 points x 64 columns)
+//    on the matrix cores: wave w takes points 16 (w / 2) .. + 15 of the stage
+//    and column tiles 2 (w % 2), 2 (w % 2) + 1, the contraction running over
+//    all 128 rows of the tile, with its Omega(I_a) operands (64 per lane)
+//    held in registers for the whole workgroup (one workgroup per CU, so a
+//    wave has the register file of its SIMD to itself).  The entries of
+//    consecutive stages alternate between two LDS buffers, and the transposed
+//    product of a stage runs in the next stage, after the row side's entries,
+//    so that a stage has two barriers.  P goes to the scratch slot of tile a,
+//    which holds points 128 (a + 1) .. n - 1, 64 doubles per point, from
+//    sym_slot(a, n) points on.
+// sketch_sym_reduce_kernel then adds to each point's row-side result the
+// slots of the tiles before its own, in increasing a (a fixed order, so the
+// result does not depend on scheduling).
+constexpr int kSymLdE = kSkF64 + 2;
+
+template <int DIM>
+struct SkSymSmem {
+  double xs[DIM][kSkF64];
+  double om[kSkF64][64 + 2];
+  double e[2][kSkRows][kSymLdE];  // K(I_a, stage points), stages alternating
+};
+
+// First scratch row of tile a's slot: sum over a' < a of (n - 128 (a' + 1)).
+__host__ __device__ inline int64_t sym_slot(int64_t a, int64_t n) { return a * n - kSkRows * a * (a + 1) / 2; }
+
+template <int DIM, int KIND>
+__global__ __launch_bounds__(256, 1) void sketch_sym_f64_kernel(int64_t n, const double* __restrict__ X,
+                                                                int64_t ldx, double c2, int ncr,
+                                                                const double* __restrict__ omega, int64_t ldo,
+                                                                double* __restrict__ y, int64_t ldy,
+                                                                double* __restrict__ z) {
+  constexpr int NC = 64, NB = 4;
+  __shared__ SkSymSmem<DIM> sm;
+  auto& xs = sm.xs;
+  auto& om = sm.om;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t a = blockIdx.x;
+  const int64_t tile0 = a * kSkRows;
+  const int64_t row0 = tile0 + wave * 32;
+
+  double xa[DIM], xb[DIM];
+  {
+    const int64_t ia = row0 + li, ib = row0 + 16 + li;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      xa[d] = ia < n ? X[d * ldx + ia] : 0.0;
+      xb[d] = ib < n ? X[d * ldx + ib] : 0.0;
+    }
+  }
+  dbl4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    acc0[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+    acc1[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  const int pb = wave >> 1, ct = 2 * (wave & 1);  // this wave's block of the transposed product
+  // B operands of the transposed product: Omega(tile0 + 4s + l/16, 16 (ct + h) + l%16)
+  double ob[2][kSkRows / 4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = 16 * (ct + h) + li;
+#pragma unroll
+    for (int s2 = 0; s2 < kSkRows / 4; ++s2) {
+      const int64_t r = tile0 + 4 * s2 + lk;
+      ob[h][s2] = (r < n && c < ncr) ? omega[c * ldo + r] : 0.0;
+    }
+  }
+  double* const zs = z + NC * sym_slot(a, n);
+
+  constexpr int PX = (DIM * kSkF64 + 255) / 256, PO = NC * kSkF64 / 256;
+  double rx[PX], ro[PO];
+  auto fetch = [&](int64_t j0) {
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u, d = e / kSkF64, jj = e % kSkF64;
+      rx[u] = (e < DIM * kSkF64 && j0 + jj < n) ? X[d * ldx + j0 + jj] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u, c = e / kSkF64, jj = e % kSkF64;
+      ro[u] = (j0 + jj < n && c < ncr) ? omega[c * ldo + j0 + jj] : 0.0;
+    }
+  };
+  // D[point][column] = sum over the 128 rows r of K(r, point) Omega(r, column)
+  // for the 32 points of stage jp (entries in buffer eb): lane l supplies
+  // A[l%16][l/16] = K(4s + l/16, point) and B[l/16][l%16] = Omega(4s + l/16, column).
+  // The result stays in registers until the next stage has passed its
+  // barriers and is stored before that stage's prefetch is issued, so the
+  // wait for the prefetch does not include fresh stores (one counter covers
+  // both).
+  dbl4 t0{0.0, 0.0, 0.0, 0.0}, t1{0.0, 0.0, 0.0, 0.0};
+  int64_t tst = -1;  // stage of the unstored result
+  // (even and odd row steps accumulate separately: four independent chains)
+  auto transposed = [&](int64_t jp, int eb) {
+    dbl4 u0{0.0, 0.0, 0.0, 0.0}, u1{0.0, 0.0, 0.0, 0.0};
+    t0 = dbl4{0.0, 0.0, 0.0, 0.0};
+    t1 = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kSkRows / 4; s += 2) {
+      const double av = sm.e[eb][4 * s + lk][16 * pb + li];
+      const double aw = sm.e[eb][4 * s + 4 + lk][16 * pb + li];
+      t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ob[0][s], t0, 0, 0, 0);
+      t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, ob[1][s], t1, 0, 0, 0);
+      u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, ob[0][s + 1], u0, 0, 0, 0);
+      u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(aw, ob[1][s + 1], u1, 0, 0, 0);
+    }
+    t0 += u0;
+    t1 += u1;
+    tst = jp;
+  };
+  auto store_transposed = [&] {
+    if (tst < 0) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t p = tst + 16 * pb + lk + 4 * q;
+      if (p < n) {
+        double* zr = zs + (p - tile0 - kSkRows) * NC;
+        zr[16 * ct + li] = t0[q];
+        zr[16 * ct + 16 + li] = t1[q];
+      }
+    }
+    tst = -1;
+  };
+  fetch(tile0);
+  int64_t pending = -1;  // stage whose transposed product is still to do
+  for (int64_t j0 = tile0; j0 < n; j0 += kSkF64) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PX; ++u) {
+      const int e = tid + 256 * u;
+      if (e < DIM * kSkF64) xs[e / kSkF64][e % kSkF64] = rx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PO; ++u) {
+      const int e = tid + 256 * u;
+      om[e % kSkF64][e / kSkF64] = ro[u];
+    }
+    __syncthreads();
+    store_transposed();
+    if (j0 + kSkF64 < n) fetch(j0 + kSkF64);
+    const bool cross = j0 >= tile0 + kSkRows;  // the same for the whole workgroup
+    const int cur = int((j0 - tile0) / kSkF64) & 1;
+#pragma unroll 4
+    for (int kk = 0; kk < kSkF64 / 4; ++kk) {
+      const int jj = kk * 4 + lk;
+      double ra = 0.0, rb = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double xj = xs[d][jj];
+        const double da = xa[d] - xj, db = xb[d] - xj;
+        ra += da * da;
+        rb += db * db;
+      }
+      const double ka = kernel_of_r2<KIND>(ra, c2);
+      const double kb = kernel_of_r2<KIND>(rb, c2);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double bv = om[jj][c * 16 + li];
+        acc0[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ka, bv, acc0[c], 0, 0, 0);
+        acc1[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(kb, bv, acc1[c], 0, 0, 0);
+      }
+      if (cross) {
+        sm.e[cur][wave * 32 + li][jj] = ka;
+        sm.e[cur][wave * 32 + 16 + li][jj] = kb;
+      }
+    }
+    // the previous stage's entries were written before this stage's barriers
+    if (pending >= 0) transposed(pending, cur ^ 1);
+    pending = cross ? j0 : -1;
+  }
+  store_transposed();
+  if (pending >= 0) {
+    __syncthreads();
+    transposed(pending, int((pending - tile0) / kSkF64) & 1);
+    store_transposed();
+  }
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    const int col = c * 16 + li;
+    if (col >= ncr) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t ra = row0 + lk + 4 * q, rb = row0 + 16 + lk + 4 * q;
+      if (ra < n) y[col * ldy + ra] = acc0[c][q];
+      if (rb < n) y[col * ldy + rb] = acc1[c][q];
+    }
+  }
+}
+
+// y(p, c) += slot a of z at point p for every tile a before p's own, in
+// increasing a.  One workgroup per 64 points (all in one 128-point tile); y is
+// read and written down its columns through an LDS transpose, z along its
+// 64-double rows.
+__global__ __launch_bounds__(256) void sketch_sym_reduce_kernel(int64_t n, int ncr, const double* __restrict__ z,
+                                                                double* __restrict__ y, int64_t ldy) {
+  __shared__ double t[64][65];  // [column][point]
+  // the last points (the most slots to add) first
+  const int64_t p0 = int64_t(gridDim.x - 1 - blockIdx.x) * 64;
+  const int64_t b = p0 / kSkRows;
+  if (b == 0) return;  // tile 0 receives nothing (uniform over the workgroup)
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k, c = e >> 6, pp = e & 63;
+    t[c][pp] = (c < ncr && p0 + pp < n) ? y[c * ldy + p0 + pp] : 0.0;
+  }
+  __syncthreads();
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k;
+    v[k] = t[e & 63][e >> 6];
+  }
+  // two slots' loads in flight before their sums (same order of additions)
+  int64_t a = 0;
+  for (; a + 1 < b; a += 2) {
+    const double* z0 = z + 64 * (sym_slot(a, n) + p0 - (a + 1) * kSkRows);
+    const double* z1 = z + 64 * (sym_slot(a + 1, n) + p0 - (a + 2) * kSkRows);
+    double w0[16], w1[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      const bool in = p0 + (e >> 6) < n;
+      w0[k] = in ? z0[e] : 0.0;
+      w1[k] = in ? z1[e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = (v[k] + w0[k]) + w1[k];
+  }
+  if (a < b) {
+    const double* z0 = z + 64 * (sym_slot(a, n) + p0 - (a + 1) * kSkRows);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k;
+      if (p0 + (e >> 6) < n) v[k] += z0[e];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k;
+    t[e & 63][e >> 6] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int e = tid + 256 * k, c = e >> 6, pp = e & 63;
+    if (c < ncr && p0 + pp < n) y[c * ldy + p0 + pp] = t[c][pp];
+  }
+}
+
 // --------------------------------------------- mixed-precision sketches
 
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -2735,11 +2999,67 @@ hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* 
   return hipGetLastError();
 }
 
+size_t sketch_sym_scratch_bytes(int64_t n) {
+  if (n <= kSkRows) return 0;
+  const int64_t tiles = (n + kSkRows - 1) / kSkRows;
+  return size_t(sym_slot(tiles - 1, n)) * 64 * sizeof(double);
+}
+
+namespace {
+
+template <int DIM, int KIND>
+void launch_sketch_sym_k(hipStream_t s, int64_t n, const double* X, int64_t ldx, double c2, int ncr,
+                         const double* om, int64_t ldo, double* y, int64_t ldy, double* z) {
+  const unsigned tiles = static_cast<unsigned>((n + kSkRows - 1) / kSkRows);
+  sketch_sym_f64_kernel<DIM, KIND><<<tiles, 256, 0, s>>>(n, X, ldx, c2, ncr, om, ldo, y, ldy, z);
+  if (tiles > 1) sketch_sym_reduce_kernel<<<static_cast<unsigned>((n + 63) / 64), 256, 0, s>>>(n, ncr, z, y, ldy);
+}
+
+hipError_t sketch_sym(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
+                      const double* omega, int64_t ldo, double* y, int64_t ldy) {
+  const double c2 = kernel_c2(k);
+  const size_t bytes = sketch_sym_scratch_bytes(n);
+  double* z = nullptr;
+  if (bytes > 0) {
+    const hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&z), bytes, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int c0 = 0; c0 < ncols; c0 += 64) {
+    const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
+    const double* om = omega + int64_t(c0) * ldo;
+    double* yy = y + int64_t(c0) * ldy;
+#define H2_SYM(D, K) launch_sketch_sym_k<D, K>(s, n, X, ldx, c2, nc, om, ldo, yy, ldy, z)
+    if (k.kind == kExp) {
+      if (dim == 1) H2_SYM(1, kExp);
+      else if (dim == 2) H2_SYM(2, kExp);
+      else H2_SYM(3, kExp);
+    } else if (k.kind == kHelm) {
+      if (dim == 1) H2_SYM(1, kHelm);
+      else if (dim == 2) H2_SYM(2, kHelm);
+      else H2_SYM(3, kHelm);
+    } else {
+      if (dim == 1) H2_SYM(1, kGauss);
+      else if (dim == 2) H2_SYM(2, kGauss);
+      else H2_SYM(3, kGauss);
+    }
+#undef H2_SYM
+  }
+  hipError_t e = hipGetLastError();
+  if (z) {
+    const hipError_t f = hipFreeAsync(z, s);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
+}
+
+}  // namespace
+
 hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
                   int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
-  if (precision < 0 || precision > 4) return hipErrorInvalidValue;
-  if (k.kind == kHelm && precision != 0) return hipErrorInvalidValue;
+  if (precision < 0 || precision > 5) return hipErrorInvalidValue;
+  if (k.kind == kHelm && precision != 0 && precision != 5) return hipErrorInvalidValue;
+  if (precision == 5) return sketch_sym(s, n, dim, X, ldx, k, ncols, omega, ldo, y, ldy);
   const double c2 = kernel_c2(k);
   // split-bf16 modes: Omega is split once per launch into stream-ordered scratch
   const int S = precision == 2 ? 2 : (precision == 4 ? 3 : 0);

@@ -1,0 +1,124 @@
+"""Symmetric-tile sketch (H2_FP64_SYM): the entries of each pair of 128-point
+tiles evaluated once and contracted with both tiles' Omega rows, the
+transposed products summed through device scratch in a fixed order.
+
+Against the oracle's dense sketch K Omega (FP64) at 1e-12 of each column's
+largest value, the bar of the dense FP64 sketch (the same products summed in
+another order, entries within a few ulps), and against the dense FP64 sketch
+of the library at 1e-13.  Cases: one point, one partial tile, exactly one
+tile, one point past a tile, ragged sizes in 1-3 dimensions, all three kernel
+functions, more than 64 columns (two column chunks), and the 131072-point
+cube on sampled rows.  A build with the mode is compared with the oracle's
+construction of the same problem, factor by factor, as the FP64 build is."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import paper_2506_16759_amd as h2
+from paper_2506_16759_amd.workloads import CUBE_131K, uniform_points
+from oracle.build import build_h2
+from oracle.kernels import KernelOperator
+from gpu_util import compare_with_oracle
+
+
+def _say(msg):
+    print(f"[gpu case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return h2.Context(0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _colmajor_from(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).cuda().T
+
+
+CASES = [
+    (1, 3, "exp", 0.2, 1), (100, 2, "exp", 0.1, 8), (128, 3, "exp", 0.2, 64), (129, 3, "gauss", 0.15, 16),
+    (777, 1, "exp", 0.3, 3), (1000, 2, "exp", 0.1, 32), (3001, 3, "exp", 0.2, 48), (4096, 3, "exp", 0.2, 64),
+    (2500, 2, "gauss", 0.05, 80), (2000, 3, "helmholtz", 3.0, 24),
+]
+
+
+@pytest.mark.parametrize("n,dim,kind,length,ncols", CASES)
+def test_sym_sketch_matches_oracle(ctx, n, dim, kind, length, ncols):
+    import torch
+    _say(f"symmetric sketch n={n} dim={dim} kernel={kind} l={length} ncols={ncols}")
+    pts = uniform_points(n, dim, 20 + n)
+    om = np.random.default_rng(n + 1).standard_normal((n, ncols))
+    tp, to = torch.from_numpy(pts), _colmajor_from(om)
+    ys = _np(h2.sketch(ctx, tp, kind, length, to, precision=h2.FP64_SYM))
+    yd = _np(h2.sketch(ctx, tp, kind, length, to))
+    ref = KernelOperator(pts, kind, length).sketch(om)
+    scale = np.abs(ref).max(axis=0)
+    assert (np.abs(ys - ref).max(axis=0) <= 1e-12 * scale).all()
+    assert (np.abs(ys - yd).max(axis=0) <= 1e-13 * scale).all()
+
+
+def test_sym_sketch_full_size_cube(ctx):
+    """The 131072-point cube, 64 columns (one build's first pass): 64 sampled
+    rows against the oracle, every row against the dense FP64 sketch."""
+    import torch
+    w = CUBE_131K
+    _say(f"symmetric sketch {w.name} n={w.n} ncols=64")
+    pts = w.points()
+    om = np.random.default_rng(6).standard_normal((w.n, 64))
+    tp, to = torch.from_numpy(pts).cuda(), _colmajor_from(om)
+    ys = h2.sketch(ctx, tp, w.kernel, w.length, to, precision=h2.FP64_SYM)
+    yd = h2.sketch(ctx, tp, w.kernel, w.length, to)
+    scale = yd.abs().amax(dim=0)
+    rel = ((ys - yd).abs().amax(dim=0) / scale).max().item()
+    _say(f"  max column-relative difference to the dense sketch {rel:.3e}")
+    assert rel <= 1e-13
+    rows = np.random.default_rng(18).choice(w.n, 64, replace=False)
+    ref = KernelOperator(pts, w.kernel, w.length).sketch_rows(rows, om)
+    assert np.abs(_np(ys)[rows] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,dim,kind,length,leaf,tol,d0,seed", [
+    (6000, 3, "exp", 0.2, 64, 1e-7, 16, 11),     # adaptive rounds at the leaves
+    (5000, 2, "gauss", 0.1, 50, 1e-6, 16, 12),   # ragged leaves, Gaussian kernel
+])
+def test_sym_build_matches_oracle(ctx, n, dim, kind, length, leaf, tol, d0, seed):
+    _say(f"symmetric-sketch build vs oracle n={n} dim={dim} {kind} l={length} leaf={leaf} tol={tol} d0={d0}")
+    pts = uniform_points(n, dim, 40 + n)
+    H = h2.build(ctx, pts, kind, length, tol=tol, leaf_size=leaf, eta=0.7, d0=d0, d_inc=16, seed=seed,
+                 precision=h2.FP64_SYM)
+    info = H.info()
+    op = KernelOperator(pts, kind, length)
+    ho = build_h2(op, pts, leaf, 0.7, tol, d0, 16, 256, seed)
+    _say(f"samples {info['samples']} (oracle {ho.samples}), rounds {info['rounds']}, "
+         f"ranks {info['rank_min']}..{info['rank_max']}")
+    assert info["samples"] == ho.samples
+    assert info["rounds"] == sum(ho.rounds.values())
+    assert abs(info["delta"] - ho.delta) <= 1e-12 * ho.delta
+    diff = compare_with_oracle(H, ho)
+    _say(f"ID matrix differences per depth {diff}")
+    x = np.random.default_rng(2).standard_normal((n, 4))
+    y, yo = _np(H.matvec(_colmajor_from(x))), ho.matvec(x)
+    assert np.linalg.norm(y - yo) / np.linalg.norm(yo) <= 1e-10
+
+
+def test_sym_limits(ctx):
+    """Sizes past the scratch limit and batched builds are refused."""
+    import torch
+    n = 163841
+    pts = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    om = torch.zeros((1, n), dtype=torch.float64, device="cuda").T
+    with pytest.raises(h2.H2Error) as e:
+        h2.sketch(ctx, pts, "exp", 0.2, om, precision=h2.FP64_SYM)
+    assert e.value.status == -7
+    with pytest.raises(h2.H2Error) as e:
+        h2.build_batched(ctx, [{"points": uniform_points(1000, 3, 1), "kernel": "exp", "length": 0.2}],
+                         precision=h2.FP64_SYM)
+    assert e.value.status == -7
