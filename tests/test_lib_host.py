@@ -30,6 +30,14 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(_lib.EXPORTED)
 
 
+def test_precision_constants_match_the_header():
+    text = open(os.path.join(ROOT, "include", "h2.h")).read()
+    body = re.search(r"typedef enum \{([^}]*)\} h2_precision;", text).group(1)
+    values = {k: int(v) for k, v in re.findall(r"H2_(\w+)\s*=\s*(\d+)", body)}
+    assert values == {"FP64": h2.FP64, "FP32": h2.FP32, "BF16X3": h2.BF16X3, "FP32E": h2.FP32E,
+                      "BF16X6": h2.BF16X6, "FP64_SYM": h2.FP64_SYM}
+
+
 def test_status_strings_and_defaults():
     lib = _lib.load()
     assert lib.h2_status_string(-5).decode() == "adaptive sampling reached d_max"
