@@ -671,7 +671,9 @@ class Builder {
     if (op_.sketch) {
       call_sketch(op_.sketch, op_.sketch_user, n, nc, om, n, y, n, s_);
     } else {
-      H2_HIP(h2dev::sketch(s_, h.opts.precision, n, dim_, points_, n, kf_, nc, om, n, y, n));
+      DevArray<double> zs;  // the symmetric-tile sketch's scratch (kept by the huge-block cache)
+      if (h.opts.precision == H2_FP64_SYM) zs.alloc(h2dev::sketch_sym_scratch_bytes(n) / sizeof(double), s_);
+      H2_HIP(h2dev::sketch(s_, h.opts.precision, n, dim_, points_, n, kf_, nc, om, n, y, n, zs.get()));
       h.sketch_flops += 2.0 * double(n) * double(n) * nc;
       h.sketch_entries += double(n) * double(n);
     }
@@ -1107,7 +1109,11 @@ h2_status h2_sketch(h2_ctx* ctx, int64_t n, int32_t dim, const double* points, c
       throw Error(H2_ERR_UNSUPPORTED, "the Helmholtz kernel is evaluated in FP64 only");
     if (precision == H2_FP64_SYM) check_sym_size(n);
     H2_HIP(hipSetDevice(ctx->device));
-    H2_HIP(h2dev::sketch(ctx->stream, precision, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy));
+    DevArray<double> zs;  // the symmetric-tile sketch's scratch (kept by the huge-block cache)
+    if (precision == H2_FP64_SYM && ncols > 0)
+      zs.alloc(h2dev::sketch_sym_scratch_bytes(n) / sizeof(double), ctx->stream);
+    H2_HIP(h2dev::sketch(ctx->stream, precision, n, dim, points, n, kernel_fn(*kernel), ncols, omega, ldo, y, ldy,
+                         zs.get()));
   });
 }
 

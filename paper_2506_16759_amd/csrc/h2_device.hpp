@@ -34,9 +34,12 @@ hipError_t gaussian(hipStream_t s, uint64_t seed, int64_t nrows, const int32_t* 
 // dimension ldx; precision is an h2_precision value (0 FP64, 1 FP32, 2
 // BF16X3, 3 FP32E, 4 BF16X6, 5 FP64 with symmetric-tile reuse).  Mixed modes
 // fold FP32 partial sums into FP64 every 64 points; y is always FP64.  The
-// split-bf16 modes and mode 5 take stream-ordered scratch (hipMallocAsync).
+// split-bf16 modes take stream-ordered scratch (hipMallocAsync); mode 5 uses
+// sym_scratch (sketch_sym_scratch_bytes(n) bytes, stream-ordered on s) when
+// given, else allocates it likewise.
 hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
-                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy);
+                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy,
+                  double* sym_scratch = nullptr);
 
 // Device scratch of one symmetric-tile sketch call (precision 5):
 // 512 * sum over tiles a of max(0, n - 128 (a + 1)) bytes, about 2 n^2.

@@ -3016,13 +3016,15 @@ void launch_sketch_sym_k(hipStream_t s, int64_t n, const double* X, int64_t ldx,
 }
 
 hipError_t sketch_sym(hipStream_t s, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k, int ncols,
-                      const double* omega, int64_t ldo, double* y, int64_t ldy) {
+                      const double* omega, int64_t ldo, double* y, int64_t ldy, double* given) {
   const double c2 = kernel_c2(k);
   const size_t bytes = sketch_sym_scratch_bytes(n);
-  double* z = nullptr;
-  if (bytes > 0) {
-    const hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&z), bytes, s);
+  double* z = given;
+  double* own = nullptr;
+  if (bytes > 0 && !z) {
+    const hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&own), bytes, s);
     if (e != hipSuccess) return e;
+    z = own;
   }
   for (int c0 = 0; c0 < ncols; c0 += 64) {
     const int nc = ncols - c0 < 64 ? ncols - c0 : 64;
@@ -3045,8 +3047,8 @@ hipError_t sketch_sym(hipStream_t s, int64_t n, int dim, const double* X, int64_
 #undef H2_SYM
   }
   hipError_t e = hipGetLastError();
-  if (z) {
-    const hipError_t f = hipFreeAsync(z, s);
+  if (own) {
+    const hipError_t f = hipFreeAsync(own, s);
     if (e == hipSuccess) e = f;
   }
   return e;
@@ -3055,11 +3057,11 @@ hipError_t sketch_sym(hipStream_t s, int64_t n, int dim, const double* X, int64_
 }  // namespace
 
 hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double* X, int64_t ldx, KernelFn k,
-                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy) {
+                  int ncols, const double* omega, int64_t ldo, double* y, int64_t ldy, double* sym_scratch) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
   if (precision < 0 || precision > 5) return hipErrorInvalidValue;
   if (k.kind == kHelm && precision != 0 && precision != 5) return hipErrorInvalidValue;
-  if (precision == 5) return sketch_sym(s, n, dim, X, ldx, k, ncols, omega, ldo, y, ldy);
+  if (precision == 5) return sketch_sym(s, n, dim, X, ldx, k, ncols, omega, ldo, y, ldy, sym_scratch);
   const double c2 = kernel_c2(k);
   // split-bf16 modes: Omega is split once per launch into stream-ordered scratch
   const int S = precision == 2 ? 2 : (precision == 4 ? 3 : 0);
