@@ -59,11 +59,13 @@ def measured_traffic(kernel: str):
         return None
 
 
-def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
+def traffic_summary(fetch_dir: str, write_dir: str, sq_dir: str | None = None) -> dict:
     """HBM bytes per sketch launch from two rocprofv3 --pmc runs of
     --profile-kernels (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
     scaled by what the same counter reads for the run's 1 GiB copy; the first
-    launch of each 64-column FP64/reduced-precision sketch counts."""
+    launch of each 64-column sketch kernel counts.  With a third run's
+    directory (SQ counters of the same command), its counters of the same
+    dispatches are attached as "sq"."""
     import csv
     import glob
     import re
@@ -92,12 +94,17 @@ def traffic_summary(fetch_dir: str, write_dir: str) -> dict:
              "sketch_f32_kernel<3,1,64>": "sketch_f32_kernel<3,exp,64>",
              "sketch_bf16_kernel<3,1,64,2>": "sketch_bf16_kernel<3,exp,64,2>",
              "sketch_e32_kernel<3,1,64>": "sketch_e32_kernel<3,exp,64>",
-             "sketch_bf16_kernel<3,1,64,3>": "sketch_bf16_kernel<3,exp,64,3>"}
+             "sketch_bf16_kernel<3,1,64,3>": "sketch_bf16_kernel<3,exp,64,3>",
+             "sketch_sym_f64_kernel<3,1>": "sketch_sym_f64_kernel<3,exp>",
+             "sketch_sym_reduce_kernel": "sketch_sym_reduce_kernel"}
+    q = _load_pmc(sq_dir) if sq_dir else {}
     kernels = {}
     for k in sorted(f):
         n = names.get(short(f[k][0]))
         if n and n not in kernels and k in w:
             kernels[n] = {"fetch_bytes": f[k][1] * fs * 1024, "write_bytes": w[k][1] * ws * 1024}
+            if k in q:
+                kernels[n]["sq"] = q[k]["c"]
     return {"source_sha256": sketch_source_digest(), "fetch_scale": fs, "write_scale": ws, "kernels": kernels}
 
 
@@ -595,15 +602,15 @@ def main():
                     help="only two FP64 builds of the benchmarked cube and a 1 GiB copy of known size, for counter "
                          "collection on every kernel of a build")
     ap.add_argument("--traffic-from", default=None,
-                    help="FETCH_DIR,WRITE_DIR: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE output directories of "
-                         "--profile-kernels; write the sketch launches' HBM bytes (scaled by the 1 GiB copy) as JSON "
-                         "to stdout")
+                    help="FETCH_DIR,WRITE_DIR[,SQ_DIR]: rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE (/ SQ counter) output "
+                         "directories of --profile-kernels; write the sketch launches' HBM bytes (scaled by the 1 GiB "
+                         "copy, with the SQ counters if given) as JSON to stdout")
     ap.add_argument("--build-counters", default=None,
                     help="FETCH_DIR,WRITE_DIR,SQ_DIR: rocprofv3 --pmc output directories of --profile-build; print "
                          "the per-kernel counter table of its second build (markdown rows)")
     ap.add_argument("--profile-kernels", action="store_true",
-                    help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6; 32 columns) twice each and a 1 GiB copy of "
-                         "known size, for counter collection")
+                    help="only run the sketch (FP64, FP32, bf16x3, FP32E, bf16x6, FP64_SYM; the first pass's 64 columns) "
+                         "twice each and a 1 GiB copy of known size, for counter collection")
     args = ap.parse_args()
     if args.traffic_from:
         print(json.dumps(traffic_summary(*args.traffic_from.split(",")), indent=1))
@@ -629,7 +636,7 @@ def main():
         pts = torch.from_numpy(w.points()).cuda()
         nc = first_pass_columns(h2, w)
         omega = h2.gaussian(ctx, w.omega_seed, torch.arange(w.n, dtype=torch.int32), 0, nc)
-        for prec in (h2.FP64, h2.FP32, h2.BF16X3, h2.FP32E, h2.BF16X6):
+        for prec in (h2.FP64, h2.FP32, h2.BF16X3, h2.FP32E, h2.BF16X6, h2.FP64_SYM):
             for _ in range(2):
                 h2.sketch(ctx, pts, w.kernel, w.length, omega, precision=prec)
         # calibration: a plain device copy of exactly 1 GiB (reads 1 GiB, writes 1 GiB)
