@@ -1114,8 +1114,9 @@ hipError_t launch_sketch_p(hipStream_t s, int64_t n, int dim, int kind, const do
 
 // ------------------------------------------------------ kernel block gen
 
-// One workgroup per block row.  The row cluster's coordinates stay in LDS for
-// the whole row.  The row's blocks are taken in stages of consecutive blocks
+// One workgroup per run of consecutive blocks of a block row (gen_part).  The
+// row cluster's coordinates stay in LDS for the whole run.  The run's blocks
+// are taken in stages of consecutive blocks
 // with at most kGenMax columns together (several small coupling blocks per
 // stage, one barrier per stage): thread t fetches the coordinates and output
 // offset of stage column t into registers while the current stage is
@@ -1246,19 +1247,30 @@ __device__ __forceinline__ void gen_row(const int32_t* __restrict__ idx, const i
   }
 }
 
+// A block row's blocks split into `parts` consecutive runs, one workgroup
+// each (workgroup b: row b / parts, run b % parts), so that a launch has
+// enough workgroups of similar size to fill the chip evenly.
+__device__ __forceinline__ void gen_part(const int32_t* __restrict__ ptr, int parts, int& i, int& jb, int& je) {
+  i = blockIdx.x / parts;
+  const int part = blockIdx.x % parts;
+  const int b0 = ptr[i], len = ptr[i + 1] - b0;
+  jb = b0 + (len * part) / parts;
+  je = b0 + (len * (part + 1)) / parts;
+}
+
 template <int DIM, int KIND>
 __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const int32_t* __restrict__ rowoff,
                                                          const int64_t* __restrict__ blkoff,
                                                          const double* __restrict__ X, int64_t ldx, double c2,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ out, int parts) {
   __shared__ double xr[DIM][kGenMax];
   __shared__ double xc[2][DIM][kGenMax];
   __shared__ int64_t off[2][kGenMax];
-  const int i = blockIdx.x;
+  int i, jb, je;
+  gen_part(ptr, parts, i, jb, je);
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  const int jb = ptr[i], je = ptr[i + 1];
   if (jb == je || m == 0) return;  // uniform over the workgroup
   gen_row<DIM>(idx, rowoff, blkoff, X, ldx, out, jb, je, r0, m, xr, xc, off,
                [c2](double r2) { return kernel_of_r2<KIND>(r2, c2); });
@@ -1274,13 +1286,13 @@ __global__ __launch_bounds__(256) void gen_blocks_batched_kernel(const int32_t* 
                                                                  const int32_t* __restrict__ rowprob,
                                                                  const int32_t* __restrict__ kinds,
                                                                  const double* __restrict__ c2s,
-                                                                 double* __restrict__ out) {
+                                                                 double* __restrict__ out, int parts) {
   __shared__ double xr[3][kGenMax];
   __shared__ double xc[2][3][kGenMax];
   __shared__ int64_t off[2][kGenMax];
-  const int i = blockIdx.x;
+  int i, jb, je;
+  gen_part(ptr, parts, i, jb, je);
   const int r0 = rowoff[i], m = rowoff[i + 1] - r0;
-  const int jb = ptr[i], je = ptr[i + 1];
   if (jb == je || m == 0) return;  // uniform over the workgroup
   const int pr = rowprob[i];
   const double c2 = c2s[pr];
@@ -3104,11 +3116,17 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
   return e;
 }
 
+// Workgroups per block row of a block generation: about 8192 workgroups in
+// all (several per CU at its occupancy), at most 8 per row.
+static int gen_parts(int nrows) { return std::max(1, std::min(8, (8192 + nrows - 1) / std::max(nrows, 1))); }
+
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out) {
   if (nrows <= 0) return hipSuccess;
   const double c2 = kernel_c2(k);
-#define H2_GEN(D, K) gen_blocks_kernel<D, K><<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, c2, out)
+  const int parts = gen_parts(nrows);
+#define H2_GEN(D, K) \
+  gen_blocks_kernel<D, K><<<nrows * parts, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, c2, out, parts)
   if (k.kind == kExp) {
     if (dim == 1) H2_GEN(1, kExp);
     else if (dim == 2) H2_GEN(2, kExp);
@@ -3362,7 +3380,9 @@ hipError_t gen_blocks_batched(hipStream_t s, int nrows, const int32_t* ptr, cons
                               const int64_t* blkoff, const double* X, int64_t ldx, const int32_t* rowprob,
                               const int32_t* kinds, const double* c2s, double* out) {
   if (nrows <= 0) return hipSuccess;
-  gen_blocks_batched_kernel<<<nrows, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, rowprob, kinds, c2s, out);
+  const int parts = gen_parts(nrows);
+  gen_blocks_batched_kernel<<<nrows * parts, 256, 0, s>>>(ptr, idx, rowoff, blkoff, X, ldx, rowprob, kinds, c2s, out,
+                                                          parts);
   return hipGetLastError();
 }
 

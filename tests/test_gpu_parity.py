@@ -451,3 +451,24 @@ def test_sketch_ahead_does_not_change_the_result(ctx):
             np.testing.assert_array_equal(a, b)
         for a, b in zip(o[4] + o[5], base[4] + base[5]):
             np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("precision", ["FP64", "BF16X6", "FP64_SYM"])
+def test_repeated_builds_are_bit_identical(ctx, precision):
+    """Two builds of the same problem give the same matrix bit for bit (no
+    atomics or scheduling-dependent sums on the path), so the benchmark may
+    measure accuracy on a build after its timed ones."""
+    n = 20000
+    _say(f"repeated builds n={n} precision={precision}")
+    pts = uniform_points(n, 3, 92)
+    outs = []
+    for _ in range(2):
+        H = h2.build(ctx, pts, "exp", 0.2, tol=1e-6, leaf_size=64, eta=0.7, d0=32, d_inc=16, seed=4,
+                     precision=getattr(h2, precision))
+        D, top = int(H.export("DEPTH")[0]), int(H.export("TOP")[0])
+        outs.append([H.export(part, t) for t in range(top, D + 1) for part in ("RANKS", "SKEL", "BASIS", "COUPLING")]
+                    + [H.export("DENSE")])
+        H.close()
+    assert len(outs[0]) == len(outs[1])
+    for a, b in zip(outs[0], outs[1]):
+        assert a.dtype == b.dtype and np.array_equal(a.view(np.uint8), b.view(np.uint8))
