@@ -1258,6 +1258,12 @@ __device__ __forceinline__ void gen_part(const int32_t* __restrict__ ptr, int pa
   je = b0 + (len * (part + 1)) / parts;
 }
 
+// Workgroups per block row of a block generation: about 16384 workgroups in
+// all (several per CU at its occupancy), at most 16 per row (measured on the
+// 131072-point cube: the leaf near field 3.54 ms with one workgroup per row,
+// 3.01 with 4, 2.80 with 8, 2.94 with 16).
+int gen_parts(int nrows) { return std::max(1, std::min(16, (16384 + nrows - 1) / std::max(nrows, 1))); }
+
 template <int DIM, int KIND>
 __global__ __launch_bounds__(256) void gen_blocks_kernel(const int32_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
@@ -3115,12 +3121,6 @@ hipError_t sketch(hipStream_t s, int precision, int64_t n, int dim, const double
   }
   return e;
 }
-
-// Workgroups per block row of a block generation: about 16384 workgroups in
-// all (several per CU at its occupancy), at most 16 per row (measured on the
-// 131072-point cube: the leaf near field 3.54 ms with one workgroup per row,
-// 3.01 with 4, 2.80 with 8, 2.94 with 16).
-static int gen_parts(int nrows) { return std::max(1, std::min(16, (16384 + nrows - 1) / std::max(nrows, 1))); }
 
 hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                       const int64_t* blkoff, int dim, const double* X, int64_t ldx, KernelFn k, double* out) {
