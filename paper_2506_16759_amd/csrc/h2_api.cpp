@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -379,7 +380,7 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
       H2_HIP(h2dev::bsr_gemm2(s, L.nn, R.fptr.get(), R.fidx.get(), L.koff.get(), C.koff.get(),
                               trans ? h.tpos[t].get() : nullptr, R.boff.get(), R.B.get(), xh[t],
                               C.koff_h.back(), yh[t], L.koff_h.back(), nc, 1.0,
-                              std::max({L.max_k, C.max_k, 1}), xrp, xr_cap));
+                              std::max({L.max_k, C.max_k, 1}), xrp, xr_cap, 64, R.forder.get()));
     }
     for (int t = h.top; t <= D; ++t) {  // downsweep
       const Level& L = dn[t];
@@ -393,7 +394,7 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
   int leaf_max = 0;
   for (int i = 0; i < nleaves; ++i) leaf_max = std::max(leaf_max, h.leafoff_h[i + 1] - h.leafoff_h[i]);
   H2_HIP(h2dev::bsr_gemm(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(), xt,
-                         ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr_cap));
+                         ldxt, yt, ldyt, nc, 1.0, leaf_max, xrp, xr_cap, 64, h.norder.get()));
   if (h.lr_rank > 0) {  // near-field part of the low-rank term: U_s sum_{b in N_s} V_b^T x_b (U, V swapped for A^T)
     const double* left = trans ? h.lrV.get() : h.lrU.get();
     const double* right = trans ? h.lrU.get() : h.lrV.get();
@@ -401,6 +402,14 @@ void matvec_tree(const h2_matrix& h, hipStream_t s, const double* xt, int64_t ld
     H2_HIP(h2dev::lr_apply(s, nleaves, h.nptr.get(), h.nidx.get(), h.leafoff.get(), n, left, n, h.lr_rank,
                            W, nc, yt, ldyt, 1.0));
   }
+}
+
+std::vector<int32_t> bsr_order(const std::vector<int32_t>& ptr) {
+  const int rows = ptr.empty() ? 0 : static_cast<int>(ptr.size()) - 1;
+  std::vector<int32_t> o(rows);
+  std::iota(o.begin(), o.end(), 0);
+  std::stable_sort(o.begin(), o.end(), [&](int32_t a, int32_t b) { return ptr[a + 1] - ptr[a] > ptr[b + 1] - ptr[b]; });
+  return o;
 }
 
 }  // namespace h2i
@@ -555,6 +564,7 @@ class Builder {
       h.perm.adopt(s_);
       h.X.adopt(s_);
       h.nptr.adopt(s_);
+      h.norder.adopt(s_);
       h.nidx.adopt(s_);
       h.leafoff.adopt(s_);
       h.doff.adopt(s_);
@@ -568,6 +578,7 @@ class Builder {
       timer_.end(ph, gs);
       ph = timer_.begin(kNearGen, gs);
       h.nptr.upload(p.near_ptr, gs);
+      h.norder.upload(bsr_order(p.near_ptr), gs);
       h.nidx.upload(p.near_idx, gs);
       h.leafoff.upload(h.leafoff_h, gs);
       h.doff.upload(h.doff_h, gs);
@@ -689,12 +700,12 @@ class Builder {
     if (t == D) {
       H2_HIP(h2dev::bsr_gemm(s_, L.nn, h.nptr.get(), h.nidx.get(), h.leafoff.get(), h.doff.get(), h.Dblk.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             L.max_m, xr, xr_.cap()));
+                             L.max_m, xr, xr_.cap(), 64, h.norder.get()));
     } else {
       Level& C = h.lv[t + 1];
       H2_HIP(h2dev::bsr_gemm(s_, C.nn, C.fptr.get(), C.fidx.get(), C.koff.get(), C.boff.get(), C.B.get(),
                              L.om.get() + int64_t(c0) * L.M, L.M, L.y.get() + int64_t(c0) * L.M, L.M, nc, -1.0,
-                             std::max(C.max_k, 1), xr, xr_.cap()));
+                             std::max(C.max_k, 1), xr, xr_.cap(), 64, C.forder.get()));
     }
   }
 
@@ -836,6 +847,7 @@ class Builder {
       for (int j = L.fptr_h[s]; j < L.fptr_h[s + 1]; ++j) bsz[j] = int64_t(L.k_h[s]) * L.k_h[L.fidx_h[j]];
     L.boff_h = prefix(bsz);
     L.fptr.upload(L.fptr_h, s_);
+    L.forder.upload(bsr_order(L.fptr_h), s_);
     L.fidx.upload(L.fidx_h, s_);
     L.boff.upload(L.boff_h, s_);
     L.B.alloc(static_cast<size_t>(L.boff_h.back()), s_);

@@ -57,11 +57,13 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
 // hipErrorInvalidValue).  tile_cols (16, 32, 48 or 64) is the column-tile width
 // of one workgroup: the columns are covered by ceil(nc / tile_cols) tiles, each
 // reading the blocks once; the sums are the same bit for bit for every width.
+// order (optional, device): the block rows in launch order, a permutation of
+// [0, nrows) (bsr_order: longest rows first); results do not depend on it.
 size_t bsr_scratch_doubles(int64_t ldx, int nc, int tile_cols = 64);
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
                     int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles,
-                    int tile_cols = 64);
+                    int tile_cols = 64, const int32_t* order = nullptr);
 
 // Two-sided form: block row i has rows [rowoff[i], rowoff[i+1]) of Y, block
 // column b rows [coloff[b], coloff[b+1]) of X; with tpos != nullptr the block of
@@ -70,7 +72,7 @@ hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t*
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     double* scratch, size_t scratch_doubles, int tile_cols = 64);
+                     double* scratch, size_t scratch_doubles, int tile_cols = 64, const int32_t* order = nullptr);
 
 // Row ID per cluster via column-pivoted QR of A = Y_loc^T (d x m): k[i], J (pivot order, local
 // row numbers, at joff[i]), U (m x k column-major at uoff[i], identity on rows J).

@@ -278,12 +278,17 @@ struct Level {
   std::vector<int32_t> fptr_h, fidx_h;
   std::vector<int64_t> boff_h;
   DevArray<int32_t> fptr, fidx;
+  DevArray<int32_t> forder;  // block rows of the far lists, longest first (may be empty)
   DevArray<int64_t> boff;
   DevArray<double> B;
   // sample buffers of row space R_t (capacity columns), only during a build
   DevArray<double> om, y;
   int64_t M = 0;
 };
+
+// Rows of a CSR list (ptr, rows + 1 entries) by decreasing length, ties in row
+// order: the launch order that balances a block-sparse product over the CUs.
+std::vector<int32_t> bsr_order(const std::vector<int32_t>& ptr);
 
 h2dev::KernelFn kernel_fn(const h2_kernel& k);
 void check_kernel(const h2_kernel* k);
@@ -382,6 +387,7 @@ struct h2_matrix {
   h2i::DevArray<int32_t> perm;
   h2i::DevArray<double> X;  // tree-ordered SoA points (single builds)
   h2i::DevArray<int32_t> nptr, nidx, leafoff;
+  h2i::DevArray<int32_t> norder;  // leaves by near-list length, longest first (may be empty)
   h2i::DevArray<int64_t> doff;
   std::vector<int64_t> doff_h;
   std::vector<int32_t> leafoff_h;

@@ -1403,7 +1403,9 @@ __device__ __forceinline__ void bsr_rows(const int32_t* __restrict__ idx, const 
 }
 
 // grid (nrows, ceil(nc / 16NB), ceil(max height / 64)); Xr has at least
-// gridDim.y * 16NB columns.  Two workgroups per CU by registers.
+// gridDim.y * 16NB columns.  Two workgroups per CU by registers.  order
+// (optional): workgroup b takes block row order[b], a permutation of the rows
+// (longest first balances the launch).
 template <int NB, bool TR>
 __global__ __launch_bounds__(256, 2) void bsr_gemm_kernel(const int32_t* __restrict__ ptr,
                                                           const int32_t* __restrict__ idx,
@@ -1413,10 +1415,11 @@ __global__ __launch_bounds__(256, 2) void bsr_gemm_kernel(const int32_t* __restr
                                                           const int64_t* __restrict__ blkoff,
                                                           const double* __restrict__ blocks,
                                                           const double* __restrict__ Xr, int ldr,
-                                                          double* __restrict__ Y, int64_t ldy, int nc, double alpha) {
+                                                          double* __restrict__ Y, int64_t ldy, int nc, double alpha,
+                                                          const int32_t* __restrict__ order) {
   constexpr int LDB = NB * 16;
   __shared__ dbl4 red[4 * 4 * 64];
-  const int i = blockIdx.x;
+  const int i = order ? order[blockIdx.x] : blockIdx.x;
   const int mfull = rowoff[i + 1] - rowoff[i];
   const int rz = blockIdx.z * 64;
   const int jb = ptr[i], je = ptr[i + 1];
@@ -3149,9 +3152,9 @@ hipError_t gen_blocks(hipStream_t s, int nrows, const int32_t* ptr, const int32_
 template <int NB, bool TR>
 void launch_bsr_nb(hipStream_t s, dim3 grid, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                    const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
-                   const double* Xr, int ldr, double* Y, int64_t ldy, int nc, double alpha) {
+                   const double* Xr, int ldr, double* Y, int64_t ldy, int nc, double alpha, const int32_t* order) {
   bsr_gemm_kernel<NB, TR><<<grid, 256, 0, s>>>(ptr, idx, rowoff, coloff, tpos, blkoff, blocks, Xr, ldr, Y, ldy, nc,
-                                               alpha);
+                                               alpha, order);
 }
 
 // 16-column groups per workgroup for nc columns and a tile width of tile_cols.
@@ -3169,7 +3172,7 @@ size_t bsr_scratch_doubles(int64_t ldx, int nc, int tile_cols) {
 hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                      const int32_t* coloff, const int64_t* tpos, const int64_t* blkoff, const double* blocks,
                      const double* X, int64_t ldx, double* Y, int64_t ldy, int nc, double alpha, int max_m,
-                     double* scratch, size_t scratch_doubles, int tile_cols) {
+                     double* scratch, size_t scratch_doubles, int tile_cols, const int32_t* order) {
   if (nrows <= 0 || nc <= 0 || ldx <= 0) return hipSuccess;
   if (tile_cols != 16 && tile_cols != 32 && tile_cols != 48 && tile_cols != 64) return hipErrorInvalidValue;
   if (max_m < 1) max_m = 1;
@@ -3183,8 +3186,10 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
   to_rows_kernel<<<tgrid, 256, 0, s>>>(ldx, nc, ldr, X, ldx, xr);
   const dim3 grid(nrows, ngrp, (max_m + 63) / 64);
 #define H2_BSR_NB(NB)                                                                                               \
-  (tpos ? launch_bsr_nb<NB, true>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha) \
-        : launch_bsr_nb<NB, false>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha))
+  (tpos ? launch_bsr_nb<NB, true>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha, \
+                                  order)                                                                             \
+        : launch_bsr_nb<NB, false>(s, grid, ptr, idx, rowoff, coloff, tpos, blkoff, blocks, xr, ldr, Y, ldy, nc, alpha, \
+                                   order))
   switch (nb) {
     case 1: H2_BSR_NB(1); break;
     case 2: H2_BSR_NB(2); break;
@@ -3198,9 +3203,9 @@ hipError_t bsr_gemm2(hipStream_t s, int nrows, const int32_t* ptr, const int32_t
 hipError_t bsr_gemm(hipStream_t s, int nrows, const int32_t* ptr, const int32_t* idx, const int32_t* rowoff,
                     const int64_t* blkoff, const double* blocks, const double* X, int64_t ldx, double* Y,
                     int64_t ldy, int nc, double alpha, int max_m, double* scratch, size_t scratch_doubles,
-                    int tile_cols) {
+                    int tile_cols, const int32_t* order) {
   return bsr_gemm2(s, nrows, ptr, idx, rowoff, rowoff, nullptr, blkoff, blocks, X, ldx, Y, ldy, nc, alpha, max_m,
-                   scratch, scratch_doubles, tile_cols);
+                   scratch, scratch_doubles, tile_cols, order);
 }
 
 hipError_t cpqr_id(hipStream_t s, int nnodes, const int32_t* rowoff, const double* Y, int64_t ldy, int d,
