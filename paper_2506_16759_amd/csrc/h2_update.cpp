@@ -108,6 +108,7 @@ class UpdateBuilder {
     h.leafoff.upload(h.leafoff_h, s_);
     h.doff.upload(h.doff_h, s_);
     h.nptr.upload(p.near_ptr, s_);
+    h.norder.upload(bsr_order(p.near_ptr), s_);
     h.nidx.upload(p.near_idx, s_);
     h.lr_rank = r_;
     if (r_ > 0) {
@@ -267,11 +268,11 @@ class UpdateBuilder {
     double* xr = xr_.get(std::max(Mr, Mc), nc, s_);
     H2_HIP(h2dev::bsr_gemm2(s_, Cr.nn, Cr.fptr.get(), Cr.fidx.get(), Cr.koff.get(), Cc.koff.get(), nullptr,
                             Cr.boff.get(), Cr.B.get(), Lr.om.get() + int64_t(c0) * Mc, Mc,
-                            Lr.y.get() + int64_t(c0) * Mr, Mr, nc, -1.0, mk, xr, xr_.cap()));
+                            Lr.y.get() + int64_t(c0) * Mr, Mr, nc, -1.0, mk, xr, xr_.cap(), 64, Cr.forder.get()));
     // column side: Z -= B_{b,s}^T (U_b^T Omega'_b)
     H2_HIP(h2dev::bsr_gemm2(s_, Cr.nn, Cr.fptr.get(), Cr.fidx.get(), Cc.koff.get(), Cr.koff.get(),
                             h.tpos[t + 1].get(), Cr.boff.get(), Cr.B.get(), Lc.om.get() + int64_t(c0) * Mr, Mr,
-                            Lc.y.get() + int64_t(c0) * Mc, Mc, nc, -1.0, mk, xr, xr_.cap()));
+                            Lc.y.get() + int64_t(c0) * Mc, Mc, nc, -1.0, mk, xr, xr_.cap(), 64, Cr.forder.get()));
   }
 
   // Shrink with each side's own ID; random vectors carried up by the other side's ID.
@@ -447,6 +448,7 @@ class UpdateBuilder {
       for (int j = Lr.fptr_h[a]; j < Lr.fptr_h[a + 1]; ++j) bsz[j] = int64_t(Lr.k_h[a]) * Lc.k_h[Lr.fidx_h[j]];
     Lr.boff_h = prefix(bsz);
     Lr.fptr.upload(Lr.fptr_h, s_);
+    Lr.forder.upload(bsr_order(Lr.fptr_h), s_);
     Lr.fidx.upload(Lr.fidx_h, s_);
     Lr.boff.upload(Lr.boff_h, s_);
     Lr.B.alloc(size_t(Lr.boff_h.back()), s_);
