@@ -122,3 +122,25 @@ def test_sym_limits(ctx):
         h2.build_batched(ctx, [{"points": uniform_points(1000, 3, 1), "kernel": "exp", "length": 0.2}],
                          precision=h2.FP64_SYM)
     assert e.value.status == -7
+
+
+def test_sym_build_helmholtz_matches_oracle(ctx):
+    """cos(3r)/r (zero on the diagonal) with the symmetric-tile sketch: the same
+    structure as the oracle's construction and its accuracy."""
+    n, kw, leaf, tol = 4096, 3.0, 64, 1e-6
+    _say(f"symmetric-sketch helmholtz build n={n} k={kw} tol={tol}")
+    pts = uniform_points(n, 3, 1234)
+    H = h2.build(ctx, pts, "helmholtz", wavenumber=kw, tol=tol, leaf_size=leaf, d0=32, d_inc=16, seed=1003,
+                 precision=h2.FP64_SYM)
+    info = H.info()
+    op = KernelOperator(pts, "helmholtz", kw)
+    ho = build_h2(op, pts, leaf, 0.7, tol, 32, 16, 256, 1003)
+    assert info["samples"] == ho.samples
+    diff = compare_with_oracle(H, ho)
+    x = np.random.default_rng(3).standard_normal((n, 4))
+    y, yo, kx = _np(H.matvec(_colmajor_from(x))), ho.matvec(x), op.sketch(x)
+    e_or = np.linalg.norm(y - yo) / np.linalg.norm(yo)
+    e_k = np.linalg.norm(y - kx) / np.linalg.norm(kx)
+    _say(f"samples {info['samples']} ranks {info['rank_min']}..{info['rank_max']} ID diff {diff} "
+         f"vs oracle {e_or:.3e} vs exact {e_k:.3e}")
+    assert e_or <= 1e-10 and e_k <= 10 * tol
