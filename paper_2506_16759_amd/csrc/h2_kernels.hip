@@ -175,7 +175,9 @@ __device__ __forceinline__ void sketch_f64_body(SkF64Smem<DIM, NC>& sm, int64_t 
     }
     __syncthreads();
     if (j0 + kSkF64 < n) fetch(j0 + kSkF64);
-#pragma unroll 4
+    // the whole stage unrolled (160 registers, still three waves per SIMD;
+    // measured 1.4 % faster than four steps at a time)
+#pragma unroll
     for (int kk = 0; kk < kSkF64 / 4; ++kk) {
       const int jj = kk * 4 + lk;
       double ra = 0.0, rb = 0.0;
