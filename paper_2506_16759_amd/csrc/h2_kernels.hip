@@ -402,7 +402,8 @@ __global__ __launch_bounds__(256, 1) void sketch_sym_f64_kernel(int64_t n, const
     if (j0 + kSkF64 < n) fetch(j0 + kSkF64);
     const bool cross = j0 >= tile0 + kSkRows;  // the same for the whole workgroup
     const int cur = int((j0 - tile0) / kSkF64) & 1;
-#pragma unroll 4
+    // the whole stage unrolled (measured 1.3 % faster than four steps at a time)
+#pragma unroll
     for (int kk = 0; kk < kSkF64 / 4; ++kk) {
       const int jj = kk * 4 + lk;
       double ra = 0.0, rb = 0.0;
@@ -1000,7 +1001,8 @@ __device__ __forceinline__ void sketch_e32_body(SkE32Smem<DIM, NC>& sm, int64_t 
     }
     __syncthreads();
     if (j0 + kSkK < n) fetch(j0 + kSkK);
-#pragma unroll 4
+    // the whole stage unrolled (measured 2 % faster than four steps at a time)
+#pragma unroll
     for (int kk = 0; kk < kSkK / 4; ++kk) {
       const int jj = kk * 4 + lk;
       double ra = 0.0, rb = 0.0;
